@@ -1,0 +1,24 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _cpu_libs():
+    """Compile the generator and oracle C libraries if nothing is built."""
+    import gen
+    import oracle
+    if not os.path.exists(gen._SO):
+        gen.build()
+    if not os.path.exists(oracle._SO):
+        oracle.build()
+    yield

@@ -1,0 +1,438 @@
+"""Pins of the CPU oracle against facts fixed outside it (no GPU needed).
+
+Each check compares the oracle with something it does not compute itself:
+pure-Python path enumeration (the definition of cost[x] in Section I), the
+paper's worked example, closed-form round counts, breadth-first search,
+numpy's stable sort, and finite differences for the gradient.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+I32_INF = np.int32(2**31 - 1)
+
+
+def _inf(dt):
+    return I32_INF if np.dtype(dt) == np.int32 else np.dtype(dt).type(np.inf)
+
+
+def tiny_graph(rng, dtype, n=None, m=None):
+    n = int(rng.integers(1, 9)) if n is None else n
+    m = int(rng.integers(0, 5 * n + 1)) if m is None else m
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    if np.dtype(dtype) == np.int32:
+        w = rng.integers(1, 20, m).astype(np.int32)
+    else:
+        w = (rng.random(m) * 4 + 2.0 ** -20).astype(dtype)
+    return n, src, dst, w, int(rng.integers(0, n))
+
+
+def brute_force_paths(n, src, dst, w, s):
+    """min over simple paths of the left-fold path sum in the weight type."""
+    dt = w.dtype.type
+    out = [None] * n
+    out[s] = dt(0)
+    adj = [[] for _ in range(n)]
+    for i in range(len(src)):
+        adj[int(src[i])].append((int(dst[i]), w[i]))
+
+    def walk(v, acc, seen):
+        for (y, wy) in adj[v]:
+            if y in seen:
+                continue
+            if np.dtype(dt) == np.int32:
+                c = dt(int(acc) + int(wy))
+            else:
+                c = dt(acc + wy)
+            if out[y] is None or c < out[y]:
+                out[y] = c
+            seen.add(y)
+            walk(y, c, seen)
+            seen.discard(y)
+
+    walk(s, dt(0), {s})
+    res = np.full(n, _inf(w.dtype), dtype=w.dtype)
+    for v in range(n):
+        if out[v] is not None:
+            res[v] = out[v]
+    return res
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32, np.float64])
+def test_dijkstra_matches_path_enumeration(dtype):
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 7)))
+        c, settles = oracle.dijkstra(n, src, dst, w, s)
+        bf = brute_force_paths(n, src, dst, w, s)
+        assert np.array_equal(c, bf), (n, src, dst, w, s, c, bf)
+        assert settles == int(np.sum(c != _inf(dtype)))
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32, np.float64])
+def test_dijkstra_matches_bellman_ford(dtype):
+    rng = np.random.default_rng(12)
+    for _ in range(3000):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 13)),
+                                       m=int(rng.integers(0, 61)))
+        c, _ = oracle.dijkstra(n, src, dst, w, s)
+        assert np.array_equal(c, oracle.bellman_ford(n, src, dst, w, s))
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_dijkstra_matches_dag_dp(dtype):
+    rng = np.random.default_rng(13)
+    for _ in range(300):
+        n = int(rng.integers(2, 40))
+        order = rng.permutation(n).astype(np.int32)
+        m = int(rng.integers(0, 4 * n))
+        a = rng.integers(0, n, m)
+        b = rng.integers(0, n, m)
+        keep = a != b
+        lo, hi = np.minimum(a, b)[keep], np.maximum(a, b)[keep]
+        src, dst = order[lo], order[hi]
+        w = (rng.integers(1, 50, len(src)).astype(np.int32) if dtype == np.int32
+             else rng.random(len(src)).astype(np.float32) + np.float32(2.0 ** -20))
+        s = int(order[0])
+        c, _ = oracle.dijkstra(n, src, dst, w, s)
+        assert np.array_equal(c, oracle.dag(n, src, dst, w, s))
+
+
+def test_unit_weights_are_bfs():
+    for side in (1, 5, 17):
+        g = gen.grid_workload(side=side)
+        w = np.ones(g.m, dtype=np.int32)
+        c, _ = oracle.dijkstra(g.n, g.src, g.dst, w, g.source)
+        hops = oracle.bfs(g.n, g.src, g.dst, g.source)
+        assert np.array_equal(np.where(hops < 0, I32_INF, hops), c)
+    g = gen.random_workload(n=500, m=1200)
+    w = np.ones(g.m, dtype=np.int32)
+    c, _ = oracle.dijkstra(g.n, g.src, g.dst, w, g.source)
+    hops = oracle.bfs(g.n, g.src, g.dst, g.source)
+    assert np.array_equal(np.where(hops < 0, I32_INF, hops), c)
+
+
+def _worked_graphs():
+    ex = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    for extra in ex["edge_into_v2_variants"]:
+        e = np.array(ex["edges_common"] + [extra], dtype=np.int64)
+        yield ex, e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2].astype(np.int32)
+
+
+def test_worked_example_costs_pred_rounds():
+    for ex, src, dst, w in _worked_graphs():
+        n, s = ex["n"], ex["source"]
+        c, settles = oracle.dijkstra(n, src, dst, w, s)
+        assert c.tolist() == ex["cost"]
+        assert settles == 5
+        # the paper's inWeight values (min in-weight other than from the
+        # vertex that discovered v, SP_2) follow from the weights
+        for v, iw in ex["inWeight"].items():
+            z = ex["discovered_by"][v]
+            assert int(w[(dst == int(v)) & (src != z)].min()) == iw
+        g = oracle.csr(n, src, dst)
+        p, ties = oracle.pred(g, w, s, c)
+        tails = [-1 if e < 0 else int(src[g.perm[e]]) for e in p]
+        assert tails == [-1, 0, 0, 2, 2] and ties == 0
+        # Hand derivation of the adopted round on this graph:
+        # round 1 relaxes v0: D1=9, D2=2; minD=2, thr=min(9+2, 2+5)=7.
+        #   v1's only in-edge is from fixed v0 -> C1 = D1 -> fixed; D2=2<=thr -> fixed.
+        # round 2 relaxes v1, v2: D3=8, D4=7; minD=7, thr=min(8+1, 7+8)=9 (or
+        #   8+inf, 7+1 with the v4->v2 variant: thr=8): both D<=thr -> fixed.
+        # round 3 relaxes v3, v4: no open vertex -> stop.  rounds=3, fixed [2,2,0].
+        r = oracle.round_sim(n, src, dst, w, s, true_cost=c)
+        assert r["cost"].tolist() == ex["cost"]
+        assert r["rounds"] == 3 and r["fixed_per_round"].tolist() == [2, 2, 0]
+        assert r["violations"] == 0
+
+
+def test_fig5_literal_order_counterexample():
+    """Fig. 5 run as printed fixes vertex 2 at 5 in round 2 (threshold is
+    inf, since vertex 2 has no out-edge) before vertex 1's out-edge is
+    relaxed; the adopted order relaxes first and gets the true cost 2."""
+    src = np.array([0, 1, 0], np.int32)
+    dst = np.array([1, 2, 2], np.int32)
+    for w in (np.array([1, 1, 5], np.int32), np.array([1, 1, 5], np.float32)):
+        lit = oracle.round_sim(3, src, dst, w, 0, mode=oracle.MODE_LITERAL_FIG5)
+        assert lit["cost"].tolist() == [0, 1, 5]
+        ok = oracle.round_sim(3, src, dst, w, 0)
+        assert ok["cost"].tolist() == [0, 1, 2] == oracle.dijkstra(3, src, dst, w, 0)[0].tolist()
+
+
+def test_round_closed_forms():
+    # path of k+1 vertices: one vertex per round, plus the final empty relax
+    for k in (1, 2, 7, 30):
+        src = np.arange(k, dtype=np.int32)
+        dst = src + 1
+        w = np.full(k, 3, np.int32)
+        r = oracle.round_sim(k + 1, src, dst, w, 0)
+        assert r["rounds"] == k + 1
+    # star: all leaves fixed in round 1 (sole in-edge from the fixed centre)
+    for leaves in (1, 5, 100):
+        src = np.zeros(leaves, np.int32)
+        dst = np.arange(1, leaves + 1, dtype=np.int32)
+        w = np.arange(1, leaves + 1, dtype=np.int32)[::-1].copy()
+        r = oracle.round_sim(leaves + 1, src, dst, w, 0)
+        assert r["rounds"] == 2 and r["fixed_per_round"].tolist() == [leaves, 0]
+    # unit weights: one BFS layer per round (SP_2 theorem on unweighted graphs)
+    for g in (gen.grid_workload(side=9), gen.random_workload(n=300, m=900)):
+        w = np.ones(g.m, np.int32)
+        hops = oracle.bfs(g.n, g.src, g.dst, g.source)
+        r = oracle.round_sim(g.n, g.src, g.dst, w, g.source)
+        assert r["rounds"] == hops.max() + 1
+        layer = np.bincount(hops[hops > 0], minlength=hops.max() + 1)[1:]
+        assert r["fixed_per_round"].tolist() == layer.tolist() + [0]
+
+
+def test_round_dag_depth_bound():
+    """Acyclic graph whose only root is the source (the SP_1 theorem's
+    condition): every vertex is fixed once all its in-neighbours are, so
+    rounds <= longest hop depth + 1."""
+    rng = np.random.default_rng(14)
+    for _ in range(100):
+        n = int(rng.integers(2, 60))
+        src, dst = [], []
+        for v in range(1, n):
+            for u in rng.choice(v, size=int(rng.integers(1, min(v, 4) + 1)), replace=False):
+                src.append(u)
+                dst.append(v)
+        src, dst = np.array(src, np.int32), np.array(dst, np.int32)
+        w = rng.integers(1, 100, len(src)).astype(np.int32)
+        depth = np.zeros(n, np.int64)
+        for v in range(1, n):
+            depth[v] = 1 + depth[src[dst == v]].max()
+        r = oracle.round_sim(n, src, dst, w, 0)
+        assert np.array_equal(r["cost"], oracle.dag(n, src, dst, w, 0))
+        assert r["rounds"] <= depth.max() + 1
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_round_sim_costs_and_invariants(dtype):
+    rng = np.random.default_rng(15)
+    for _ in range(400):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 30)))
+        c, settles = oracle.dijkstra(n, src, dst, w, s)
+        for mode in (oracle.MODE_ADOPTED, oracle.MODE_SCOPE_ALL):
+            r = oracle.round_sim(n, src, dst, w, s, mode=mode, true_cost=c)
+            assert np.array_equal(r["cost"], c)
+            assert r["violations"] == 0
+            assert 1 <= r["rounds"] <= settles
+            assert sum(r["fixed_per_round"]) == settles - 1
+
+
+@pytest.mark.parametrize("family", ["random", "grid", "rmat", "batch"])
+def test_round_sim_matches_dijkstra_on_workload_families(family):
+    if family == "random":
+        g = gen.random_workload()
+    elif family == "grid":
+        g = gen.grid_workload(side=40)
+    elif family == "rmat":
+        g = gen.rmat_workload(scale=12)
+    else:
+        g = gen.batch_workload(count=2, nmin=500, nmax=3000)[1]
+    c, settles = oracle.dijkstra(g.n, g.src, g.dst, g.w, g.source)
+    r = oracle.round_sim(g.n, g.src, g.dst, g.w, g.source, true_cost=c)
+    assert np.array_equal(r["cost"], c)
+    assert r["violations"] == 0
+    assert r["rounds"] <= settles
+    assert r["relaxed_edges"] == int(np.sum(c[g.src] != _inf(g.w.dtype)))
+
+
+def test_csr_matches_numpy_stable_sort():
+    g = gen.rmat_workload(scale=10)
+    G = oracle.csr(g.n, g.src, g.dst)
+    perm = np.argsort(g.src, kind="stable")
+    assert np.array_equal(G.perm, perm)
+    assert np.array_equal(G.out_dst, g.dst[perm])
+    assert np.array_equal(G.out_off, np.concatenate([[0], np.cumsum(np.bincount(g.src, minlength=g.n))]))
+    eids = np.argsort(g.dst[perm], kind="stable")
+    assert np.array_equal(G.in_eid, eids)
+    assert np.array_equal(G.in_src, g.src[perm][eids])
+    ow, iw, wmin = G.weights(g.w)
+    assert np.array_equal(ow, g.w[perm]) and np.array_equal(iw, ow[eids])
+    ref = np.full(g.n, I32_INF, np.int32)
+    np.minimum.at(ref, g.src, g.w)
+    assert np.array_equal(wmin, ref)
+
+
+def brute_pred(n, src, dst, w, s, cost, perm):
+    """Tie rule by enumeration: eid = stable CSR position (inverse of perm)."""
+    eid_of = np.empty(len(src), np.int64)
+    eid_of[perm] = np.arange(len(src))
+    inf = _inf(w.dtype)
+    dt = w.dtype.type
+
+    def add(a, b):
+        if np.dtype(dt) == np.int32:
+            return inf if (a == inf or b == inf) else dt(int(a) + int(b))
+        return dt(a + b)
+
+    tight = [[] for _ in range(n)]
+    for i in range(len(src)):
+        u, y = int(src[i]), int(dst[i])
+        if cost[u] != inf and cost[y] != inf and add(cost[u], w[i]) == cost[y]:
+            tight[y].append((int(eid_of[i]), u))
+    pred = np.full(n, -1, np.int64)
+    level = {s: 0}
+    for y in range(n):
+        if y == s or cost[y] == inf:
+            continue
+        strict = [e for (e, u) in tight[y] if cost[u] < cost[y]]
+        if strict:
+            pred[y] = min(strict)
+            level[y] = 0
+    frontier = [v for v in level]
+    lv = 0
+    while frontier:
+        nxt = []
+        for y in range(n):
+            if y in level or y == s or cost[y] == inf:
+                continue
+            if any(u in level and level[u] == lv and cost[u] == cost[y] for (_, u) in tight[y]):
+                nxt.append(y)
+        for y in nxt:
+            level[y] = lv + 1
+        frontier = nxt
+        lv += 1
+    for y in range(n):
+        if y == s or cost[y] == inf or pred[y] >= 0:
+            continue
+        pred[y] = min(e for (e, u) in tight[y] if level.get(u) == level[y] - 1 and cost[u] == cost[y])
+    return pred
+
+
+def check_tree(n, s, cost, pred, out_src_of_eid, inf):
+    for y in range(n):
+        if y == s or cost[y] == inf:
+            assert pred[y] == -1
+            continue
+        assert pred[y] >= 0
+        seen = set()
+        v = y
+        while v != s:
+            assert v not in seen
+            seen.add(v)
+            v = out_src_of_eid[pred[v]]
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_pred_tie_rule_brute_force(dtype):
+    rng = np.random.default_rng(16)
+    for _ in range(400):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 12)))
+        if dtype == np.int32:
+            w = rng.integers(1, 4, len(src)).astype(np.int32)  # many ties
+        c, _ = oracle.dijkstra(n, src, dst, w, s)
+        g = oracle.csr(n, src, dst)
+        p, _ = oracle.pred(g, w, s, c)
+        assert np.array_equal(p, brute_pred(n, src, dst, w, s, c, g.perm))
+        check_tree(n, s, c, p, src[g.perm], _inf(dtype))
+
+
+def test_pred_equal_cost_float_ties():
+    """Edges of weight 2^-30 on cost-1.0 vertices are tight at equal cost
+    (1 + 2^-30 rounds to 1 in float32); the level rule keeps a tree."""
+    tiny = np.float32(2.0 ** -30)
+    # s=0 -> a=1 (1.0); a->b, b->c, c->b, c->a, b->a all tiny; ids chosen so
+    # that the smallest tight id into b comes from c (a cycle if taken).
+    src = np.array([2, 0, 1, 1, 2, 3], np.int32)
+    dst = np.array([1, 1, 2, 1, 3, 2], np.int32)
+    w = np.array([tiny, 1.0, tiny, tiny, tiny, tiny], np.float32)
+    n, s = 4, 0
+    c, _ = oracle.dijkstra(n, src, dst, w, s)
+    assert c.tolist() == [0.0, 1.0, 1.0, 1.0]
+    g = oracle.csr(n, src, dst)
+    p, ties = oracle.pred(g, w, s, c)
+    assert ties == 2
+    assert np.array_equal(p, brute_pred(n, src, dst, w, s, c, g.perm))
+    check_tree(n, s, c, p, src[g.perm], np.float32(np.inf))
+    tails = src[g.perm][p[1:]]
+    assert tails.tolist() == [0, 1, 2]
+
+
+def test_gradient_matches_path_sums_and_fd():
+    rng = np.random.default_rng(17)
+    for trial in range(20):
+        n = int(rng.integers(3, 25))
+        m = int(rng.integers(n, 5 * n))
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        w = rng.random(m) + 0.1
+        S = 3
+        sources = rng.choice(n, S, replace=False).astype(np.int32)
+        gco = rng.standard_normal((S, n))
+        G = oracle.csr(n, src, dst)
+        preds, costs = [], []
+        for s in sources:
+            c, _ = oracle.dijkstra(n, src, dst, w, int(s))
+            p, ties = oracle.pred(G, w, int(s), c)
+            assert ties == 0
+            preds.append(p)
+            costs.append(c)
+        grad = oracle.grad(G, sources, np.array(preds), gco)
+        # brute force: each reachable x adds g[s,x] to every edge on its tree path
+        tail_of = src[G.perm]
+        ref = np.zeros(m)
+        for si, s in enumerate(sources):
+            for x in range(n):
+                if x == s or not np.isfinite(costs[si][x]):
+                    continue
+                v = x
+                while v != s:
+                    e = preds[si][v]
+                    ref[e] += gco[si, x]
+                    v = tail_of[e]
+        np.testing.assert_allclose(grad, ref, rtol=1e-12, atol=1e-12)
+        # central finite differences in fp64 (paths unique a.s. for random w)
+        wcsr = w[G.perm]
+
+        def loss(wc):
+            wcoo = np.empty(m)
+            wcoo[G.perm] = wc
+            tot = 0.0
+            for si, s in enumerate(sources):
+                c, _ = oracle.dijkstra(n, src, dst, wcoo, int(s))
+                fin = np.isfinite(c)
+                tot += float(np.sum(gco[si][fin] * c[fin]))
+            return tot
+
+        h = 1e-7
+        for e in rng.choice(m, min(m, 8), replace=False):
+            d = np.zeros(m)
+            d[e] = h
+            fd = (loss(wcsr + d) - loss(wcsr - d)) / (2 * h)
+            assert abs(fd - grad[e]) <= 1e-5 * max(1.0, abs(grad[e]))
+
+
+def test_generators_deterministic_and_in_range():
+    a = gen.random_workload()
+    b = gen.random_workload()
+    assert np.array_equal(a.src, b.src) and np.array_equal(a.w, b.w)
+    assert a.m == 32768 and a.n == 4096 and a.source == 0
+    assert not np.any(a.src == a.dst)
+    assert a.w.min() >= 1 and a.w.max() <= 100
+    gr = gen.grid_workload(side=16)
+    assert gr.m == 2 * 2 * 16 * 15 and gr.source == 8 * 16 + 8
+    assert gr.w.min() >= 1 and gr.w.max() <= 1000
+    r = gen.rmat_workload(scale=10)
+    assert r.m == 16 * 1024
+    deg = np.bincount(r.src, minlength=r.n)
+    assert deg[r.source] == deg.max() and r.source == int(np.argmax(deg))
+    assert r.w.min() >= 1 and r.w.max() <= 255
+    bl = gen.batch_workload(count=3, nmin=1000, nmax=2000)
+    for g in bl:
+        assert 1000 <= g.n <= 2000 and g.m == 8 * g.n and 0 <= g.source < g.n
+        assert g.w.min() > 0 and g.w.max() <= 1.0
+        assert np.all((g.w * np.float32(2 ** 24)) == np.round(g.w * np.float32(2 ** 24)))
+    d, gco = gen.diff_workload(side=16, num_sources=5)
+    assert len(set(d.sources.tolist())) == 5 and gco.shape == (5, 256)
+    assert d.w.min() >= 0.5 and d.w.max() <= 1.5
+    assert abs(float(gen.normal_f32(1, 100000).std()) - 1.0) < 0.02
