@@ -1,0 +1,196 @@
+/*
+ * sssp.h -- C ABI of the MI355X (gfx950) lower/upper-bound single-source
+ * shortest-path library.
+ *
+ * Method: V. K. Garg, "Removing Sequential Bottleneck of Dijkstra's
+ * Algorithm for the Shortest Path Problem".  Every vertex x carries an upper
+ * bound D[x] (a feasible path cost, as in Dijkstra's algorithm, Fig. 1) and
+ * a lower bound C[x] (Section IV: no path to x is cheaper than C[x]).  One
+ * data-parallel round (the Section V / Fig. 5 iteration, in the sound order
+ * documented at sssp_solve) relaxes the out-edges of the vertices fixed in
+ * the previous round, raises C of every discovered non-fixed vertex from its
+ * in-edges (Eq. 1 with the global bound of Lemma crule2), and fixes every
+ * vertex whose bounds meet or whose D is within the threshold of Lemma
+ * crauser.  Many vertices settle per round instead of Dijkstra's one.
+ *
+ * Conventions shared by every call:
+ *  - Graph and state pointers are DEVICE pointers owned by the caller; they
+ *    must stay valid until the work queued on `stream` has completed.
+ *    Pointers documented as host pointers are read before the call returns.
+ *  - Vertex ids are int32 in [0, n).  Edge ids are positions in the CSR by
+ *    tail (the builder's stable order: edges of one tail keep their input
+ *    order).  m < 2^31.
+ *  - Weights are strictly positive (Section I) and finite: int32 >= 1, or
+ *    float32 > 0.  INF ("no path") is INT32_MAX for int32 and +inf for
+ *    float32.  For int32 graphs the library requires (n-1) * w_max <
+ *    INT32_MAX so that no finite path cost reaches INF.
+ *  - Path costs are exact: int32 sums, or the float32 left fold of the path
+ *    in path order with one round-to-nearest-even add per edge.  Since
+ *    rounding is monotone, the float32 minimum over paths does not depend
+ *    on the order in which edges are relaxed.
+ *  - Calls are asynchronous on `stream` unless stated otherwise.  Errors a
+ *    host can see (null pointers, bad sizes, ids out of range, dtype,
+ *    overflow precondition) are returned synchronously and nothing is
+ *    queued.  No C++ exception crosses this boundary.
+ *  - The library keeps a per-device workspace cache (allocated with
+ *    hipMalloc on first use or growth, freed by sssp_release_workspace).
+ *    Concurrent calls on one device from several host threads are
+ *    serialized by the library.
+ */
+#ifndef SSSP_H
+#define SSSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SSSP_I32 = 0, SSSP_F32 = 1 } sssp_dtype;
+
+typedef enum {
+  SSSP_OK = 0,
+  SSSP_ERR_ARG = 1,      /* null pointer, bad size, id out of range, dtype */
+  SSSP_ERR_GRAPH = 2,    /* edge endpoint out of range in the input edges */
+  SSSP_ERR_WEIGHT = 3,   /* weight <= 0, NaN or infinite */
+  SSSP_ERR_OVERFLOW = 4, /* int32: (n-1) * w_max >= INT32_MAX */
+  SSSP_ERR_NOMEM = 5,    /* workspace allocation failed */
+  SSSP_ERR_HIP = 6,      /* a HIP runtime call failed */
+  SSSP_ERR_INTERNAL = 7  /* round watchdog tripped (rounds > n + 1) */
+} sssp_status;
+
+/*
+ * A built graph: CSR by tail plus CSC by head (the incoming-edge access the
+ * method assumes, Section I).  All arrays are device arrays.
+ *   out_off[n+1], out_dst[m], out_w[m]        CSR; edge id = CSR position
+ *   in_off[n+1],  in_src[m], in_eid[m], in_w[m]
+ *       CSC; in_eid[j] is the edge id of CSC entry j, and each vertex's
+ *       in-list is ascending by edge id; in_w[j] = out_w[in_eid[j]]
+ *   out_wmin[n]   minimum out-edge weight per vertex, INF if none (the
+ *                 outWeight array of SP_3 and SP_4, Figs. 4 and 5)
+ *   w_max         largest weight (filled by the builder; used for the
+ *                 int32 overflow precondition)
+ */
+typedef struct {
+  int32_t n;
+  int32_t m;
+  int32_t dtype; /* sssp_dtype */
+  int32_t reserved;
+  const int32_t *out_off;
+  const int32_t *out_dst;
+  const void *out_w;
+  const int32_t *in_off;
+  const int32_t *in_src;
+  const int32_t *in_eid;
+  const void *in_w;
+  const void *out_wmin;
+  double w_max;
+} sssp_csr;
+
+/* Per-solve counters (host struct). */
+typedef struct {
+  int32_t rounds;            /* rounds of the method (non-empty frontiers) */
+  int32_t settled;           /* reachable vertices (Dijkstra's removeMin count) */
+  int64_t relaxed_edges;     /* out-edges of fixed vertices relaxed (once each) */
+  int64_t scanned_in_edges;  /* in-edges scanned by the lower-bound step */
+} sssp_stats;
+
+/*
+ * Bytes of the device buffer sssp_build_csr fills for a graph of n vertices,
+ * m edges and the given dtype.  Returns 0 for invalid sizes.
+ */
+size_t sssp_build_csr_bytes(int32_t n, int32_t m, sssp_dtype dtype);
+
+/*
+ * Build the CSR/CSC of a directed graph from COO edges on the GPU.
+ * Inputs (device): src[m], dst[m] vertex ids; w[m] weights (int32 or
+ * float32 per dtype).  Self-loops and duplicate edges are kept.
+ * buffer: device buffer of at least sssp_build_csr_bytes(n, m, dtype)
+ * bytes, owned by the caller; *out receives pointers into it.
+ * perm (device, nullable): perm[k] = COO index of edge id k.
+ * Validates endpoints (SSSP_ERR_GRAPH), weights (SSSP_ERR_WEIGHT) and the
+ * int32 overflow precondition (SSSP_ERR_OVERFLOW).  SYNCHRONOUS: returns
+ * after the stream work has completed.
+ */
+sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, const int32_t *src,
+                           const int32_t *dst, const void *w, void *buffer, size_t buffer_bytes,
+                           sssp_csr *out, int32_t *perm, void *stream);
+
+/*
+ * Replace the weights of a built graph: w[m] (device) is given in edge-id
+ * order; out_w, in_w, out_wmin and w_max of *g are rewritten in place (the
+ * arrays live in the caller's build buffer).  Validates weights and the
+ * overflow precondition.  SYNCHRONOUS.
+ */
+sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream);
+
+/*
+ * Single-source shortest paths by rounds of the lower/upper-bound method.
+ *   cost[n] (device, dtype of g): cost[x] = minimum path cost (Section I),
+ *           INF if x is unreachable.
+ *   pred[n] (device, nullable): parent pointer (Section I) as an edge id:
+ *           the smallest id among tight in-edges (cost[v] + w == cost[x])
+ *           with cost[v] < cost[x]; for float32 graphs where only
+ *           equal-cost tight in-edges exist (w below half an ulp of cost),
+ *           the smallest id among those whose tail is one breadth-first
+ *           level closer to a vertex with a strict tight in-edge inside the
+ *           equal-cost class.  -1 for the source and unreachable vertices.
+ *   stats (host, nullable): if non-null the call synchronizes the stream
+ *           and fills *stats.
+ * One round, with O the discovered non-fixed vertices:
+ *   (A) relax out-edges of the previous round's newly fixed vertices;
+ *   (B) minD = min D over O; thr = min over O of D[y] + out_wmin[y];
+ *   (C) for y in O: m_y = min over in-edges (v,y,w), v not fixed, of
+ *       max(C[v], minD) + w;  C'[y] = max(C[y], minD, min(D[y], m_y))
+ *       (all reads of C before any write);
+ *   (D) fix y iff C'[y] >= D[y] or D[y] <= thr; stop when (A) leaves O
+ *       empty.  rounds <= settled.
+ */
+sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
+                       sssp_stats *stats, void *stream);
+
+/*
+ * Many independent solves in one persistent launch.
+ *   graphs[num_graphs] (host array of built graphs, all of one dtype)
+ *   inst_graph[num_inst], inst_source[num_inst] (host): instance i solves
+ *           graph inst_graph[i] from inst_source[i].
+ *   cost, pred (device): instance i occupies entries
+ *           [base_i, base_i + n_i) with base_i = sum_{j<i} n of graph
+ *           inst_graph[j]; pred is nullable.  sum of n_i < 2^31.
+ *   stats (host, nullable): num_inst entries; synchronizes.
+ * Results are identical, instance by instance, to sssp_solve.
+ */
+sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
+                             const int32_t *inst_graph, const int32_t *inst_source,
+                             int32_t num_inst, void *cost, int32_t *pred, sssp_stats *stats,
+                             void *stream);
+
+/*
+ * Gradient of L = sum_i sum_x grad_cost[base_i + x] * cost_i[x] with respect
+ * to every edge weight, taking cost_i[x] as the weight sum along the pred
+ * tree path (an exact derivative where shortest paths are unique).
+ *   graphs, inst_graph, inst_source, num_inst as in sssp_solve_batch;
+ *   pred (device): the pred output of the forward solve, same layout.
+ *   grad_cost (device float32, same layout): entries of unreachable
+ *           vertices are ignored.
+ *   grad_w (device float32, overwritten): graph g's edges occupy
+ *           [ebase_g, ebase_g + m_g) with ebase_g = sum_{h<g} m_h, in edge-id
+ *           order; each graph's gradient is summed over its instances in
+ *           instance order, so results are deterministic.
+ */
+sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int32_t *inst_graph,
+                          const int32_t *inst_source, int32_t num_inst, const int32_t *pred,
+                          const float *grad_cost, float *grad_w, void *stream);
+
+/* Free the calling device's workspace cache (synchronizes the device). */
+sssp_status sssp_release_workspace(void);
+
+/* Static message for a status code. */
+const char *sssp_strerror(sssp_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSSP_H */

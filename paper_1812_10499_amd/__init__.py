@@ -1,0 +1,16 @@
+"""MI355X (gfx950) lower/upper-bound single-source shortest paths.
+
+The method (V. K. Garg, "Removing Sequential Bottleneck of Dijkstra's
+Algorithm for the Shortest Path Problem") keeps an upper bound D and a lower
+bound C per vertex and fixes every vertex whose bounds meet, many per round.
+The rounds run as hand-written HIP kernels in libsssp.so behind the C ABI of
+include/sssp.h; this package is its Python binding.
+"""
+from ._abi import (  # noqa: F401
+    EXPORTS, LIB_PATH, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_HIP, SSSP_ERR_INTERNAL,
+    SSSP_ERR_NOMEM, SSSP_ERR_OVERFLOW, SSSP_ERR_WEIGHT, SSSP_F32, SSSP_I32, SSSP_OK, Csr,
+    SSSPError, Stats, lib, sssp_backward,
+    sssp_build_csr, sssp_build_csr_bytes, sssp_release_workspace, sssp_set_weights, sssp_solve,
+    sssp_solve_batch, sssp_strerror)
+from .graph import (  # noqa: F401
+    I32_INF, Graph, SSSPFunction, backward, batch_layout, shortest_paths, solve, solve_batch)

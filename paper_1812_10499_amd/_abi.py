@@ -1,0 +1,137 @@
+"""ctypes binding of the C ABI declared in include/sssp.h.
+
+Argument marshalling only: every function here forwards to the function of
+the same name in libsssp.so and raises :class:`SSSPError` on a non-zero
+status.  Pointers are passed as Python ints (device addresses, e.g.
+``tensor.data_ptr()``), streams as the raw HIP stream handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (load PyTorch's HIP runtime first: one runtime per process)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsssp.so")
+
+SSSP_I32, SSSP_F32 = 0, 1
+(SSSP_OK, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_WEIGHT, SSSP_ERR_OVERFLOW, SSSP_ERR_NOMEM,
+ SSSP_ERR_HIP, SSSP_ERR_INTERNAL) = range(8)
+
+EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_solve",
+           "sssp_solve_batch", "sssp_backward", "sssp_release_workspace", "sssp_strerror")
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("out_off", ctypes.c_void_p), ("out_dst", ctypes.c_void_p),
+                ("out_w", ctypes.c_void_p), ("in_off", ctypes.c_void_p),
+                ("in_src", ctypes.c_void_p), ("in_eid", ctypes.c_void_p),
+                ("in_w", ctypes.c_void_p), ("out_wmin", ctypes.c_void_p),
+                ("w_max", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("settled", ctypes.c_int32),
+                ("relaxed_edges", ctypes.c_int64), ("scanned_in_edges", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SSSPError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (where, sssp_strerror(status), status))
+
+
+_lib = None
+
+
+def lib():
+    """Load libsssp.so; fails loudly if the HIP library was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsssp.so is not built; run paper_1812_10499_amd.build.build() "
+                              "(hipcc --offload-arch=gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p
+        L.sssp_build_csr_bytes.argtypes = [i32, i32, ctypes.c_int]
+        L.sssp_build_csr_bytes.restype = ctypes.c_size_t
+        L.sssp_build_csr.argtypes = [i32, i32, ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t,
+                                     ctypes.POINTER(Csr), vp, vp]
+        L.sssp_build_csr.restype = ctypes.c_int
+        L.sssp_set_weights.argtypes = [ctypes.POINTER(Csr), vp, vp]
+        L.sssp_set_weights.restype = ctypes.c_int
+        L.sssp_solve.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, ctypes.POINTER(Stats), vp]
+        L.sssp_solve.restype = ctypes.c_int
+        L.sssp_solve_batch.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, i32, vp, vp,
+                                       ctypes.POINTER(Stats), vp]
+        L.sssp_solve_batch.restype = ctypes.c_int
+        L.sssp_backward.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, i32, vp, vp, vp, vp]
+        L.sssp_backward.restype = ctypes.c_int
+        L.sssp_release_workspace.argtypes = []
+        L.sssp_release_workspace.restype = ctypes.c_int
+        L.sssp_strerror.argtypes = [ctypes.c_int]
+        L.sssp_strerror.restype = ctypes.c_char_p
+        del i64p
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != SSSP_OK:
+        raise SSSPError(status, where)
+
+
+def _arr(ctype, values):
+    values = [int(v) for v in values]
+    return (ctype * len(values))(*values)
+
+
+def sssp_strerror(status: int) -> str:
+    return lib().sssp_strerror(int(status)).decode()
+
+
+def sssp_build_csr_bytes(n: int, m: int, dtype: int) -> int:
+    return int(lib().sssp_build_csr_bytes(n, m, dtype))
+
+
+def sssp_build_csr(n, m, dtype, src, dst, w, buffer, buffer_bytes, out: Csr, perm, stream):
+    _check(lib().sssp_build_csr(n, m, dtype, src, dst, w, buffer, buffer_bytes,
+                                ctypes.byref(out), perm, stream), "sssp_build_csr")
+
+
+def sssp_set_weights(g: Csr, w, stream):
+    _check(lib().sssp_set_weights(ctypes.byref(g), w, stream), "sssp_set_weights")
+
+
+def sssp_solve(g: Csr, source, cost, pred, stats, stream):
+    _check(lib().sssp_solve(ctypes.byref(g), source, cost, pred,
+                            ctypes.byref(stats) if stats is not None else None, stream),
+           "sssp_solve")
+
+
+def sssp_solve_batch(graphs, inst_graph, inst_source, cost, pred, stats, stream):
+    ga = (Csr * len(graphs))(*graphs)
+    ig = _arr(ctypes.c_int32, inst_graph)
+    isrc = _arr(ctypes.c_int32, inst_source)
+    _check(lib().sssp_solve_batch(ga, len(graphs), ctypes.cast(ig, ctypes.c_void_p),
+                                  ctypes.cast(isrc, ctypes.c_void_p), len(ig), cost, pred,
+                                  stats, stream), "sssp_solve_batch")
+
+
+def sssp_backward(graphs, inst_graph, inst_source, pred, grad_cost, grad_w, stream):
+    ga = (Csr * len(graphs))(*graphs)
+    ig = _arr(ctypes.c_int32, inst_graph)
+    isrc = _arr(ctypes.c_int32, inst_source)
+    _check(lib().sssp_backward(ga, len(graphs), ctypes.cast(ig, ctypes.c_void_p),
+                               ctypes.cast(isrc, ctypes.c_void_p), len(ig), pred, grad_cost,
+                               grad_w, stream), "sssp_backward")
+
+
+def sssp_release_workspace():
+    _check(lib().sssp_release_workspace(), "sssp_release_workspace")

@@ -1,0 +1,599 @@
+// Host runtime behind the C ABI in include/sssp.h: argument checks, the
+// per-device workspace cache, launch geometry, and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "sssp.h"
+#include "sssp_kernels.h"
+
+using namespace sssp;
+
+namespace {
+
+enum Slot {
+  S_C, S_MTMP, S_OV0, S_OP0, S_OI0, S_OV1, S_OP1, S_OI1, S_FV, S_FP, S_FI, S_CTL,
+  S_IMIN, S_ITHR, S_IROUNDS, S_ISCAN, S_HEAVY, S_DEGEN, S_LVL, S_FLAG, S_SPRED, S_ISTAT,
+  S_GTAB, S_ITAB,
+  S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
+  S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
+  NSLOTS
+};
+
+struct DevWS {
+  bool init = false;
+  void *buf[NSLOTS] = {};
+  size_t cap[NSLOTS] = {};
+  int cus = 0;
+  int bpc[4] = {0, 0, 0, 0};  // blocks per CU of the round kernel per (f32, batch)
+  void *pinned = nullptr;     // host staging for tables and stats
+  size_t pinned_cap = 0;
+  hipEvent_t last = nullptr;  // completion of the previous call's work
+  hipEvent_t staged = nullptr;
+};
+
+std::mutex g_mu;
+DevWS g_ws[64];
+
+struct Guard {
+  std::lock_guard<std::mutex> lk;
+  Guard() : lk(g_mu) {}
+};
+
+sssp_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return SSSP_OK;
+  if (e == hipErrorOutOfMemory) return SSSP_ERR_NOMEM;
+  return SSSP_ERR_HIP;
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t _e = (x);                            \
+    if (_e != hipSuccess) return hip_status(_e);    \
+  } while (0)
+
+sssp_status ws_get(DevWS &w, int slot, size_t bytes, void **out) {
+  if (bytes == 0) bytes = 256;
+  if (w.cap[slot] < bytes) {
+    if (w.buf[slot]) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(w.buf[slot]));
+      w.buf[slot] = nullptr;
+      w.cap[slot] = 0;
+    }
+    size_t want = bytes + bytes / 8;  // headroom against repeated growth
+    if (hipMalloc(&w.buf[slot], want) != hipSuccess) {
+      (void)hipGetLastError();
+      w.buf[slot] = nullptr;
+      return SSSP_ERR_NOMEM;
+    }
+    w.cap[slot] = want;
+  }
+  *out = w.buf[slot];
+  return SSSP_OK;
+}
+
+template <class T>
+sssp_status ws_arr(DevWS &w, int slot, size_t count, T **out) {
+  void *p = nullptr;
+  sssp_status s = ws_get(w, slot, count * sizeof(T), &p);
+  *out = (T *)p;
+  return s;
+}
+
+sssp_status pinned_get(DevWS &w, size_t bytes, void **out) {
+  // the previous call's host->device table copy must have consumed the buffer
+  if (w.staged) HIPCHK(hipEventSynchronize(w.staged));
+  if (w.pinned_cap < bytes) {
+    if (w.pinned) HIPCHK(hipHostFree(w.pinned));
+    w.pinned = nullptr;
+    w.pinned_cap = 0;
+    if (hipHostMalloc(&w.pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      w.pinned = nullptr;
+      return SSSP_ERR_NOMEM;
+    }
+    w.pinned_cap = bytes;
+  }
+  *out = w.pinned;
+  return SSSP_OK;
+}
+
+sssp_status ws_for_current(DevWS **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SSSP_ERR_ARG;
+  DevWS &w = g_ws[dev];
+  if (!w.init) {
+    HIPCHK(hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipEventCreateWithFlags(&w.last, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&w.staged, hipEventDisableTiming));
+    w.init = true;
+  }
+  *out = &w;
+  return SSSP_OK;
+}
+
+// Persistent grid: co-resident blocks, capped at SSSP_BLOCKS_PER_CU (default 2).
+sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
+  const int k = (f32 ? 1 : 0) + (batch ? 2 : 0);
+  if (w.bpc[k] == 0) {
+    int occ = 0;
+    HIPCHK(round_kernel_occupancy(f32, batch, &occ));
+    int cap = 2;
+    if (const char *s = getenv("SSSP_BLOCKS_PER_CU")) {
+      int v = atoi(s);
+      if (v >= 1 && v <= 16) cap = v;
+    }
+    w.bpc[k] = occ < cap ? occ : cap;
+    if (w.bpc[k] < 1) return SSSP_ERR_HIP;
+  }
+  geo->blocks = w.cus * w.bpc[k];
+  geo->cus = w.cus;
+  return SSSP_OK;
+}
+
+bool csr_ok(const sssp_csr *g) {
+  return g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
+         g->out_off && g->in_off && g->out_wmin &&
+         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w));
+}
+
+bool overflow_risk(const sssp_csr *g) {
+  if (g->dtype != SSSP_I32) return false;
+  return (double)(g->n - 1) * g->w_max >= (double)INT_MAX;
+}
+
+GraphDev graph_dev(const sssp_csr *g) {
+  GraphDev d;
+  d.out_off = g->out_off;
+  d.out_dst = g->out_dst;
+  d.out_w = (const int32_t *)g->out_w;
+  d.in_off = g->in_off;
+  d.in_src = g->in_src;
+  d.in_eid = g->in_eid;
+  d.in_w = (const int32_t *)g->in_w;
+  d.out_wmin = (const int32_t *)g->out_wmin;
+  d.n = g->n;
+  d.m = g->m;
+  return d;
+}
+
+struct Layout {
+  size_t off[8];
+  size_t total;
+};
+
+Layout build_layout(int32_t n, int32_t m) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  L.off[0] = take(sizeof(int32_t) * ((size_t)n + 1));  // out_off
+  L.off[1] = take(sizeof(int32_t) * (size_t)m);        // out_dst
+  L.off[2] = take(sizeof(int32_t) * (size_t)m);        // out_w
+  L.off[3] = take(sizeof(int32_t) * ((size_t)n + 1));  // in_off
+  L.off[4] = take(sizeof(int32_t) * (size_t)m);        // in_src
+  L.off[5] = take(sizeof(int32_t) * (size_t)m);        // in_eid
+  L.off[6] = take(sizeof(int32_t) * (size_t)m);        // in_w
+  L.off[7] = take(sizeof(int32_t) * (size_t)n);        // out_wmin
+  L.total = o;
+  return L;
+}
+
+// Round-state buffers for `total` state entries.
+sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
+                          RoundArgs &a) {
+  const size_t T = (size_t)total;
+  sssp_status s;
+  if ((s = ws_arr(w, S_C, T, &a.C))) return s;
+  if ((s = ws_arr(w, S_MTMP, T, &a.mtmp))) return s;
+  if ((s = ws_arr(w, S_OV0, T, &a.open_v0))) return s;
+  if ((s = ws_arr(w, S_OP0, T, &a.open_p0))) return s;
+  if ((s = ws_arr(w, S_OV1, T, &a.open_v1))) return s;
+  if ((s = ws_arr(w, S_OP1, T, &a.open_p1))) return s;
+  if ((s = ws_arr(w, S_FV, T, &a.front_v))) return s;
+  if ((s = ws_arr(w, S_FP, T, &a.front_p))) return s;
+  if ((s = ws_arr(w, S_CTL, 1, &a.ctl))) return s;
+  if ((s = ws_arr(w, S_HEAVY, 2 * T, &a.heavy))) return s;
+  if ((s = ws_arr(w, S_DEGEN, 2 * T, &a.degen))) return s;
+  if ((s = ws_arr(w, S_LVL, T, &a.lvl))) return s;
+  if ((s = ws_arr(w, S_FLAG, T, &a.flag))) return s;
+  if (batch) {
+    if ((s = ws_arr(w, S_OI0, T, &a.open_i0))) return s;
+    if ((s = ws_arr(w, S_OI1, T, &a.open_i1))) return s;
+    if ((s = ws_arr(w, S_FI, T, &a.front_i))) return s;
+    if ((s = ws_arr(w, S_IMIN, 3 * (size_t)num_inst, &a.imin))) return s;
+    if ((s = ws_arr(w, S_ITHR, 3 * (size_t)num_inst, &a.ithr))) return s;
+    if ((s = ws_arr(w, S_IROUNDS, (size_t)num_inst, &a.irounds))) return s;
+    if ((s = ws_arr(w, S_ISCAN, (size_t)num_inst, &a.iscanned))) return s;
+  }
+  return SSSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sssp_strerror(sssp_status st) {
+  switch (st) {
+    case SSSP_OK: return "ok";
+    case SSSP_ERR_ARG: return "invalid argument";
+    case SSSP_ERR_GRAPH: return "edge endpoint out of range";
+    case SSSP_ERR_WEIGHT: return "weight not strictly positive and finite";
+    case SSSP_ERR_OVERFLOW: return "int32 path costs could reach INT32_MAX ((n-1)*w_max too large)";
+    case SSSP_ERR_NOMEM: return "device workspace allocation failed";
+    case SSSP_ERR_HIP: return "HIP runtime error";
+    case SSSP_ERR_INTERNAL: return "internal error (round watchdog)";
+  }
+  return "unknown status";
+}
+
+size_t sssp_build_csr_bytes(int32_t n, int32_t m, sssp_dtype dtype) {
+  if (n <= 0 || m < 0 || (dtype != SSSP_I32 && dtype != SSSP_F32)) return 0;
+  return build_layout(n, m).total;
+}
+
+sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, const int32_t *src,
+                           const int32_t *dst, const void *w, void *buffer, size_t buffer_bytes,
+                           sssp_csr *out, int32_t *perm, void *stream_) {
+  if (n <= 0 || m < 0 || (dtype != SSSP_I32 && dtype != SSSP_F32) || !out || !buffer)
+    return SSSP_ERR_ARG;
+  if (m > 0 && (!src || !dst || !w)) return SSSP_ERR_ARG;
+  const Layout L = build_layout(n, m);
+  if (buffer_bytes < L.total) return SSSP_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool f32 = dtype == SSSP_F32;
+  Guard guard;
+  DevWS *wp;
+  sssp_status s;
+  if ((s = ws_for_current(&wp))) return s;
+  DevWS &ws = *wp;
+  HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
+  char *b = (char *)buffer;
+  int32_t *out_off = (int32_t *)(b + L.off[0]), *out_dst = (int32_t *)(b + L.off[1]);
+  int32_t *out_w = (int32_t *)(b + L.off[2]), *in_off = (int32_t *)(b + L.off[3]);
+  int32_t *in_src = (int32_t *)(b + L.off[4]), *in_eid = (int32_t *)(b + L.off[5]);
+  int32_t *in_w = (int32_t *)(b + L.off[6]), *out_wmin = (int32_t *)(b + L.off[7]);
+  BuildTemps t;
+  const size_t M = (size_t)(m > 0 ? m : 1);
+  if ((s = ws_arr(ws, S_BK_KA, M, &t.ka))) return s;
+  if ((s = ws_arr(ws, S_BK_KB, M, &t.kb))) return s;
+  if ((s = ws_arr(ws, S_BK_VA, M, &t.va))) return s;
+  if ((s = ws_arr(ws, S_BK_VB, M, &t.vb))) return s;
+  if ((s = ws_arr(ws, S_BK_TAIL, M, &t.tail))) return s;
+  if ((s = ws_arr(ws, S_BK_HIST, build_hist_entries(m), &t.hist))) return s;
+  if ((s = ws_arr(ws, S_BK_STATUS, 2, &t.status))) return s;
+  HIPCHK(hipMemsetAsync(t.status, 0, 2 * sizeof(int32_t), stream));
+  HIPCHK(launch_validate(n, m, f32, src, dst, (const int32_t *)w, t.status, stream));
+  int32_t hs[2];
+  HIPCHK(hipMemcpyAsync(hs, t.status, sizeof(hs), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (hs[0] & 1) return SSSP_ERR_GRAPH;
+  if (hs[0] & 2) return SSSP_ERR_WEIGHT;
+  out->n = n;
+  out->m = m;
+  out->dtype = dtype;
+  out->reserved = 0;
+  out->out_off = out_off;
+  out->out_dst = out_dst;
+  out->out_w = out_w;
+  out->in_off = in_off;
+  out->in_src = in_src;
+  out->in_eid = in_eid;
+  out->in_w = in_w;
+  out->out_wmin = out_wmin;
+  if (f32) {
+    float f;
+    memcpy(&f, &hs[1], sizeof(f));
+    out->w_max = (double)f;
+  } else {
+    out->w_max = (double)hs[1];
+  }
+  if (overflow_risk(out)) return SSSP_ERR_OVERFLOW;
+  HIPCHK(launch_build(n, m, f32, src, dst, (const int32_t *)w, out_off, out_dst, out_w, in_off,
+                      in_src, in_eid, in_w, out_wmin, perm, t, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  HIPCHK(hipEventRecord(ws.last, stream));
+  return SSSP_OK;
+}
+
+sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
+  if (!csr_ok(g) || (g->m > 0 && !w)) return SSSP_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool f32 = g->dtype == SSSP_F32;
+  Guard guard;
+  DevWS *wp;
+  sssp_status s;
+  if ((s = ws_for_current(&wp))) return s;
+  DevWS &ws = *wp;
+  HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
+  int32_t *status;
+  if ((s = ws_arr(ws, S_BK_STATUS, 2, &status))) return s;
+  HIPCHK(hipMemsetAsync(status, 0, 2 * sizeof(int32_t), stream));
+  HIPCHK(launch_set_weights(g->n, g->m, f32, (const int32_t *)w, g->out_off, g->in_eid,
+                            (int32_t *)g->out_w, (int32_t *)g->in_w, (int32_t *)g->out_wmin,
+                            status, stream));
+  int32_t hs[2];
+  HIPCHK(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  HIPCHK(hipEventRecord(ws.last, stream));
+  if (hs[0] & 2) return SSSP_ERR_WEIGHT;
+  if (f32) {
+    float f;
+    memcpy(&f, &hs[1], sizeof(f));
+    g->w_max = (double)f;
+  } else {
+    g->w_max = (double)hs[1];
+  }
+  if (overflow_risk(g)) return SSSP_ERR_OVERFLOW;
+  return SSSP_OK;
+}
+
+sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
+                       sssp_stats *stats, void *stream_) {
+  if (!csr_ok(g) || !cost || source < 0 || source >= g->n) return SSSP_ERR_ARG;
+  if (overflow_risk(g)) return SSSP_ERR_OVERFLOW;
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool f32 = g->dtype == SSSP_F32;
+  Guard guard;
+  DevWS *wp;
+  sssp_status s;
+  if ((s = ws_for_current(&wp))) return s;
+  DevWS &ws = *wp;
+  RoundArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = graph_dev(g);
+  a.num_inst = 1;
+  a.source = source;
+  a.total = g->n;
+  a.max_rounds = g->n + 1;
+  a.D = (int32_t *)cost;
+  if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
+  LaunchGeom geo;
+  if ((s = geometry(ws, f32, false, &geo))) return s;
+  HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
+  HIPCHK(launch_solve(f32, false, a, pred, geo, nullptr, g->n, stream));
+  if (stats) {
+    void *hp;
+    if ((s = pinned_get(ws, sizeof(Ctl), &hp))) return s;
+    HIPCHK(hipMemcpyAsync(hp, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const Ctl *c = (const Ctl *)hp;
+    stats->rounds = c->rounds;
+    stats->settled = (int32_t)c->settled;
+    stats->relaxed_edges = c->relaxed;
+    stats->scanned_in_edges = c->scanned;
+    if (c->status) {
+      HIPCHK(hipEventRecord(ws.last, stream));
+      return SSSP_ERR_INTERNAL;
+    }
+  }
+  HIPCHK(hipEventRecord(ws.last, stream));
+  return SSSP_OK;
+}
+
+sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
+                             const int32_t *inst_graph, const int32_t *inst_source,
+                             int32_t num_inst, void *cost, int32_t *pred, sssp_stats *stats,
+                             void *stream_) {
+  if (!graphs || num_graphs <= 0 || !inst_graph || !inst_source || num_inst <= 0 || !cost)
+    return SSSP_ERR_ARG;
+  const int32_t dtype = graphs[0].dtype;
+  for (int32_t gi = 0; gi < num_graphs; ++gi) {
+    if (!csr_ok(&graphs[gi]) || graphs[gi].dtype != dtype) return SSSP_ERR_ARG;
+    if (overflow_risk(&graphs[gi])) return SSSP_ERR_OVERFLOW;
+  }
+  int64_t total = 0;
+  int32_t max_n = 0;
+  for (int32_t i = 0; i < num_inst; ++i) {
+    const int32_t gi = inst_graph[i];
+    if (gi < 0 || gi >= num_graphs) return SSSP_ERR_ARG;
+    const int32_t n = graphs[gi].n;
+    if (inst_source[i] < 0 || inst_source[i] >= n) return SSSP_ERR_ARG;
+    total += n;
+    if (n > max_n) max_n = n;
+  }
+  if (total >= (int64_t)INT_MAX) return SSSP_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool f32 = dtype == SSSP_F32;
+  Guard guard;
+  DevWS *wp;
+  sssp_status s;
+  if ((s = ws_for_current(&wp))) return s;
+  DevWS &ws = *wp;
+  RoundArgs a;
+  memset(&a, 0, sizeof(a));
+  a.num_inst = num_inst;
+  a.total = (int32_t)total;
+  a.max_rounds = max_n + 1;
+  a.D = (int32_t *)cost;
+  if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
+  GraphDev *dg;
+  InstDev *di;
+  if ((s = ws_arr(ws, S_GTAB, (size_t)num_graphs, &dg))) return s;
+  if ((s = ws_arr(ws, S_ITAB, (size_t)num_inst, &di))) return s;
+  long long *istat = nullptr;
+  if (stats) {
+    if ((s = ws_arr(ws, S_ISTAT, 4 * (size_t)num_inst, &istat))) return s;
+    a.istat = istat;
+    if (!pred && (s = ws_arr(ws, S_SPRED, (size_t)a.total, &a.scratch_pred))) return s;
+  }
+  const size_t tab_bytes = sizeof(GraphDev) * num_graphs + sizeof(InstDev) * num_inst;
+  const size_t stat_bytes = (sizeof(long long) * 4 + sizeof(int32_t) + 8) * (size_t)num_inst;
+  void *hp;
+  if ((s = pinned_get(ws, tab_bytes + stat_bytes + 64, &hp))) return s;
+  GraphDev *hg = (GraphDev *)hp;
+  InstDev *hi = (InstDev *)(hg + num_graphs);
+  for (int32_t gi = 0; gi < num_graphs; ++gi) hg[gi] = graph_dev(&graphs[gi]);
+  int32_t base = 0;
+  for (int32_t i = 0; i < num_inst; ++i) {
+    hi[i].graph = inst_graph[i];
+    hi[i].source = inst_source[i];
+    hi[i].sbase = base;
+    hi[i].n = graphs[inst_graph[i]].n;
+    base += hi[i].n;
+  }
+  a.graphs = dg;
+  a.insts = di;
+  LaunchGeom geo;
+  if ((s = geometry(ws, f32, true, &geo))) return s;
+  HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
+  HIPCHK(hipMemcpyAsync(dg, hg, sizeof(GraphDev) * num_graphs, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(di, hi, sizeof(InstDev) * num_inst, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(ws.staged, stream));
+  HIPCHK(launch_solve(f32, true, a, pred, geo, istat, max_n, stream));
+  if (stats) {
+    // pinned space after the tables
+    char *hb = (char *)hp + ((tab_bytes + 63) & ~(size_t)63);
+    long long *hst = (long long *)hb;
+    int32_t *hr = (int32_t *)(hst + 4 * (size_t)num_inst);
+    HIPCHK(hipMemcpyAsync(hst, istat, sizeof(long long) * 4 * num_inst, hipMemcpyDeviceToHost,
+                          stream));
+    HIPCHK(hipMemcpyAsync(hr, a.irounds, sizeof(int32_t) * num_inst, hipMemcpyDeviceToHost,
+                          stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    std::vector<unsigned long long> sc(num_inst);
+    HIPCHK(hipMemcpy(sc.data(), a.iscanned, sizeof(unsigned long long) * num_inst,
+                     hipMemcpyDeviceToHost));
+    Ctl c;
+    HIPCHK(hipMemcpy(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < num_inst; ++i) {
+      stats[i].rounds = hr[i];
+      stats[i].settled = (int32_t)hst[4 * i + 1];
+      stats[i].relaxed_edges = hst[4 * i + 2];
+      stats[i].scanned_in_edges = (int64_t)sc[i];
+    }
+    HIPCHK(hipEventRecord(ws.last, stream));
+    if (c.status) return SSSP_ERR_INTERNAL;
+    return SSSP_OK;
+  }
+  HIPCHK(hipEventRecord(ws.last, stream));
+  return SSSP_OK;
+}
+
+sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int32_t *inst_graph,
+                          const int32_t *inst_source, int32_t num_inst, const int32_t *pred,
+                          const float *grad_cost, float *grad_w, void *stream_) {
+  if (!graphs || num_graphs <= 0 || !inst_graph || !inst_source || num_inst <= 0 || !pred ||
+      !grad_cost || !grad_w)
+    return SSSP_ERR_ARG;
+  for (int32_t gi = 0; gi < num_graphs; ++gi)
+    if (!csr_ok(&graphs[gi])) return SSSP_ERR_ARG;
+  int64_t total = 0, total_m = 0;
+  for (int32_t gi = 0; gi < num_graphs; ++gi) total_m += graphs[gi].m;
+  for (int32_t i = 0; i < num_inst; ++i) {
+    const int32_t gi = inst_graph[i];
+    if (gi < 0 || gi >= num_graphs) return SSSP_ERR_ARG;
+    if (inst_source[i] < 0 || inst_source[i] >= graphs[gi].n) return SSSP_ERR_ARG;
+    total += graphs[gi].n;
+  }
+  if (total >= (int64_t)INT_MAX || total_m >= (int64_t)INT_MAX) return SSSP_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  Guard guard;
+  DevWS *wp;
+  sssp_status s;
+  if ((s = ws_for_current(&wp))) return s;
+  DevWS &ws = *wp;
+  BackArgs b;
+  memset(&b, 0, sizeof(b));
+  b.num_inst = num_inst;
+  b.total = (int32_t)total;
+  b.pred = pred;
+  b.gcost = grad_cost;
+  GraphDev *dg;
+  InstDev *di;
+  int32_t *goff, *ginst, *ebase;
+  unsigned int *bctl;
+  if ((s = ws_arr(ws, S_GTAB, (size_t)num_graphs, &dg))) return s;
+  if ((s = ws_arr(ws, S_ITAB, (size_t)num_inst, &di))) return s;
+  if ((s = ws_arr(ws, S_BW_ACC, (size_t)total, &b.acc))) return s;
+  if ((s = ws_arr(ws, S_BW_LV, (size_t)total, &b.lv_v))) return s;
+  if ((s = ws_arr(ws, S_BW_LI, (size_t)total, &b.lv_i))) return s;
+  if ((s = ws_arr(ws, S_BW_LOFF, (size_t)total + 2, &b.lv_off))) return s;
+  if ((s = ws_arr(ws, S_BW_CTL, 8, &bctl))) return s;
+  if ((s = ws_arr(ws, S_BW_GOFF, (size_t)num_graphs + 1, &goff))) return s;
+  if ((s = ws_arr(ws, S_BW_GINST, (size_t)num_inst, &ginst))) return s;
+  if ((s = ws_arr(ws, S_BW_EBASE, (size_t)num_graphs + 1, &ebase))) return s;
+  b.barrier = bctl;
+  b.ctr = bctl + 1;
+  b.nlevels = (int32_t *)(bctl + 2);
+  b.graphs = dg;
+  b.insts = di;
+  const size_t tab_bytes = sizeof(GraphDev) * num_graphs + sizeof(InstDev) * num_inst +
+                           sizeof(int32_t) * (3 * (size_t)num_graphs + 2 + num_inst) + 64;
+  void *hp;
+  if ((s = pinned_get(ws, tab_bytes, &hp))) return s;
+  GraphDev *hg = (GraphDev *)hp;
+  InstDev *hi = (InstDev *)(hg + num_graphs);
+  int32_t *hgoff = (int32_t *)(hi + num_inst);
+  int32_t *hginst = hgoff + num_graphs + 1;
+  int32_t *hebase = hginst + num_inst;
+  for (int32_t gi = 0; gi < num_graphs; ++gi) hg[gi] = graph_dev(&graphs[gi]);
+  int32_t base = 0;
+  for (int32_t i = 0; i < num_inst; ++i) {
+    hi[i].graph = inst_graph[i];
+    hi[i].source = inst_source[i];
+    hi[i].sbase = base;
+    hi[i].n = graphs[inst_graph[i]].n;
+    base += hi[i].n;
+  }
+  // instances grouped by graph, in instance order within a graph
+  for (int32_t gi = 0; gi <= num_graphs; ++gi) hgoff[gi] = 0;
+  for (int32_t i = 0; i < num_inst; ++i) hgoff[inst_graph[i] + 1]++;
+  for (int32_t gi = 0; gi < num_graphs; ++gi) hgoff[gi + 1] += hgoff[gi];
+  {
+    std::vector<int32_t> fill(hgoff, hgoff + num_graphs);
+    for (int32_t i = 0; i < num_inst; ++i) hginst[fill[inst_graph[i]]++] = i;
+  }
+  int32_t eb = 0;
+  for (int32_t gi = 0; gi < num_graphs; ++gi) {
+    hebase[gi] = eb;
+    eb += graphs[gi].m;
+  }
+  hebase[num_graphs] = eb;
+  LaunchGeom geo;
+  if ((s = geometry(ws, true, true, &geo))) return s;
+  HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
+  HIPCHK(hipMemcpyAsync(dg, hg, sizeof(GraphDev) * num_graphs, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(di, hi, sizeof(InstDev) * num_inst, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(goff, hgoff, sizeof(int32_t) * (num_graphs + 1), hipMemcpyHostToDevice,
+                        stream));
+  HIPCHK(hipMemcpyAsync(ginst, hginst, sizeof(int32_t) * num_inst, hipMemcpyHostToDevice,
+                        stream));
+  HIPCHK(hipMemcpyAsync(ebase, hebase, sizeof(int32_t) * (num_graphs + 1),
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(ws.staged, stream));
+  HIPCHK(launch_backward(b, geo, goff, ginst, ebase, num_graphs, (int32_t)total_m, grad_w,
+                         stream));
+  HIPCHK(hipEventRecord(ws.last, stream));
+  return SSSP_OK;
+}
+
+sssp_status sssp_release_workspace(void) {
+  Guard guard;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SSSP_ERR_ARG;
+  DevWS &w = g_ws[dev];
+  if (!w.init) return SSSP_OK;
+  HIPCHK(hipDeviceSynchronize());
+  for (int i = 0; i < NSLOTS; ++i) {
+    if (w.buf[i]) HIPCHK(hipFree(w.buf[i]));
+    w.buf[i] = nullptr;
+    w.cap[i] = 0;
+  }
+  if (w.pinned) HIPCHK(hipHostFree(w.pinned));
+  w.pinned = nullptr;
+  w.pinned_cap = 0;
+  return SSSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Backward pass of the shortest-path costs with respect to edge weights.
+//
+// With cost_i[x] the weight sum along the pred-tree path from instance i's
+// source to x, L = sum_i sum_x g_i[x] * cost_i[x] has
+//   dL/dw[e] = sum_i [e == pred_i[head(e)]] * acc_i[head(e)],
+//   acc_i[y] = g_i[y] + sum over tree children c of y of acc_i[c].
+// The tree's children of y are the heads of y's out-edges e with
+// pred[head(e)] == e, so no child lists are built: a top-down pass records
+// the tree level by level (persistent kernel, one grid barrier per level),
+// and a bottom-up pass computes acc deepest level first, each vertex adding
+// its children in edge-id order.  A final edge-parallel kernel sums the
+// instances of each graph in instance order.  Every sum has a fixed order,
+// so the result is deterministic.
+#include "sssp_dev.h"
+#include "sssp_kernels.h"
+
+namespace sssp {
+
+constexpr int BBS = kRoundBlock;
+
+__global__ void bw_init_kernel(BackArgs a) {
+  for (int i = threadIdx.x; i < a.num_inst; i += blockDim.x) {
+    const InstDev id = a.insts[i];
+    a.lv_v[i] = id.sbase + id.source;
+    a.lv_i[i] = i;
+  }
+  if (threadIdx.x == 0) {
+    *a.barrier = 0u;
+    *a.ctr = (unsigned int)a.num_inst;
+    a.lv_off[0] = 0;
+    a.lv_off[1] = a.num_inst;
+    *a.nlevels = 0;
+  }
+}
+
+__global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
+  __shared__ uint64_t scan[BBS / SSSP_WAVE + 1];
+  __shared__ unsigned int sbase;
+  const int tid = threadIdx.x;
+  const int nb = gridDim.x, bid = blockIdx.x;
+  unsigned int epoch = 0;
+  // ---- top-down: level L occupies [s, e) of the level list
+  int s = 0, e = a.num_inst, L = 0;
+  while (s < e) {
+    for (int b0 = s + bid * BBS; b0 < e; b0 += nb * BBS) {
+      const int idx = b0 + tid;
+      int32_t x = 0, ins = 0, sb = 0, vx = 0, k0 = 0, k1 = 0;
+      const GraphDev *G = nullptr;
+      uint32_t nch = 0;
+      if (idx < e) {
+        x = a.lv_v[idx];
+        ins = a.lv_i[idx];
+        const InstDev id = a.insts[ins];
+        sb = id.sbase;
+        G = &a.graphs[id.graph];
+        vx = x - sb;
+        k0 = G->out_off[vx];
+        k1 = G->out_off[vx + 1];
+        for (int32_t k = k0; k < k1; ++k)
+          if (a.pred[sb + G->out_dst[k]] == k) ++nch;
+      }
+      uint64_t tot;
+      const uint64_t ex = block_excl_scan64<BBS>((uint64_t)nch, scan, &tot);
+      if (tot > 0) {
+        if (tid == 0) sbase = atomicAdd(a.ctr, (unsigned int)tot);
+        __syncthreads();
+        uint32_t p = sbase + (uint32_t)ex;
+        if (idx < e && nch) {
+          for (int32_t k = k0; k < k1; ++k) {
+            const int32_t c = G->out_dst[k];
+            if (a.pred[sb + c] == k) {
+              a.lv_v[p] = sb + c;
+              a.lv_i[p] = ins;
+              ++p;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    grid_barrier(a.barrier, epoch);
+    s = e;
+    e = (int)__hip_atomic_load(a.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ++L;
+    if (bid == 0 && tid == 0) a.lv_off[L + 1] = e;
+  }
+  // levels 0..L-1 are non-empty; lv_off[0..L] are their bounds
+  grid_barrier(a.barrier, epoch);
+  // ---- bottom-up: deepest level first
+  for (int lv = L - 1; lv >= 0; --lv) {
+    const int ls = a.lv_off[lv], le = a.lv_off[lv + 1];
+    for (int idx = ls + bid * BBS + tid; idx < le; idx += nb * BBS) {
+      const int32_t y = a.lv_v[idx];
+      const InstDev id = a.insts[a.lv_i[idx]];
+      const GraphDev &G = a.graphs[id.graph];
+      const int32_t sb = id.sbase, vy = y - sb;
+      float acc = a.gcost[y];
+      for (int32_t k = G.out_off[vy]; k < G.out_off[vy + 1]; ++k) {
+        const int32_t c = sb + G.out_dst[k];
+        if (a.pred[c] == k) acc = __fadd_rn(acc, a.acc[c]);
+      }
+      a.acc[y] = acc;
+    }
+    grid_barrier(a.barrier, epoch);
+  }
+  if (bid == 0 && tid == 0) *a.nlevels = L;
+}
+
+// grad_w[ebase[g] + e] = sum over instances i of graph g (instance order) of
+// acc_i[head(e)] if pred_i[head(e)] == e
+__global__ void bw_grad_kernel(BackArgs a, const int32_t *goff, const int32_t *ginst,
+                               const int32_t *ebase, int32_t num_graphs, int32_t total_m,
+                               float *grad_w) {
+  for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < total_m;
+       q += gridDim.x * blockDim.x) {
+    int lo = 0, hi = num_graphs;  // ebase[lo] <= q < ebase[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (ebase[mid] <= q) lo = mid;
+      else hi = mid;
+    }
+    const GraphDev &G = a.graphs[lo];
+    const int32_t e = q - ebase[lo];
+    const int32_t y = G.out_dst[e];
+    float sum = 0.0f;
+    for (int32_t j = goff[lo]; j < goff[lo + 1]; ++j) {
+      const int32_t sb = a.insts[ginst[j]].sbase;
+      if (a.pred[sb + y] == e) sum = __fadd_rn(sum, a.acc[sb + y]);
+    }
+    grad_w[q] = sum;
+  }
+}
+
+hipError_t launch_backward(const BackArgs &a, const LaunchGeom &geo, const int32_t *goff,
+                           const int32_t *ginst, const int32_t *ebase, int32_t num_graphs,
+                           int32_t total_m, float *grad_w, hipStream_t stream) {
+  hipError_t e;
+  hipLaunchKernelGGL(bw_init_kernel, dim3(1), dim3(256), 0, stream, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int occ = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)bw_levels_kernel,
+                                                        BBS, 0)) != hipSuccess)
+    return e;
+  int per_cu = geo.blocks / (geo.cus > 0 ? geo.cus : 1);
+  if (occ < per_cu) per_cu = occ;
+  if (per_cu < 1) return hipErrorLaunchFailure;
+  BackArgs arg = a;
+  void *params[] = {&arg};
+  e = hipLaunchCooperativeKernel((const void *)bw_levels_kernel, dim3(geo.cus * per_cu),
+                                 dim3(BBS), params, 0, stream);
+  if (e != hipSuccess) return e;
+  int blocks = (total_m + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(bw_grad_kernel, dim3(blocks), dim3(256), 0, stream, a, goff, ginst, ebase,
+                     num_graphs, total_m, grad_w);
+  return hipGetLastError();
+}
+
+}  // namespace sssp

@@ -1,0 +1,339 @@
+// Graph builder on gfx950: COO edges -> CSR by tail (stable: the edges of a
+// tail keep their input order; edge id = CSR position) and CSC by head over
+// edge ids in increasing order (so every in-list is ascending by edge id).
+// This is the incoming-edge access the method assumes, built once per
+// graph; out_wmin is the per-vertex minimum out-edge weight (outWeight of
+// Figs. 4 and 5).
+//
+// Sorting: LSD radix sort of (key, value) int32 pairs with 8-bit digits;
+// each pass is a per-tile digit histogram, an exclusive scan over
+// (digit, tile) in digit-major order, and a stable scatter that ranks equal
+// digits inside a tile with 64-lane ballots.  Offsets come from the sorted
+// keys (position of each key change), so no atomics decide any order.
+#include "sssp_dev.h"
+#include "sssp_kernels.h"
+
+namespace sssp {
+
+constexpr int SBS = 256;             // threads per sort block
+constexpr int SKPT = 8;              // keys per thread per tile
+constexpr int STILE = SBS * SKPT;    // keys per tile
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_PT = 16;
+constexpr int SCAN_TILE = SCAN_BS * SCAN_PT;
+
+enum : int32_t { BAD_GRAPH = 1, BAD_WEIGHT = 2 };
+
+static inline int tiles_of(int32_t m) { return (m + STILE - 1) / STILE; }
+
+size_t build_hist_entries(int32_t m) {
+  const size_t nt = (size_t)tiles_of(m > 0 ? m : 1);
+  const size_t h = 256 * nt;
+  return h + (h + SCAN_TILE - 1) / SCAN_TILE + 64;
+}
+
+// -------------------------------------------------------------- validate
+__global__ void validate_kernel(int32_t n, int32_t m, int f32, const int32_t *src,
+                                const int32_t *dst, const int32_t *w, int32_t *status) {
+  int32_t bad = 0, wmax = 0;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const int32_t k = w[i];
+    if (src) {
+      const int32_t s = src[i], d = dst[i];
+      if (s < 0 || s >= n || d < 0 || d >= n) bad |= BAD_GRAPH;
+    }
+    // int32: w >= 1.  float32 key: w > 0 and finite  <=>  0 < bits < 0x7f800000
+    if (f32 ? (k <= 0 || k >= 0x7f800000) : (k < 1)) bad |= BAD_WEIGHT;
+    else wmax = kmax(wmax, k);
+  }
+  if (bad) atomicOr(&status[0], bad);
+  if (wmax) atomicMax(&status[1], wmax);
+}
+
+hipError_t launch_validate(int32_t n, int32_t m, bool f32, const int32_t *src,
+                           const int32_t *dst, const int32_t *w, int32_t *status,
+                           hipStream_t stream) {
+  const int blocks = m > 0 ? ((m + 255) / 256 < 8192 ? (m + 255) / 256 : 8192) : 1;
+  hipLaunchKernelGGL(validate_kernel, dim3(blocks), dim3(256), 0, stream, n, m, f32 ? 1 : 0,
+                     src, dst, w, status);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scan
+// exclusive prefix sum of int32 data[L] in place, three passes
+__global__ void scan_reduce_kernel(const int32_t *data, int32_t L, int32_t *sums) {
+  __shared__ uint64_t sc[SCAN_BS / SSSP_WAVE + 1];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int32_t s = 0;
+  for (int j = 0; j < SCAN_PT; ++j) {
+    const int64_t i = base + (int64_t)j * SCAN_BS + threadIdx.x;
+    if (i < L) s += data[i];
+  }
+  uint64_t tot;
+  block_excl_scan64<SCAN_BS>((uint64_t)(uint32_t)s, sc, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = (int32_t)tot;
+}
+
+__global__ void scan_sums_kernel(int32_t *sums, int32_t ns) {
+  __shared__ uint64_t sc[SCAN_BS / SSSP_WAVE + 1];
+  uint64_t run = 0;
+  for (int b0 = 0; b0 < ns; b0 += SCAN_BS) {
+    const int i = b0 + threadIdx.x;
+    const uint32_t v = i < ns ? (uint32_t)sums[i] : 0u;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan64<SCAN_BS>((uint64_t)v, sc, &tot);
+    if (i < ns) sums[i] = (int32_t)(run + ex);
+    run += tot;
+  }
+}
+
+__global__ void scan_apply_kernel(int32_t *data, int32_t L, const int32_t *sums) {
+  __shared__ uint64_t sc[SCAN_BS / SSSP_WAVE + 1];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  // each thread owns SCAN_PT consecutive elements
+  int32_t v[SCAN_PT];
+  int32_t s = 0;
+  const int64_t mine = base + (int64_t)threadIdx.x * SCAN_PT;
+  for (int j = 0; j < SCAN_PT; ++j) {
+    const int64_t i = mine + j;
+    v[j] = i < L ? data[i] : 0;
+    s += v[j];
+  }
+  uint64_t tot;
+  const uint64_t ex = block_excl_scan64<SCAN_BS>((uint64_t)(uint32_t)s, sc, &tot);
+  int32_t run = sums[blockIdx.x] + (int32_t)ex;
+  for (int j = 0; j < SCAN_PT; ++j) {
+    const int64_t i = mine + j;
+    if (i < L) data[i] = run;
+    run += v[j];
+  }
+}
+
+static hipError_t exclusive_scan(int32_t *data, int32_t L, int32_t *sums, hipStream_t stream) {
+  const int nb = (L + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(SCAN_BS), 0, stream, data, L, sums);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_BS), 0, stream, sums, nb);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(SCAN_BS), 0, stream, data, L, sums);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- radix sort
+__global__ void iota_kernel(int32_t *v, int32_t m) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    v[i] = i;
+}
+
+__global__ __launch_bounds__(SBS) void radix_hist_kernel(const int32_t *keys, int32_t m,
+                                                         int shift, int32_t *hist, int nt) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * STILE;
+  for (int j = 0; j < SKPT; ++j) {
+    const int64_t i = base + (int64_t)j * SBS + threadIdx.x;
+    if (i < m) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nt + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(SBS) void radix_scatter_kernel(const int32_t *kin,
+                                                            const int32_t *vin, int32_t *kout,
+                                                            int32_t *vout, int32_t m, int shift,
+                                                            const int32_t *offs, int nt) {
+  constexpr int NW = SBS / SSSP_WAVE;
+  __shared__ int32_t run[256];
+  __shared__ int32_t wcnt[NW][256];
+  const int t = threadIdx.x, w = t / SSSP_WAVE, l = lane_id();
+  run[t] = offs[(int64_t)t * nt + blockIdx.x];
+  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+  const int64_t base = (int64_t)blockIdx.x * STILE;
+  for (int j = 0; j < SKPT; ++j) {
+    const int64_t i = base + (int64_t)j * SBS + t;
+    const bool valid = i < m;
+    int32_t key = 0, val = 0, d = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+      d = (key >> shift) & 255;
+    }
+    uint64_t mask = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t bb = __ballot(valid && bit);
+      mask &= bit ? bb : ~bb;
+    }
+    const int rank = __popcll(mask & lt);
+    const int cnt = __popcll(mask);
+#pragma unroll
+    for (int q = 0; q < NW; ++q) wcnt[q][t] = 0;
+    __syncthreads();
+    if (valid && rank == 0) wcnt[w][d] = cnt;
+    __syncthreads();
+    if (valid) {
+      int32_t pos = run[d] + rank;
+      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    int32_t add = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) add += wcnt[q][t];
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// Sorts (ka, va) by key; the result ends in (ka, va) again (even pass
+// count) or is copied back.  Keys are < n.
+static hipError_t radix_sort(int32_t *ka, int32_t *va, int32_t *kb, int32_t *vb, int32_t m,
+                             int32_t n, int32_t *hist, hipStream_t stream) {
+  if (m <= 0) return hipSuccess;
+  int bits = 0;
+  while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
+  const int passes = (bits + 7) / 8;
+  const int nt = tiles_of(m);
+  const int32_t L = 256 * nt;
+  int32_t *sums = hist + L;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nt), dim3(SBS), 0, stream, ka, m, shift, hist,
+                       nt);
+    hipError_t e = exclusive_scan(hist, L, sums, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nt), dim3(SBS), 0, stream, ka, va, kb, vb, m,
+                       shift, hist, nt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int32_t *t;
+    t = ka; ka = kb; kb = t;
+    t = va; va = vb; vb = t;
+  }
+  if (passes & 1) {
+    // result is in the "b" buffers of the caller: copy back
+    hipError_t e = hipMemcpyAsync(kb, ka, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice,
+                                  stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(vb, va, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------- assembling
+// offsets from sorted keys: off[v] = first position with key >= v
+__global__ void offsets_kernel(const int32_t *skeys, int32_t m, int32_t n, int32_t *off) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= m; k += gridDim.x * blockDim.x) {
+    const int32_t prev = (k == 0) ? -1 : skeys[k - 1];
+    const int32_t cur = (k == m) ? n : skeys[k];
+    for (int32_t v = prev + 1; v <= cur; ++v) off[v] = k;
+  }
+}
+
+__global__ void gather_csr_kernel(const int32_t *perm, const int32_t *src, const int32_t *dst,
+                                  const int32_t *w, int32_t m, int32_t *out_dst, int32_t *out_w,
+                                  int32_t *tail, int32_t *perm_out) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < m; k += gridDim.x * blockDim.x) {
+    const int32_t i = perm[k];
+    out_dst[k] = dst[i];
+    out_w[k] = w[i];
+    tail[k] = src[i];
+    if (perm_out) perm_out[k] = i;
+  }
+}
+
+__global__ void gather_csc_kernel(const int32_t *eid, const int32_t *tail, const int32_t *out_w,
+                                  int32_t m, int32_t *in_src, int32_t *in_w) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+    const int32_t e = eid[j];
+    in_src[j] = tail[e];
+    in_w[j] = out_w[e];
+  }
+}
+
+template <bool F32>
+__global__ void wmin_kernel(const int32_t *out_off, const int32_t *out_w, int32_t n,
+                            int32_t *out_wmin) {
+  constexpr int32_t INF = F32 ? KeyF32::INF : KeyI32::INF;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    int32_t mn = INF;
+    for (int32_t k = out_off[v]; k < out_off[v + 1]; ++k) mn = kmin(mn, out_w[k]);
+    out_wmin[v] = mn;
+  }
+}
+
+static inline int grid_for(int64_t work) {
+  int64_t b = (work + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return (int)b;
+}
+
+hipError_t launch_build(int32_t n, int32_t m, bool f32, const int32_t *src, const int32_t *dst,
+                        const int32_t *w, int32_t *out_off, int32_t *out_dst, int32_t *out_w,
+                        int32_t *in_off, int32_t *in_src, int32_t *in_eid, int32_t *in_w,
+                        int32_t *out_wmin, int32_t *perm, const BuildTemps &t,
+                        hipStream_t stream) {
+  hipError_t e;
+  const int gm = grid_for(m), gn = grid_for((int64_t)n + 1);
+  // CSR: sort edge indices by tail
+  if (m > 0) {
+    e = hipMemcpyAsync(t.ka, src, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(iota_kernel, dim3(gm), dim3(256), 0, stream, t.va, m);
+    if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(gather_csr_kernel, dim3(gm), dim3(256), 0, stream, t.va, src, dst, w, m,
+                       out_dst, out_w, t.tail, perm);
+  }
+  hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, out_off);
+  // CSC: sort edge ids (already increasing) by head
+  if (m > 0) {
+    e = hipMemcpyAsync(t.ka, out_dst, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice,
+                       stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(iota_kernel, dim3(gm), dim3(256), 0, stream, t.va, m);
+    if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
+    e = hipMemcpyAsync(in_eid, t.va, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice,
+                       stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gather_csc_kernel, dim3(gm), dim3(256), 0, stream, in_eid, t.tail, out_w,
+                       m, in_src, in_w);
+  }
+  hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, in_off);
+  if (f32)
+    hipLaunchKernelGGL(wmin_kernel<true>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
+                       out_w, n, out_wmin);
+  else
+    hipLaunchKernelGGL(wmin_kernel<false>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
+                       out_w, n, out_wmin);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- reweighting
+__global__ void set_weights_kernel(const int32_t *w, const int32_t *in_eid, int32_t m,
+                                   int32_t *out_w, int32_t *in_w) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+    out_w[j] = w[j];
+    in_w[j] = w[in_eid[j]];
+  }
+}
+
+hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
+                              const int32_t *out_off, const int32_t *in_eid, int32_t *out_w,
+                              int32_t *in_w, int32_t *out_wmin, int32_t *status,
+                              hipStream_t stream) {
+  hipError_t e = launch_validate(n, m, f32, nullptr, nullptr, w, status, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(set_weights_kernel, dim3(grid_for(m)), dim3(256), 0, stream, w, in_eid, m,
+                     out_w, in_w);
+  if (f32)
+    hipLaunchKernelGGL(wmin_kernel<true>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
+                       out_w, n, out_wmin);
+  else
+    hipLaunchKernelGGL(wmin_kernel<false>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
+                       out_w, n, out_wmin);
+  return hipGetLastError();
+}
+
+}  // namespace sssp

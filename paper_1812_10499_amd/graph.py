@@ -1,0 +1,162 @@
+"""PyTorch-facing helpers over the C ABI: device memory, streams and shapes.
+
+PyTorch only allocates device memory and supplies the current stream; every
+step of the method runs in libsssp.so.  Nothing here computes a shortest
+path.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import Csr, SSSP_F32, SSSP_I32, Stats
+
+I32_INF = 2**31 - 1
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_i32(a, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.int32).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+
+
+class Graph:
+    """A directed graph built on the GPU (CSR by tail + CSC by head).
+
+    Edge ids are positions in the CSR; ``perm[k]`` is the input (COO) index
+    of edge id ``k``.  Weights are int32 (>= 1) or float32 (> 0).
+    """
+
+    def __init__(self, n: int, src, dst, w, device="cuda"):
+        device = torch.device(device)
+        if isinstance(w, torch.Tensor):
+            wt = w.to(device).contiguous()
+        else:
+            wt = torch.from_numpy(np.ascontiguousarray(w)).to(device)
+        if wt.dtype == torch.int32:
+            self.dtype = SSSP_I32
+        elif wt.dtype == torch.float32:
+            self.dtype = SSSP_F32
+        else:
+            raise TypeError("weights must be int32 or float32, got %s" % wt.dtype)
+        s = _dev_i32(src, device)
+        d = _dev_i32(dst, device)
+        m = int(s.numel())
+        if d.numel() != m or wt.numel() != m:
+            raise ValueError("src, dst and w must have the same length")
+        self.n, self.m, self.device = int(n), m, device
+        nbytes = _abi.sssp_build_csr_bytes(self.n, m, self.dtype)
+        if nbytes == 0:
+            raise ValueError("invalid graph size n=%d m=%d" % (n, m))
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.perm = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+        self.csr = Csr()
+        _abi.sssp_build_csr(self.n, m, self.dtype, s.data_ptr(), d.data_ptr(), wt.data_ptr(),
+                            self.buffer.data_ptr(), nbytes, self.csr, self.perm.data_ptr(),
+                            _stream())
+        self.perm = self.perm[:m]
+
+    @property
+    def value_dtype(self):
+        return torch.float32 if self.dtype == SSSP_F32 else torch.int32
+
+    def _view(self, ptr, count, dtype=torch.int32):
+        off = ptr - self.buffer.data_ptr()
+        return self.buffer[off:off + 4 * count].view(dtype)
+
+    def arrays(self) -> dict:
+        """Views of the built arrays (out_off, out_dst, out_w, in_off, in_src,
+        in_eid, in_w, out_wmin)."""
+        c, n, m, vt = self.csr, self.n, self.m, self.value_dtype
+        return dict(out_off=self._view(c.out_off, n + 1), out_dst=self._view(c.out_dst, m),
+                    out_w=self._view(c.out_w, m, vt), in_off=self._view(c.in_off, n + 1),
+                    in_src=self._view(c.in_src, m), in_eid=self._view(c.in_eid, m),
+                    in_w=self._view(c.in_w, m, vt), out_wmin=self._view(c.out_wmin, n, vt))
+
+    def set_weights(self, w_eid: torch.Tensor):
+        """Replace the weights; w_eid is given in edge-id order."""
+        w_eid = w_eid.to(device=self.device, dtype=self.value_dtype).contiguous()
+        if w_eid.numel() != self.m:
+            raise ValueError("expected %d weights" % self.m)
+        _abi.sssp_set_weights(self.csr, w_eid.data_ptr(), _stream())
+
+
+def solve(g: Graph, source: int, with_pred: bool = True, with_stats: bool = False):
+    """Returns (cost[n], pred[n] or None, stats dict or None)."""
+    cost = torch.empty(g.n, dtype=g.value_dtype, device=g.device)
+    pred = torch.empty(g.n, dtype=torch.int32, device=g.device) if with_pred else None
+    st = Stats() if with_stats else None
+    _abi.sssp_solve(g.csr, int(source), cost.data_ptr(), pred.data_ptr() if with_pred else None,
+                    st, _stream())
+    return cost, pred, (st.as_dict() if st is not None else None)
+
+
+def batch_layout(graphs: Sequence[Graph], inst_graph: Sequence[int]):
+    bases, b = [], 0
+    for gi in inst_graph:
+        bases.append(b)
+        b += graphs[gi].n
+    return bases, b
+
+
+def solve_batch(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source: Sequence[int],
+                with_pred: bool = True, with_stats: bool = False):
+    """Returns (cost[total], pred[total] or None, list of stats dicts or None);
+    instance i occupies [base_i, base_i + n_i)."""
+    _, total = batch_layout(graphs, inst_graph)
+    dev = graphs[0].device
+    cost = torch.empty(total, dtype=graphs[0].value_dtype, device=dev)
+    pred = torch.empty(total, dtype=torch.int32, device=dev) if with_pred else None
+    st = (Stats * len(inst_graph))() if with_stats else None
+    _abi.sssp_solve_batch([g.csr for g in graphs], inst_graph, inst_source, cost.data_ptr(),
+                          pred.data_ptr() if with_pred else None, st, _stream())
+    stats = [s.as_dict() for s in st] if st is not None else None
+    return cost, pred, stats
+
+
+def backward(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source: Sequence[int],
+             pred: torch.Tensor, grad_cost: torch.Tensor) -> torch.Tensor:
+    """dL/dw for L = sum grad_cost * cost over the pred trees; returns
+    float32[sum of m] with graph g's edges (edge-id order) at its offset."""
+    total_m = sum(g.m for g in graphs)
+    dev = graphs[0].device
+    grad_w = torch.empty(max(total_m, 1), dtype=torch.float32, device=dev)
+    gc = grad_cost.to(device=dev, dtype=torch.float32).contiguous()
+    pr = pred.to(device=dev, dtype=torch.int32).contiguous()
+    _abi.sssp_backward([g.csr for g in graphs], inst_graph, inst_source, pr.data_ptr(),
+                       gc.data_ptr(), grad_w.data_ptr(), _stream())
+    return grad_w[:total_m]
+
+
+class SSSPFunction(torch.autograd.Function):
+    """cost[S, n] = shortest-path costs from S sources on one float32 graph,
+    differentiable in the edge weights (given in edge-id order)."""
+
+    @staticmethod
+    def forward(ctx, w_eid: torch.Tensor, graph: Graph, sources: Sequence[int]):
+        graph.set_weights(w_eid.detach())
+        S = len(sources)
+        cost, pred, _ = solve_batch([graph], [0] * S, list(sources), with_pred=True)
+        ctx.graph, ctx.sources = graph, list(sources)
+        ctx.save_for_backward(pred)
+        return cost.view(S, graph.n)
+
+    @staticmethod
+    def backward(ctx, grad_cost):
+        (pred,) = ctx.saved_tensors
+        g = ctx.graph
+        gw = backward([g], [0] * len(ctx.sources), ctx.sources, pred,
+                      grad_cost.reshape(-1))
+        return gw, None, None
+
+
+def shortest_paths(w_eid: torch.Tensor, graph: Graph, sources: Sequence[int]) -> torch.Tensor:
+    return SSSPFunction.apply(w_eid, graph, sources)

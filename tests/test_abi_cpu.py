@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load, export every function include/sssp.h declares, and
+reject host-checkable bad arguments before touching the GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sssp.h")
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_1812_10499_amd as sp
+    if not os.path.exists(sp.LIB_PATH):
+        from paper_1812_10499_amd import build
+        build.build()
+    return sp
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sssp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    assert names == sorted(["sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights",
+                            "sssp_solve", "sssp_solve_batch", "sssp_backward",
+                            "sssp_release_workspace", "sssp_strerror"])
+
+
+def test_library_exports_every_declared_symbol(sp):
+    L = ctypes.CDLL(sp.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(sp.EXPORTS) == set(declared_functions())
+
+
+def test_strerror_and_sizes(sp):
+    assert sp.sssp_strerror(0) == "ok"
+    for s in range(1, 8):
+        assert sp.sssp_strerror(s) and sp.sssp_strerror(s) != "unknown status"
+    assert sp.sssp_build_csr_bytes(0, 10, sp.SSSP_I32) == 0
+    assert sp.sssp_build_csr_bytes(10, -1, sp.SSSP_I32) == 0
+    assert sp.sssp_build_csr_bytes(10, 10, 7) == 0
+    b = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32)
+    assert b >= 4 * (2 * 1001 + 5 * 5000 + 1000)
+
+
+def _fake_csr(sp, n=10, m=20, dtype=0, w_max=5.0):
+    c = sp.Csr()
+    c.n, c.m, c.dtype, c.w_max = n, m, dtype, w_max
+    for f in ("out_off", "out_dst", "out_w", "in_off", "in_src", "in_eid", "in_w", "out_wmin"):
+        setattr(c, f, 0x1000)  # never dereferenced: every call below fails its host checks
+    return c
+
+
+def _status(fn):
+    try:
+        fn()
+    except Exception as e:  # SSSPError
+        return e.status
+    return 0
+
+
+def test_host_argument_errors(sp):
+    c = _fake_csr(sp)
+    S = sp.SSSP_ERR_ARG
+    assert _status(lambda: sp.sssp_solve(c, -1, 0x1000, None, None, None)) == S
+    assert _status(lambda: sp.sssp_solve(c, 10, 0x1000, None, None, None)) == S
+    assert _status(lambda: sp.sssp_solve(c, 0, None, None, None, None)) == S
+    bad = _fake_csr(sp, n=0)
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    bad = _fake_csr(sp, dtype=5)
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    bad = _fake_csr(sp)
+    bad.in_src = None
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    # int32 overflow precondition: (n-1) * w_max >= INT32_MAX
+    big = _fake_csr(sp, n=1 << 22, w_max=1000.0)
+    assert _status(lambda: sp.sssp_solve(big, 0, 0x1000, None, None, None)) == \
+        sp._abi.SSSP_ERR_OVERFLOW
+    ok_f32 = _fake_csr(sp, n=1 << 22, w_max=1000.0, dtype=1)
+    # float32 graphs have no overflow precondition: this fails only on the
+    # source range check
+    assert _status(lambda: sp.sssp_solve(ok_f32, -5, 0x1000, None, None, None)) == S
+    # batch: instance graph / source out of range, mixed dtypes
+    assert _status(lambda: sp.sssp_solve_batch([c], [1], [0], 0x1000, None, None, None)) == S
+    assert _status(lambda: sp.sssp_solve_batch([c], [0], [10], 0x1000, None, None, None)) == S
+    f = _fake_csr(sp, dtype=1)
+    assert _status(lambda: sp.sssp_solve_batch([c, f], [0, 1], [0, 0], 0x1000, None, None,
+                                               None)) == S
+    assert _status(lambda: sp.sssp_backward([c], [0], [10], 0x1000, 0x1000, 0x1000, None)) == S
+    assert _status(lambda: sp.sssp_backward([c], [0], [0], None, 0x1000, 0x1000, None)) == S
+    # builder: bad sizes, missing pointers, short buffer
+    out = sp.Csr()
+    assert _status(lambda: sp.sssp_build_csr(0, 5, 0, 0x1000, 0x1000, 0x1000, 0x1000, 1 << 20,
+                                             out, None, None)) == S
+    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, None, 0x1000, 0x1000, 0x1000, 1 << 20,
+                                             out, None, None)) == S
+    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, 0x1000, 0x1000, 0x1000, 0x1000, 16, out,
+                                             None, None)) == S

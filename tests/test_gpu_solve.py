@@ -1,0 +1,194 @@
+"""GPU parity of the builder and the single solve against the CPU oracle.
+
+Every case runs the same seeded arrays through libsssp.so (via the C ABI)
+and through the oracle, and compares: the built CSR/CSC arrays exactly,
+costs bit-exactly (int32 and float32), pred exactly under the tie rule, and
+rounds / settled / relaxed / scanned exactly against the round simulator.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import assert_same_solution, oracle_solution, sync, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_1812_10499_amd as sp
+    assert torch.cuda.is_available()
+    return sp
+
+
+def check_build(sp, n, src, dst, w):
+    G = sp.Graph(n, src, dst, w)
+    A = {k: to_np(v) for k, v in G.arrays().items()}
+    O = oracle.csr(n, src, dst)
+    ow, iw, wmin = O.weights(w)
+    assert np.array_equal(A["out_off"], O.out_off)
+    assert np.array_equal(A["out_dst"], O.out_dst)
+    assert np.array_equal(A["in_off"], O.in_off)
+    assert np.array_equal(A["in_src"], O.in_src)
+    assert np.array_equal(A["in_eid"], O.in_eid)
+    assert np.array_equal(to_np(G.perm), O.perm)
+    if w.dtype == np.int32:
+        assert np.array_equal(A["out_w"], ow) and np.array_equal(A["in_w"], iw)
+        assert np.array_equal(A["out_wmin"], wmin)
+    else:
+        assert np.array_equal(A["out_w"].view(np.int32), ow.view(np.int32))
+        assert np.array_equal(A["in_w"].view(np.int32), iw.view(np.int32))
+        assert np.array_equal(A["out_wmin"].view(np.int32), wmin.view(np.int32))
+    assert G.csr.w_max == float(w.max()) if len(w) else True
+    return G
+
+
+def run_case(sp, n, src, dst, w, source, label):
+    print("case", label, "n=%d m=%d" % (n, len(src)), flush=True)
+    G = check_build(sp, n, src, dst, w)
+    cost, pred, st = sp.solve(G, source, with_pred=True, with_stats=True)
+    sync()
+    ref = oracle_solution(n, src, dst, w, source)
+    assert_same_solution(cost, pred, st, ref, label)
+    # a second solve on the same graph reuses the workspace
+    cost2, pred2, _ = sp.solve(G, source, with_pred=True)
+    sync()
+    assert np.array_equal(to_np(cost2), to_np(cost)) and np.array_equal(to_np(pred2), to_np(pred))
+    return G, st
+
+
+def test_tiny_worked_example(sp):
+    src = np.array([0, 0, 1, 1, 2, 2, 4, 3], np.int32)
+    dst = np.array([1, 2, 3, 4, 3, 4, 3, 2], np.int32)
+    w = np.array([9, 2, 3, 2, 6, 5, 8, 1], np.int32)
+    G, st = run_case(sp, 5, src, dst, w, 0, "worked-example")
+    assert st["rounds"] == 3 and to_np(sp.solve(G, 0)[0]).tolist() == [0, 9, 2, 8, 7]
+
+
+def test_edge_cases(sp):
+    # single vertex, no edges
+    run_case(sp, 1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32), 0,
+             "n1")
+    # source without out-edges, others unreachable
+    run_case(sp, 4, np.array([1, 2], np.int32), np.array([2, 3], np.int32),
+             np.array([5, 5], np.int32), 0, "isolated-source")
+    # self-loops and duplicates only
+    run_case(sp, 3, np.array([0, 0, 0, 1, 1], np.int32), np.array([0, 1, 1, 1, 2], np.int32),
+             np.array([1, 7, 3, 2, 4], np.int32), 0, "loops-dups")
+    # path: rounds = k + 1
+    k = 300
+    src = np.arange(k, dtype=np.int32)
+    G, st = run_case(sp, k + 1, src, src + 1, np.full(k, 2, np.int32), 0, "path")
+    assert st["rounds"] == k + 1
+    # star with a hub of 100k leaves (one huge frontier item)
+    leaves = 100000
+    src = np.zeros(leaves, np.int32)
+    dst = np.arange(1, leaves + 1, dtype=np.int32)
+    w = gen.weights_int(7, leaves, 1, 1000)
+    G, st = run_case(sp, leaves + 1, src, dst, w, 0, "star")
+    assert st["rounds"] == 2
+    # in-star: a vertex with 200k in-edges from a fan (huge open item)
+    fan = 200000
+    src = np.concatenate([np.zeros(fan, np.int32), np.arange(1, fan + 1, dtype=np.int32)])
+    dst = np.concatenate([np.arange(1, fan + 1, dtype=np.int32),
+                          np.full(fan, fan + 1, np.int32)])
+    w = gen.weights_int(8, 2 * fan, 1, 1000)
+    run_case(sp, fan + 2, src, dst, w, 0, "in-star")
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_random_small(sp, dtype):
+    rng = np.random.default_rng(21)
+    for trial in range(30):
+        n = int(rng.integers(1, 300))
+        m = int(rng.integers(0, 6 * n))
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        if dtype == "i32":
+            w = rng.integers(1, 50, m).astype(np.int32)
+        else:
+            w = (rng.integers(1, 2**24, m) * 2.0 ** -24).astype(np.float32)
+        run_case(sp, n, src, dst, w, int(rng.integers(0, n)), "rand-%s-%d" % (dtype, trial))
+
+
+def test_unit_weights_bfs(sp):
+    g = gen.grid_workload(side=64)
+    w = np.ones(g.m, np.int32)
+    G, st = run_case(sp, g.n, g.src, g.dst, w, g.source, "grid64-unit")
+    hops = oracle.bfs(g.n, g.src, g.dst, g.source)
+    assert st["rounds"] == hops.max() + 1
+
+
+def test_float_equal_cost_ties(sp):
+    tiny = np.float32(2.0 ** -30)
+    src = np.array([2, 0, 1, 1, 2, 3], np.int32)
+    dst = np.array([1, 1, 2, 1, 3, 2], np.int32)
+    w = np.array([tiny, 1.0, tiny, tiny, tiny, tiny], np.float32)
+    run_case(sp, 4, src, dst, w, 0, "f32-ties")
+    # many equal-cost tiny edges on a grid of cost-1 vertices
+    gr = gen.grid_workload(side=40)
+    w = np.full(gr.m, tiny, np.float32)
+    src = np.concatenate([gr.src, np.full(1, gr.n, np.int32)])
+    dst = np.concatenate([gr.dst, np.full(1, gr.source, np.int32)])
+    w = np.concatenate([w, np.ones(1, np.float32)])
+    run_case(sp, gr.n + 1, src, dst, w, gr.n, "f32-ties-grid")
+
+
+def test_workload_random_4096(sp):
+    g = gen.random_workload()
+    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "random4096")
+
+
+@pytest.mark.parametrize("scale", [10, 14, 16])
+def test_rmat_scaled(sp, scale):
+    g = gen.rmat_workload(scale=scale)
+    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "rmat%d" % scale)
+
+
+@pytest.mark.parametrize("side", [32, 128])
+def test_grid_scaled(sp, side):
+    g = gen.grid_workload(side=side)
+    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "grid%d" % side)
+
+
+def test_batch_shape_graphs_single(sp):
+    for g in gen.batch_workload(count=3, nmin=1000, nmax=30000):
+        run_case(sp, g.n, g.src, g.dst, g.w, g.source, g.name)
+
+
+def test_weight_and_graph_errors(sp):
+    src = np.array([0, 1], np.int32)
+    dst = np.array([1, 2], np.int32)
+    with pytest.raises(sp.SSSPError) as e:
+        sp.Graph(3, src, dst, np.array([1, 0], np.int32))
+    assert e.value.status == sp.SSSP_ERR_WEIGHT
+    with pytest.raises(sp.SSSPError) as e:
+        sp.Graph(3, src, dst, np.array([1.0, np.nan], np.float32))
+    assert e.value.status == sp.SSSP_ERR_WEIGHT
+    with pytest.raises(sp.SSSPError) as e:
+        sp.Graph(3, src, dst, np.array([1.0, -2.0], np.float32))
+    assert e.value.status == sp.SSSP_ERR_WEIGHT
+    with pytest.raises(sp.SSSPError) as e:
+        sp.Graph(2, src, dst, np.array([1, 1], np.int32))
+    assert e.value.status == sp.SSSP_ERR_GRAPH
+    with pytest.raises(sp.SSSPError) as e:
+        sp.Graph(3, src, dst, np.array([1, 2**30], np.int32))
+    assert e.value.status == sp.SSSP_ERR_OVERFLOW
+
+
+def test_workload_grid_1024_full(sp):
+    g = gen.grid_workload()
+    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "grid1024")
+
+
+def test_workload_rmat22_full(sp):
+    g = gen.rmat_workload()
+    G = sp.Graph(g.n, g.src, g.dst, g.w)
+    print("case rmat22 built", flush=True)
+    cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
+    sync()
+    ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source)
+    assert_same_solution(cost, pred, st, ref, "rmat22")
+    print("rmat22 rounds", st, flush=True)
