@@ -94,6 +94,7 @@ typedef struct {
   int32_t settled;           /* reachable vertices (Dijkstra's removeMin count) */
   int64_t relaxed_edges;     /* out-edges of fixed vertices relaxed (once each) */
   int64_t scanned_in_edges;  /* in-edges scanned by the lower-bound step */
+  int64_t open_visits;       /* sum over rounds of |O| (open vertices processed) */
 } sssp_stats;
 
 /*
@@ -185,6 +186,18 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
 
 /* Free the calling device's workspace cache (synchronizes the device). */
 sssp_status sssp_release_workspace(void);
+
+/*
+ * Diagnostics for measurement.  While enabled (on != 0), every launch of
+ * the persistent round kernel by sssp_solve / sssp_solve_batch is bracketed
+ * by a pair of HIP events recorded on the caller's stream (at most 4096
+ * pairs are kept; later launches are not timed until the next read).
+ * sssp_profile_read waits for the recorded events, returns the number of
+ * timed launches and their summed duration in milliseconds since the last
+ * read, and starts a new count.  Both pointers are host pointers.
+ */
+sssp_status sssp_profile_enable(int on);
+sssp_status sssp_profile_read(int64_t *launches, double *total_ms);
 
 /* Static message for a status code. */
 const char *sssp_strerror(sssp_status status);

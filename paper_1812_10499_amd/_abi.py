@@ -20,7 +20,8 @@ SSSP_I32, SSSP_F32 = 0, 1
  SSSP_ERR_HIP, SSSP_ERR_INTERNAL) = range(8)
 
 EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_solve",
-           "sssp_solve_batch", "sssp_backward", "sssp_release_workspace", "sssp_strerror")
+           "sssp_solve_batch", "sssp_backward", "sssp_release_workspace", "sssp_strerror",
+           "sssp_profile_enable", "sssp_profile_read")
 
 
 class Csr(ctypes.Structure):
@@ -35,7 +36,8 @@ class Csr(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("settled", ctypes.c_int32),
-                ("relaxed_edges", ctypes.c_int64), ("scanned_in_edges", ctypes.c_int64)]
+                ("relaxed_edges", ctypes.c_int64), ("scanned_in_edges", ctypes.c_int64),
+                ("open_visits", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +77,11 @@ def lib():
         L.sssp_backward.restype = ctypes.c_int
         L.sssp_release_workspace.argtypes = []
         L.sssp_release_workspace.restype = ctypes.c_int
+        L.sssp_profile_enable.argtypes = [ctypes.c_int]
+        L.sssp_profile_enable.restype = ctypes.c_int
+        L.sssp_profile_read.argtypes = [ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.sssp_profile_read.restype = ctypes.c_int
         L.sssp_strerror.argtypes = [ctypes.c_int]
         L.sssp_strerror.restype = ctypes.c_char_p
         del i64p
@@ -131,6 +138,18 @@ def sssp_backward(graphs, inst_graph, inst_source, pred, grad_cost, grad_w, stre
     _check(lib().sssp_backward(ga, len(graphs), ctypes.cast(ig, ctypes.c_void_p),
                                ctypes.cast(isrc, ctypes.c_void_p), len(ig), pred, grad_cost,
                                grad_w, stream), "sssp_backward")
+
+
+def sssp_profile_enable(on: bool):
+    _check(lib().sssp_profile_enable(1 if on else 0), "sssp_profile_enable")
+
+
+def sssp_profile_read():
+    """(timed round-kernel launches, their summed milliseconds) since the last read."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(lib().sssp_profile_read(ctypes.byref(n), ctypes.byref(ms)), "sssp_profile_read")
+    return n.value, ms.value
 
 
 def sssp_release_workspace():

@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "sssp.h"
@@ -21,6 +23,7 @@ enum Slot {
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
+  S_TRACE, S_FLAGS, S_PART,
   NSLOTS
 };
 
@@ -118,6 +121,11 @@ sssp_status ws_for_current(DevWS **out) {
   return SSSP_OK;
 }
 
+int env_flag(const char *name, int dflt) {
+  const char *s = getenv(name);
+  return s ? atoi(s) : dflt;
+}
+
 // Persistent grid: co-resident blocks, capped at SSSP_BLOCKS_PER_CU (default 2).
 sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
   const int k = (f32 ? 1 : 0) + (batch ? 2 : 0);
@@ -202,6 +210,8 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
   if ((s = ws_arr(w, S_FV, T, &a.front_v))) return s;
   if ((s = ws_arr(w, S_FP, T, &a.front_p))) return s;
   if ((s = ws_arr(w, S_CTL, 1, &a.ctl))) return s;
+  if ((s = ws_arr(w, S_FLAGS, (size_t)kMaxBlocks * kFlagStride, &a.flags))) return s;
+  if ((s = ws_arr(w, S_PART, (size_t)kParts * kMaxBlocks, &a.part))) return s;
   if ((s = ws_arr(w, S_HEAVY, 2 * T, &a.heavy))) return s;
   if ((s = ws_arr(w, S_DEGEN, 2 * T, &a.degen))) return s;
   if ((s = ws_arr(w, S_LVL, T, &a.lvl))) return s;
@@ -213,14 +223,114 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
     if ((s = ws_arr(w, S_IMIN, 3 * (size_t)num_inst, &a.imin))) return s;
     if ((s = ws_arr(w, S_ITHR, 3 * (size_t)num_inst, &a.ithr))) return s;
     if ((s = ws_arr(w, S_IROUNDS, (size_t)num_inst, &a.irounds))) return s;
-    if ((s = ws_arr(w, S_ISCAN, (size_t)num_inst, &a.iscanned))) return s;
+    if ((s = ws_arr(w, S_ISCAN, 2 * (size_t)num_inst, &a.iscanned))) return s;
   }
   return SSSP_OK;
+}
+
+// Round trace: with SSSP_TRACE=<path> in the environment, a solve records
+// per-round timestamps and list sizes on the device and, after the kernel,
+// appends them as CSV lines to <path> (synchronizes the stream).
+constexpr int kTraceRounds = 100000;
+constexpr int kTraceBlkRounds = 64;  // rounds with per-block phase end times
+
+sssp_status trace_begin(DevWS &w, RoundArgs &a, hipStream_t stream) {
+  if (!getenv("SSSP_TRACE")) return SSSP_OK;
+  sssp_status s;
+  const size_t cnt = (size_t)kTraceRounds * kTraceFields;
+  const size_t bcnt = (size_t)kTraceBlkRounds * 3 * kMaxBlocks;
+  if ((s = ws_arr(w, S_TRACE, cnt + bcnt, &a.trace))) return s;
+  a.trace_rounds = kTraceRounds;
+  a.trace_blk = a.trace + cnt;
+  a.trace_blk_rounds = kTraceBlkRounds;
+  HIPCHK(hipMemsetAsync(a.trace, 0, (cnt + bcnt) * sizeof(long long), stream));
+  return SSSP_OK;
+}
+
+sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
+  const char *path = getenv("SSSP_TRACE");
+  if (!path || !a.trace) return SSSP_OK;
+  Ctl c;
+  HIPCHK(hipStreamSynchronize(stream));
+  HIPCHK(hipMemcpy(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  const int nr = c.rounds < kTraceRounds ? c.rounds : kTraceRounds;
+  std::vector<long long> h((size_t)nr * kTraceFields);
+  HIPCHK(hipMemcpy(h.data(), a.trace, h.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  FILE *f = fopen(path, "a");
+  if (!f) return SSSP_ERR_ARG;
+  fprintf(f, "round,start,arr_relax,end_relax,arr_lb,end_lb,arr_fix,end_fix,nf,ef,no,eo\n");
+  for (int r = 0; r < nr; ++r) {
+    fprintf(f, "%d", r + 1);
+    for (int k = 0; k < kTraceFields; ++k) fprintf(f, ",%lld", h[(size_t)r * kTraceFields + k]);
+    fprintf(f, "\n");
+  }
+  fclose(f);
+  // per-block phase end times: <path>.blk, one line per (round, phase)
+  const int nbr = nr < kTraceBlkRounds ? nr : kTraceBlkRounds;
+  std::vector<long long> hb((size_t)nbr * 3 * kMaxBlocks);
+  HIPCHK(hipMemcpy(hb.data(), a.trace_blk, hb.size() * sizeof(long long),
+                   hipMemcpyDeviceToHost));
+  std::string bp = std::string(path) + ".blk";
+  f = fopen(bp.c_str(), "a");
+  if (!f) return SSSP_ERR_ARG;
+  for (int r = 0; r < nbr; ++r)
+    for (int ph = 0; ph < 3; ++ph) {
+      fprintf(f, "%d,%d", r + 1, ph);
+      for (int b = 0; b < nblocks; ++b)
+        fprintf(f, ",%lld", hb[((size_t)r * 3 + ph) * kMaxBlocks + b]);
+      fprintf(f, "\n");
+    }
+  fclose(f);
+  return SSSP_OK;
+}
+
+// Event pairs bracketing round-kernel launches while profiling is enabled.
+struct Profiler {
+  bool on = false;
+  std::vector<KernelTimer> pool;
+  size_t used = 0;
+};
+Profiler g_prof;
+
+const KernelTimer *prof_timer(KernelTimer *out) {
+  if (!g_prof.on) return nullptr;
+  if (g_prof.used == g_prof.pool.size()) {
+    if (g_prof.pool.size() >= 4096) return nullptr;
+    KernelTimer t;
+    if (hipEventCreate(&t.start) != hipSuccess) return nullptr;
+    if (hipEventCreate(&t.stop) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(t);
+  }
+  *out = g_prof.pool[g_prof.used++];
+  return out;
 }
 
 }  // namespace
 
 extern "C" {
+
+sssp_status sssp_profile_enable(int on) {
+  Guard guard;
+  g_prof.on = on != 0;
+  return SSSP_OK;
+}
+
+sssp_status sssp_profile_read(int64_t *launches, double *total_ms) {
+  if (!launches || !total_ms) return SSSP_ERR_ARG;
+  Guard guard;
+  double tot = 0.0;
+  for (size_t i = 0; i < g_prof.used; ++i) {
+    HIPCHK(hipEventSynchronize(g_prof.pool[i].stop));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, g_prof.pool[i].start, g_prof.pool[i].stop));
+    tot += ms;
+  }
+  *launches = (int64_t)g_prof.used;
+  *total_ms = tot;
+  g_prof.used = 0;
+  return SSSP_OK;
+}
+
 
 const char *sssp_strerror(sssp_status st) {
   switch (st) {
@@ -356,11 +466,16 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
   a.total = g->n;
   a.max_rounds = g->n + 1;
   a.D = (int32_t *)cost;
+  a.coherent_filter = env_flag("SSSP_COHERENT_FILTER", 0);
   if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
   LaunchGeom geo;
   if ((s = geometry(ws, f32, false, &geo))) return s;
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
-  HIPCHK(launch_solve(f32, false, a, pred, geo, nullptr, g->n, stream));
+  KernelTimer tm;
+  const KernelTimer *timer = prof_timer(&tm);
+  if ((s = trace_begin(ws, a, stream))) return s;
+  HIPCHK(launch_solve(f32, false, a, pred, geo, nullptr, g->n, timer, stream));
+  if ((s = trace_end(a, geo.blocks, stream))) return s;
   if (stats) {
     void *hp;
     if ((s = pinned_get(ws, sizeof(Ctl), &hp))) return s;
@@ -371,6 +486,7 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
     stats->settled = (int32_t)c->settled;
     stats->relaxed_edges = c->relaxed;
     stats->scanned_in_edges = c->scanned;
+    stats->open_visits = c->open_visits;
     if (c->status) {
       HIPCHK(hipEventRecord(ws.last, stream));
       return SSSP_ERR_INTERNAL;
@@ -415,6 +531,7 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   a.total = (int32_t)total;
   a.max_rounds = max_n + 1;
   a.D = (int32_t *)cost;
+  a.coherent_filter = env_flag("SSSP_COHERENT_FILTER", 0);
   if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
   GraphDev *dg;
   InstDev *di;
@@ -449,7 +566,9 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   HIPCHK(hipMemcpyAsync(dg, hg, sizeof(GraphDev) * num_graphs, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(di, hi, sizeof(InstDev) * num_inst, hipMemcpyHostToDevice, stream));
   HIPCHK(hipEventRecord(ws.staged, stream));
-  HIPCHK(launch_solve(f32, true, a, pred, geo, istat, max_n, stream));
+  KernelTimer tm;
+  const KernelTimer *timer = prof_timer(&tm);
+  HIPCHK(launch_solve(f32, true, a, pred, geo, istat, max_n, timer, stream));
   if (stats) {
     // pinned space after the tables
     char *hb = (char *)hp + ((tab_bytes + 63) & ~(size_t)63);
@@ -460,8 +579,8 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
     HIPCHK(hipMemcpyAsync(hr, a.irounds, sizeof(int32_t) * num_inst, hipMemcpyDeviceToHost,
                           stream));
     HIPCHK(hipStreamSynchronize(stream));
-    std::vector<unsigned long long> sc(num_inst);
-    HIPCHK(hipMemcpy(sc.data(), a.iscanned, sizeof(unsigned long long) * num_inst,
+    std::vector<unsigned long long> sc(2 * (size_t)num_inst);
+    HIPCHK(hipMemcpy(sc.data(), a.iscanned, sizeof(unsigned long long) * 2 * num_inst,
                      hipMemcpyDeviceToHost));
     Ctl c;
     HIPCHK(hipMemcpy(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
@@ -469,7 +588,8 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
       stats[i].rounds = hr[i];
       stats[i].settled = (int32_t)hst[4 * i + 1];
       stats[i].relaxed_edges = hst[4 * i + 2];
-      stats[i].scanned_in_edges = (int64_t)sc[i];
+      stats[i].scanned_in_edges = (int64_t)sc[2 * i];
+      stats[i].open_visits = (int64_t)sc[2 * i + 1];
     }
     HIPCHK(hipEventRecord(ws.last, stream));
     if (c.status) return SSSP_ERR_INTERNAL;
@@ -522,7 +642,8 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
   if ((s = ws_arr(ws, S_BW_GOFF, (size_t)num_graphs + 1, &goff))) return s;
   if ((s = ws_arr(ws, S_BW_GINST, (size_t)num_inst, &ginst))) return s;
   if ((s = ws_arr(ws, S_BW_EBASE, (size_t)num_graphs + 1, &ebase))) return s;
-  b.barrier = bctl;
+  if ((s = ws_arr(ws, S_FLAGS, (size_t)kMaxBlocks * kFlagStride, &b.flags))) return s;
+  b.go = bctl;
   b.ctr = bctl + 1;
   b.nlevels = (int32_t *)(bctl + 2);
   b.graphs = dg;

@@ -24,8 +24,9 @@ __global__ void bw_init_kernel(BackArgs a) {
     a.lv_v[i] = id.sbase + id.source;
     a.lv_i[i] = i;
   }
+  for (int b = threadIdx.x; b < kMaxBlocks; b += blockDim.x) a.flags[b * kFlagStride] = 0u;
   if (threadIdx.x == 0) {
-    *a.barrier = 0u;
+    *a.go = 0u;
     *a.ctr = (unsigned int)a.num_inst;
     a.lv_off[0] = 0;
     a.lv_off[1] = a.num_inst;
@@ -78,14 +79,14 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
         __syncthreads();
       }
     }
-    grid_barrier(a.barrier, epoch);
+    grid_barrier(a.flags, a.go, epoch);
     s = e;
     e = (int)__hip_atomic_load(a.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ++L;
     if (bid == 0 && tid == 0) a.lv_off[L + 1] = e;
   }
   // levels 0..L-1 are non-empty; lv_off[0..L] are their bounds
-  grid_barrier(a.barrier, epoch);
+  grid_barrier(a.flags, a.go, epoch);
   // ---- bottom-up: deepest level first
   for (int lv = L - 1; lv >= 0; --lv) {
     const int ls = a.lv_off[lv], le = a.lv_off[lv + 1];
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
       }
       a.acc[y] = acc;
     }
-    grid_barrier(a.barrier, epoch);
+    grid_barrier(a.flags, a.go, epoch);
   }
   if (bid == 0 && tid == 0) *a.nlevels = L;
 }

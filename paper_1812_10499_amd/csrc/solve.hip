@@ -24,7 +24,9 @@
 // 64-bit atomicAdd per flush that reserves both the slots and the degree
 // range, so the prefix stays consistent.  The relax and LB phases split the
 // list's total edge count evenly across blocks (edge-balanced), so a
-// million-edge hub and a degree-2 vertex cost the same per edge.
+// million-edge hub and a degree-2 vertex cost the same per edge.  The
+// global minima (minD, thr) of a single solve go through per-block slots
+// reduced by every reader, never through one contended word.
 #include "sssp_dev.h"
 #include "sssp_kernels.h"
 
@@ -78,7 +80,7 @@ struct SmemAll {
     SmemLB l;
     SmemFix f;
   } u;
-  uint64_t scan[RBS / SSSP_WAVE + 1];
+  uint64_t scan[2 * (RBS / SSSP_WAVE + 1)];
   int32_t red[RBS / SSSP_WAVE];
   int32_t tmax;
 };
@@ -89,13 +91,29 @@ __device__ __forceinline__ const GraphDev &graph_of(const RoundArgs &a, int gi) 
   else return a.g;
 }
 
+__device__ __forceinline__ int32_t *part_slot(const RoundArgs &a, int k) {
+  return a.part + (size_t)k * kMaxBlocks;
+}
+
+// min over the per-block partial slots p0[0..nb) (and p1 if given)
+template <class V>
+__device__ int32_t reduce_parts(const int32_t *p0, const int32_t *p1, uint32_t nb,
+                                SmemAll &sm) {
+  int32_t m = V::INF;
+  for (uint32_t b = threadIdx.x; b < nb; b += RBS) {
+    m = kmin(m, p0[b]);
+    if (p1) m = kmin(m, p1[b]);
+  }
+  return block_min<RBS>(m, sm.red);
+}
+
 // -------------------------------------------------------------- staging
-// Block-collective push of up to K items per thread into an LDS stager;
-// flushes to the global list when it would overflow.  All threads call.
+// Block-collective flush of an LDS stager into the global list: one 64-bit
+// atomicAdd reserves (slots, degree range).  All threads call, after a
+// barrier that made st.cnt current.
 template <int CAP>
 __device__ void stage_flush(Stager<CAP> &st, unsigned long long *ctr, int32_t *lv, int32_t *lp,
-                            int32_t *li, bool batch, SmemAll &sm) {
-  // st.cnt is read by all threads after the caller's barrier
+                            int32_t *li, bool batch) {
   const int cnt = st.cnt;
   if (cnt == 0) return;
   if (threadIdx.x == 0) {
@@ -119,8 +137,9 @@ __device__ void stage_flush(Stager<CAP> &st, unsigned long long *ctr, int32_t *l
   __syncthreads();
 }
 
-// Entry j of the thread's v/d/ins arrays is pushed iff bit j of `mask` is
-// set (arrays are indexed by compile-time j only, so they stay in VGPRs).
+// Block-collective push: entry j of the thread's v/d/ins arrays is pushed
+// iff bit j of `mask` is set (arrays are indexed by compile-time j only, so
+// they stay in VGPRs).  Flushes first when the stager would overflow.
 template <int CAP, int K>
 __device__ void stage_push(Stager<CAP> &st, uint32_t mask, const int32_t (&v)[K],
                            const int32_t (&d)[K], const int32_t (&ins)[K],
@@ -134,12 +153,11 @@ __device__ void stage_push(Stager<CAP> &st, uint32_t mask, const int32_t (&v)[K]
       dsum += (uint32_t)d[j];
       ++n_local;
     }
-  uint64_t mine = ((uint64_t)n_local << 32) | dsum;
   uint64_t tot;
-  uint64_t ex = block_excl_scan64<RBS>(mine, sm.scan, &tot);
+  const uint64_t ex = block_excl_scan64<RBS>(((uint64_t)n_local << 32) | dsum, sm.scan, &tot);
   const int tcnt = (int)(tot >> 32);
   if (tcnt == 0) return;  // uniform
-  if (st.cnt + tcnt > CAP) stage_flush(st, ctr, lv, lp, li, batch, sm);
+  if (st.cnt + tcnt > CAP) stage_flush(st, ctr, lv, lp, li, batch);
   int pos = st.cnt + (int)(ex >> 32);
   uint32_t dpos = st.deg + (uint32_t)(ex & 0xffffffffull);
 #pragma unroll
@@ -156,6 +174,45 @@ __device__ void stage_push(Stager<CAP> &st, uint32_t mask, const int32_t (&v)[K]
   if (threadIdx.x == 0) {
     st.cnt += tcnt;
     st.deg += (uint32_t)(tot & 0xffffffffull);
+  }
+  __syncthreads();
+}
+
+// One item per thread into each of two stagers, with a single scan.
+struct ListRef {
+  unsigned long long *ctr;
+  int32_t *v, *p, *i;
+};
+
+__device__ void stage_push2(Stager<CAP_F> &s1, bool h1, int32_t v1, int32_t d1, int32_t i1,
+                            const ListRef &l1, Stager<CAP_F> &s2, bool h2, int32_t v2,
+                            int32_t d2, int32_t i2, const ListRef &l2, bool batch,
+                            SmemAll &sm) {
+  const uint64_t m1 = h1 ? ((1ull << 32) | (uint32_t)d1) : 0ull;
+  const uint64_t m2 = h2 ? ((1ull << 32) | (uint32_t)d2) : 0ull;
+  uint64_t ex1, ex2, t1, t2;
+  block_excl_scan64x2<RBS>(m1, m2, sm.scan, &ex1, &ex2, &t1, &t2);
+  const int c1 = (int)(t1 >> 32), c2 = (int)(t2 >> 32);
+  if (c1 && s1.cnt + c1 > CAP_F) stage_flush(s1, l1.ctr, l1.v, l1.p, l1.i, batch);
+  if (c2 && s2.cnt + c2 > CAP_F) stage_flush(s2, l2.ctr, l2.v, l2.p, l2.i, batch);
+  if (h1) {
+    const int pos = s1.cnt + (int)(ex1 >> 32);
+    s1.v[pos] = v1;
+    s1.d[pos] = (int32_t)(s1.deg + (uint32_t)(ex1 & 0xffffffffull));
+    s1.inst[pos] = i1;
+  }
+  if (h2) {
+    const int pos = s2.cnt + (int)(ex2 >> 32);
+    s2.v[pos] = v2;
+    s2.d[pos] = (int32_t)(s2.deg + (uint32_t)(ex2 & 0xffffffffull));
+    s2.inst[pos] = i2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s1.cnt += c1;
+    s1.deg += (uint32_t)(t1 & 0xffffffffull);
+    s2.cnt += c2;
+    s2.deg += (uint32_t)(t2 & 0xffffffffull);
   }
   __syncthreads();
 }
@@ -207,7 +264,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   unsigned int epoch = 0;
   int r = 0;
   // single-instance counters, kept by block 0 thread 0
-  long long st_settled = 0, st_relaxed = 0, st_scanned = 0;
+  long long st_settled = 0, st_relaxed = 0, st_scanned = 0, st_open = 0;
 
   for (;;) {
     ++r;
@@ -215,9 +272,9 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     int32_t *Ov = cur ? a.open_v1 : a.open_v0;
     int32_t *Op = cur ? a.open_p1 : a.open_p0;
     int32_t *Oi = cur ? a.open_i1 : a.open_i0;
-    int32_t *Nv = cur ? a.open_v0 : a.open_v1;
-    int32_t *Np = cur ? a.open_p0 : a.open_p1;
-    int32_t *Ni = cur ? a.open_i0 : a.open_i1;
+    const ListRef next_open = {&ctl->open_ctr[cur ^ 1], cur ? a.open_v0 : a.open_v1,
+                               cur ? a.open_p0 : a.open_p1, cur ? a.open_i0 : a.open_i1};
+    const ListRef front = {&ctl->front_ctr, a.front_v, a.front_p, a.front_i};
     const int s_now = r % 3, s_next = (r + 1) % 3;
 
     if (r > a.max_rounds) {  // watchdog: rounds never exceed the reachable count
@@ -229,6 +286,13 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     const uint64_t fc = ld_relaxed64(&ctl->front_ctr);
     const int NF = (int)(fc >> 32);
     const uint32_t EF = (uint32_t)(fc & 0xffffffffull);
+    long long *tr = (a.trace && r <= a.trace_rounds) ? a.trace + (size_t)(r - 1) * kTraceFields
+                                                      : nullptr;
+    if (tr && bid == 0 && tid == 0) {
+      tr[TR_START] = (long long)wall_clock64();
+      tr[TR_NF] = NF;
+      tr[TR_EF] = EF;
+    }
     if (bid == 0) {
       if (tid == 0) {
         ctl->open_ctr[cur ^ 1] = 0ull;
@@ -239,11 +303,6 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
         for (int i = tid; i < I; i += RBS) {
           a.imin[s_next * I + i] = V::INF;
           a.ithr[s_next * I + i] = V::INF;
-        }
-      } else {
-        if (tid == 0) {
-          ctl->minD[s_next] = V::INF;
-          ctl->thr[s_next] = V::INF;
         }
       }
     }
@@ -289,32 +348,67 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           __syncthreads();
           const uint32_t wend = min((uint32_t)S.pfx[WIN], e1);
           for (uint32_t cb = k; cb < wend; cb += RBS * EPT) {
+            // gathers for all EPT edges are issued before any result is used
+            int it[EPT];
+            int32_t pos[EPT], y[EPT], wt[EPT], cand[EPT], gy[EPT], dy[EPT];
+            bool val[EPT];
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+              const uint32_t e = cb + (uint32_t)(j * RBS + tid);
+              val[j] = e < wend;
+              it[j] = val[j] ? window_item(S.pfx, e) : 0;
+              pos[j] = S.base[it[j]] + (int32_t)(e - (uint32_t)S.pfx[it[j]]);
+            }
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+              if (val[j]) {
+                const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
+                y[j] = G.out_dst[pos[j]];
+                wt[j] = G.out_w[pos[j]];
+              }
+            }
+            if (a.coherent_filter) {
+#pragma unroll
+              for (int j = 0; j < EPT; ++j) {
+                if (val[j]) {
+                  cand[j] = V::add(S.dx[it[j]], wt[j]);
+                  gy[j] = S.sb[it[j]] + y[j];
+                  dy[j] = ld_relaxed(&a.D[gy[j]]);
+                }
+              }
+            } else {
+#pragma unroll
+              for (int j = 0; j < EPT; ++j) {
+                if (val[j]) {
+                  cand[j] = V::add(S.dx[it[j]], wt[j]);
+                  gy[j] = S.sb[it[j]] + y[j];
+                  dy[j] = a.D[gy[j]];
+                }
+              }
+            }
             int32_t nv[EPT], nd[EPT], ni[EPT];
             uint32_t nmask = 0;
 #pragma unroll
             for (int j = 0; j < EPT; ++j) {
-              const uint32_t e = cb + (uint32_t)(j * RBS + tid);
-              if (e < wend) {
-                const int it = window_item(S.pfx, e);
-                const GraphDev &G = graph_of<BATCH>(a, S.gi[it]);
-                const int32_t pos = S.base[it] + (int32_t)(e - (uint32_t)S.pfx[it]);
-                const int32_t y = G.out_dst[pos];
-                const int32_t cand = V::add(S.dx[it], G.out_w[pos]);
-                const int32_t gy = S.sb[it] + y;
-                if (cand < a.D[gy]) {
-                  const int32_t old = atomicMin(&a.D[gy], cand);
-                  if constexpr (BATCH) {
-                    atomicMin(&a.imin[s_now * I + S.inst[it]], cand);
-                  } else {
-                    lmin = kmin(lmin, cand);
-                  }
-                  if (old == V::INF) {
-                    nv[j] = gy;
-                    nd[j] = G.in_off[y + 1] - G.in_off[y];
-                    ni[j] = S.inst[it];
-                    nmask |= 1u << j;
-                  }
+              if (val[j] && cand[j] < dy[j]) {
+                const int32_t old = atomicMin(&a.D[gy[j]], cand[j]);
+                if constexpr (BATCH) {
+                  atomicMin(&a.imin[s_now * I + S.inst[it[j]]], cand[j]);
+                } else {
+                  lmin = kmin(lmin, cand[j]);
                 }
+                if (old == V::INF) nmask |= 1u << j;
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+              if ((nmask >> j) & 1u) {
+                const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
+                nv[j] = gy[j];
+                nd[j] = G.in_off[y[j] + 1] - G.in_off[y[j]];
+                ni[j] = S.inst[it[j]];
+              } else {
+                nv[j] = nd[j] = ni[j] = 0;
               }
             }
             stage_push<CAP_R, EPT>(S.st, nmask, nv, nd, ni, &ctl->open_ctr[cur], Ov, Op, Oi,
@@ -326,28 +420,40 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
         }
       }
       __syncthreads();
-      stage_flush(S.st, &ctl->open_ctr[cur], Ov, Op, Oi, BATCH, sm);
+      stage_flush(S.st, &ctl->open_ctr[cur], Ov, Op, Oi, BATCH);
       if constexpr (!BATCH) {
         const int32_t bm = block_min<RBS>(lmin, sm.red);
-        if (tid == 0 && bm < V::INF) atomicMin(&ctl->minD[s_now], bm);
+        if (tid == 0) part_slot(a, P_CAND0 + cur)[bid] = bm;
       }
     }
-    grid_barrier(&ctl->barrier, epoch);
+    long long *tb = (a.trace_blk && r <= a.trace_blk_rounds)
+                        ? a.trace_blk + (size_t)(r - 1) * 3 * kMaxBlocks + bid
+                        : nullptr;
+    if (tb && tid == 0) tb[0] = (long long)wall_clock64();
+    if (tr && bid == 0 && tid == 0) tr[TR_ARR_RELAX] = (long long)wall_clock64();
+    grid_barrier(a.flags, &ctl->go, epoch);
 
     const uint64_t oc = ld_relaxed64(&ctl->open_ctr[cur]);
     const int NO = (int)(oc >> 32);
     const uint32_t EO = (uint32_t)(oc & 0xffffffffull);
+    if (tr && bid == 0 && tid == 0) {
+      tr[TR_END_RELAX] = (long long)wall_clock64();
+      tr[TR_NO] = NO;
+      tr[TR_EO] = EO;
+    }
     if (NO == 0) break;  // nothing left open: every reachable vertex is fixed
 
     // ================================================================== LB
     if (bid == 0 && tid == 0) {
       ctl->front_ctr = 0ull;
       st_scanned += EO;
+      st_open += NO;
     }
+    int32_t mind_all = V::INF;
+    if constexpr (!BATCH)
+      mind_all = reduce_parts<V>(part_slot(a, P_SURV0 + cur), part_slot(a, P_CAND0 + cur), nb, sm);
     {
       int32_t lthr = V::INF;
-      int32_t mind_all = V::INF;
-      if constexpr (!BATCH) mind_all = ld_relaxed(&ctl->minD[s_now]);
       const uint32_t e0 = (uint32_t)(((uint64_t)EO * bid) / nb);
       const uint32_t e1 = (uint32_t)(((uint64_t)EO * (bid + 1)) / nb);
       SmemLB &S = sm.u.l;
@@ -382,32 +488,43 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           __syncthreads();
           const uint32_t wend = min((uint32_t)S.pfx[WIN], e1);
           for (uint32_t cb = k; cb < wend; cb += RBS * EPT) {
+            int it[EPT];
+            int32_t pos[EPT], v[EPT], wt[EPT], cv[EPT];
+            bool val[EPT];
 #pragma unroll
             for (int j = 0; j < EPT; ++j) {
               const uint32_t e = cb + (uint32_t)(j * RBS + tid);
-              const bool valid = e < wend;
-              int it = -1;
-              int32_t t = V::INF;
-              if (valid) {
-                it = window_item(S.pfx, e);
-                const GraphDev &G = graph_of<BATCH>(a, S.gi[it]);
-                const int32_t pos = S.base[it] + (int32_t)(e - (uint32_t)S.pfx[it]);
-                const int32_t v = G.in_src[pos];
-                const int32_t cv = a.C[S.sb[it] + v];
-                t = V::add(kmax(cv, S.mind[it]), G.in_w[pos]);
+              val[j] = e < wend;
+              it[j] = val[j] ? window_item(S.pfx, e) : 0;
+              pos[j] = S.base[it[j]] + (int32_t)(e - (uint32_t)S.pfx[it[j]]);
+            }
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+              if (val[j]) {
+                const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
+                v[j] = G.in_src[pos[j]];
+                wt[j] = G.in_w[pos[j]];
               }
+            }
+#pragma unroll
+            for (int j = 0; j < EPT; ++j)
+              if (val[j]) cv[j] = a.C[S.sb[it[j]] + v[j]];
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+              const int32_t t = val[j] ? V::add(kmax(cv[j], S.mind[it[j]]), wt[j]) : V::INF;
+              const int myit = val[j] ? it[j] : -1;
               // segmented min into LDS; one LDS atomic per wave when the
               // whole wave works on one item (hub vertices)
-              const uint64_t act = __ballot(valid);
+              const uint64_t act = __ballot(val[j]);
               if (act) {
                 const int lead = __ffsll((unsigned long long)act) - 1;
-                const int it0 = __shfl(it, lead, SSSP_WAVE);
-                const uint64_t same = __ballot(valid && it == it0);
+                const int it0 = __shfl(myit, lead, SSSP_WAVE);
+                const uint64_t same = __ballot(val[j] && myit == it0);
                 if (same == act) {
                   const int32_t wm = wave_min(t);
                   if (lane_id() == lead && wm < V::INF) atomicMin(&S.acc[it0], wm);
-                } else if (valid && t < V::INF) {
-                  atomicMin(&S.acc[it], t);
+                } else if (val[j] && t < V::INF) {
+                  atomicMin(&S.acc[myit], t);
                 }
               }
             }
@@ -425,11 +542,12 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
             if (p0 >= e0 && p0 < e1) {  // owner of the item's first edge
               const GraphDev &G = graph_of<BATCH>(a, S.gi[tid]);
               const int32_t gy = Ov[idx];
-              const int32_t y = gy - S.sb[tid];
-              const int32_t th = V::add(a.D[gy], G.out_wmin[y]);
+              const int32_t yl = gy - S.sb[tid];
+              const int32_t th = V::add(a.D[gy], G.out_wmin[yl]);
               if constexpr (BATCH) {
                 atomicMin(&a.ithr[s_now * I + S.inst[tid]], th);
-                atomicAdd(&a.iscanned[S.inst[tid]], (unsigned long long)(p1 - p0));
+                atomicAdd(&a.iscanned[2 * S.inst[tid]], (unsigned long long)(p1 - p0));
+                atomicAdd(&a.iscanned[2 * S.inst[tid] + 1], 1ull);
               } else {
                 lthr = kmin(lthr, th);
               }
@@ -442,10 +560,13 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
       }
       if constexpr (!BATCH) {
         const int32_t bm = block_min<RBS>(lthr, sm.red);
-        if (tid == 0 && bm < V::INF) atomicMin(&ctl->thr[s_now], bm);
+        if (tid == 0) part_slot(a, P_THR0 + cur)[bid] = bm;
       }
     }
-    grid_barrier(&ctl->barrier, epoch);
+    if (tb && tid == 0) tb[kMaxBlocks] = (long long)wall_clock64();
+    if (tr && bid == 0 && tid == 0) tr[TR_ARR_LB] = (long long)wall_clock64();
+    grid_barrier(a.flags, &ctl->go, epoch);
+    if (tr && bid == 0 && tid == 0) tr[TR_END_LB] = (long long)wall_clock64();
 
     // ================================================================= fix
     {
@@ -456,24 +577,21 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
         S.op.cnt = 0;
         S.op.deg = 0;
       }
+      int32_t thr_all = V::INF;
+      if constexpr (!BATCH) thr_all = reduce_parts<V>(part_slot(a, P_THR0 + cur), nullptr, nb, sm);
       __syncthreads();
       int32_t lnext = V::INF;
-      int32_t mind_all = V::INF, thr_all = V::INF;
-      if constexpr (!BATCH) {
-        mind_all = ld_relaxed(&ctl->minD[s_now]);
-        thr_all = ld_relaxed(&ctl->thr[s_now]);
-      }
       for (int b0 = (int)bid * RBS; b0 < NO; b0 += (int)nb * RBS) {
         const int idx = b0 + tid;
-        int32_t fv[1] = {0}, fd[1] = {0}, fi[1] = {0}, ov[1] = {0}, od[1] = {0}, oi[1] = {0};
-        uint32_t nf = 0, no = 0;
+        bool hf = false, ho = false;
+        int32_t gy = 0, fd = 0, od = 0, ins = 0;
         if (idx < NO) {
-          const int32_t gy = Ov[idx];
+          gy = Ov[idx];
           const int32_t m = a.mtmp[idx];
           a.mtmp[idx] = V::INF;
           const uint32_t p0 = (uint32_t)Op[idx];
           const uint32_t p1 = (idx + 1 < NO) ? (uint32_t)Op[idx + 1] : EO;
-          int32_t sb = 0, gi = 0, ins = 0;
+          int32_t sb = 0, gi = 0;
           int32_t md = mind_all, th = thr_all;
           if constexpr (BATCH) {
             ins = Oi[idx];
@@ -489,34 +607,30 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           if (Cn >= Dy || Dy <= th) {
             a.C[gy] = V::INF;  // fixed: drops out of every later lower-bound scan
             const GraphDev &G = graph_of<BATCH>(a, gi);
-            const int32_t y = gy - sb;
-            fv[0] = gy;
-            fd[0] = G.out_off[y + 1] - G.out_off[y];
-            fi[0] = ins;
-            nf = 1;
+            const int32_t yl = gy - sb;
+            fd = G.out_off[yl + 1] - G.out_off[yl];
+            hf = true;
           } else {
             a.C[gy] = Cn;
-            ov[0] = gy;
-            od[0] = (int32_t)(p1 - p0);
-            oi[0] = ins;
-            no = 1;
+            od = (int32_t)(p1 - p0);
+            ho = true;
             if constexpr (BATCH) atomicMin(&a.imin[s_next * I + ins], Dy);
             else lnext = kmin(lnext, Dy);
           }
         }
-        stage_push<CAP_F, 1>(S.fr, nf, fv, fd, fi, &ctl->front_ctr, a.front_v, a.front_p,
-                             a.front_i, BATCH, sm);
-        stage_push<CAP_F, 1>(S.op, no, ov, od, oi, &ctl->open_ctr[cur ^ 1], Nv, Np, Ni, BATCH,
-                             sm);
+        stage_push2(S.fr, hf, gy, fd, ins, front, S.op, ho, gy, od, ins, next_open, BATCH, sm);
       }
-      stage_flush(S.fr, &ctl->front_ctr, a.front_v, a.front_p, a.front_i, BATCH, sm);
-      stage_flush(S.op, &ctl->open_ctr[cur ^ 1], Nv, Np, Ni, BATCH, sm);
+      stage_flush(S.fr, front.ctr, front.v, front.p, front.i, BATCH);
+      stage_flush(S.op, next_open.ctr, next_open.v, next_open.p, next_open.i, BATCH);
       if constexpr (!BATCH) {
         const int32_t bm = block_min<RBS>(lnext, sm.red);
-        if (tid == 0 && bm < V::INF) atomicMin(&ctl->minD[s_next], bm);
+        if (tid == 0) part_slot(a, P_SURV0 + (cur ^ 1))[bid] = bm;
       }
     }
-    grid_barrier(&ctl->barrier, epoch);
+    if (tb && tid == 0) tb[2 * kMaxBlocks] = (long long)wall_clock64();
+    if (tr && bid == 0 && tid == 0) tr[TR_ARR_FIX] = (long long)wall_clock64();
+    grid_barrier(a.flags, &ctl->go, epoch);
+    if (tr && bid == 0 && tid == 0) tr[TR_END_FIX] = (long long)wall_clock64();
   }
 
   if (bid == 0 && tid == 0) {
@@ -524,20 +638,25 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     ctl->settled = st_settled;
     ctl->relaxed = st_relaxed;
     ctl->scanned = st_scanned;
+    ctl->open_visits = st_open;
   }
 }
 
 // ------------------------------------------------------------------ init
-// D = INF, C = 0, mtmp = INF over all state entries; each instance's
-// source gets D = 0 and the fixed marker C = INF.
+// D = INF, C = 0, mtmp = INF over all state entries; barrier flags and the
+// per-block partial slots are reset.
 template <class V>
-__global__ void init_fill_kernel(int32_t *D, int32_t *C, int32_t *mtmp, int32_t total) {
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += gridDim.x * blockDim.x) {
+__global__ void init_fill_kernel(int32_t *D, int32_t *C, int32_t *mtmp, int32_t total,
+                                 unsigned int *flags, int32_t *part) {
+  const int32_t stride = gridDim.x * blockDim.x;
+  const int32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int32_t i = t0; i < total; i += stride) {
     D[i] = V::INF;
     C[i] = 0;
     mtmp[i] = V::INF;
   }
+  for (int32_t i = t0; i < kMaxBlocks; i += stride) flags[i * kFlagStride] = 0u;
+  for (int32_t i = t0; i < kParts * kMaxBlocks; i += stride) part[i] = V::INF;
 }
 
 // One block: seeds every instance's source, the first frontier (with its
@@ -572,14 +691,13 @@ __global__ void init_seed_kernel(RoundArgs a) {
       a.front_p[i] = (int32_t)(run + ex);
       if constexpr (BATCH) {
         a.front_i[i] = i;
-        a.imin[0 * I + i] = V::INF;
-        a.imin[1 * I + i] = V::INF;
-        a.imin[2 * I + i] = V::INF;
-        a.ithr[0 * I + i] = V::INF;
-        a.ithr[1 * I + i] = V::INF;
-        a.ithr[2 * I + i] = V::INF;
+        for (int s = 0; s < 3; ++s) {
+          a.imin[s * I + i] = V::INF;
+          a.ithr[s * I + i] = V::INF;
+        }
         a.irounds[i] = 0;
-        a.iscanned[i] = 0ull;
+        a.iscanned[2 * i] = 0ull;
+        a.iscanned[2 * i + 1] = 0ull;
         if (a.istat) {
           a.istat[4 * i + 0] = 0;
           a.istat[4 * i + 1] = 0;
@@ -595,14 +713,10 @@ __global__ void init_seed_kernel(RoundArgs a) {
     c->front_ctr = ((unsigned long long)I << 32) | (run & 0xffffffffull);
     c->open_ctr[0] = 0ull;
     c->open_ctr[1] = 0ull;
-    c->barrier = 0u;
+    c->go = 0u;
     c->status = 0;
-    for (int s = 0; s < 3; ++s) {
-      c->minD[s] = V::INF;
-      c->thr[s] = V::INF;
-    }
     c->rounds = 0;
-    c->settled = c->relaxed = c->scanned = 0;
+    c->settled = c->relaxed = c->scanned = c->open_visits = 0;
     c->deg_count = 0;
     c->heavy_count = 0;
   }
@@ -648,20 +762,15 @@ __global__ __launch_bounds__(256) void pred_light_kernel(RoundArgs a, int32_t *p
         heavy[q] = gy;
         heavy[a.total + q] = inst;
       } else {
-        bool eq = false;
         for (int32_t j = j0; j < j1; ++j) {
           const int32_t dv = a.D[sb + G.in_src[j]];
-          if (V::add(dv, G.in_w[j]) == dy) {
-            if (dv < dy) {
-              p = G.in_eid[j];
-              break;
-            }
-            eq = true;
+          if (dv < dy && V::add(dv, G.in_w[j]) == dy) {
+            p = G.in_eid[j];
+            break;
           }
         }
         if (p < 0) {
-          // reachable, no strict tight edge: only equal-cost tight edges
-          (void)eq;
+          // reachable with no strict tight in-edge: only equal-cost ones
           p = -2;
           const int q = atomicAdd(&a.ctl->deg_count, 1);
           degen[q] = gy;
@@ -813,12 +922,16 @@ __global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *
 // ------------------------------------------------------- host launchers
 template <class V, bool BATCH>
 static hipError_t launch_solve_t(const RoundArgs &a, int32_t *pred, const LaunchGeom &geo,
-                                 long long *istat, int32_t max_n, hipStream_t stream) {
+                                 long long *istat, int32_t max_n, const KernelTimer *timer,
+                                 hipStream_t stream) {
   hipError_t e;
+  if (geo.blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
   {
-    const int blocks = (int)((a.total + 255) / 256 < 4096 ? (a.total + 255) / 256 : 4096);
-    hipLaunchKernelGGL(init_fill_kernel<V>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, stream,
-                       a.D, a.C, a.mtmp, a.total);
+    int blocks = (int)((a.total + 255) / 256);
+    if (blocks < (kParts * kMaxBlocks) / 256) blocks = (kParts * kMaxBlocks) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(init_fill_kernel<V>, dim3(blocks), dim3(256), 0, stream, a.D, a.C,
+                       a.mtmp, a.total, a.flags, a.part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((init_seed_kernel<V, BATCH>), dim3(1), dim3(RBS), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -826,9 +939,11 @@ static hipError_t launch_solve_t(const RoundArgs &a, int32_t *pred, const Launch
   {
     RoundArgs arg = a;
     void *params[] = {&arg};
+    if (timer && (e = hipEventRecord(timer->start, stream)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel((const void *)rounds_kernel<V, BATCH>, dim3(geo.blocks),
                                    dim3(RBS), params, 0, stream);
     if (e != hipSuccess) return e;
+    if (timer && (e = hipEventRecord(timer->stop, stream)) != hipSuccess) return e;
   }
   if (pred || istat) {
     int32_t *p = pred ? pred : a.scratch_pred;
@@ -852,13 +967,13 @@ static hipError_t launch_solve_t(const RoundArgs &a, int32_t *pred, const Launch
 
 hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                         const LaunchGeom &geo, long long *istat, int32_t max_n,
-                        hipStream_t stream) {
+                        const KernelTimer *timer, hipStream_t stream) {
   if (f32) {
-    return batch ? launch_solve_t<KeyF32, true>(a, pred, geo, istat, max_n, stream)
-                 : launch_solve_t<KeyF32, false>(a, pred, geo, istat, max_n, stream);
+    return batch ? launch_solve_t<KeyF32, true>(a, pred, geo, istat, max_n, timer, stream)
+                 : launch_solve_t<KeyF32, false>(a, pred, geo, istat, max_n, timer, stream);
   }
-  return batch ? launch_solve_t<KeyI32, true>(a, pred, geo, istat, max_n, stream)
-               : launch_solve_t<KeyI32, false>(a, pred, geo, istat, max_n, stream);
+  return batch ? launch_solve_t<KeyI32, true>(a, pred, geo, istat, max_n, timer, stream)
+               : launch_solve_t<KeyI32, false>(a, pred, geo, istat, max_n, timer, stream);
 }
 
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu) {

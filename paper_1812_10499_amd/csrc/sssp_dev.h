@@ -116,6 +116,38 @@ __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t *scra
   return res;
 }
 
+// Two independent block-wide exclusive scans in one pass (one barrier pair).
+// scratch: 2 * (BS/64 + 1) entries.
+template <int BS>
+__device__ __forceinline__ void block_excl_scan64x2(uint64_t v1, uint64_t v2, uint64_t *scratch,
+                                                    uint64_t *ex1, uint64_t *ex2,
+                                                    uint64_t *tot1, uint64_t *tot2) {
+  constexpr int NW = BS / SSSP_WAVE;
+  const int w = threadIdx.x / SSSP_WAVE, l = lane_id();
+  const uint64_t i1 = wave_incl_scan64(v1), i2 = wave_incl_scan64(v2);
+  if (l == SSSP_WAVE - 1) {
+    scratch[w] = i1;
+    scratch[NW + 1 + w] = i2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    uint64_t *s = scratch + threadIdx.x * (NW + 1);
+    uint64_t run = 0;
+    for (int i = 0; i < NW; ++i) {
+      const uint64_t t = s[i];
+      s[i] = run;
+      run += t;
+    }
+    s[NW] = run;
+  }
+  __syncthreads();
+  *ex1 = scratch[w] + i1 - v1;
+  *ex2 = scratch[NW + 1 + w] + i2 - v2;
+  *tot1 = scratch[NW];
+  *tot2 = scratch[2 * NW + 1];
+  __syncthreads();
+}
+
 // Block-wide min; result valid in all threads.  scratch: BS/64 entries.
 template <int BS>
 __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *scratch) {
@@ -132,29 +164,55 @@ __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *scratch) {
 }
 
 // ------------------------------------------------------- grid barrier
-// Sense-free barrier for a cooperative (all blocks co-resident) launch:
-// `counter` only grows; the k-th barrier completes when it reaches
-// k * gridDim.x.  Thread 0 of each block publishes the block's writes with
-// an agent-scope release (write-back of this XCD's L2) and, once all blocks
-// arrived, acquires (invalidate) before the block continues.  `epoch` is
-// the block's own count of barriers passed (same in every block).
-// The counter may wrap past 2^32 on very long solves; the wait compares the
-// signed difference, which stays correct while fewer than 2^31 arrivals
-// separate any two blocks (they are at most one barrier apart).
-__device__ __forceinline__ void grid_barrier(unsigned int *counter, unsigned int &epoch) {
-  // every wave publishes its own stores before the block meets
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+// Barrier for a cooperative launch (all blocks co-resident) that uses no
+// same-address atomics: 512 blocks incrementing one counter serialize at
+// the memory side (tens of microseconds per barrier on MI355X).  Instead
+// each block owns a flag word on its own 64-byte line:
+//   1. every wave waits for its own stores (vmcnt(0)) so that they sit in
+//      this XCD's L2; thread 0 writes the L2 back (agent release) and
+//      stores the block's epoch into its flag;
+//   2. block 0's threads poll all flags in parallel, then thread 0 stores
+//      the epoch into `go`;
+//   3. every block waits for `go`, then invalidates its L1/L2 (agent
+//      acquire) so that later loads see the other XCDs' writes.
+// `epoch` is the block's count of barriers passed (equal in all blocks);
+// flags and `go` must be zero at launch.  Comparisons use the signed
+// difference, so epoch wrap-around is harmless.
+constexpr int kFlagStride = 16;  // ints between flags (64 bytes)
+
+__device__ __forceinline__ void wait_own_stores() {
+  // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15): only vector memory counts
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+__device__ __forceinline__ unsigned int ld_flag(const unsigned int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void grid_barrier(unsigned int *flags, unsigned int *go,
+                                             unsigned int &epoch) {
+  wait_own_stores();
   __syncthreads();
   epoch += 1;
+  const unsigned int ep = epoch;
   if (threadIdx.x == 0) {
-    const unsigned int target = epoch * gridDim.x;
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    while ((int)(__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) -
-                 target) < 0)
-      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&flags[blockIdx.x * kFlagStride], ep, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (blockIdx.x == 0) {
+    for (unsigned int b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+      while ((int)(ld_flag(&flags[b * kFlagStride]) - ep) < 0) __builtin_amdgcn_s_sleep(1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_store(go, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    while ((int)(ld_flag(go) - ep) < 0) __builtin_amdgcn_s_sleep(1);
+  }
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {

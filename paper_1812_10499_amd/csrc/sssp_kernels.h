@@ -9,20 +9,37 @@
 namespace sssp {
 
 constexpr int kRoundBlock = 512;  // threads per block of the persistent kernels
+constexpr int kMaxBlocks = 4096;  // upper bound on a persistent grid
+
+// Per-block partial minima of a single solve, [kParts][kMaxBlocks]: every
+// block overwrites its own slot each round and readers reduce over blocks,
+// so no two blocks ever update the same word.
+enum PartSlot {
+  P_SURV0 = 0,  // min D of the open vertices that stay open (for the next round), by parity
+  P_SURV1,
+  P_CAND0,      // min successful relaxation candidate, by round parity
+  P_CAND1,
+  P_THR0,       // min D[y] + out_wmin[y] over the open set, by round parity
+  P_THR1,
+  kParts
+};
 
 // Control block of one persistent solve, in device memory.
 struct Ctl {
   unsigned long long front_ctr;    // (items << 32) | out-degree sum of the next frontier
   unsigned long long open_ctr[2];  // same for the two open-list buffers
-  unsigned int barrier;            // grid barrier counter
+  unsigned int go;                 // grid barrier release word
   int32_t status;                  // 0, or an sssp_status code set on the device
-  int32_t minD[3];                 // per round (mod 3) minimum D over the open set
-  int32_t thr[3];                  // per round (mod 3) threshold
   int32_t rounds;
   int32_t deg_count;    // pred: vertices queued for the equal-cost pass
   int32_t heavy_count;  // pred: vertices queued for the wave-per-vertex pass
   int32_t pad;
-  long long settled, relaxed, scanned;
+  long long settled, relaxed, scanned, open_visits;
+};
+
+// Optional event pair recorded around the persistent kernel launch.
+struct KernelTimer {
+  hipEvent_t start, stop;
 };
 
 struct RoundArgs {
@@ -39,9 +56,25 @@ struct RoundArgs {
   int32_t *front_v, *front_p, *front_i;
   Ctl *ctl;
   int32_t *imin, *ithr, *irounds;  // batch: [3][I], [3][I], [I]
-  unsigned long long *iscanned;    // batch: [I]
+  unsigned long long *iscanned;    // batch: [I][2] scanned in-edges, open visits
   int32_t *heavy, *degen, *lvl, *flag, *scratch_pred;
   long long *istat;                // batch stats [4][I], zeroed by the seed kernel
+  // optional round trace (SSSP_TRACE): per round kTraceFields entries
+  long long *trace;
+  int32_t trace_rounds;
+  int32_t trace_blk_rounds;  // rounds with per-block phase end times
+  long long *trace_blk;      // [round][3 phases][kMaxBlocks] wall-clock at each block's phase end
+  unsigned int *flags;  // grid barrier flags, kMaxBlocks * kFlagStride
+  int32_t *part;        // per-block partial minima, kParts * kMaxBlocks
+  int32_t coherent_filter;  // relax reads D[head] with an agent-coherent load
+};
+
+// Trace record of one round: wall-clock (100 MHz) at relax start, the last
+// block's arrival and the release of each of the three barriers, and the
+// list sizes the round processed.
+enum TraceField {
+  TR_START = 0, TR_ARR_RELAX, TR_END_RELAX, TR_ARR_LB, TR_END_LB, TR_ARR_FIX, TR_END_FIX,
+  TR_NF, TR_EF, TR_NO, TR_EO, kTraceFields
 };
 
 struct LaunchGeom {
@@ -51,7 +84,7 @@ struct LaunchGeom {
 
 hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                         const LaunchGeom &geo, long long *istat, int32_t max_n,
-                        hipStream_t stream);
+                        const KernelTimer *timer, hipStream_t stream);
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
 
 // ------------------------------------------------------------- builder
@@ -87,7 +120,8 @@ struct BackArgs {
   int32_t *lv_v, *lv_i;       // level lists (vertex state index, instance)
   int32_t *lv_off;            // level offsets, capacity total + 2
   int32_t *nlevels;           // device scalar: number of non-empty levels
-  unsigned int *barrier;
+  unsigned int *flags;        // grid barrier flags, kMaxBlocks * kFlagStride
+  unsigned int *go;           // grid barrier release word
   unsigned int *ctr;          // append counter for the level being built
 };
 hipError_t launch_backward(const BackArgs &a, const LaunchGeom &geo, const int32_t *ginst_off,
