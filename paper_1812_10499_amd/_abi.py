@@ -13,7 +13,8 @@ import os
 import torch  # noqa: F401  (load PyTorch's HIP runtime first: one runtime per process)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsssp.so")
+# SSSP_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SSSP_LIBRARY") or os.path.join(_HERE, "libsssp.so")
 
 SSSP_I32, SSSP_F32 = 0, 1
 (SSSP_OK, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_WEIGHT, SSSP_ERR_OVERFLOW, SSSP_ERR_NOMEM,

@@ -18,12 +18,12 @@ using namespace sssp;
 namespace {
 
 enum Slot {
-  S_C, S_MTMP, S_OV0, S_OP0, S_OI0, S_OV1, S_OP1, S_OI1, S_FV, S_FP, S_FI, S_CTL,
+  S_C, S_C1, S_ARRIVE, S_MTMP, S_OV0, S_OP0, S_OI0, S_OV1, S_OP1, S_OI1, S_FV, S_FP, S_FI, S_CTL,
   S_IMIN, S_ITHR, S_IROUNDS, S_ISCAN, S_HEAVY, S_DEGEN, S_LVL, S_FLAG, S_SPRED, S_ISTAT,
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
-  S_TRACE, S_FLAGS, S_PART,
+  S_TRACE, S_FLAGS, S_PART, S_D64,
   NSLOTS
 };
 
@@ -201,7 +201,10 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
                           RoundArgs &a) {
   const size_t T = (size_t)total;
   sssp_status s;
-  if ((s = ws_arr(w, S_C, T, &a.C))) return s;
+  if ((s = ws_arr(w, S_D64, T, &a.D64))) return s;
+  if ((s = ws_arr(w, S_C, T, &a.C0))) return s;
+  if ((s = ws_arr(w, S_C1, T, &a.C1))) return s;
+  if ((s = ws_arr(w, S_ARRIVE, T, &a.arrive))) return s;
   if ((s = ws_arr(w, S_MTMP, T, &a.mtmp))) return s;
   if ((s = ws_arr(w, S_OV0, T, &a.open_v0))) return s;
   if ((s = ws_arr(w, S_OP0, T, &a.open_p0))) return s;
@@ -238,7 +241,7 @@ sssp_status trace_begin(DevWS &w, RoundArgs &a, hipStream_t stream) {
   if (!getenv("SSSP_TRACE")) return SSSP_OK;
   sssp_status s;
   const size_t cnt = (size_t)kTraceRounds * kTraceFields;
-  const size_t bcnt = (size_t)kTraceBlkRounds * 3 * kMaxBlocks;
+  const size_t bcnt = (size_t)kTraceBlkRounds * 2 * kMaxBlocks;
   if ((s = ws_arr(w, S_TRACE, cnt + bcnt, &a.trace))) return s;
   a.trace_rounds = kTraceRounds;
   a.trace_blk = a.trace + cnt;
@@ -258,7 +261,7 @@ sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
   HIPCHK(hipMemcpy(h.data(), a.trace, h.size() * sizeof(long long), hipMemcpyDeviceToHost));
   FILE *f = fopen(path, "a");
   if (!f) return SSSP_ERR_ARG;
-  fprintf(f, "round,start,arr_relax,end_relax,arr_lb,end_lb,arr_fix,end_fix,nf,ef,no,eo\n");
+  fprintf(f, "round,start,arr_relax,end_relax,arr_fused,end_fused,nf,ef,no,eo,mode\n");
   for (int r = 0; r < nr; ++r) {
     fprintf(f, "%d", r + 1);
     for (int k = 0; k < kTraceFields; ++k) fprintf(f, ",%lld", h[(size_t)r * kTraceFields + k]);
@@ -267,17 +270,17 @@ sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
   fclose(f);
   // per-block phase end times: <path>.blk, one line per (round, phase)
   const int nbr = nr < kTraceBlkRounds ? nr : kTraceBlkRounds;
-  std::vector<long long> hb((size_t)nbr * 3 * kMaxBlocks);
+  std::vector<long long> hb((size_t)nbr * 2 * kMaxBlocks);
   HIPCHK(hipMemcpy(hb.data(), a.trace_blk, hb.size() * sizeof(long long),
                    hipMemcpyDeviceToHost));
   std::string bp = std::string(path) + ".blk";
   f = fopen(bp.c_str(), "a");
   if (!f) return SSSP_ERR_ARG;
   for (int r = 0; r < nbr; ++r)
-    for (int ph = 0; ph < 3; ++ph) {
+    for (int ph = 0; ph < 2; ++ph) {
       fprintf(f, "%d,%d", r + 1, ph);
       for (int b = 0; b < nblocks; ++b)
-        fprintf(f, ",%lld", hb[((size_t)r * 3 + ph) * kMaxBlocks + b]);
+        fprintf(f, ",%lld", hb[((size_t)r * 2 + ph) * kMaxBlocks + b]);
       fprintf(f, "\n");
     }
   fclose(f);
@@ -466,7 +469,7 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
   a.total = g->n;
   a.max_rounds = g->n + 1;
   a.D = (int32_t *)cost;
-  a.coherent_filter = env_flag("SSSP_COHERENT_FILTER", 0);
+  a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
   LaunchGeom geo;
   if ((s = geometry(ws, f32, false, &geo))) return s;
@@ -531,7 +534,7 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   a.total = (int32_t)total;
   a.max_rounds = max_n + 1;
   a.D = (int32_t *)cost;
-  a.coherent_filter = env_flag("SSSP_COHERENT_FILTER", 0);
+  a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
   GraphDev *dg;
   InstDev *di;

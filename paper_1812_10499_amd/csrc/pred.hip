@@ -1,0 +1,178 @@
+// Emit pass of a solve (single or batched): costs and parent pointers from
+// the 64-bit (D, parent) keys the relax phase leaves behind, and the
+// equal-cost level pass for float32 ties.  Runs after the persistent round
+// kernel on the same stream.
+//
+// Parent rule (parent pointers, Section I): pred[y] is the smallest edge id
+// among tight in-edges (v, y, w), D[v] + w == D[y], with D[v] < D[y].  The
+// key's atomicMin already selected it: every in-edge of a reachable vertex
+// was offered exactly once, from a tail with its final cost, with the
+// equal-cost flag set when D[v] + w == D[v].  If the minimum key carries the
+// flag, y has no strict tight in-edge (only float32 edges below half an ulp
+// of the cost reach it at equal cost); such vertices get the level rule:
+// level 0 holds the source and every vertex with a strict tight in-edge, a
+// queued y gets level(y) = 1 + min level over equal-cost tight tails, and
+// pred[y] = the smallest such edge id with level(v) = level(y) - 1.
+#include "sssp_dev.h"
+#include "sssp_kernels.h"
+
+namespace sssp {
+
+template <class V, bool BATCH>
+__global__ __launch_bounds__(256) void emit_kernel(RoundArgs a, int32_t *pred, int32_t *degen,
+                                                   int32_t *lvl, long long *istat) {
+  const int inst = BATCH ? (int)blockIdx.y : 0;
+  int32_t sb = 0, gi = 0, s = a.source, n = a.g.n;
+  if constexpr (BATCH) {
+    const InstDev id = a.insts[inst];
+    sb = id.sbase;
+    gi = id.graph;
+    s = id.source;
+    n = id.n;
+  }
+  const GraphDev &G = graph_of<BATCH>(a, gi);
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  long long c_settled = 0, c_relaxed = 0;
+  if (y < n) {
+    const int32_t gy = sb + y;
+    const unsigned long long k = a.D64[gy];
+    const int32_t d = (int32_t)(k >> 32);
+    a.D[gy] = d;
+    if (d != V::INF) {
+      c_settled = 1;
+      c_relaxed = G.out_off[y + 1] - G.out_off[y];
+    }
+    if (pred) {
+      int32_t p = -1;
+      if (y != s && d != V::INF) {
+        if (k & kKeyEqualCost) {
+          p = -2;
+          const int q = atomicAdd(&a.ctl->deg_count, 1);
+          degen[q] = gy;
+          degen[a.total + q] = inst;
+          lvl[gy] = -1;
+        } else {
+          p = (int32_t)(k & kKeyEidMask);
+        }
+      }
+      pred[gy] = p;
+    }
+  }
+  if (istat) {
+    const long long s1 = wave_sum64(c_settled), s2 = wave_sum64(c_relaxed);
+    if (lane_id() == 0 && (s1 | s2)) {
+      atomicAdd((unsigned long long *)&istat[4 * inst + 1], (unsigned long long)s1);
+      atomicAdd((unsigned long long *)&istat[4 * inst + 2], (unsigned long long)s2);
+    }
+  }
+}
+
+// Equal-cost tie pass (float32 only; one block; the queue is tiny in
+// practice).
+template <class V, bool BATCH>
+__global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *pred,
+                                                          const int32_t *degen, int32_t *lvl,
+                                                          int32_t *flag) {
+  __shared__ int changed;
+  const int nd = ld_relaxed(&a.ctl->deg_count);
+  if (nd == 0) return;
+  for (int lv = 0;; ++lv) {
+    if (threadIdx.x == 0) changed = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+      flag[q] = 0;
+      const int32_t gy = degen[q];
+      if (lvl[gy] != -1) continue;
+      const int inst = degen[a.total + q];
+      int32_t sb = 0, gi = 0;
+      if constexpr (BATCH) {
+        const InstDev id = a.insts[inst];
+        sb = id.sbase;
+        gi = id.graph;
+      }
+      const GraphDev &G = graph_of<BATCH>(a, gi);
+      const int32_t y = gy - sb, dy = a.D[gy];
+      for (int32_t j = G.in_off[y]; j < G.in_off[y + 1]; ++j) {
+        const int32_t gv = sb + G.in_src[j];
+        const int32_t dv = a.D[gv];
+        if (dv == dy && V::add(dv, G.in_w[j]) == dy) {
+          const int32_t lv_v = (pred[gv] == -2) ? lvl[gv] : 0;
+          if (lv_v == lv) {
+            flag[q] = 1;
+            break;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+      if (flag[q]) {
+        lvl[degen[q]] = lv + 1;
+        changed = 1;
+      }
+    }
+    __syncthreads();
+    if (!changed) break;
+  }
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    const int32_t gy = degen[q];
+    const int inst = degen[a.total + q];
+    int32_t sb = 0, gi = 0;
+    if constexpr (BATCH) {
+      const InstDev id = a.insts[inst];
+      sb = id.sbase;
+      gi = id.graph;
+    }
+    const GraphDev &G = graph_of<BATCH>(a, gi);
+    const int32_t y = gy - sb, dy = a.D[gy], ly = lvl[gy];
+    int32_t best = -1;
+    if (ly >= 1) {
+      for (int32_t j = G.in_off[y]; j < G.in_off[y + 1]; ++j) {
+        const int32_t gv = sb + G.in_src[j];
+        const int32_t dv = a.D[gv];
+        if (dv == dy && V::add(dv, G.in_w[j]) == dy) {
+          const int32_t lv_v = (pred[gv] == -2) ? lvl[gv] : 0;
+          if (lv_v == ly - 1) {
+            best = G.in_eid[j];
+            break;
+          }
+        }
+      }
+    }
+    flag[q] = best;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    pred[degen[q]] = flag[q];
+    if (flag[q] < 0) a.ctl->status = 7;
+  }
+}
+
+template <class V, bool BATCH>
+static hipError_t launch_emit_t(const RoundArgs &a, int32_t *pred, long long *istat,
+                                int32_t max_n, hipStream_t stream) {
+  hipError_t e;
+  const dim3 grid((max_n + 255) / 256, BATCH ? a.num_inst : 1);
+  hipLaunchKernelGGL((emit_kernel<V, BATCH>), grid, dim3(256), 0, stream, a, pred, a.degen,
+                     a.lvl, istat);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (pred && V::INF == KeyF32::INF) {
+    hipLaunchKernelGGL((pred_degen_kernel<V, BATCH>), dim3(1), dim3(1024), 0, stream, a, pred,
+                       a.degen, a.lvl, a.flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
+                       const LaunchGeom &geo, long long *istat, int32_t max_n,
+                       hipStream_t stream) {
+  (void)geo;
+  if (f32)
+    return batch ? launch_emit_t<KeyF32, true>(a, pred, istat, max_n, stream)
+                 : launch_emit_t<KeyF32, false>(a, pred, istat, max_n, stream);
+  return batch ? launch_emit_t<KeyI32, true>(a, pred, istat, max_n, stream)
+               : launch_emit_t<KeyI32, false>(a, pred, istat, max_n, stream);
+}
+
+}  // namespace sssp

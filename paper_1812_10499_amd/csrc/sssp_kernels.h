@@ -12,29 +12,33 @@ constexpr int kRoundBlock = 512;  // threads per block of the persistent kernels
 constexpr int kMaxBlocks = 4096;  // upper bound on a persistent grid
 
 // Per-block partial minima of a single solve, [kParts][kMaxBlocks]: every
-// block overwrites its own slot each round and readers reduce over blocks,
-// so no two blocks ever update the same word.
+// block overwrites its own slot in each phase and readers reduce over all
+// slots, so no two blocks ever update the same word.  Slots come in pairs
+// indexed by round parity.
 enum PartSlot {
-  P_SURV0 = 0,  // min D of the open vertices that stay open (for the next round), by parity
+  P_SURV0 = 0,  // min D of the vertices that stay open, for the next round
   P_SURV1,
-  P_CAND0,      // min successful relaxation candidate, by round parity
+  P_TSURV0,     // min D + out_wmin of the vertices that stay open, next round
+  P_TSURV1,
+  P_CAND0,      // min successful relaxation candidate of this round's relax
   P_CAND1,
-  P_THR0,       // min D[y] + out_wmin[y] over the open set, by round parity
-  P_THR1,
+  P_TCAND0,     // min candidate + out_wmin of the head, this round's relax
+  P_TCAND1,
   kParts
 };
 
 // Control block of one persistent solve, in device memory.
 struct Ctl {
-  unsigned long long front_ctr;    // (items << 32) | out-degree sum of the next frontier
-  unsigned long long open_ctr[2];  // same for the two open-list buffers
-  unsigned int go;                 // grid barrier release word
-  int32_t status;                  // 0, or an sssp_status code set on the device
+  unsigned long long front_ctr[2];  // by round parity: (items << 32) | out-degree sum
+  unsigned long long open_ctr[2];   // by round parity: (items << 32) | in-degree sum
+  unsigned int go;                  // grid barrier / hand-over release word
+  int32_t status;                   // 0, or an sssp_status code set on the device
   int32_t rounds;
   int32_t deg_count;    // pred: vertices queued for the equal-cost pass
   int32_t heavy_count;  // pred: vertices queued for the wave-per-vertex pass
-  int32_t pad;
+  int32_t resume_round, resume_phase, done;  // hand-over from a one-block stretch
   long long settled, relaxed, scanned, open_visits;
+  long long solo_phases;  // phases run by block 0 alone
 };
 
 // Optional event pair recorded around the persistent kernel launch.
@@ -50,7 +54,15 @@ struct RoundArgs {
   int32_t source;            // single solve
   int32_t total;             // state entries (sum of instance vertex counts)
   int32_t max_rounds;
-  int32_t *D, *C, *mtmp;
+  int32_t *D;                // the caller's cost array (written by the emit pass)
+  // Upper bound and parent candidate per state entry, one 64-bit key:
+  // (D << 32) | (equal-cost flag << 31) | edge id.  atomicMin on the key
+  // keeps the least D and, among candidates that reach it, strict ones
+  // (tail cost below D) before equal-cost ones, then the smallest edge id.
+  unsigned long long *D64;
+  int32_t *C0, *C1;          // lower bounds, double-buffered by round parity
+  int32_t *mtmp;             // per open slot: partial m_y of items split over blocks
+  unsigned int *arrive;      // per open slot: contributing blocks that finished
   int32_t *open_v0, *open_p0, *open_i0;
   int32_t *open_v1, *open_p1, *open_i1;
   int32_t *front_v, *front_p, *front_i;
@@ -63,18 +75,18 @@ struct RoundArgs {
   long long *trace;
   int32_t trace_rounds;
   int32_t trace_blk_rounds;  // rounds with per-block phase end times
-  long long *trace_blk;      // [round][3 phases][kMaxBlocks] wall-clock at each block's phase end
-  unsigned int *flags;  // grid barrier flags, kMaxBlocks * kFlagStride
-  int32_t *part;        // per-block partial minima, kParts * kMaxBlocks
-  int32_t coherent_filter;  // relax reads D[head] with an agent-coherent load
+  long long *trace_blk;      // [round][2 phases][kMaxBlocks] wall-clock at each block's phase end
+  unsigned int *flags;       // grid barrier flags, kMaxBlocks * kFlagStride
+  int32_t *part;             // per-block partial minima, kParts * kMaxBlocks
+  int32_t solo_edges;        // phases with at most this many edges run on block 0 alone
 };
 
-// Trace record of one round: wall-clock (100 MHz) at relax start, the last
-// block's arrival and the release of each of the three barriers, and the
-// list sizes the round processed.
+// Trace record of one round: wall-clock (100 MHz) at the relax start, block
+// 0's arrival at and release from each of the two barriers, the list sizes,
+// and which phases ran on one block (bit 0 relax, bit 1 bound-and-fix).
 enum TraceField {
-  TR_START = 0, TR_ARR_RELAX, TR_END_RELAX, TR_ARR_LB, TR_END_LB, TR_ARR_FIX, TR_END_FIX,
-  TR_NF, TR_EF, TR_NO, TR_EO, kTraceFields
+  TR_START = 0, TR_ARR_RELAX, TR_END_RELAX, TR_ARR_FUSED, TR_END_FUSED,
+  TR_NF, TR_EF, TR_NO, TR_EO, TR_MODE, kTraceFields
 };
 
 struct LaunchGeom {
@@ -82,9 +94,33 @@ struct LaunchGeom {
   int cus;
 };
 
+constexpr unsigned long long kKeyEidMask = 0x7fffffffull;
+constexpr unsigned long long kKeyEqualCost = 0x80000000ull;
+
+__device__ __forceinline__ unsigned long long make_key(int32_t d, int32_t eid, bool equal_cost) {
+  return ((unsigned long long)(uint32_t)d << 32) | (equal_cost ? kKeyEqualCost : 0ull) |
+         (unsigned long long)(uint32_t)eid;
+}
+
+// address of the D half of a key (little-endian: the high word)
+__device__ __forceinline__ int32_t *key_d(unsigned long long *k) {
+  return reinterpret_cast<int32_t *>(k) + 1;
+}
+
+// Graph of an item: the kernel argument for a single solve, the table
+// entry for a batch.
+template <bool BATCH>
+__device__ __forceinline__ const GraphDev &graph_of(const RoundArgs &a, int gi) {
+  if constexpr (BATCH) return a.graphs[gi];
+  else return a.g;
+}
+
 hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                         const LaunchGeom &geo, long long *istat, int32_t max_n,
                         const KernelTimer *timer, hipStream_t stream);
+hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
+                       const LaunchGeom &geo, long long *istat, int32_t max_n,
+                       hipStream_t stream);
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
 
 // ------------------------------------------------------------- builder
