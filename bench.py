@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--order", default="auto", choices=["auto", "input", "degree"],
+                    help="vertex numbering of the solver's working copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the method runs on a single device here); "
@@ -108,7 +110,7 @@ def main():
     log("generating", args.workload)
     g, wname, wdesc = make_workload(args.workload)
     log("building graph n=%d m=%d" % (g.n, g.m))
-    G = sp.Graph(g.n, g.src, g.dst, g.w, device="cuda:0")
+    G = sp.Graph(g.n, g.src, g.dst, g.w, device="cuda:0", order=args.order)
     cost = torch.empty(g.n, dtype=G.value_dtype, device="cuda:0")
     pred = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
     stream = torch.cuda.current_stream()
@@ -171,6 +173,7 @@ def main():
         "dtype": "int32" if G.value_dtype == torch.int32 else "f32",
         "data": "synthetic",
         "config": {"workload": wname, "n": g.n, "m": g.m, "source": g.source,
+                   "vertex_order": G.order,
                    "weights": wdesc, "m_reach": m_reach},
         "hbm_gbps_algorithmic": round(achieved, 1),
         "rounds": stats["rounds"],

@@ -61,8 +61,22 @@ typedef enum {
 } sssp_status;
 
 /*
+ * Vertex numbering of the solver's working copy of a graph.  The rounds
+ * gather lower and upper bounds of in- and out-neighbours; on skewed
+ * degree distributions a numbering by descending degree packs the bounds
+ * that are gathered most into few cache lines.  It changes no result:
+ * every output and every edge id stays in the caller's numbering.
+ *   SSSP_ORDER_AUTO    degree order when the largest total degree is at
+ *                      least 16 times the mean, else the input order
+ *   SSSP_ORDER_INPUT   the caller's vertex ids
+ *   SSSP_ORDER_DEGREE  descending out-degree + in-degree, ties by vertex id
+ */
+typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 } sssp_order;
+
+/*
  * A built graph: CSR by tail plus CSC by head (the incoming-edge access the
- * method assumes, Section I).  All arrays are device arrays.
+ * method assumes, Section I).  All arrays are device arrays in the caller's
+ * build buffer.
  *   out_off[n+1], out_dst[m], out_w[m]        CSR; edge id = CSR position
  *   in_off[n+1],  in_src[m], in_eid[m], in_w[m]
  *       CSC; in_eid[j] is the edge id of CSC entry j, and each vertex's
@@ -71,12 +85,23 @@ typedef enum {
  *                 outWeight array of SP_3 and SP_4, Figs. 4 and 5)
  *   w_max         largest weight (filled by the builder; used for the
  *                 int32 overflow precondition)
+ * The solver's working copy (order == SSSP_ORDER_DEGREE; with
+ * SSSP_ORDER_INPUT the s_ arrays alias the arrays above and vid, rank,
+ * s_out_eid and s_in_eid are NULL, meaning the identity):
+ *   vid[k]  vertex id of solver vertex k;  rank[v]  solver id of vertex v
+ *   s_out_off[n+1], s_out_dst[m] (solver ids), s_out_w[m], s_out_eid[m]
+ *       CSR over solver ids, each out-list ascending by head solver id;
+ *       s_out_eid holds the edge id of each entry
+ *   s_in_off[n+1], s_in_src[m] (solver ids), s_in_eid[m], s_in_w[m]
+ *       CSC over solver ids, each in-list ascending by tail solver id
+ *   s_out_wmin[n]  out_wmin by solver id
+ * These arrays are library-internal; callers only keep them valid.
  */
 typedef struct {
   int32_t n;
   int32_t m;
   int32_t dtype; /* sssp_dtype */
-  int32_t reserved;
+  int32_t order; /* sssp_order the builder applied: INPUT or DEGREE */
   const int32_t *out_off;
   const int32_t *out_dst;
   const void *out_w;
@@ -86,6 +111,17 @@ typedef struct {
   const void *in_w;
   const void *out_wmin;
   double w_max;
+  const int32_t *vid;
+  const int32_t *rank;
+  const int32_t *s_out_off;
+  const int32_t *s_out_dst;
+  const void *s_out_w;
+  const int32_t *s_out_eid;
+  const int32_t *s_in_off;
+  const int32_t *s_in_src;
+  const int32_t *s_in_eid;
+  const void *s_in_w;
+  const void *s_out_wmin;
 } sssp_csr;
 
 /* Per-solve counters (host struct). */
@@ -99,29 +135,32 @@ typedef struct {
 
 /*
  * Bytes of the device buffer sssp_build_csr fills for a graph of n vertices,
- * m edges and the given dtype.  Returns 0 for invalid sizes.
+ * m edges, the given dtype and vertex order (SSSP_ORDER_INPUT needs no
+ * working copy; AUTO and DEGREE reserve room for one).  Returns 0 for
+ * invalid arguments.
  */
-size_t sssp_build_csr_bytes(int32_t n, int32_t m, sssp_dtype dtype);
+size_t sssp_build_csr_bytes(int32_t n, int32_t m, sssp_dtype dtype, sssp_order order);
 
 /*
- * Build the CSR/CSC of a directed graph from COO edges on the GPU.
+ * Build the CSR/CSC of a directed graph from COO edges on the GPU, plus the
+ * solver's working copy in the requested vertex order.
  * Inputs (device): src[m], dst[m] vertex ids; w[m] weights (int32 or
  * float32 per dtype).  Self-loops and duplicate edges are kept.
- * buffer: device buffer of at least sssp_build_csr_bytes(n, m, dtype)
- * bytes, owned by the caller; *out receives pointers into it.
+ * buffer: device buffer of at least sssp_build_csr_bytes(n, m, dtype,
+ * order) bytes, owned by the caller; *out receives pointers into it.
  * perm (device, nullable): perm[k] = COO index of edge id k.
  * Validates endpoints (SSSP_ERR_GRAPH), weights (SSSP_ERR_WEIGHT) and the
  * int32 overflow precondition (SSSP_ERR_OVERFLOW).  SYNCHRONOUS: returns
  * after the stream work has completed.
  */
-sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, const int32_t *src,
-                           const int32_t *dst, const void *w, void *buffer, size_t buffer_bytes,
-                           sssp_csr *out, int32_t *perm, void *stream);
+sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order order,
+                           const int32_t *src, const int32_t *dst, const void *w, void *buffer,
+                           size_t buffer_bytes, sssp_csr *out, int32_t *perm, void *stream);
 
 /*
  * Replace the weights of a built graph: w[m] (device) is given in edge-id
- * order; out_w, in_w, out_wmin and w_max of *g are rewritten in place (the
- * arrays live in the caller's build buffer).  Validates weights and the
+ * order; every weight array of *g (also the working copy's) and w_max are
+ * rewritten in place (the arrays live in the caller's build buffer).  Validates weights and the
  * overflow precondition.  SYNCHRONOUS.
  */
 sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream);

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SSSP_LIBRARY") or os.path.join(_HERE, "libsssp.so")
 
 SSSP_I32, SSSP_F32 = 0, 1
+SSSP_ORDER_AUTO, SSSP_ORDER_INPUT, SSSP_ORDER_DEGREE = 0, 1, 2
 (SSSP_OK, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_WEIGHT, SSSP_ERR_OVERFLOW, SSSP_ERR_NOMEM,
  SSSP_ERR_HIP, SSSP_ERR_INTERNAL) = range(8)
 
@@ -27,12 +28,18 @@ EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_s
 
 class Csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("order", ctypes.c_int32),
                 ("out_off", ctypes.c_void_p), ("out_dst", ctypes.c_void_p),
                 ("out_w", ctypes.c_void_p), ("in_off", ctypes.c_void_p),
                 ("in_src", ctypes.c_void_p), ("in_eid", ctypes.c_void_p),
                 ("in_w", ctypes.c_void_p), ("out_wmin", ctypes.c_void_p),
-                ("w_max", ctypes.c_double)]
+                ("w_max", ctypes.c_double),
+                ("vid", ctypes.c_void_p), ("rank", ctypes.c_void_p),
+                ("s_out_off", ctypes.c_void_p), ("s_out_dst", ctypes.c_void_p),
+                ("s_out_w", ctypes.c_void_p), ("s_out_eid", ctypes.c_void_p),
+                ("s_in_off", ctypes.c_void_p), ("s_in_src", ctypes.c_void_p),
+                ("s_in_eid", ctypes.c_void_p), ("s_in_w", ctypes.c_void_p),
+                ("s_out_wmin", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -62,10 +69,10 @@ def lib():
                               "(hipcc --offload-arch=gfx950)")
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p
-        L.sssp_build_csr_bytes.argtypes = [i32, i32, ctypes.c_int]
+        L.sssp_build_csr_bytes.argtypes = [i32, i32, ctypes.c_int, ctypes.c_int]
         L.sssp_build_csr_bytes.restype = ctypes.c_size_t
-        L.sssp_build_csr.argtypes = [i32, i32, ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t,
-                                     ctypes.POINTER(Csr), vp, vp]
+        L.sssp_build_csr.argtypes = [i32, i32, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp,
+                                     ctypes.c_size_t, ctypes.POINTER(Csr), vp, vp]
         L.sssp_build_csr.restype = ctypes.c_int
         L.sssp_set_weights.argtypes = [ctypes.POINTER(Csr), vp, vp]
         L.sssp_set_weights.restype = ctypes.c_int
@@ -104,12 +111,13 @@ def sssp_strerror(status: int) -> str:
     return lib().sssp_strerror(int(status)).decode()
 
 
-def sssp_build_csr_bytes(n: int, m: int, dtype: int) -> int:
-    return int(lib().sssp_build_csr_bytes(n, m, dtype))
+def sssp_build_csr_bytes(n: int, m: int, dtype: int, order: int) -> int:
+    return int(lib().sssp_build_csr_bytes(n, m, dtype, order))
 
 
-def sssp_build_csr(n, m, dtype, src, dst, w, buffer, buffer_bytes, out: Csr, perm, stream):
-    _check(lib().sssp_build_csr(n, m, dtype, src, dst, w, buffer, buffer_bytes,
+def sssp_build_csr(n, m, dtype, order, src, dst, w, buffer, buffer_bytes, out: Csr, perm,
+                   stream):
+    _check(lib().sssp_build_csr(n, m, dtype, order, src, dst, w, buffer, buffer_bytes,
                                 ctypes.byref(out), perm, stream), "sssp_build_csr")
 
 

@@ -146,9 +146,15 @@ sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
 }
 
 bool csr_ok(const sssp_csr *g) {
-  return g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
-         g->out_off && g->in_off && g->out_wmin &&
-         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w));
+  if (!(g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
+        g->out_off && g->in_off && g->out_wmin &&
+        (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w))))
+    return false;
+  if (g->order == SSSP_ORDER_INPUT) return true;
+  return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && g->s_out_off && g->s_in_off &&
+         g->s_out_wmin &&
+         (g->m == 0 || (g->s_out_dst && g->s_out_w && g->s_out_eid && g->s_in_src &&
+                        g->s_in_eid && g->s_in_w));
 }
 
 bool overflow_risk(const sssp_csr *g) {
@@ -156,42 +162,56 @@ bool overflow_risk(const sssp_csr *g) {
   return (double)(g->n - 1) * g->w_max >= (double)INT_MAX;
 }
 
+// Device view of a built graph: the solver-numbered arrays for the rounds,
+// the caller-numbered ones for the parent tie pass and the backward pass.
 GraphDev graph_dev(const sssp_csr *g) {
   GraphDev d;
-  d.out_off = g->out_off;
-  d.out_dst = g->out_dst;
-  d.out_w = (const int32_t *)g->out_w;
-  d.in_off = g->in_off;
-  d.in_src = g->in_src;
-  d.in_eid = g->in_eid;
-  d.in_w = (const int32_t *)g->in_w;
-  d.out_wmin = (const int32_t *)g->out_wmin;
+  const bool copy = g->order == SSSP_ORDER_DEGREE;
+  d.out_off = copy ? g->s_out_off : g->out_off;
+  d.out_dst = copy ? g->s_out_dst : g->out_dst;
+  d.out_w = (const int32_t *)(copy ? g->s_out_w : g->out_w);
+  d.out_eid = copy ? g->s_out_eid : nullptr;
+  d.in_off = copy ? g->s_in_off : g->in_off;
+  d.in_src = copy ? g->s_in_src : g->in_src;
+  d.in_w = (const int32_t *)(copy ? g->s_in_w : g->in_w);
+  d.out_wmin = (const int32_t *)(copy ? g->s_out_wmin : g->out_wmin);
+  d.vid = copy ? g->vid : nullptr;
+  d.rank = copy ? g->rank : nullptr;
+  d.u_out_off = g->out_off;
+  d.u_out_dst = g->out_dst;
+  d.u_in_off = g->in_off;
+  d.u_in_src = g->in_src;
+  d.u_in_eid = g->in_eid;
+  d.u_in_w = (const int32_t *)g->in_w;
   d.n = g->n;
   d.m = g->m;
   return d;
 }
 
+// Build buffer: the caller-numbered CSR/CSC, then (degree order) the
+// solver-numbered copy.
+enum BufArr {
+  B_OUT_OFF, B_OUT_DST, B_OUT_W, B_IN_OFF, B_IN_SRC, B_IN_EID, B_IN_W, B_OUT_WMIN,
+  B_VID, B_RANK, B_S_OUT_OFF, B_S_OUT_DST, B_S_OUT_W, B_S_OUT_EID, B_S_IN_OFF, B_S_IN_SRC,
+  B_S_IN_EID, B_S_IN_W, B_S_OUT_WMIN, B_COUNT
+};
+
 struct Layout {
-  size_t off[8];
+  size_t off[B_COUNT];
   size_t total;
 };
 
-Layout build_layout(int32_t n, int32_t m) {
+Layout build_layout(int32_t n, int32_t m, bool copy) {
   Layout L;
   size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t at = o;
-    o += (bytes + 255) & ~(size_t)255;
-    return at;
-  };
-  L.off[0] = take(sizeof(int32_t) * ((size_t)n + 1));  // out_off
-  L.off[1] = take(sizeof(int32_t) * (size_t)m);        // out_dst
-  L.off[2] = take(sizeof(int32_t) * (size_t)m);        // out_w
-  L.off[3] = take(sizeof(int32_t) * ((size_t)n + 1));  // in_off
-  L.off[4] = take(sizeof(int32_t) * (size_t)m);        // in_src
-  L.off[5] = take(sizeof(int32_t) * (size_t)m);        // in_eid
-  L.off[6] = take(sizeof(int32_t) * (size_t)m);        // in_w
-  L.off[7] = take(sizeof(int32_t) * (size_t)n);        // out_wmin
+  const size_t N = (size_t)n, M = (size_t)m;
+  const size_t count[B_COUNT] = {N + 1, M, M, N + 1, M, M, M, N,
+                                 N, N, N + 1, M, M, M, N + 1, M, M, M, N};
+  const int narr = copy ? B_COUNT : B_VID;
+  for (int i = 0; i < B_COUNT; ++i) {
+    L.off[i] = o;
+    if (i < narr) o += (sizeof(int32_t) * count[i] + 255) & ~(size_t)255;
+  }
   L.total = o;
   return L;
 }
@@ -349,18 +369,22 @@ const char *sssp_strerror(sssp_status st) {
   return "unknown status";
 }
 
-size_t sssp_build_csr_bytes(int32_t n, int32_t m, sssp_dtype dtype) {
+size_t sssp_build_csr_bytes(int32_t n, int32_t m, sssp_dtype dtype, sssp_order order) {
   if (n <= 0 || m < 0 || (dtype != SSSP_I32 && dtype != SSSP_F32)) return 0;
-  return build_layout(n, m).total;
+  if (order != SSSP_ORDER_AUTO && order != SSSP_ORDER_INPUT && order != SSSP_ORDER_DEGREE)
+    return 0;
+  return build_layout(n, m, order != SSSP_ORDER_INPUT).total;
 }
 
-sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, const int32_t *src,
-                           const int32_t *dst, const void *w, void *buffer, size_t buffer_bytes,
-                           sssp_csr *out, int32_t *perm, void *stream_) {
+sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order order,
+                           const int32_t *src, const int32_t *dst, const void *w, void *buffer,
+                           size_t buffer_bytes, sssp_csr *out, int32_t *perm, void *stream_) {
   if (n <= 0 || m < 0 || (dtype != SSSP_I32 && dtype != SSSP_F32) || !out || !buffer)
     return SSSP_ERR_ARG;
+  if (order != SSSP_ORDER_AUTO && order != SSSP_ORDER_INPUT && order != SSSP_ORDER_DEGREE)
+    return SSSP_ERR_ARG;
   if (m > 0 && (!src || !dst || !w)) return SSSP_ERR_ARG;
-  const Layout L = build_layout(n, m);
+  const Layout L = build_layout(n, m, order != SSSP_ORDER_INPUT);
   if (buffer_bytes < L.total) return SSSP_ERR_ARG;
   hipStream_t stream = (hipStream_t)stream_;
   const bool f32 = dtype == SSSP_F32;
@@ -371,30 +395,31 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, const int32_t
   DevWS &ws = *wp;
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
   char *b = (char *)buffer;
-  int32_t *out_off = (int32_t *)(b + L.off[0]), *out_dst = (int32_t *)(b + L.off[1]);
-  int32_t *out_w = (int32_t *)(b + L.off[2]), *in_off = (int32_t *)(b + L.off[3]);
-  int32_t *in_src = (int32_t *)(b + L.off[4]), *in_eid = (int32_t *)(b + L.off[5]);
-  int32_t *in_w = (int32_t *)(b + L.off[6]), *out_wmin = (int32_t *)(b + L.off[7]);
+  auto arr = [&](int i) { return (int32_t *)(b + L.off[i]); };
+  int32_t *out_off = arr(B_OUT_OFF), *out_dst = arr(B_OUT_DST), *out_w = arr(B_OUT_W);
+  int32_t *in_off = arr(B_IN_OFF), *in_src = arr(B_IN_SRC), *in_eid = arr(B_IN_EID);
+  int32_t *in_w = arr(B_IN_W), *out_wmin = arr(B_OUT_WMIN);
   BuildTemps t;
-  const size_t M = (size_t)(m > 0 ? m : 1);
+  const size_t M = (size_t)(m > n ? m : n);
   if ((s = ws_arr(ws, S_BK_KA, M, &t.ka))) return s;
   if ((s = ws_arr(ws, S_BK_KB, M, &t.kb))) return s;
   if ((s = ws_arr(ws, S_BK_VA, M, &t.va))) return s;
   if ((s = ws_arr(ws, S_BK_VB, M, &t.vb))) return s;
-  if ((s = ws_arr(ws, S_BK_TAIL, M, &t.tail))) return s;
-  if ((s = ws_arr(ws, S_BK_HIST, build_hist_entries(m), &t.hist))) return s;
-  if ((s = ws_arr(ws, S_BK_STATUS, 2, &t.status))) return s;
-  HIPCHK(hipMemsetAsync(t.status, 0, 2 * sizeof(int32_t), stream));
+  if ((s = ws_arr(ws, S_BK_TAIL, (size_t)(m > 0 ? m : 1), &t.tail))) return s;
+  if ((s = ws_arr(ws, S_BK_HIST, build_hist_entries(m > n ? m : n), &t.hist))) return s;
+  if ((s = ws_arr(ws, S_BK_STATUS, 4, &t.status))) return s;
+  HIPCHK(hipMemsetAsync(t.status, 0, 4 * sizeof(int32_t), stream));
   HIPCHK(launch_validate(n, m, f32, src, dst, (const int32_t *)w, t.status, stream));
-  int32_t hs[2];
+  int32_t hs[4];
   HIPCHK(hipMemcpyAsync(hs, t.status, sizeof(hs), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   if (hs[0] & 1) return SSSP_ERR_GRAPH;
   if (hs[0] & 2) return SSSP_ERR_WEIGHT;
+  memset(out, 0, sizeof(*out));
   out->n = n;
   out->m = m;
   out->dtype = dtype;
-  out->reserved = 0;
+  out->order = SSSP_ORDER_INPUT;
   out->out_off = out_off;
   out->out_dst = out_dst;
   out->out_w = out_w;
@@ -413,6 +438,50 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, const int32_t
   if (overflow_risk(out)) return SSSP_ERR_OVERFLOW;
   HIPCHK(launch_build(n, m, f32, src, dst, (const int32_t *)w, out_off, out_dst, out_w, in_off,
                       in_src, in_eid, in_w, out_wmin, perm, t, stream));
+  if (order != SSSP_ORDER_INPUT && m > 0) {
+    HIPCHK(launch_degree(n, out_off, in_off, t, stream));
+    HIPCHK(hipMemcpyAsync(hs, t.status, sizeof(hs), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const int32_t dmax = hs[2];
+    // skewed: largest total degree >= 16 x the mean 2m/n
+    const bool skewed = (int64_t)dmax * n >= 32 * (int64_t)m;
+    if (order == SSSP_ORDER_DEGREE || skewed) {
+      SolverCopy c;
+      c.vid = arr(B_VID);
+      c.rank = arr(B_RANK);
+      c.out_off = arr(B_S_OUT_OFF);
+      c.out_dst = arr(B_S_OUT_DST);
+      c.out_w = arr(B_S_OUT_W);
+      c.out_eid = arr(B_S_OUT_EID);
+      c.in_off = arr(B_S_IN_OFF);
+      c.in_src = arr(B_S_IN_SRC);
+      c.in_eid = arr(B_S_IN_EID);
+      c.in_w = arr(B_S_IN_W);
+      c.out_wmin = arr(B_S_OUT_WMIN);
+      HIPCHK(launch_solver_copy(n, m, dmax, out_dst, out_w, out_wmin, c, t, stream));
+      out->order = SSSP_ORDER_DEGREE;
+      out->vid = c.vid;
+      out->rank = c.rank;
+      out->s_out_off = c.out_off;
+      out->s_out_dst = c.out_dst;
+      out->s_out_w = c.out_w;
+      out->s_out_eid = c.out_eid;
+      out->s_in_off = c.in_off;
+      out->s_in_src = c.in_src;
+      out->s_in_eid = c.in_eid;
+      out->s_in_w = c.in_w;
+      out->s_out_wmin = c.out_wmin;
+    }
+  }
+  if (out->order == SSSP_ORDER_INPUT) {
+    out->s_out_off = out_off;
+    out->s_out_dst = out_dst;
+    out->s_out_w = out_w;
+    out->s_in_off = in_off;
+    out->s_in_src = in_src;
+    out->s_in_w = in_w;
+    out->s_out_wmin = out_wmin;
+  }
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));
   return SSSP_OK;
@@ -431,9 +500,20 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
   int32_t *status;
   if ((s = ws_arr(ws, S_BK_STATUS, 2, &status))) return s;
   HIPCHK(hipMemsetAsync(status, 0, 2 * sizeof(int32_t), stream));
+  SolverCopy c;
+  memset(&c, 0, sizeof(c));
+  const bool copy = g->order == SSSP_ORDER_DEGREE;
+  if (copy) {
+    c.vid = (int32_t *)g->vid;
+    c.out_eid = (int32_t *)g->s_out_eid;
+    c.in_eid = (int32_t *)g->s_in_eid;
+    c.out_w = (int32_t *)g->s_out_w;
+    c.in_w = (int32_t *)g->s_in_w;
+    c.out_wmin = (int32_t *)g->s_out_wmin;
+  }
   HIPCHK(launch_set_weights(g->n, g->m, f32, (const int32_t *)w, g->out_off, g->in_eid,
                             (int32_t *)g->out_w, (int32_t *)g->in_w, (int32_t *)g->out_wmin,
-                            status, stream));
+                            copy ? &c : nullptr, status, stream));
   int32_t hs[2];
   HIPCHK(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));

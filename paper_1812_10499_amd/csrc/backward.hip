@@ -55,10 +55,10 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
         sb = id.sbase;
         G = &a.graphs[id.graph];
         vx = x - sb;
-        k0 = G->out_off[vx];
-        k1 = G->out_off[vx + 1];
+        k0 = G->u_out_off[vx];
+        k1 = G->u_out_off[vx + 1];
         for (int32_t k = k0; k < k1; ++k)
-          if (a.pred[sb + G->out_dst[k]] == k) ++nch;
+          if (a.pred[sb + G->u_out_dst[k]] == k) ++nch;
       }
       uint64_t tot;
       const uint64_t ex = block_excl_scan64<BBS>((uint64_t)nch, scan, &tot);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
         uint32_t p = sbase + (uint32_t)ex;
         if (idx < e && nch) {
           for (int32_t k = k0; k < k1; ++k) {
-            const int32_t c = G->out_dst[k];
+            const int32_t c = G->u_out_dst[k];
             if (a.pred[sb + c] == k) {
               a.lv_v[p] = sb + c;
               a.lv_i[p] = ins;
@@ -96,8 +96,8 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
       const GraphDev &G = a.graphs[id.graph];
       const int32_t sb = id.sbase, vy = y - sb;
       float acc = a.gcost[y];
-      for (int32_t k = G.out_off[vy]; k < G.out_off[vy + 1]; ++k) {
-        const int32_t c = sb + G.out_dst[k];
+      for (int32_t k = G.u_out_off[vy]; k < G.u_out_off[vy + 1]; ++k) {
+        const int32_t c = sb + G.u_out_dst[k];
         if (a.pred[c] == k) acc = __fadd_rn(acc, a.acc[c]);
       }
       a.acc[y] = acc;
@@ -122,7 +122,7 @@ __global__ void bw_grad_kernel(BackArgs a, const int32_t *goff, const int32_t *g
     }
     const GraphDev &G = a.graphs[lo];
     const int32_t e = q - ebase[lo];
-    const int32_t y = G.out_dst[e];
+    const int32_t y = G.u_out_dst[e];
     float sum = 0.0f;
     for (int32_t j = goff[lo]; j < goff[lo + 1]; ++j) {
       const int32_t sb = a.insts[ginst[j]].sbase;

@@ -310,29 +310,150 @@ hipError_t launch_build(int32_t n, int32_t m, bool f32, const int32_t *src, cons
   return hipGetLastError();
 }
 
+// ------------------------------------------------ solver numbering (copy)
+// total degree per vertex, and its maximum into status[2]
+__global__ void degree_kernel(const int32_t *out_off, const int32_t *in_off, int32_t n,
+                              int32_t *deg, int32_t *status) {
+  int32_t mx = 0;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int32_t d = (out_off[v + 1] - out_off[v]) + (in_off[v + 1] - in_off[v]);
+    deg[v] = d;
+    mx = kmax(mx, d);
+  }
+  if (mx) atomicMax(&status[2], mx);
+}
+
+// sort key for descending degree: dmax - deg; values = vertex ids
+__global__ void degree_key_kernel(int32_t *key, int32_t *val, int32_t n, int32_t dmax) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    key[v] = dmax - key[v];
+    val[v] = v;
+  }
+}
+
+__global__ void rank_kernel(const int32_t *vid, int32_t n, int32_t *vid_out, int32_t *rank) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int32_t v = vid[k];
+    vid_out[k] = v;
+    rank[v] = k;
+  }
+}
+
+// key[i] = rank[ends[val[i]]] (val: edge ids, ends: tail or head per edge
+// id); with iota = true the value array is (re)set to the identity first
+__global__ void edge_key_kernel(const int32_t *ends, const int32_t *rank, int32_t m,
+                                int32_t *key, int32_t *val, bool iota) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    if (iota) val[i] = i;
+    key[i] = rank[ends[val[i]]];
+  }
+}
+
+// entry p of a solver-numbered list: edge id eid[p]; the neighbour id
+// (through rank) and weight come from the caller-numbered arrays
+__global__ void copy_gather_kernel(const int32_t *eid, const int32_t *ends, const int32_t *rank,
+                                   const int32_t *out_w, int32_t m, int32_t *s_nbr,
+                                   int32_t *s_w) {
+  for (int32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+    const int32_t e = eid[p];
+    s_nbr[p] = rank[ends[e]];
+    s_w[p] = out_w[e];
+  }
+}
+
+__global__ void copy_wmin_kernel(const int32_t *vid, const int32_t *out_wmin, int32_t n,
+                                 int32_t *s_out_wmin) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    s_out_wmin[k] = out_wmin[vid[k]];
+}
+
+hipError_t launch_degree(int32_t n, const int32_t *out_off, const int32_t *in_off,
+                         const BuildTemps &t, hipStream_t stream) {
+  hipLaunchKernelGGL(degree_kernel, dim3(grid_for(n)), dim3(256), 0, stream, out_off, in_off, n,
+                     t.ka, t.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_solver_copy(int32_t n, int32_t m, int32_t dmax, const int32_t *out_dst,
+                              const int32_t *out_w,
+                              const int32_t *out_wmin, const SolverCopy &c, const BuildTemps &t,
+                              hipStream_t stream) {
+  hipError_t e;
+  const int gm = grid_for(m), gn = grid_for((int64_t)n + 1);
+  // vertex order: stable sort by dmax - degree (t.ka holds the degrees)
+  hipLaunchKernelGGL(degree_key_kernel, dim3(grid_for(n)), dim3(256), 0, stream, t.ka, t.va, n,
+                     dmax);
+  if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, n, dmax + 1, t.hist, stream)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(rank_kernel, dim3(grid_for(n)), dim3(256), 0, stream, t.va, n, c.vid,
+                     c.rank);
+  if (m > 0) {
+    // CSR: edges by (rank of tail, rank of head): LSD order, head first
+    hipLaunchKernelGGL(edge_key_kernel, dim3(gm), dim3(256), 0, stream, out_dst, c.rank, m, t.ka,
+                       t.va, true);
+    if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(edge_key_kernel, dim3(gm), dim3(256), 0, stream, t.tail, c.rank, m, t.ka,
+                       t.va, false);
+    if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
+    e = hipMemcpyAsync(c.out_eid, t.va, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice,
+                       stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(copy_gather_kernel, dim3(gm), dim3(256), 0, stream, c.out_eid, out_dst,
+                       c.rank, out_w, m, c.out_dst, c.out_w);
+  }
+  hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, c.out_off);
+  if (m > 0) {
+    // CSC: edges by (rank of head, rank of tail)
+    hipLaunchKernelGGL(edge_key_kernel, dim3(gm), dim3(256), 0, stream, t.tail, c.rank, m, t.ka,
+                       t.va, true);
+    if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(edge_key_kernel, dim3(gm), dim3(256), 0, stream, out_dst, c.rank, m, t.ka,
+                       t.va, false);
+    if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
+    e = hipMemcpyAsync(c.in_eid, t.va, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice,
+                       stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(copy_gather_kernel, dim3(gm), dim3(256), 0, stream, c.in_eid, t.tail,
+                       c.rank, out_w, m, c.in_src, c.in_w);
+  }
+  hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, c.in_off);
+  hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c.vid, out_wmin,
+                     n, c.out_wmin);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------- reweighting
 __global__ void set_weights_kernel(const int32_t *w, const int32_t *in_eid, int32_t m,
-                                   int32_t *out_w, int32_t *in_w) {
+                                   int32_t *out_w, int32_t *in_w, const int32_t *s_out_eid,
+                                   const int32_t *s_in_eid, int32_t *s_out_w, int32_t *s_in_w) {
   for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
     out_w[j] = w[j];
     in_w[j] = w[in_eid[j]];
+    if (s_out_eid) {
+      s_out_w[j] = w[s_out_eid[j]];
+      s_in_w[j] = w[s_in_eid[j]];
+    }
   }
 }
 
 hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
                               const int32_t *out_off, const int32_t *in_eid, int32_t *out_w,
-                              int32_t *in_w, int32_t *out_wmin, int32_t *status,
-                              hipStream_t stream) {
+                              int32_t *in_w, int32_t *out_wmin, const SolverCopy *c,
+                              int32_t *status, hipStream_t stream) {
   hipError_t e = launch_validate(n, m, f32, nullptr, nullptr, w, status, stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(set_weights_kernel, dim3(grid_for(m)), dim3(256), 0, stream, w, in_eid, m,
-                     out_w, in_w);
+                     out_w, in_w, c ? c->out_eid : nullptr, c ? c->in_eid : nullptr,
+                     c ? c->out_w : nullptr, c ? c->in_w : nullptr);
   if (f32)
     hipLaunchKernelGGL(wmin_kernel<true>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
                        out_w, n, out_wmin);
   else
     hipLaunchKernelGGL(wmin_kernel<false>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
                        out_w, n, out_wmin);
+  if (c)
+    hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c->vid,
+                       out_wmin, n, c->out_wmin);
   return hipGetLastError();
 }
 

@@ -31,11 +31,12 @@ __global__ __launch_bounds__(256) void emit_kernel(RoundArgs a, int32_t *pred, i
     n = id.n;
   }
   const GraphDev &G = graph_of<BATCH>(a, gi);
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;  // solver id
   long long c_settled = 0, c_relaxed = 0;
   if (y < n) {
-    const int32_t gy = sb + y;
-    const unsigned long long k = a.D64[gy];
+    const unsigned long long k = a.D64[sb + y];
+    const int32_t uy = G.vid ? G.vid[y] : y;  // the caller's id
+    const int32_t gy = sb + uy;
     const int32_t d = (int32_t)(k >> 32);
     a.D[gy] = d;
     if (d != V::INF) {
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void emit_kernel(RoundArgs a, int32_t *pred, i
     }
     if (pred) {
       int32_t p = -1;
-      if (y != s && d != V::INF) {
+      if (uy != s && d != V::INF) {
         if (k & kKeyEqualCost) {
           p = -2;
           const int q = atomicAdd(&a.ctl->deg_count, 1);
@@ -92,10 +93,10 @@ __global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *
       }
       const GraphDev &G = graph_of<BATCH>(a, gi);
       const int32_t y = gy - sb, dy = a.D[gy];
-      for (int32_t j = G.in_off[y]; j < G.in_off[y + 1]; ++j) {
-        const int32_t gv = sb + G.in_src[j];
+      for (int32_t j = G.u_in_off[y]; j < G.u_in_off[y + 1]; ++j) {
+        const int32_t gv = sb + G.u_in_src[j];
         const int32_t dv = a.D[gv];
-        if (dv == dy && V::add(dv, G.in_w[j]) == dy) {
+        if (dv == dy && V::add(dv, G.u_in_w[j]) == dy) {
           const int32_t lv_v = (pred[gv] == -2) ? lvl[gv] : 0;
           if (lv_v == lv) {
             flag[q] = 1;
@@ -127,13 +128,13 @@ __global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *
     const int32_t y = gy - sb, dy = a.D[gy], ly = lvl[gy];
     int32_t best = -1;
     if (ly >= 1) {
-      for (int32_t j = G.in_off[y]; j < G.in_off[y + 1]; ++j) {
-        const int32_t gv = sb + G.in_src[j];
+      for (int32_t j = G.u_in_off[y]; j < G.u_in_off[y + 1]; ++j) {
+        const int32_t gv = sb + G.u_in_src[j];
         const int32_t dv = a.D[gv];
-        if (dv == dy && V::add(dv, G.in_w[j]) == dy) {
+        if (dv == dy && V::add(dv, G.u_in_w[j]) == dy) {
           const int32_t lv_v = (pred[gv] == -2) ? lvl[gv] : 0;
           if (lv_v == ly - 1) {
-            best = G.in_eid[j];
+            best = G.u_in_eid[j];
             break;
           }
         }

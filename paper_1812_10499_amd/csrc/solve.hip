@@ -368,13 +368,22 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           if (val[j]) {
-            const int32_t dx = S.dx[it[j]];
-            cand[j] = V::add(dx, wt[j]);
+            cand[j] = V::add(S.dx[it[j]], wt[j]);
             gy[j] = S.sb[it[j]] + y[j];
-            // the edge id is the CSR position; a float edge that leaves the
-            // cost unchanged (w below half an ulp) is an equal-cost parent
-            key[j] = make_key(cand[j], pos[j], cand[j] == dx);
             dk[j] = a.D64[gy[j]];  // may be stale: only filters the atomic
+          }
+        }
+        // Only candidates no worse than the current D need the edge id (the
+        // caller's CSR position, through out_eid under a renumbering); a
+        // float edge that leaves the cost unchanged (w below half an ulp) is
+        // an equal-cost parent.
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          val[j] = val[j] && cand[j] <= (int32_t)(dk[j] >> 32);
+          if (val[j]) {
+            const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
+            const int32_t eid = G.out_eid ? G.out_eid[pos[j]] : pos[j];
+            key[j] = make_key(cand[j], eid, cand[j] == S.dx[it[j]]);
           }
         }
         int32_t nv[EPT], nd[EPT], ni[EPT];
@@ -799,6 +808,7 @@ __global__ void init_seed_kernel(RoundArgs a) {
         s = id.source;
       }
       const GraphDev &G = graph_of<BATCH>(a, gi);
+      if (G.rank) s = G.rank[s];  // the solver's id of the source
       gs = sb + s;
       deg = (uint32_t)(G.out_off[s + 1] - G.out_off[s]);
       a.D64[gs] = make_key(0, -1, false);

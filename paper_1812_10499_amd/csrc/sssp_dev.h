@@ -40,10 +40,18 @@ __device__ __forceinline__ int32_t kmin(int32_t a, int32_t b) { return a < b ? a
 __device__ __forceinline__ int32_t kmax(int32_t a, int32_t b) { return a > b ? a : b; }
 
 // ---------------------------------------------------------- descriptors
+// The round kernel works on the solver numbering (out_*, in_*, out_wmin);
+// out_eid maps a CSR position there to the caller's edge id, vid a solver
+// vertex to the caller's vertex id, rank the reverse (all three null when
+// the numberings coincide).  The u_ arrays are the caller-numbered CSR/CSC
+// that the parent tie pass and the backward pass walk.
 struct GraphDev {
-  const int32_t *out_off, *out_dst, *out_w;
-  const int32_t *in_off, *in_src, *in_eid, *in_w;
+  const int32_t *out_off, *out_dst, *out_w, *out_eid;
+  const int32_t *in_off, *in_src, *in_w;
   const int32_t *out_wmin;
+  const int32_t *vid, *rank;
+  const int32_t *u_out_off, *u_out_dst;
+  const int32_t *u_in_off, *u_in_src, *u_in_eid, *u_in_w;
   int32_t n, m;
 };
 

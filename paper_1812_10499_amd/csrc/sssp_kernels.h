@@ -125,10 +125,17 @@ hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
 
 // ------------------------------------------------------------- builder
 struct BuildTemps {
-  int32_t *ka, *kb, *va, *vb;  // radix sort ping-pong, m each
+  int32_t *ka, *kb, *va, *vb;  // radix sort ping-pong, max(m, n) each
   int32_t *hist;               // 256 * tiles (+ scan sums)
   int32_t *tail;               // m: tail of each edge id
-  int32_t *status;             // [0] error flags, [1] max weight key
+  int32_t *status;             // [0] error flags, [1] max weight key, [2] max total degree
+};
+// The solver-numbered working copy of a graph (arrays in the build buffer).
+struct SolverCopy {
+  int32_t *vid, *rank;
+  int32_t *out_off, *out_dst, *out_w, *out_eid;
+  int32_t *in_off, *in_src, *in_eid, *in_w;
+  int32_t *out_wmin;
 };
 size_t build_hist_entries(int32_t m);
 hipError_t launch_validate(int32_t n, int32_t m, bool f32, const int32_t *src,
@@ -139,10 +146,19 @@ hipError_t launch_build(int32_t n, int32_t m, bool f32, const int32_t *src, cons
                         int32_t *in_off, int32_t *in_src, int32_t *in_eid, int32_t *in_w,
                         int32_t *out_wmin, int32_t *perm, const BuildTemps &t,
                         hipStream_t stream);
+// degrees into t.ka, their maximum into t.status[2]
+hipError_t launch_degree(int32_t n, const int32_t *out_off, const int32_t *in_off,
+                         const BuildTemps &t, hipStream_t stream);
+// the working copy in descending-degree order, from the built CSR/CSC and
+// the degrees left in t.ka by launch_degree (dmax: their maximum)
+hipError_t launch_solver_copy(int32_t n, int32_t m, int32_t dmax, const int32_t *out_dst,
+                              const int32_t *out_w, const int32_t *out_wmin,
+                              const SolverCopy &c, const BuildTemps &t, hipStream_t stream);
+// c: the working copy to reweight too, or null
 hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
                               const int32_t *out_off, const int32_t *in_eid, int32_t *out_w,
-                              int32_t *in_w, int32_t *out_wmin, int32_t *status,
-                              hipStream_t stream);
+                              int32_t *in_w, int32_t *out_wmin, const SolverCopy *c,
+                              int32_t *status, hipStream_t stream);
 
 // ------------------------------------------------------------ backward
 struct BackArgs {

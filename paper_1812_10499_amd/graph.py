@@ -13,9 +13,11 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import Csr, SSSP_F32, SSSP_I32, Stats
+from ._abi import (Csr, SSSP_F32, SSSP_I32, SSSP_ORDER_AUTO, SSSP_ORDER_DEGREE,
+                   SSSP_ORDER_INPUT, Stats)
 
 I32_INF = 2**31 - 1
+ORDERS = {"auto": SSSP_ORDER_AUTO, "input": SSSP_ORDER_INPUT, "degree": SSSP_ORDER_DEGREE}
 
 
 def _stream() -> int:
@@ -32,10 +34,12 @@ class Graph:
     """A directed graph built on the GPU (CSR by tail + CSC by head).
 
     Edge ids are positions in the CSR; ``perm[k]`` is the input (COO) index
-    of edge id ``k``.  Weights are int32 (>= 1) or float32 (> 0).
+    of edge id ``k``.  Weights are int32 (>= 1) or float32 (> 0).  ``order``
+    picks the vertex numbering of the solver's working copy ("auto",
+    "input" or "degree"); results never depend on it.
     """
 
-    def __init__(self, n: int, src, dst, w, device="cuda"):
+    def __init__(self, n: int, src, dst, w, device="cuda", order: str = "auto"):
         device = torch.device(device)
         if isinstance(w, torch.Tensor):
             wt = w.to(device).contiguous()
@@ -53,16 +57,23 @@ class Graph:
         if d.numel() != m or wt.numel() != m:
             raise ValueError("src, dst and w must have the same length")
         self.n, self.m, self.device = int(n), m, device
-        nbytes = _abi.sssp_build_csr_bytes(self.n, m, self.dtype)
+        if order not in ORDERS:
+            raise ValueError("order must be one of %s" % sorted(ORDERS))
+        nbytes = _abi.sssp_build_csr_bytes(self.n, m, self.dtype, ORDERS[order])
         if nbytes == 0:
             raise ValueError("invalid graph size n=%d m=%d" % (n, m))
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.perm = torch.empty(max(m, 1), dtype=torch.int32, device=device)
         self.csr = Csr()
-        _abi.sssp_build_csr(self.n, m, self.dtype, s.data_ptr(), d.data_ptr(), wt.data_ptr(),
-                            self.buffer.data_ptr(), nbytes, self.csr, self.perm.data_ptr(),
-                            _stream())
+        _abi.sssp_build_csr(self.n, m, self.dtype, ORDERS[order], s.data_ptr(), d.data_ptr(),
+                            wt.data_ptr(), self.buffer.data_ptr(), nbytes, self.csr,
+                            self.perm.data_ptr(), _stream())
         self.perm = self.perm[:m]
+
+    @property
+    def order(self) -> str:
+        """The numbering the builder applied: "input" or "degree"."""
+        return "degree" if self.csr.order == SSSP_ORDER_DEGREE else "input"
 
     @property
     def value_dtype(self):
@@ -80,6 +91,18 @@ class Graph:
                     out_w=self._view(c.out_w, m, vt), in_off=self._view(c.in_off, n + 1),
                     in_src=self._view(c.in_src, m), in_eid=self._view(c.in_eid, m),
                     in_w=self._view(c.in_w, m, vt), out_wmin=self._view(c.out_wmin, n, vt))
+
+    def solver_arrays(self) -> dict:
+        """Views of the solver-numbered working copy (degree order only)."""
+        c, n, m, vt = self.csr, self.n, self.m, self.value_dtype
+        if self.csr.order != SSSP_ORDER_DEGREE:
+            raise ValueError("the graph uses the input numbering")
+        return dict(vid=self._view(c.vid, n), rank=self._view(c.rank, n),
+                    out_off=self._view(c.s_out_off, n + 1), out_dst=self._view(c.s_out_dst, m),
+                    out_w=self._view(c.s_out_w, m, vt), out_eid=self._view(c.s_out_eid, m),
+                    in_off=self._view(c.s_in_off, n + 1), in_src=self._view(c.s_in_src, m),
+                    in_eid=self._view(c.s_in_eid, m), in_w=self._view(c.s_in_w, m, vt),
+                    out_wmin=self._view(c.s_out_wmin, n, vt))
 
     def set_weights(self, w_eid: torch.Tensor):
         """Replace the weights; w_eid is given in edge-id order."""

@@ -41,3 +41,42 @@ def assert_same_solution(cost, pred, stats, ref, label=""):
 
 def sync():
     torch.cuda.synchronize()
+
+
+def expected_order(n, src, dst):
+    """The builder's automatic choice: degree order iff the largest total
+    degree is at least 16 times the mean total degree 2m/n."""
+    m = len(src)
+    if m == 0:
+        return "input"
+    deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
+    return "degree" if int(deg.max()) * n >= 32 * m else "input"
+
+
+def check_solver_copy(G, n, src, dst, w):
+    """The degree-ordered working copy, rebuilt from its definition: vertices
+    by descending total degree (ties by id); out-lists by (tail, head) solver
+    id, in-lists by (head, tail) solver id, ties by edge id."""
+    O = oracle.csr(n, src, dst)
+    ow, _, wmin = O.weights(w)
+    S = {k: to_np(v) for k, v in G.solver_arrays().items()}
+    deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
+    vid = np.argsort(-deg, kind="stable")
+    rank = np.empty(n, np.int64)
+    rank[vid] = np.arange(n)
+    assert np.array_equal(S["vid"], vid) and np.array_equal(S["rank"], rank)
+    m = len(src)
+    eid = np.arange(m)
+    tail = np.repeat(np.arange(n), np.diff(O.out_off))
+    head = O.out_dst.astype(np.int64)
+    bits = lambda a: a.view(np.int32) if a.dtype == np.float32 else a
+    for side, (key, nbr) in {"out": (rank[tail], rank[head]),
+                             "in": (rank[head], rank[tail])}.items():
+        order = np.lexsort((eid, nbr, key))
+        off = np.concatenate([[0], np.cumsum(np.bincount(key, minlength=n))])
+        assert np.array_equal(S[side + "_off"], off), side
+        assert np.array_equal(S[side + "_eid"], order), side
+        nb = S["out_dst"] if side == "out" else S["in_src"]
+        assert np.array_equal(nb, nbr[order]), side
+        assert np.array_equal(bits(S[side + "_w"]), bits(ow[order])), side
+    assert np.array_equal(bits(S["out_wmin"]), bits(wmin[vid]))

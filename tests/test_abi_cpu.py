@@ -47,16 +47,22 @@ def test_strerror_and_sizes(sp):
     assert sp.sssp_strerror(0) == "ok"
     for s in range(1, 8):
         assert sp.sssp_strerror(s) and sp.sssp_strerror(s) != "unknown status"
-    assert sp.sssp_build_csr_bytes(0, 10, sp.SSSP_I32) == 0
-    assert sp.sssp_build_csr_bytes(10, -1, sp.SSSP_I32) == 0
-    assert sp.sssp_build_csr_bytes(10, 10, 7) == 0
-    b = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32)
+    I, A, D = sp.SSSP_ORDER_INPUT, sp.SSSP_ORDER_AUTO, sp.SSSP_ORDER_DEGREE
+    assert sp.sssp_build_csr_bytes(0, 10, sp.SSSP_I32, I) == 0
+    assert sp.sssp_build_csr_bytes(10, -1, sp.SSSP_I32, I) == 0
+    assert sp.sssp_build_csr_bytes(10, 10, 7, I) == 0
+    assert sp.sssp_build_csr_bytes(10, 10, sp.SSSP_I32, 3) == 0
+    b = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, I)
     assert b >= 4 * (2 * 1001 + 5 * 5000 + 1000)
+    # the working copy: vid, rank, wmin (n), two offset arrays (n+1), 6 edge arrays
+    bd = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, D)
+    assert bd >= b + 4 * (3 * 1000 + 2 * 1001 + 6 * 5000)
+    assert sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, A) == bd
 
 
 def _fake_csr(sp, n=10, m=20, dtype=0, w_max=5.0):
     c = sp.Csr()
-    c.n, c.m, c.dtype, c.w_max = n, m, dtype, w_max
+    c.n, c.m, c.dtype, c.w_max, c.order = n, m, dtype, w_max, sp.SSSP_ORDER_INPUT
     for f in ("out_off", "out_dst", "out_w", "in_off", "in_src", "in_eid", "in_w", "out_wmin"):
         setattr(c, f, 0x1000)  # never dereferenced: every call below fails its host checks
     return c
@@ -83,6 +89,17 @@ def test_host_argument_errors(sp):
     bad = _fake_csr(sp)
     bad.in_src = None
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    # a built graph records INPUT or DEGREE; DEGREE needs the working copy
+    bad = _fake_csr(sp)
+    bad.order = sp.SSSP_ORDER_AUTO
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    bad.order = sp.SSSP_ORDER_DEGREE
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    for f in ("vid", "rank", "s_out_off", "s_out_dst", "s_out_w", "s_out_eid", "s_in_off",
+              "s_in_src", "s_in_eid", "s_in_w", "s_out_wmin"):
+        setattr(bad, f, 0x1000)
+    bad.s_in_eid = None
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
     # int32 overflow precondition: (n-1) * w_max >= INT32_MAX
     big = _fake_csr(sp, n=1 << 22, w_max=1000.0)
     assert _status(lambda: sp.sssp_solve(big, 0, 0x1000, None, None, None)) == \
@@ -101,9 +118,16 @@ def test_host_argument_errors(sp):
     assert _status(lambda: sp.sssp_backward([c], [0], [0], None, 0x1000, 0x1000, None)) == S
     # builder: bad sizes, missing pointers, short buffer
     out = sp.Csr()
-    assert _status(lambda: sp.sssp_build_csr(0, 5, 0, 0x1000, 0x1000, 0x1000, 0x1000, 1 << 20,
+    I = sp.SSSP_ORDER_INPUT
+    assert _status(lambda: sp.sssp_build_csr(0, 5, 0, I, 0x1000, 0x1000, 0x1000, 0x1000,
+                                             1 << 20, out, None, None)) == S
+    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, I, None, 0x1000, 0x1000, 0x1000,
+                                             1 << 20, out, None, None)) == S
+    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, I, 0x1000, 0x1000, 0x1000, 0x1000, 16,
                                              out, None, None)) == S
-    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, None, 0x1000, 0x1000, 0x1000, 1 << 20,
-                                             out, None, None)) == S
-    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, 0x1000, 0x1000, 0x1000, 0x1000, 16, out,
-                                             None, None)) == S
+    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, 9, 0x1000, 0x1000, 0x1000, 0x1000,
+                                             1 << 20, out, None, None)) == S
+    # a buffer large enough for the input order but not for the working copy
+    small = sp.sssp_build_csr_bytes(5, 5, 0, I)
+    assert _status(lambda: sp.sssp_build_csr(5, 5, 0, sp.SSSP_ORDER_DEGREE, 0x1000, 0x1000,
+                                             0x1000, 0x1000, small, out, None, None)) == S

@@ -61,7 +61,9 @@ def test_batch_mixed_small(sp):
         dst = rng.integers(0, n, m).astype(np.int32)
         w = (rng.integers(1, 2**24, m) * 2.0 ** -24).astype(np.float32)
         glist.append(gen.Graph("g%d" % k, n, src, dst, w, 0))
-    graphs = [sp.Graph(g.n, g.src, g.dst, g.w) for g in glist]
+    # one batch mixes graphs in both numberings
+    graphs = [sp.Graph(g.n, g.src, g.dst, g.w, order=("degree" if k % 2 else "input"))
+              for k, g in enumerate(glist)]
     inst_graph = [0, 1, 2, 3, 4, 2, 2, 0]
     inst_source = [int(rng.integers(0, glist[g].n)) for g in inst_graph]
     check_batch(sp, graphs, glist, inst_graph, inst_source, "mixed-small")
@@ -104,9 +106,10 @@ def grad_reference(glist, graphs_np_csr, inst_graph, inst_source, preds, gco, ba
     return np.concatenate(out)
 
 
-def test_backward_matches_oracle_gradient(sp):
+@pytest.mark.parametrize("order", ["auto", "degree"])
+def test_backward_matches_oracle_gradient(sp, order):
     d, gco_full = gen.diff_workload(side=64, num_sources=8)
-    G = sp.Graph(d.n, d.src, d.dst, d.w)
+    G = sp.Graph(d.n, d.src, d.dst, d.w, order=order)
     srcs = [int(s) for s in d.sources]
     cost, pred, _ = sp.solve_batch([G], [0] * len(srcs), srcs)
     gcost = torch.from_numpy(gco_full.reshape(-1)).cuda()
@@ -127,7 +130,8 @@ def test_backward_matches_oracle_gradient(sp):
 
 def test_backward_multi_graph(sp):
     glist = gen.batch_workload(count=4, nmin=500, nmax=3000)
-    graphs = [sp.Graph(g.n, g.src, g.dst, g.w) for g in glist]
+    graphs = [sp.Graph(g.n, g.src, g.dst, g.w, order=("degree" if k in (1, 2) else "auto"))
+              for k, g in enumerate(glist)]
     inst_graph = [0, 1, 1, 2, 3, 3, 3]
     rng = np.random.default_rng(5)
     inst_source = [int(rng.integers(0, glist[g].n)) for g in inst_graph]
@@ -190,9 +194,10 @@ def test_backward_finite_differences_fp64(sp):
     assert checked >= 10
 
 
-def test_autograd_function(sp):
+@pytest.mark.parametrize("order", ["auto", "degree"])
+def test_autograd_function(sp, order):
     d, gco = gen.diff_workload(side=20, num_sources=4)
-    G = sp.Graph(d.n, d.src, d.dst, d.w)
+    G = sp.Graph(d.n, d.src, d.dst, d.w, order=order)
     w_eid = torch.from_numpy(d.w[to_np(G.perm)]).cuda().requires_grad_(True)
     srcs = [int(s) for s in d.sources]
     cost = sp.shortest_paths(w_eid, G, srcs)

@@ -11,7 +11,8 @@ import torch
 
 import gen
 import oracle
-from gpu_util import assert_same_solution, oracle_solution, sync, to_np
+from gpu_util import (assert_same_solution, check_solver_copy, expected_order, oracle_solution,
+                      sync, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +24,12 @@ def sp():
     return sp
 
 
-def check_build(sp, n, src, dst, w):
-    G = sp.Graph(n, src, dst, w)
+def check_build(sp, n, src, dst, w, order="auto"):
+    G = sp.Graph(n, src, dst, w, order=order)
+    want = expected_order(n, src, dst) if order == "auto" else order
+    assert G.order == (want if len(src) else "input"), (G.order, want)
+    if G.order == "degree":
+        check_solver_copy(G, n, src, dst, w)
     A = {k: to_np(v) for k, v in G.arrays().items()}
     O = oracle.csr(n, src, dst)
     ow, iw, wmin = O.weights(w)
@@ -45,9 +50,9 @@ def check_build(sp, n, src, dst, w):
     return G
 
 
-def run_case(sp, n, src, dst, w, source, label):
-    print("case", label, "n=%d m=%d" % (n, len(src)), flush=True)
-    G = check_build(sp, n, src, dst, w)
+def run_case(sp, n, src, dst, w, source, label, order="auto"):
+    print("case", label, "n=%d m=%d order=%s" % (n, len(src), order), flush=True)
+    G = check_build(sp, n, src, dst, w, order)
     cost, pred, st = sp.solve(G, source, with_pred=True, with_stats=True)
     sync()
     ref = oracle_solution(n, src, dst, w, source)
@@ -98,8 +103,9 @@ def test_edge_cases(sp):
     run_case(sp, fan + 2, src, dst, w, 0, "in-star")
 
 
+@pytest.mark.parametrize("order", ["auto", "degree"])
 @pytest.mark.parametrize("dtype", ["i32", "f32"])
-def test_random_small(sp, dtype):
+def test_random_small(sp, dtype, order):
     rng = np.random.default_rng(21)
     for trial in range(30):
         n = int(rng.integers(1, 300))
@@ -110,7 +116,8 @@ def test_random_small(sp, dtype):
             w = rng.integers(1, 50, m).astype(np.int32)
         else:
             w = (rng.integers(1, 2**24, m) * 2.0 ** -24).astype(np.float32)
-        run_case(sp, n, src, dst, w, int(rng.integers(0, n)), "rand-%s-%d" % (dtype, trial))
+        run_case(sp, n, src, dst, w, int(rng.integers(0, n)), "rand-%s-%d" % (dtype, trial),
+                 order)
 
 
 def test_unit_weights_bfs(sp):
@@ -121,30 +128,35 @@ def test_unit_weights_bfs(sp):
     assert st["rounds"] == hops.max() + 1
 
 
-def test_float_equal_cost_ties(sp):
+@pytest.mark.parametrize("order", ["input", "degree"])
+def test_float_equal_cost_ties(sp, order):
     tiny = np.float32(2.0 ** -30)
     src = np.array([2, 0, 1, 1, 2, 3], np.int32)
     dst = np.array([1, 1, 2, 1, 3, 2], np.int32)
     w = np.array([tiny, 1.0, tiny, tiny, tiny, tiny], np.float32)
-    run_case(sp, 4, src, dst, w, 0, "f32-ties")
+    run_case(sp, 4, src, dst, w, 0, "f32-ties", order)
     # many equal-cost tiny edges on a grid of cost-1 vertices
     gr = gen.grid_workload(side=40)
     w = np.full(gr.m, tiny, np.float32)
     src = np.concatenate([gr.src, np.full(1, gr.n, np.int32)])
     dst = np.concatenate([gr.dst, np.full(1, gr.source, np.int32)])
     w = np.concatenate([w, np.ones(1, np.float32)])
-    run_case(sp, gr.n + 1, src, dst, w, gr.n, "f32-ties-grid")
+    run_case(sp, gr.n + 1, src, dst, w, gr.n, "f32-ties-grid", order)
 
 
-def test_workload_random_4096(sp):
+@pytest.mark.parametrize("order", ["auto", "degree"])
+def test_workload_random_4096(sp, order):
     g = gen.random_workload()
-    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "random4096")
+    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "random4096", order)
 
 
-@pytest.mark.parametrize("scale", [10, 14, 16])
-def test_rmat_scaled(sp, scale):
+@pytest.mark.parametrize("scale,order", [(10, "auto"), (10, "input"), (14, "auto"),
+                                         (14, "input"), (16, "auto")])
+def test_rmat_scaled(sp, scale, order):
     g = gen.rmat_workload(scale=scale)
-    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "rmat%d" % scale)
+    G, _ = run_case(sp, g.n, g.src, g.dst, g.w, g.source, "rmat%d" % scale, order)
+    if order == "auto":
+        assert G.order == "degree"
 
 
 @pytest.mark.parametrize("side", [32, 128])
@@ -156,6 +168,26 @@ def test_grid_scaled(sp, side):
 def test_batch_shape_graphs_single(sp):
     for g in gen.batch_workload(count=3, nmin=1000, nmax=30000):
         run_case(sp, g.n, g.src, g.dst, g.w, g.source, g.name)
+
+
+@pytest.mark.parametrize("order", ["input", "degree"])
+def test_set_weights_then_solve(sp, order):
+    g = gen.rmat_workload(scale=12)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, order=order)
+    w2 = gen.weights_int(77, g.m, 1, 255)
+    G.set_weights(torch.from_numpy(w2[to_np(G.perm)]).cuda())
+    sync()
+    O = oracle.csr(g.n, g.src, g.dst)
+    ow, iw, wmin = O.weights(w2)
+    A = {k: to_np(v) for k, v in G.arrays().items()}
+    assert np.array_equal(A["out_w"], ow) and np.array_equal(A["in_w"], iw)
+    assert np.array_equal(A["out_wmin"], wmin)
+    if order == "degree":
+        check_solver_copy(G, g.n, g.src, g.dst, w2)
+    cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
+    sync()
+    assert_same_solution(cost, pred, st, oracle_solution(g.n, g.src, g.dst, w2, g.source),
+                         "rmat12-reweighted-" + order)
 
 
 def test_weight_and_graph_errors(sp):
@@ -180,13 +212,15 @@ def test_weight_and_graph_errors(sp):
 
 def test_workload_grid_1024_full(sp):
     g = gen.grid_workload()
-    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "grid1024")
+    G, _ = run_case(sp, g.n, g.src, g.dst, g.w, g.source, "grid1024")
+    assert G.order == "input"
 
 
 def test_workload_rmat22_full(sp):
     g = gen.rmat_workload()
     G = sp.Graph(g.n, g.src, g.dst, g.w)
-    print("case rmat22 built", flush=True)
+    print("case rmat22 built", G.order, flush=True)
+    assert G.order == "degree"
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
     ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source)
