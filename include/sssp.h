@@ -85,16 +85,18 @@ typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 
  *                 outWeight array of SP_3 and SP_4, Figs. 4 and 5)
  *   w_max         largest weight (filled by the builder; used for the
  *                 int32 overflow precondition)
- * The solver's working copy (order == SSSP_ORDER_DEGREE; with
- * SSSP_ORDER_INPUT the s_ arrays alias the arrays above and vid, rank,
- * s_out_eid and s_in_eid are NULL, meaning the identity):
+ * The solver's working copy.  Always: in-lists ordered by weight, so that
+ * the in-edges a lower-bound step needs (minD + w < D[y]) form a prefix:
+ *   s_in_off[n+1], s_in_src[m] (solver ids), s_in_eid[m], s_in_w[m]
+ *       each in-list ascending by (weight, tail solver id, edge id);
+ *       s_in_eid holds the edge id of each entry
+ * With order == SSSP_ORDER_DEGREE also a renumbered CSR:
  *   vid[k]  vertex id of solver vertex k;  rank[v]  solver id of vertex v
  *   s_out_off[n+1], s_out_dst[m] (solver ids), s_out_w[m], s_out_eid[m]
- *       CSR over solver ids, each out-list ascending by head solver id;
- *       s_out_eid holds the edge id of each entry
- *   s_in_off[n+1], s_in_src[m] (solver ids), s_in_eid[m], s_in_w[m]
- *       CSC over solver ids, each in-list ascending by tail solver id
+ *       each out-list ascending by (head solver id, edge id)
  *   s_out_wmin[n]  out_wmin by solver id
+ * With SSSP_ORDER_INPUT, solver ids are vertex ids: vid, rank and
+ * s_out_eid are NULL and s_out_off/dst/w/wmin alias the CSR arrays.
  * These arrays are library-internal; callers only keep them valid.
  */
 typedef struct {
@@ -129,15 +131,16 @@ typedef struct {
   int32_t rounds;            /* rounds of the method (non-empty frontiers) */
   int32_t settled;           /* reachable vertices (Dijkstra's removeMin count) */
   int64_t relaxed_edges;     /* out-edges of fixed vertices relaxed (once each) */
-  int64_t scanned_in_edges;  /* in-edges scanned by the lower-bound step */
+  int64_t scanned_in_edges;  /* in-edges the lower-bound step covers: the in-degree
+                                summed over open vertices and rounds (an edge with
+                                minD + w >= D[y] is covered without gathering C) */
   int64_t open_visits;       /* sum over rounds of |O| (open vertices processed) */
 } sssp_stats;
 
 /*
  * Bytes of the device buffer sssp_build_csr fills for a graph of n vertices,
- * m edges, the given dtype and vertex order (SSSP_ORDER_INPUT needs no
- * working copy; AUTO and DEGREE reserve room for one).  Returns 0 for
- * invalid arguments.
+ * m edges, the given dtype and vertex order (AUTO and DEGREE reserve room
+ * for the renumbered CSR).  Returns 0 for invalid arguments.
  */
 size_t sssp_build_csr_bytes(int32_t n, int32_t m, sssp_dtype dtype, sssp_order order);
 
@@ -159,9 +162,10 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
 
 /*
  * Replace the weights of a built graph: w[m] (device) is given in edge-id
- * order; every weight array of *g (also the working copy's) and w_max are
- * rewritten in place (the arrays live in the caller's build buffer).  Validates weights and the
- * overflow precondition.  SYNCHRONOUS.
+ * order; every weight array of *g and w_max are rewritten in place and the
+ * working copy's weight-ordered in-lists are rebuilt (the arrays live in the
+ * caller's build buffer).  Validates weights and the overflow precondition;
+ * on an error nothing is written.  SYNCHRONOUS.
  */
 sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream);
 

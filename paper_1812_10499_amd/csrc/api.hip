@@ -147,14 +147,13 @@ sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
 
 bool csr_ok(const sssp_csr *g) {
   if (!(g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
-        g->out_off && g->in_off && g->out_wmin &&
-        (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w))))
+        g->out_off && g->in_off && g->out_wmin && g->s_out_off && g->s_in_off &&
+        g->s_out_wmin &&
+        (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
+                       g->s_out_dst && g->s_out_w && g->s_in_src && g->s_in_eid && g->s_in_w))))
     return false;
   if (g->order == SSSP_ORDER_INPUT) return true;
-  return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && g->s_out_off && g->s_in_off &&
-         g->s_out_wmin &&
-         (g->m == 0 || (g->s_out_dst && g->s_out_w && g->s_out_eid && g->s_in_src &&
-                        g->s_in_eid && g->s_in_w));
+  return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && (g->m == 0 || g->s_out_eid);
 }
 
 bool overflow_risk(const sssp_csr *g) {
@@ -162,21 +161,20 @@ bool overflow_risk(const sssp_csr *g) {
   return (double)(g->n - 1) * g->w_max >= (double)INT_MAX;
 }
 
-// Device view of a built graph: the solver-numbered arrays for the rounds,
-// the caller-numbered ones for the parent tie pass and the backward pass.
+// Device view of a built graph: the working copy for the rounds, the
+// caller-numbered arrays for the parent tie pass and the backward pass.
 GraphDev graph_dev(const sssp_csr *g) {
   GraphDev d;
-  const bool copy = g->order == SSSP_ORDER_DEGREE;
-  d.out_off = copy ? g->s_out_off : g->out_off;
-  d.out_dst = copy ? g->s_out_dst : g->out_dst;
-  d.out_w = (const int32_t *)(copy ? g->s_out_w : g->out_w);
-  d.out_eid = copy ? g->s_out_eid : nullptr;
-  d.in_off = copy ? g->s_in_off : g->in_off;
-  d.in_src = copy ? g->s_in_src : g->in_src;
-  d.in_w = (const int32_t *)(copy ? g->s_in_w : g->in_w);
-  d.out_wmin = (const int32_t *)(copy ? g->s_out_wmin : g->out_wmin);
-  d.vid = copy ? g->vid : nullptr;
-  d.rank = copy ? g->rank : nullptr;
+  d.out_off = g->s_out_off;
+  d.out_dst = g->s_out_dst;
+  d.out_w = (const int32_t *)g->s_out_w;
+  d.out_eid = g->s_out_eid;
+  d.in_off = g->s_in_off;
+  d.in_src = g->s_in_src;
+  d.in_w = (const int32_t *)g->s_in_w;
+  d.out_wmin = (const int32_t *)g->s_out_wmin;
+  d.vid = g->vid;
+  d.rank = g->rank;
   d.u_out_off = g->out_off;
   d.u_out_dst = g->out_dst;
   d.u_in_off = g->in_off;
@@ -188,12 +186,12 @@ GraphDev graph_dev(const sssp_csr *g) {
   return d;
 }
 
-// Build buffer: the caller-numbered CSR/CSC, then (degree order) the
-// solver-numbered copy.
+// Build buffer: the caller-numbered CSR/CSC, the working copy's
+// weight-ordered in-lists, then (degree order) the renumbered CSR.
 enum BufArr {
   B_OUT_OFF, B_OUT_DST, B_OUT_W, B_IN_OFF, B_IN_SRC, B_IN_EID, B_IN_W, B_OUT_WMIN,
-  B_VID, B_RANK, B_S_OUT_OFF, B_S_OUT_DST, B_S_OUT_W, B_S_OUT_EID, B_S_IN_OFF, B_S_IN_SRC,
-  B_S_IN_EID, B_S_IN_W, B_S_OUT_WMIN, B_COUNT
+  B_S_IN_OFF, B_S_IN_SRC, B_S_IN_EID, B_S_IN_W,
+  B_VID, B_RANK, B_S_OUT_OFF, B_S_OUT_DST, B_S_OUT_W, B_S_OUT_EID, B_S_OUT_WMIN, B_COUNT
 };
 
 struct Layout {
@@ -201,19 +199,50 @@ struct Layout {
   size_t total;
 };
 
-Layout build_layout(int32_t n, int32_t m, bool copy) {
+Layout build_layout(int32_t n, int32_t m, bool renumber) {
   Layout L;
   size_t o = 0;
   const size_t N = (size_t)n, M = (size_t)m;
-  const size_t count[B_COUNT] = {N + 1, M, M, N + 1, M, M, M, N,
-                                 N, N, N + 1, M, M, M, N + 1, M, M, M, N};
-  const int narr = copy ? B_COUNT : B_VID;
+  const size_t count[B_COUNT] = {N + 1, M, M, N + 1, M, M, M, N, N + 1, M, M, M,
+                                 N,     N, N + 1, M, M, M, N};
+  const int narr = renumber ? B_COUNT : B_VID;
   for (int i = 0; i < B_COUNT; ++i) {
     L.off[i] = o;
     if (i < narr) o += (sizeof(int32_t) * count[i] + 255) & ~(size_t)255;
   }
   L.total = o;
   return L;
+}
+
+// the working copy's arrays as recorded in a built graph
+SolverCopy solver_copy(const sssp_csr *g) {
+  SolverCopy c;
+  c.vid = (int32_t *)g->vid;
+  c.rank = (int32_t *)g->rank;
+  c.out_off = (int32_t *)g->s_out_off;
+  c.out_dst = (int32_t *)g->s_out_dst;
+  c.out_w = (int32_t *)g->s_out_w;
+  c.out_eid = (int32_t *)g->s_out_eid;
+  c.in_off = (int32_t *)g->s_in_off;
+  c.in_src = (int32_t *)g->s_in_src;
+  c.in_eid = (int32_t *)g->s_in_eid;
+  c.in_w = (int32_t *)g->s_in_w;
+  c.out_wmin = (int32_t *)g->s_out_wmin;
+  return c;
+}
+
+// Sort temporaries of the builder for n vertices and m edges.
+sssp_status build_temps(DevWS &ws, int32_t n, int32_t m, BuildTemps *t) {
+  sssp_status s;
+  const size_t M = (size_t)(m > n ? m : n);
+  if ((s = ws_arr(ws, S_BK_KA, M, &t->ka))) return s;
+  if ((s = ws_arr(ws, S_BK_KB, M, &t->kb))) return s;
+  if ((s = ws_arr(ws, S_BK_VA, M, &t->va))) return s;
+  if ((s = ws_arr(ws, S_BK_VB, M, &t->vb))) return s;
+  if ((s = ws_arr(ws, S_BK_TAIL, (size_t)(m > 0 ? m : 1), &t->tail))) return s;
+  if ((s = ws_arr(ws, S_BK_HIST, build_hist_entries(m > n ? m : n), &t->hist))) return s;
+  if ((s = ws_arr(ws, S_BK_STATUS, 4, &t->status))) return s;
+  return SSSP_OK;
 }
 
 // Round-state buffers for `total` state entries.
@@ -261,7 +290,7 @@ sssp_status trace_begin(DevWS &w, RoundArgs &a, hipStream_t stream) {
   if (!getenv("SSSP_TRACE")) return SSSP_OK;
   sssp_status s;
   const size_t cnt = (size_t)kTraceRounds * kTraceFields;
-  const size_t bcnt = (size_t)kTraceBlkRounds * 2 * kMaxBlocks;
+  const size_t bcnt = (size_t)kTraceBlkRounds * 2 * kMaxBlocks * kBlkFields;
   if ((s = ws_arr(w, S_TRACE, cnt + bcnt, &a.trace))) return s;
   a.trace_rounds = kTraceRounds;
   a.trace_blk = a.trace + cnt;
@@ -288,21 +317,21 @@ sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
     fprintf(f, "\n");
   }
   fclose(f);
-  // per-block phase end times: <path>.blk, one line per (round, phase)
+  // per-block records: <path>.blk, one line per (round, phase, block):
+  // round,phase,block,end,windows,first_item,units
   const int nbr = nr < kTraceBlkRounds ? nr : kTraceBlkRounds;
-  std::vector<long long> hb((size_t)nbr * 2 * kMaxBlocks);
+  std::vector<long long> hb((size_t)nbr * 2 * kMaxBlocks * kBlkFields);
   HIPCHK(hipMemcpy(hb.data(), a.trace_blk, hb.size() * sizeof(long long),
                    hipMemcpyDeviceToHost));
   std::string bp = std::string(path) + ".blk";
   f = fopen(bp.c_str(), "a");
   if (!f) return SSSP_ERR_ARG;
   for (int r = 0; r < nbr; ++r)
-    for (int ph = 0; ph < 2; ++ph) {
-      fprintf(f, "%d,%d", r + 1, ph);
-      for (int b = 0; b < nblocks; ++b)
-        fprintf(f, ",%lld", hb[((size_t)r * 2 + ph) * kMaxBlocks + b]);
-      fprintf(f, "\n");
-    }
+    for (int ph = 0; ph < 2; ++ph)
+      for (int b = 0; b < nblocks; ++b) {
+        const long long *e = &hb[(((size_t)r * 2 + ph) * kMaxBlocks + b) * kBlkFields];
+        fprintf(f, "%d,%d,%d,%lld,%lld,%lld,%lld\n", r + 1, ph, b, e[0], e[1], e[2], e[3]);
+      }
   fclose(f);
   return SSSP_OK;
 }
@@ -400,14 +429,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   int32_t *in_off = arr(B_IN_OFF), *in_src = arr(B_IN_SRC), *in_eid = arr(B_IN_EID);
   int32_t *in_w = arr(B_IN_W), *out_wmin = arr(B_OUT_WMIN);
   BuildTemps t;
-  const size_t M = (size_t)(m > n ? m : n);
-  if ((s = ws_arr(ws, S_BK_KA, M, &t.ka))) return s;
-  if ((s = ws_arr(ws, S_BK_KB, M, &t.kb))) return s;
-  if ((s = ws_arr(ws, S_BK_VA, M, &t.va))) return s;
-  if ((s = ws_arr(ws, S_BK_VB, M, &t.vb))) return s;
-  if ((s = ws_arr(ws, S_BK_TAIL, (size_t)(m > 0 ? m : 1), &t.tail))) return s;
-  if ((s = ws_arr(ws, S_BK_HIST, build_hist_entries(m > n ? m : n), &t.hist))) return s;
-  if ((s = ws_arr(ws, S_BK_STATUS, 4, &t.status))) return s;
+  if ((s = build_temps(ws, n, m, &t))) return s;
   HIPCHK(hipMemsetAsync(t.status, 0, 4 * sizeof(int32_t), stream));
   HIPCHK(launch_validate(n, m, f32, src, dst, (const int32_t *)w, t.status, stream));
   int32_t hs[4];
@@ -415,6 +437,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   HIPCHK(hipStreamSynchronize(stream));
   if (hs[0] & 1) return SSSP_ERR_GRAPH;
   if (hs[0] & 2) return SSSP_ERR_WEIGHT;
+  const int32_t wkey_max = hs[1];
   memset(out, 0, sizeof(*out));
   out->n = n;
   out->m = m;
@@ -430,14 +453,24 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->out_wmin = out_wmin;
   if (f32) {
     float f;
-    memcpy(&f, &hs[1], sizeof(f));
+    memcpy(&f, &wkey_max, sizeof(f));
     out->w_max = (double)f;
   } else {
-    out->w_max = (double)hs[1];
+    out->w_max = (double)wkey_max;
   }
   if (overflow_risk(out)) return SSSP_ERR_OVERFLOW;
   HIPCHK(launch_build(n, m, f32, src, dst, (const int32_t *)w, out_off, out_dst, out_w, in_off,
                       in_src, in_eid, in_w, out_wmin, perm, t, stream));
+  SolverCopy c;
+  memset(&c, 0, sizeof(c));
+  c.out_off = out_off;
+  c.out_dst = out_dst;
+  c.out_w = out_w;
+  c.out_wmin = out_wmin;
+  c.in_off = arr(B_S_IN_OFF);
+  c.in_src = arr(B_S_IN_SRC);
+  c.in_eid = arr(B_S_IN_EID);
+  c.in_w = arr(B_S_IN_W);
   if (order != SSSP_ORDER_INPUT && m > 0) {
     HIPCHK(launch_degree(n, out_off, in_off, t, stream));
     HIPCHK(hipMemcpyAsync(hs, t.status, sizeof(hs), hipMemcpyDeviceToHost, stream));
@@ -446,42 +479,29 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
     // skewed: largest total degree >= 16 x the mean 2m/n
     const bool skewed = (int64_t)dmax * n >= 32 * (int64_t)m;
     if (order == SSSP_ORDER_DEGREE || skewed) {
-      SolverCopy c;
       c.vid = arr(B_VID);
       c.rank = arr(B_RANK);
       c.out_off = arr(B_S_OUT_OFF);
       c.out_dst = arr(B_S_OUT_DST);
       c.out_w = arr(B_S_OUT_W);
       c.out_eid = arr(B_S_OUT_EID);
-      c.in_off = arr(B_S_IN_OFF);
-      c.in_src = arr(B_S_IN_SRC);
-      c.in_eid = arr(B_S_IN_EID);
-      c.in_w = arr(B_S_IN_W);
       c.out_wmin = arr(B_S_OUT_WMIN);
-      HIPCHK(launch_solver_copy(n, m, dmax, out_dst, out_w, out_wmin, c, t, stream));
+      HIPCHK(launch_renumber(n, m, dmax, out_dst, out_w, out_wmin, c, t, stream));
       out->order = SSSP_ORDER_DEGREE;
-      out->vid = c.vid;
-      out->rank = c.rank;
-      out->s_out_off = c.out_off;
-      out->s_out_dst = c.out_dst;
-      out->s_out_w = c.out_w;
-      out->s_out_eid = c.out_eid;
-      out->s_in_off = c.in_off;
-      out->s_in_src = c.in_src;
-      out->s_in_eid = c.in_eid;
-      out->s_in_w = c.in_w;
-      out->s_out_wmin = c.out_wmin;
     }
   }
-  if (out->order == SSSP_ORDER_INPUT) {
-    out->s_out_off = out_off;
-    out->s_out_dst = out_dst;
-    out->s_out_w = out_w;
-    out->s_in_off = in_off;
-    out->s_in_src = in_src;
-    out->s_in_w = in_w;
-    out->s_out_wmin = out_wmin;
-  }
+  HIPCHK(launch_in_lists(n, m, wkey_max, out_off, out_dst, out_w, c, t, stream));
+  out->vid = c.vid;
+  out->rank = c.rank;
+  out->s_out_off = c.out_off;
+  out->s_out_dst = c.out_dst;
+  out->s_out_w = c.out_w;
+  out->s_out_eid = c.out_eid;
+  out->s_in_off = c.in_off;
+  out->s_in_src = c.in_src;
+  out->s_in_eid = c.in_eid;
+  out->s_in_w = c.in_w;
+  out->s_out_wmin = c.out_wmin;
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));
   return SSSP_OK;
@@ -497,36 +517,40 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
   if ((s = ws_for_current(&wp))) return s;
   DevWS &ws = *wp;
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
-  int32_t *status;
-  if ((s = ws_arr(ws, S_BK_STATUS, 2, &status))) return s;
-  HIPCHK(hipMemsetAsync(status, 0, 2 * sizeof(int32_t), stream));
-  SolverCopy c;
-  memset(&c, 0, sizeof(c));
-  const bool copy = g->order == SSSP_ORDER_DEGREE;
-  if (copy) {
-    c.vid = (int32_t *)g->vid;
-    c.out_eid = (int32_t *)g->s_out_eid;
-    c.in_eid = (int32_t *)g->s_in_eid;
-    c.out_w = (int32_t *)g->s_out_w;
-    c.in_w = (int32_t *)g->s_in_w;
-    c.out_wmin = (int32_t *)g->s_out_wmin;
-  }
-  HIPCHK(launch_set_weights(g->n, g->m, f32, (const int32_t *)w, g->out_off, g->in_eid,
-                            (int32_t *)g->out_w, (int32_t *)g->in_w, (int32_t *)g->out_wmin,
-                            copy ? &c : nullptr, status, stream));
-  int32_t hs[2];
-  HIPCHK(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, stream));
+  BuildTemps t;
+  if ((s = build_temps(ws, g->n, g->m, &t))) return s;
+  // validate before anything is written: on error the graph is unchanged
+  HIPCHK(hipMemsetAsync(t.status, 0, 4 * sizeof(int32_t), stream));
+  HIPCHK(launch_validate(g->n, g->m, f32, nullptr, nullptr, (const int32_t *)w, t.status,
+                         stream));
+  int32_t hs[4];
+  HIPCHK(hipMemcpyAsync(hs, t.status, sizeof(hs), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-  HIPCHK(hipEventRecord(ws.last, stream));
-  if (hs[0] & 2) return SSSP_ERR_WEIGHT;
+  if (hs[0] & 2) {
+    HIPCHK(hipEventRecord(ws.last, stream));
+    return SSSP_ERR_WEIGHT;
+  }
+  double w_max;
   if (f32) {
     float f;
     memcpy(&f, &hs[1], sizeof(f));
-    g->w_max = (double)f;
+    w_max = (double)f;
   } else {
-    g->w_max = (double)hs[1];
+    w_max = (double)hs[1];
   }
-  if (overflow_risk(g)) return SSSP_ERR_OVERFLOW;
+  if (g->dtype == SSSP_I32 && (double)(g->n - 1) * w_max >= (double)INT_MAX) {
+    HIPCHK(hipEventRecord(ws.last, stream));
+    return SSSP_ERR_OVERFLOW;
+  }
+  const SolverCopy c = solver_copy(g);
+  HIPCHK(launch_set_weights(g->n, g->m, f32, (const int32_t *)w, g->out_off, g->in_eid,
+                            (int32_t *)g->out_w, (int32_t *)g->in_w, (int32_t *)g->out_wmin, c,
+                            stream));
+  HIPCHK(launch_in_lists(g->n, g->m, hs[1], g->out_off, g->out_dst, (const int32_t *)g->out_w,
+                         c, t, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  HIPCHK(hipEventRecord(ws.last, stream));
+  g->w_max = w_max;
   return SSSP_OK;
 }
 

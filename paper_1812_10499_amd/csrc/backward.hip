@@ -16,7 +16,7 @@
 
 namespace sssp {
 
-constexpr int BBS = kRoundBlock;
+constexpr int BBS = kBackBlock;
 
 __global__ void bw_init_kernel(BackArgs a) {
   for (int i = threadIdx.x; i < a.num_inst; i += blockDim.x) {

@@ -5,6 +5,12 @@
 // graph; out_wmin is the per-vertex minimum out-edge weight (outWeight of
 // Figs. 4 and 5).
 //
+// The solver's working copy: an optional renumbering by descending total
+// degree (CSR copy, vid/rank), and always a CSC whose in-lists are ascending
+// by weight.  The lower-bound step only needs the in-edges (v, y, w) with
+// minD + w < D[y]; with weight-ordered in-lists they are a prefix of y's
+// list whose length one binary search finds.
+//
 // Sorting: LSD radix sort of (key, value) int32 pairs with 8-bit digits;
 // each pass is a per-tile digit histogram, an exclusive scan over
 // (digit, tile) in digit-major order, and a stable scatter that ranks equal
@@ -310,7 +316,7 @@ hipError_t launch_build(int32_t n, int32_t m, bool f32, const int32_t *src, cons
   return hipGetLastError();
 }
 
-// ------------------------------------------------ solver numbering (copy)
+// --------------------------------------------------- the working copy
 // total degree per vertex, and its maximum into status[2]
 __global__ void degree_kernel(const int32_t *out_off, const int32_t *in_off, int32_t n,
                               int32_t *deg, int32_t *status) {
@@ -339,24 +345,47 @@ __global__ void rank_kernel(const int32_t *vid, int32_t n, int32_t *vid_out, int
   }
 }
 
-// key[i] = rank[ends[val[i]]] (val: edge ids, ends: tail or head per edge
-// id); with iota = true the value array is (re)set to the identity first
+// tail of every edge id from the CSR offsets
+__global__ void tail_kernel(const int32_t *out_off, int32_t n, int32_t m, int32_t *tail) {
+  for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = n;  // out_off[lo] <= e < out_off[hi]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (out_off[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    tail[e] = lo;
+  }
+}
+
+// key[i] = solver id of ends[val[i]] (val: edge ids; ends: tail or head per
+// edge id; rank null = identity); with iota the values are reset first
 __global__ void edge_key_kernel(const int32_t *ends, const int32_t *rank, int32_t m,
                                 int32_t *key, int32_t *val, bool iota) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
     if (iota) val[i] = i;
-    key[i] = rank[ends[val[i]]];
+    const int32_t v = ends[val[i]];
+    key[i] = rank ? rank[v] : v;
   }
 }
 
-// entry p of a solver-numbered list: edge id eid[p]; the neighbour id
-// (through rank) and weight come from the caller-numbered arrays
+// key[i] = weight bits of edge val[i] (positive int32 or float32: the bit
+// patterns order like the values)
+__global__ void weight_key_kernel(const int32_t *w, int32_t m, int32_t *key,
+                                  const int32_t *val) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    key[i] = w[val[i]];
+}
+
+// entry p of a solver-numbered list: edge id eid[p]; the neighbour's solver
+// id and the weight come from the caller-numbered arrays
 __global__ void copy_gather_kernel(const int32_t *eid, const int32_t *ends, const int32_t *rank,
                                    const int32_t *out_w, int32_t m, int32_t *s_nbr,
                                    int32_t *s_w) {
   for (int32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
     const int32_t e = eid[p];
-    s_nbr[p] = rank[ends[e]];
+    const int32_t v = ends[e];
+    if (s_nbr) s_nbr[p] = rank ? rank[v] : v;
     s_w[p] = out_w[e];
   }
 }
@@ -374,10 +403,9 @@ hipError_t launch_degree(int32_t n, const int32_t *out_off, const int32_t *in_of
   return hipGetLastError();
 }
 
-hipError_t launch_solver_copy(int32_t n, int32_t m, int32_t dmax, const int32_t *out_dst,
-                              const int32_t *out_w,
-                              const int32_t *out_wmin, const SolverCopy &c, const BuildTemps &t,
-                              hipStream_t stream) {
+hipError_t launch_renumber(int32_t n, int32_t m, int32_t dmax, const int32_t *out_dst,
+                           const int32_t *out_w, const int32_t *out_wmin, const SolverCopy &c,
+                           const BuildTemps &t, hipStream_t stream) {
   hipError_t e;
   const int gm = grid_for(m), gn = grid_for((int64_t)n + 1);
   // vertex order: stable sort by dmax - degree (t.ka holds the degrees)
@@ -388,7 +416,7 @@ hipError_t launch_solver_copy(int32_t n, int32_t m, int32_t dmax, const int32_t 
   hipLaunchKernelGGL(rank_kernel, dim3(grid_for(n)), dim3(256), 0, stream, t.va, n, c.vid,
                      c.rank);
   if (m > 0) {
-    // CSR: edges by (rank of tail, rank of head): LSD order, head first
+    // CSR: edges by (solver id of tail, solver id of head): LSD, head first
     hipLaunchKernelGGL(edge_key_kernel, dim3(gm), dim3(256), 0, stream, out_dst, c.rank, m, t.ka,
                        t.va, true);
     if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
@@ -402,11 +430,25 @@ hipError_t launch_solver_copy(int32_t n, int32_t m, int32_t dmax, const int32_t 
                        c.rank, out_w, m, c.out_dst, c.out_w);
   }
   hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, c.out_off);
+  hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c.vid, out_wmin,
+                     n, c.out_wmin);
+  return hipGetLastError();
+}
+
+hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t *out_off,
+                           const int32_t *out_dst, const int32_t *out_w, const SolverCopy &c,
+                           const BuildTemps &t, hipStream_t stream) {
+  hipError_t e;
+  const int gm = grid_for(m), gn = grid_for((int64_t)n + 1);
   if (m > 0) {
-    // CSC: edges by (rank of head, rank of tail)
+    hipLaunchKernelGGL(tail_kernel, dim3(gm), dim3(256), 0, stream, out_off, n, m, t.tail);
+    // edges by (solver id of head, weight, solver id of tail): LSD order
     hipLaunchKernelGGL(edge_key_kernel, dim3(gm), dim3(256), 0, stream, t.tail, c.rank, m, t.ka,
                        t.va, true);
     if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(weight_key_kernel, dim3(gm), dim3(256), 0, stream, out_w, m, t.ka, t.va);
+    const int32_t wb = wkey_max < 0x7fffffff ? wkey_max + 1 : 0x7fffffff;
+    if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, wb, t.hist, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(edge_key_kernel, dim3(gm), dim3(256), 0, stream, out_dst, c.rank, m, t.ka,
                        t.va, false);
     if ((e = radix_sort(t.ka, t.va, t.kb, t.vb, m, n, t.hist, stream)) != hipSuccess) return e;
@@ -417,43 +459,35 @@ hipError_t launch_solver_copy(int32_t n, int32_t m, int32_t dmax, const int32_t 
                        c.rank, out_w, m, c.in_src, c.in_w);
   }
   hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, c.in_off);
-  hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c.vid, out_wmin,
-                     n, c.out_wmin);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------- reweighting
 __global__ void set_weights_kernel(const int32_t *w, const int32_t *in_eid, int32_t m,
                                    int32_t *out_w, int32_t *in_w, const int32_t *s_out_eid,
-                                   const int32_t *s_in_eid, int32_t *s_out_w, int32_t *s_in_w) {
+                                   int32_t *s_out_w) {
   for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
     out_w[j] = w[j];
     in_w[j] = w[in_eid[j]];
-    if (s_out_eid) {
-      s_out_w[j] = w[s_out_eid[j]];
-      s_in_w[j] = w[s_in_eid[j]];
-    }
+    if (s_out_eid) s_out_w[j] = w[s_out_eid[j]];
   }
 }
 
 hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
                               const int32_t *out_off, const int32_t *in_eid, int32_t *out_w,
-                              int32_t *in_w, int32_t *out_wmin, const SolverCopy *c,
-                              int32_t *status, hipStream_t stream) {
-  hipError_t e = launch_validate(n, m, f32, nullptr, nullptr, w, status, stream);
-  if (e != hipSuccess) return e;
+                              int32_t *in_w, int32_t *out_wmin, const SolverCopy &c,
+                              hipStream_t stream) {
   hipLaunchKernelGGL(set_weights_kernel, dim3(grid_for(m)), dim3(256), 0, stream, w, in_eid, m,
-                     out_w, in_w, c ? c->out_eid : nullptr, c ? c->in_eid : nullptr,
-                     c ? c->out_w : nullptr, c ? c->in_w : nullptr);
+                     out_w, in_w, c.out_eid, c.out_w);
   if (f32)
     hipLaunchKernelGGL(wmin_kernel<true>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
                        out_w, n, out_wmin);
   else
     hipLaunchKernelGGL(wmin_kernel<false>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
                        out_w, n, out_wmin);
-  if (c)
-    hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c->vid,
-                       out_wmin, n, c->out_wmin);
+  if (c.vid)
+    hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c.vid,
+                       out_wmin, n, c.out_wmin);
   return hipGetLastError();
 }
 

@@ -22,8 +22,9 @@
 // so all reads precede all writes (Jacobi) and rounds are deterministic.
 //
 // Lists (F, O) are compacted arrays of state indices with an exclusive
-// prefix of the degree the next phase expands (out-degree for F, in-degree
-// for O).  Blocks append through an LDS staging buffer and one 64-bit
+// prefix of the work the next phase expands: the out-degree for F; for O
+// the number of in-edges (v, y, w) with minD + w < D[y], the only ones that
+// can move C'[y] (weight-ordered in-lists make them a prefix).  Blocks append through an LDS staging buffer and one 64-bit
 // atomicAdd per flush that reserves slots and degree range together.  Each
 // phase splits the list's edge count into equal contiguous chunks, one per
 // block (edge-balanced): a million-edge hub and a degree-2 vertex cost the
@@ -100,6 +101,13 @@ struct SmemAll {
 struct PhaseCtx {
   uint32_t vnb, vbid;
   bool solo;
+};
+
+// What a block's share of a phase was (for the round trace).
+struct PhaseWork {
+  int windows = 0;
+  int first_item = -1;
+  uint32_t units = 0;
 };
 
 __device__ __forceinline__ int32_t *part_slot(const RoundArgs &a, int k) {
@@ -280,10 +288,32 @@ __device__ __forceinline__ uint32_t chunk_of(uint32_t E, uint32_t vnb) {
   return (E + vnb - 1) / vnb;
 }
 
+// Work of an open vertex y in the bound step: its in-edges (v, y, w) with
+// md + w < dy.  The working copy's in-lists are ascending by weight and the
+// rounded add is monotone, so they are a prefix of y's list; its length is
+// found by binary search (short lists are taken whole).  With md at most
+// the minD of the round that scans y and dy at least that round's D[y],
+// the prefix covers every edge the bound step needs.
+template <class V>
+__device__ __forceinline__ int32_t useful_in_edges(const GraphDev &G, int32_t y, int32_t md,
+                                                   int32_t dy) {
+  const int32_t b = G.in_off[y];
+  int32_t lo = 0, hi = G.in_off[y + 1] - b;
+  if (hi <= 16) return hi;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (V::add(md, G.in_w[b + mid]) < dy) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // ================================================================== relax
+// md_prev: a minD of an earlier round (0 before the first), a lower bound of
+// this round's minD for the work counts of newly discovered vertices.
 template <class V, bool BATCH>
 __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NF,
-                            uint32_t EF) {
+                            uint32_t EF, int32_t md_prev, PhaseWork &pw) {
   const int tid = threadIdx.x;
   const int cur = r & 1, s_now = r % 3;
   const int I = a.num_inst;
@@ -312,6 +342,8 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
   if (e0 < e1) {
     int i = find_start_item(a.front_p, NF, CW_RELAX, e0, sm);
     uint32_t k = e0;
+    pw.first_item = i;
+    pw.units = e1 - e0;
     while (k < e1) {
       const int idx = i + tid;
       if (idx < NF) {
@@ -414,8 +446,18 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
               ltmin = kmin(ltmin, th);
             }
             if ((nmask >> j) & 1u) {
+              // queued for this round's bound step; D[y] can only drop
+              // below cand before it runs
+              int32_t md = md_prev;
+              if constexpr (BATCH) {
+                md = 0;
+                if (r > 1) {
+                  md = ld_relaxed(&a.imin[((r + 2) % 3) * I + S.inst[it[j]]]);
+                  if (md == V::INF) md = 0;
+                }
+              }
               nv[j] = gy[j];
-              nd[j] = G.in_off[y[j] + 1] - G.in_off[y[j]];
+              nd[j] = useful_in_edges<V>(G, y[j], md, cand[j]);
               ni[j] = S.inst[it[j]];
             }
           }
@@ -425,6 +467,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       __syncthreads();
       k = wend;
       i += WIN;
+      ++pw.windows;
     }
   }
   __syncthreads();
@@ -438,9 +481,12 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
 }
 
 // ========================================================== bound-and-fix
+// scanned: the thread's running sum of the in-degrees of the open items it
+// finished (single solve; batches count per instance)
 template <class V, bool BATCH>
 __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NO,
-                            uint32_t EO, int32_t mind_all, int32_t thr_all) {
+                            uint32_t EO, int32_t mind_all, int32_t thr_all,
+                            long long &scanned, PhaseWork &pw) {
   const int tid = threadIdx.x;
   const int cur = r & 1, s_now = r % 3, s_next = (r + 1) % 3;
   const int I = a.num_inst;
@@ -469,6 +515,8 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
   if (e0 < e1) {
     int i = find_start_item(Op, NO, CW_FUSED, e0, sm);
     uint32_t k = e0;
+    pw.first_item = i;
+    pw.units = e1 - e0;
     while (k < e1) {
       const int idx = i + tid;
       S.acc[tid] = V::INF;
@@ -520,9 +568,16 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             wt[j] = G.in_w[pos[j]];
           }
         }
+        // An in-edge can only lower min(D[y], m_y) below D[y] if
+        // minD + w < D[y]: its term max(C[v], minD) + w is at least
+        // minD + w (rounding is monotone).  Every other edge leaves C'[y]
+        // exactly as it is, so its tail's lower bound is not gathered.
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
+        for (int j = 0; j < EPT; ++j) {
+          const int32_t md = BATCH ? (val[j] ? S.mind[it[j]] : 0) : mind_all;
+          val[j] = val[j] && V::add(md, wt[j]) < S.dy[it[j]];
           if (val[j]) cv[j] = Cold[S.sb[it[j]] + v[j]];
+        }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           const int32_t md = BATCH ? (val[j] ? S.mind[it[j]] : 0) : mind_all;
@@ -550,7 +605,6 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       int32_t gy = 0, fd = 0, od = 0, ins = 0;
       if (idx < NO) {
         const uint32_t p0 = (uint32_t)S.pfx[tid], p1 = (uint32_t)S.pfx[tid + 1];
-        const uint32_t deg = p1 - p0 - CW_FUSED;               // the item's in-degree
         const uint32_t fb = p0 / chunk, lb = (p1 - 1) / chunk;  // p1 > p0 always
         if (fb <= pc.vbid && pc.vbid <= lb) {
           int32_t m = S.acc[tid];
@@ -574,12 +628,6 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             }
           }
           ins = S.inst[tid];
-          if constexpr (BATCH) {
-            if (fb == pc.vbid) {
-              atomicAdd(&a.iscanned[2 * ins], (unsigned long long)deg);
-              atomicAdd(&a.iscanned[2 * ins + 1], 1ull);
-            }
-          }
           if (fin) {
             gy = Ov[idx];
             const int32_t md = BATCH ? S.mind[tid] : mind_all;
@@ -588,13 +636,22 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             const int32_t Cn = kmax(kmax(Cy, md), kmin(Dy, m));
             const GraphDev &G = graph_of<BATCH>(a, S.gi[tid]);
             const int32_t yl = gy - S.sb[tid];
+            // the method's count: every in-edge of an open vertex is covered
+            const long long deg = G.in_off[yl + 1] - G.in_off[yl];
+            if constexpr (BATCH) {
+              atomicAdd(&a.iscanned[2 * ins], (unsigned long long)deg);
+              atomicAdd(&a.iscanned[2 * ins + 1], 1ull);
+            } else {
+              scanned += deg;
+            }
             if (Cn >= Dy || Dy <= th) {
               Cnew[gy] = V::INF;  // fixed: drops out of every later bound step
               fd = G.out_off[yl + 1] - G.out_off[yl];
               hf = true;
             } else {
               Cnew[gy] = Cn;
-              od = (int32_t)deg;
+              // next round: minD >= md and D[y] <= Dy
+              od = useful_in_edges<V>(G, yl, md, Dy);
               ho = true;
               const int32_t tn = V::add(Dy, G.out_wmin[yl]);
               if constexpr (BATCH) {
@@ -611,6 +668,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       stage_push2(S.fr, hf, gy, fd, ins, front, S.op, ho, gy, od, ins, next_open, BATCH, sm);
       k = wend;
       i += WIN;
+      ++pw.windows;
     }
   }
   stage_flush(S.fr, front.ctr, front.v, front.p, front.i, BATCH);
@@ -672,6 +730,8 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   unsigned int epoch = 0;
   int r = 1, phase = 0;  // phase 0: relax, 1: bound-and-fix
   bool solo = false;
+  int32_t md_prev = 0;     // the last minD this block computed (0 before round 1)
+  long long scanned = 0;   // this thread's share of the scanned in-edge count
 
   for (;;) {
     const int cur = r & 1;
@@ -705,7 +765,8 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     long long *tr = (a.trace && r <= a.trace_rounds) ? a.trace + (size_t)(r - 1) * kTraceFields
                                                       : nullptr;
     long long *tb = (a.trace_blk && r <= a.trace_blk_rounds)
-                        ? a.trace_blk + ((size_t)(r - 1) * 2 + phase) * kMaxBlocks + bid
+                        ? a.trace_blk + (((size_t)(r - 1) * 2 + phase) * kMaxBlocks + bid) *
+                                            kBlkFields
                         : nullptr;
     if (bid == 0) {
       if (tid == 0) {
@@ -716,7 +777,6 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           ctl->settled += N;
           ctl->relaxed += E;
         } else {
-          ctl->scanned += E;
           ctl->open_visits += N;
         }
         if (solo) ctl->solo_phases += 1;
@@ -742,17 +802,24 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
         }
       }
     }
+    PhaseWork pw;
     if (phase == 0) {
-      relax_phase<V, BATCH>(a, sm, pc, r, N, E);
+      relax_phase<V, BATCH>(a, sm, pc, r, N, E, md_prev, pw);
     } else {
       int32_t mind_all = V::INF, thr_all = V::INF;
       if constexpr (!BATCH) {
         mind_all = reduce_parts<V>(part_slot(a, P_SURV0 + cur), part_slot(a, P_CAND0 + cur), sm);
         thr_all = reduce_parts<V>(part_slot(a, P_TSURV0 + cur), part_slot(a, P_TCAND0 + cur), sm);
+        if (mind_all != V::INF) md_prev = mind_all;  // minD never decreases over rounds
       }
-      fused_phase<V, BATCH>(a, sm, pc, r, N, E, mind_all, thr_all);
+      fused_phase<V, BATCH>(a, sm, pc, r, N, E, mind_all, thr_all, scanned, pw);
     }
-    if (tb && tid == 0) tb[0] = (long long)wall_clock64();
+    if (tb && tid == 0) {
+      tb[0] = (long long)wall_clock64();
+      tb[1] = pw.windows;
+      tb[2] = pw.first_item;
+      tb[3] = pw.units;
+    }
     if (tr && bid == 0 && tid == 0) tr[phase == 0 ? TR_ARR_RELAX : TR_ARR_FUSED] = (long long)wall_clock64();
     if (solo) {
       wait_own_stores();
@@ -767,6 +834,11 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
       phase = 0;
       ++r;
     }
+  }
+  if constexpr (!BATCH) {
+    uint64_t tot;
+    block_excl_scan64<RBS>((uint64_t)scanned, sm.scan, &tot);
+    if (tid == 0 && tot) atomicAdd((unsigned long long *)&ctl->scanned, (unsigned long long)tot);
   }
 }
 

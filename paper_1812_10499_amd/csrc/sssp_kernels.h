@@ -8,7 +8,10 @@
 
 namespace sssp {
 
-constexpr int kRoundBlock = 512;  // threads per block of the persistent kernels
+// Threads per block of the persistent round kernel: one block per CU (16
+// waves) keeps the grid barrier at 256 participants while filling the CU.
+constexpr int kRoundBlock = 1024;
+constexpr int kBackBlock = 512;   // threads per block of the backward kernels
 constexpr int kMaxBlocks = 4096;  // upper bound on a persistent grid
 
 // Per-block partial minima of a single solve, [kParts][kMaxBlocks]: every
@@ -74,8 +77,11 @@ struct RoundArgs {
   // optional round trace (SSSP_TRACE): per round kTraceFields entries
   long long *trace;
   int32_t trace_rounds;
-  int32_t trace_blk_rounds;  // rounds with per-block phase end times
-  long long *trace_blk;      // [round][2 phases][kMaxBlocks] wall-clock at each block's phase end
+  int32_t trace_blk_rounds;  // rounds with per-block records
+  // [round][2 phases][kMaxBlocks][kBlkFields]: per block, the wall-clock at
+  // its phase end, the list windows it walked, its first list item and the
+  // work units of its chunk
+  long long *trace_blk;
   unsigned int *flags;       // grid barrier flags, kMaxBlocks * kFlagStride
   int32_t *part;             // per-block partial minima, kParts * kMaxBlocks
   int32_t solo_edges;        // phases with at most this many edges run on block 0 alone
@@ -88,6 +94,8 @@ enum TraceField {
   TR_START = 0, TR_ARR_RELAX, TR_END_RELAX, TR_ARR_FUSED, TR_END_FUSED,
   TR_NF, TR_EF, TR_NO, TR_EO, TR_MODE, kTraceFields
 };
+
+constexpr int kBlkFields = 4;
 
 struct LaunchGeom {
   int blocks;  // persistent grid size (co-resident)
@@ -130,7 +138,9 @@ struct BuildTemps {
   int32_t *tail;               // m: tail of each edge id
   int32_t *status;             // [0] error flags, [1] max weight key, [2] max total degree
 };
-// The solver-numbered working copy of a graph (arrays in the build buffer).
+// The solver's working copy of a graph (arrays in the build buffer).  In
+// the input numbering vid, rank, out_eid are null and out_* alias the CSR;
+// the in-lists are always a copy, ascending by weight.
 struct SolverCopy {
   int32_t *vid, *rank;
   int32_t *out_off, *out_dst, *out_w, *out_eid;
@@ -149,16 +159,22 @@ hipError_t launch_build(int32_t n, int32_t m, bool f32, const int32_t *src, cons
 // degrees into t.ka, their maximum into t.status[2]
 hipError_t launch_degree(int32_t n, const int32_t *out_off, const int32_t *in_off,
                          const BuildTemps &t, hipStream_t stream);
-// the working copy in descending-degree order, from the built CSR/CSC and
-// the degrees left in t.ka by launch_degree (dmax: their maximum)
-hipError_t launch_solver_copy(int32_t n, int32_t m, int32_t dmax, const int32_t *out_dst,
-                              const int32_t *out_w, const int32_t *out_wmin,
-                              const SolverCopy &c, const BuildTemps &t, hipStream_t stream);
-// c: the working copy to reweight too, or null
+// vid, rank and the CSR copy in descending-degree order, from the built CSR
+// and the degrees left in t.ka by launch_degree (dmax: their maximum)
+hipError_t launch_renumber(int32_t n, int32_t m, int32_t dmax, const int32_t *out_dst,
+                           const int32_t *out_w, const int32_t *out_wmin, const SolverCopy &c,
+                           const BuildTemps &t, hipStream_t stream);
+// the weight-ordered in-lists of the copy (c.rank null: input numbering);
+// wkey_max: the largest weight's bit pattern.  Overwrites t.tail.
+hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t *out_off,
+                           const int32_t *out_dst, const int32_t *out_w, const SolverCopy &c,
+                           const BuildTemps &t, hipStream_t stream);
+// new weights (validated by the caller) into the CSR/CSC, out_wmin and the
+// copy's out-lists; the copy's in-lists are rebuilt by launch_in_lists
 hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
                               const int32_t *out_off, const int32_t *in_eid, int32_t *out_w,
-                              int32_t *in_w, int32_t *out_wmin, const SolverCopy *c,
-                              int32_t *status, hipStream_t stream);
+                              int32_t *in_w, int32_t *out_wmin, const SolverCopy &c,
+                              hipStream_t stream);
 
 // ------------------------------------------------------------ backward
 struct BackArgs {

@@ -93,16 +93,18 @@ class Graph:
                     in_w=self._view(c.in_w, m, vt), out_wmin=self._view(c.out_wmin, n, vt))
 
     def solver_arrays(self) -> dict:
-        """Views of the solver-numbered working copy (degree order only)."""
+        """Views of the solver's working copy: the weight-ordered in-lists,
+        and in degree order also vid, rank and the renumbered out-lists."""
         c, n, m, vt = self.csr, self.n, self.m, self.value_dtype
-        if self.csr.order != SSSP_ORDER_DEGREE:
-            raise ValueError("the graph uses the input numbering")
-        return dict(vid=self._view(c.vid, n), rank=self._view(c.rank, n),
-                    out_off=self._view(c.s_out_off, n + 1), out_dst=self._view(c.s_out_dst, m),
-                    out_w=self._view(c.s_out_w, m, vt), out_eid=self._view(c.s_out_eid, m),
-                    in_off=self._view(c.s_in_off, n + 1), in_src=self._view(c.s_in_src, m),
-                    in_eid=self._view(c.s_in_eid, m), in_w=self._view(c.s_in_w, m, vt),
-                    out_wmin=self._view(c.s_out_wmin, n, vt))
+        out = dict(in_off=self._view(c.s_in_off, n + 1), in_src=self._view(c.s_in_src, m),
+                   in_eid=self._view(c.s_in_eid, m), in_w=self._view(c.s_in_w, m, vt))
+        if self.csr.order == SSSP_ORDER_DEGREE:
+            out.update(vid=self._view(c.vid, n), rank=self._view(c.rank, n),
+                       out_off=self._view(c.s_out_off, n + 1),
+                       out_dst=self._view(c.s_out_dst, m), out_w=self._view(c.s_out_w, m, vt),
+                       out_eid=self._view(c.s_out_eid, m),
+                       out_wmin=self._view(c.s_out_wmin, n, vt))
+        return out
 
     def set_weights(self, w_eid: torch.Tensor):
         """Replace the weights; w_eid is given in edge-id order."""

@@ -54,29 +54,37 @@ def expected_order(n, src, dst):
 
 
 def check_solver_copy(G, n, src, dst, w):
-    """The degree-ordered working copy, rebuilt from its definition: vertices
-    by descending total degree (ties by id); out-lists by (tail, head) solver
-    id, in-lists by (head, tail) solver id, ties by edge id."""
+    """The working copy, rebuilt from its definition.  Degree order: vertices
+    by descending total degree (ties by id), out-lists by (tail, head) solver
+    id then edge id.  Both orders: in-lists by (head solver id, weight, tail
+    solver id, edge id)."""
     O = oracle.csr(n, src, dst)
     ow, _, wmin = O.weights(w)
     S = {k: to_np(v) for k, v in G.solver_arrays().items()}
-    deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
-    vid = np.argsort(-deg, kind="stable")
+    if G.order == "degree":
+        deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
+        vid = np.argsort(-deg, kind="stable")
+    else:
+        vid = np.arange(n)
     rank = np.empty(n, np.int64)
     rank[vid] = np.arange(n)
-    assert np.array_equal(S["vid"], vid) and np.array_equal(S["rank"], rank)
     m = len(src)
     eid = np.arange(m)
     tail = np.repeat(np.arange(n), np.diff(O.out_off))
     head = O.out_dst.astype(np.int64)
     bits = lambda a: a.view(np.int32) if a.dtype == np.float32 else a
-    for side, (key, nbr) in {"out": (rank[tail], rank[head]),
-                             "in": (rank[head], rank[tail])}.items():
-        order = np.lexsort((eid, nbr, key))
+    wkey = bits(np.ascontiguousarray(ow)).astype(np.int64)  # positive: bits order like values
+    sides = {"in": np.lexsort((eid, rank[tail], wkey, rank[head]))}
+    if G.order == "degree":
+        assert np.array_equal(S["vid"], vid) and np.array_equal(S["rank"], rank)
+        sides["out"] = np.lexsort((eid, rank[head], rank[tail]))
+        assert np.array_equal(bits(S["out_wmin"]), bits(wmin[vid]))
+    for side, order in sides.items():
+        key = rank[tail] if side == "out" else rank[head]
+        nbr = rank[head] if side == "out" else rank[tail]
         off = np.concatenate([[0], np.cumsum(np.bincount(key, minlength=n))])
         assert np.array_equal(S[side + "_off"], off), side
         assert np.array_equal(S[side + "_eid"], order), side
         nb = S["out_dst"] if side == "out" else S["in_src"]
         assert np.array_equal(nb, nbr[order]), side
         assert np.array_equal(bits(S[side + "_w"]), bits(ow[order])), side
-    assert np.array_equal(bits(S["out_wmin"]), bits(wmin[vid]))

@@ -53,17 +53,21 @@ def test_strerror_and_sizes(sp):
     assert sp.sssp_build_csr_bytes(10, 10, 7, I) == 0
     assert sp.sssp_build_csr_bytes(10, 10, sp.SSSP_I32, 3) == 0
     b = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, I)
-    assert b >= 4 * (2 * 1001 + 5 * 5000 + 1000)
-    # the working copy: vid, rank, wmin (n), two offset arrays (n+1), 6 edge arrays
+    # CSR/CSC (2 offset arrays, 5 edge arrays, out_wmin) + the weight-ordered
+    # in-lists of the working copy (offsets, 3 edge arrays)
+    assert b >= 4 * (3 * 1001 + 8 * 5000 + 1000)
+    # degree order adds vid, rank, out_wmin (n), offsets (n+1), 3 edge arrays
     bd = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, D)
-    assert bd >= b + 4 * (3 * 1000 + 2 * 1001 + 6 * 5000)
+    assert bd >= b + 4 * (3 * 1000 + 1001 + 3 * 5000)
     assert sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, A) == bd
 
 
 def _fake_csr(sp, n=10, m=20, dtype=0, w_max=5.0):
     c = sp.Csr()
     c.n, c.m, c.dtype, c.w_max, c.order = n, m, dtype, w_max, sp.SSSP_ORDER_INPUT
-    for f in ("out_off", "out_dst", "out_w", "in_off", "in_src", "in_eid", "in_w", "out_wmin"):
+    for f in ("out_off", "out_dst", "out_w", "in_off", "in_src", "in_eid", "in_w", "out_wmin",
+              "s_out_off", "s_out_dst", "s_out_w", "s_in_off", "s_in_src", "s_in_eid", "s_in_w",
+              "s_out_wmin"):
         setattr(c, f, 0x1000)  # never dereferenced: every call below fails its host checks
     return c
 
@@ -93,12 +97,10 @@ def test_host_argument_errors(sp):
     bad = _fake_csr(sp)
     bad.order = sp.SSSP_ORDER_AUTO
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
-    bad.order = sp.SSSP_ORDER_DEGREE
+    bad.order = sp.SSSP_ORDER_DEGREE  # without vid, rank, s_out_eid
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
-    for f in ("vid", "rank", "s_out_off", "s_out_dst", "s_out_w", "s_out_eid", "s_in_off",
-              "s_in_src", "s_in_eid", "s_in_w", "s_out_wmin"):
-        setattr(bad, f, 0x1000)
-    bad.s_in_eid = None
+    bad = _fake_csr(sp)
+    bad.s_in_w = None  # the in-list copy is required in every order
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
     # int32 overflow precondition: (n-1) * w_max >= INT32_MAX
     big = _fake_csr(sp, n=1 << 22, w_max=1000.0)

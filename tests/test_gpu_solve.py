@@ -28,8 +28,7 @@ def check_build(sp, n, src, dst, w, order="auto"):
     G = sp.Graph(n, src, dst, w, order=order)
     want = expected_order(n, src, dst) if order == "auto" else order
     assert G.order == (want if len(src) else "input"), (G.order, want)
-    if G.order == "degree":
-        check_solver_copy(G, n, src, dst, w)
+    check_solver_copy(G, n, src, dst, w)
     A = {k: to_np(v) for k, v in G.arrays().items()}
     O = oracle.csr(n, src, dst)
     ow, iw, wmin = O.weights(w)
@@ -182,12 +181,19 @@ def test_set_weights_then_solve(sp, order):
     A = {k: to_np(v) for k, v in G.arrays().items()}
     assert np.array_equal(A["out_w"], ow) and np.array_equal(A["in_w"], iw)
     assert np.array_equal(A["out_wmin"], wmin)
-    if order == "degree":
-        check_solver_copy(G, g.n, g.src, g.dst, w2)
+    check_solver_copy(G, g.n, g.src, g.dst, w2)
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
     assert_same_solution(cost, pred, st, oracle_solution(g.n, g.src, g.dst, w2, g.source),
                          "rmat12-reweighted-" + order)
+    # invalid weights are refused before anything is written
+    bad = torch.from_numpy(w2[to_np(G.perm)]).cuda()
+    bad[g.m // 2] = 0
+    with pytest.raises(sp.SSSPError) as e:
+        G.set_weights(bad)
+    assert e.value.status == sp.SSSP_ERR_WEIGHT
+    sync()
+    check_solver_copy(G, g.n, g.src, g.dst, w2)
 
 
 def test_weight_and_graph_errors(sp):
