@@ -14,7 +14,6 @@ with HIP events recorded on the launch stream by the library.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -24,29 +23,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# Algorithmic bytes of the round kernel per unit ("Bytes
-# model"): 4-byte elements each kernel phase must read or write once.
+# Algorithmic bytes per unit of work: the 4-byte elements the method itself
+# must move once (reads and writes), counted on the work the method defines.
+# Round kernel (relax + reduce + lower bound + fix):
 BYTES_PER_RELAXED_EDGE = 12   # out_dst, out_w, D[head]
-BYTES_PER_SCANNED_EDGE = 12   # in_src, in_w, C[tail]
-BYTES_PER_SETTLED = 40        # frontier entry r/w, out_off, D, in-degree, list append
-BYTES_PER_OPEN_VISIT = 64     # open entry r/w, in_off, D, C r/w, out_wmin, m_y r/w
+BYTES_PER_SETTLED = 12        # frontier entry, out_off, D
+BYTES_PER_SCANNED_EDGE = 12   # in_src, in_w, C[tail]: every in-edge of every open vertex
+BYTES_PER_OPEN_VISIT = 28     # offsets, D, C, C', out_wmin, list entries
+# Parent pointers (a separate pass in a plain implementation):
+BYTES_PER_PRED_EDGE = 16      # in_src, in_w, in_eid, D[tail] per reachable edge
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("solve.hip", "sssp_dev.h", "sssp_kernels.h"):
-        with open(os.path.join(ROOT, "paper_1812_10499_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+    """HBM bytes per round-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    from paper_1812_10499_amd.build import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "rounds_kernel_%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None
@@ -144,9 +139,10 @@ def main():
     m_reach = stats["relaxed_edges"]
     gteps = m_reach / (ms_step * 1e-3) / 1e9
     alg_bytes = (BYTES_PER_RELAXED_EDGE * stats["relaxed_edges"] +
-                 BYTES_PER_SCANNED_EDGE * stats["scanned_in_edges"] +
                  BYTES_PER_SETTLED * stats["settled"] +
+                 BYTES_PER_SCANNED_EDGE * stats["scanned_in_edges"] +
                  BYTES_PER_OPEN_VISIT * stats["open_visits"])
+    solve_bytes = alg_bytes + BYTES_PER_PRED_EDGE * m_reach
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
     log("step %.3f ms, round kernel %.3f ms (%d launches), %.2f GTEPS, %.1f GB/s algorithmic"
@@ -175,7 +171,7 @@ def main():
         "config": {"workload": wname, "n": g.n, "m": g.m, "source": g.source,
                    "vertex_order": G.order,
                    "weights": wdesc, "m_reach": m_reach},
-        "hbm_gbps_algorithmic": round(achieved, 1),
+        "solve_gbps_algorithmic": round(solve_bytes / (ms_step * 1e-3) / 1e9, 1),
         "rounds": stats["rounds"],
         "dijkstra_settles": stats["settled"],
         "settles_per_round": round(stats["settled"] / max(stats["rounds"], 1), 1),
@@ -183,7 +179,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "kernel": "rounds_kernel",
-                     "kernel_ms": round(k_ms, 4), "algorithmic_bytes": alg_bytes},
+                     "kernel_ms": round(k_ms, 4), "algorithmic_bytes": alg_bytes,
+                     "traffic_gbps": (round(traffic / (k_ms * 1e-3) / 1e9, 1)
+                                      if traffic is not None else None)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1,6 +1,7 @@
 """Compile the gfx950 HIP library libsssp.so in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 
@@ -25,6 +26,16 @@ HIPCC_FLAGS = [
 
 def sources():
     return [os.path.join(CSRC, s) for s in SOURCES]
+
+
+def kernel_source_hash() -> str:
+    """Hash of the round kernel's sources (identifies which kernel a set of
+    profiler counters describes)."""
+    h = hashlib.sha256()
+    for f in ("solve.hip", "sssp_dev.h", "sssp_kernels.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def build(verbose: bool = False) -> str:
