@@ -5,8 +5,8 @@
  * Method: V. K. Garg, "Removing Sequential Bottleneck of Dijkstra's
  * Algorithm for the Shortest Path Problem".  Every vertex x carries an upper
  * bound D[x] (a feasible path cost, as in Dijkstra's algorithm, Fig. 1) and
- * a lower bound C[x] (Section IV: no path to x is cheaper than C[x]).  One
- * data-parallel round (the Section V / Fig. 5 iteration, in the sound order
+ * a lower bound C[x] (Section V: no path to x is cheaper than C[x]).  One
+ * data-parallel round (the Section VI / Fig. 6 iteration, in the sound order
  * documented at sssp_solve) relaxes the out-edges of the vertices fixed in
  * the previous round, raises C of every discovered non-fixed vertex from its
  * in-edges (Eq. 1 with the global bound of Lemma crule2), and fixes every
@@ -82,7 +82,7 @@ typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 
  *       CSC; in_eid[j] is the edge id of CSC entry j, and each vertex's
  *       in-list is ascending by edge id; in_w[j] = out_w[in_eid[j]]
  *   out_wmin[n]   minimum out-edge weight per vertex, INF if none (the
- *                 outWeight array of SP_3 and SP_4, Figs. 4 and 5)
+ *                 outWeight array of SP_3 and SP_4, Figs. 5 and 6)
  *   w_max         largest weight (filled by the builder; used for the
  *                 int32 overflow precondition)
  * The solver's working copy.  Always: in-lists ordered by weight, so that

@@ -15,11 +15,11 @@ Functions and the passages they follow:
   theorems give on acyclic graphs.
 * :func:`bfs` -- hop distances; the SP_2 theorem on unweighted graphs.
 * :func:`csr` / :func:`csr_weights` -- stable CSR by tail and CSC by head
-  (incoming-edge access, Section I) and ``outWeight`` (Figs. 4 and 5).
+  (incoming-edge access, Section I) and ``outWeight`` (Figs. 5 and 6).
 * :func:`pred` -- parent pointers (Section I) under the smallest-tight-edge
   tie rule, with the equal-cost level rule for float ties.
 * :func:`round_sim` -- the method's rounds (Eq. 1, Lemmas crule2 and crauser,
-  Fig. 5's steps in the adopted sound order; mode 2 is Fig. 5 as printed).
+  Fig. 6's steps in the adopted sound order; mode 2 is Fig. 6 as printed).
 * :func:`grad` -- fp64 subtree-sum gradient of ``sum g * cost`` over the
   pred tree.
 """

@@ -3,7 +3,7 @@
 // edge ids in increasing order (so every in-list is ascending by edge id).
 // This is the incoming-edge access the method assumes, built once per
 // graph; out_wmin is the per-vertex minimum out-edge weight (outWeight of
-// Figs. 4 and 5).
+// Figs. 5 and 6).
 //
 // The solver's working copy: an optional renumbering by descending total
 // degree (CSR copy, vid/rank), and always a CSC whose in-lists are ascending

@@ -4,7 +4,7 @@
 // One round r (D = upper bound, C = lower bound, O = discovered non-fixed
 // vertices, F = vertices fixed in round r-1), in two phases:
 //   relax : out-edges of F into D with atomicMin on keys (the relaxation of
-//           Fig. 1; label-setting form of Fig. 5 step 3).  A head whose old D
+//           Fig. 1; label-setting form of Fig. 6 step 3).  A head whose old D
 //           was INF joins O.  Each successful candidate c for head y also
 //           offers c to minD and c + out_wmin[y] to thr.
 //   bound-and-fix, for y in O:

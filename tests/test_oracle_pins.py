@@ -155,7 +155,7 @@ def test_worked_example_costs_pred_rounds():
 
 
 def test_fig5_literal_order_counterexample():
-    """Fig. 5 run as printed fixes vertex 2 at 5 in round 2 (threshold is
+    """Fig. 6 run as printed fixes vertex 2 at 5 in round 2 (threshold is
     inf, since vertex 2 has no out-edge) before vertex 1's out-edge is
     relaxed; the adopted order relaxes first and gets the true cost 2."""
     src = np.array([0, 1, 0], np.int32)
