@@ -6,6 +6,10 @@ progress goes to stderr.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22]
 
+Other workloads: grid1024, random4096, rmatNN (single solves, same fields),
+batch256 (256 instances in one launch against 256 single solves) and
+diff512 (64-source forward, backward and both against 64 single solves).
+
 value = GTEPS = m_reach / t_step (m_reach: edges whose tail is reachable,
 each relaxed exactly once per solve).  roofline.achieved = algorithmic bytes
 of the persistent round kernel per launch / its average launch time, timed
@@ -22,6 +26,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "GTEPS + achieved HBM GB/s per SSSP solve at RMAT-22; rounds vs Dijkstra settles"
 HBM_PEAK_GBPS = 8000.0
 # Algorithmic bytes per unit of work: the 4-byte elements the method itself
 # must move once (reads and writes), counted on the work the method defines.
@@ -82,6 +87,148 @@ def cpu_baseline(g, m_reach, budget_s=12.0):
                       "adjacency build is inside its time; %.2f s per solve" % (runs, per)}
 
 
+def timed(fn, steps, stream):
+    """Mean milliseconds of fn() over `steps` calls, bracketed by events on
+    `stream` (the work is queued back to back)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def oracle_sample(instances, budget_s=12.0):
+    """Times the oracle on instances (graph, source) in order until the
+    budget is spent; returns (edges with a reachable tail, seconds, count)."""
+    import numpy as np
+    import oracle
+    t0, edges, k = time.perf_counter(), 0, 0
+    for g, s in instances:
+        cost, _ = oracle.dijkstra(g.n, g.src, g.dst, g.w, s)
+        reach = np.isfinite(cost) if cost.dtype.kind == "f" else cost != np.iinfo(np.int32).max
+        edges += int(reach[g.src].sum())
+        k += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    return edges, time.perf_counter() - t0, k
+
+
+def bench_batch(args, sp, torch):
+    """256 independent instances in one persistent launch, against 256
+    single solves of the same instances on the same stream."""
+    import gen
+    glist = gen.batch_workload()
+    log("building %d graphs" % len(glist))
+    graphs = [sp.Graph(g.n, g.src, g.dst, g.w, device="cuda:0") for g in glist]
+    ig = list(range(len(glist)))
+    isrc = [g.source for g in glist]
+    bases, total = sp.batch_layout(graphs, ig)
+    cost = torch.empty(total, dtype=torch.float32, device="cuda:0")
+    pred = torch.empty(total, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    _, _, stats = sp.solve_batch(graphs, ig, isrc, with_pred=True, with_stats=True)
+    m_reach = sum(s["relaxed_edges"] for s in stats)
+    csrs = [g.csr for g in graphs]
+
+    def batched():
+        sp.sssp_solve_batch(csrs, ig, isrc, cost.data_ptr(), pred.data_ptr(), None,
+                            stream.cuda_stream)
+
+    def singles():
+        for i, g in enumerate(graphs):
+            sp.sssp_solve(g.csr, isrc[i], cost.data_ptr() + 4 * bases[i],
+                          pred.data_ptr() + 4 * bases[i], None, stream.cuda_stream)
+
+    for _ in range(args.warmup):
+        batched()
+        singles()
+    t_batch = timed(batched, args.steps, stream)
+    t_single = timed(singles, max(1, args.steps // 4), stream)
+    log("batch %.2f ms, 256 singles %.2f ms" % (t_batch, t_single))
+    cpu = None
+    if not args.no_cpu_baseline:
+        e, sec, k = oracle_sample(list(zip(glist, isrc)))
+        cpu = {"value": e / sec / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "the first %d of the 256 instances, one thread, %.1f s" % (k, sec)}
+    return {
+        "value": round(m_reach / (t_batch * 1e-3) / 1e9, 4), "ms_per_step": round(t_batch, 4),
+        "dtype": "f32",
+        "config": {"workload": "batch256_random_deg8_f32", "instances": len(glist),
+                   "sum_n": total, "sum_m": sum(g.m for g in glist), "m_reach": m_reach},
+        "single_solves_ms": round(t_single, 3),
+        "batched_vs_single_speedup": round(t_single / t_batch, 3),
+        "rounds_max": max(s["rounds"] for s in stats),
+        "rounds_sum": sum(s["rounds"] for s in stats),
+        "dijkstra_settles": sum(s["settled"] for s in stats),
+        "cpu_baseline": cpu,
+    }
+
+
+def bench_diff(args, sp, torch):
+    """Forward (64 sources, one launch), backward, and both, against 64
+    single solves; one float32 512x512 grid."""
+    import gen
+    d, gco = gen.diff_workload()
+    G = sp.Graph(d.n, d.src, d.dst, d.w, device="cuda:0")
+    srcs = [int(s) for s in d.sources]
+    S = len(srcs)
+    ig = [0] * S
+    stream = torch.cuda.current_stream()
+    cost = torch.empty(S * d.n, dtype=torch.float32, device="cuda:0")
+    pred = torch.empty(S * d.n, dtype=torch.int32, device="cuda:0")
+    gcost = torch.from_numpy(gco.reshape(-1)).to("cuda:0")
+    grad_w = torch.empty(d.m, dtype=torch.float32, device="cuda:0")
+    _, _, stats = sp.solve_batch([G], ig, srcs, with_pred=True, with_stats=True)
+    m_reach = sum(s["relaxed_edges"] for s in stats)
+
+    def fwd():
+        sp.sssp_solve_batch([G.csr], ig, srcs, cost.data_ptr(), pred.data_ptr(), None,
+                            stream.cuda_stream)
+
+    def bwd():
+        sp.sssp_backward([G.csr], ig, srcs, pred.data_ptr(), gcost.data_ptr(),
+                         grad_w.data_ptr(), stream.cuda_stream)
+
+    def both():
+        fwd()
+        bwd()
+
+    def singles():
+        for i, s in enumerate(srcs):
+            sp.sssp_solve(G.csr, s, cost.data_ptr() + 4 * i * d.n,
+                          pred.data_ptr() + 4 * i * d.n, None, stream.cuda_stream)
+
+    for _ in range(args.warmup):
+        both()
+        singles()
+    t_fwd = timed(fwd, args.steps, stream)
+    t_bwd = timed(bwd, args.steps, stream)
+    t_both = timed(both, args.steps, stream)
+    t_single = timed(singles, max(1, args.steps // 4), stream)
+    log("fwd %.2f bwd %.2f both %.2f ms; 64 singles %.2f ms" % (t_fwd, t_bwd, t_both, t_single))
+    cpu = None
+    if not args.no_cpu_baseline:
+        e, sec, k = oracle_sample([(d, s) for s in srcs])
+        cpu = {"value": e / sec / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "forward only: %d of the 64 sources, one thread, %.1f s" % (k, sec)}
+    return {
+        "value": round(m_reach / (t_both * 1e-3) / 1e9, 4), "ms_per_step": round(t_both, 4),
+        "dtype": "f32",
+        "config": {"workload": "diff_grid512_f32_x64", "n": d.n, "m": d.m, "sources": S,
+                   "m_reach": m_reach},
+        "forward_ms": round(t_fwd, 3), "backward_ms": round(t_bwd, 3),
+        "forward_backward_ms": round(t_both, 3), "single_solves_ms": round(t_single, 3),
+        "rounds_max": max(s["rounds"] for s in stats),
+        "dijkstra_settles": sum(s["settled"] for s in stats),
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +249,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload in ("batch256", "diff512"):
+        res = (bench_batch if args.workload == "batch256" else bench_diff)(args, sp, torch)
+        out = {"metric": METRIC, "value": res.pop("value"), "unit": "GTEPS", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"),
+               "data": "synthetic"}
+        out.update(res)
+        print(json.dumps(out), flush=True)
+        return
     log("generating", args.workload)
     g, wname, wdesc = make_workload(args.workload)
     log("building graph n=%d m=%d" % (g.n, g.m))
@@ -155,8 +312,7 @@ def main():
         log("cpu", cpu)
 
     out = {
-        "metric": "GTEPS + achieved HBM GB/s per SSSP solve at RMAT-22; rounds vs Dijkstra "
-                  "settles",
+        "metric": METRIC,
         "value": round(gteps, 4),
         "unit": "GTEPS",
         "n_gpus": 1,

@@ -97,6 +97,82 @@ struct SmemAll {
   unsigned int res_go;
 };
 
+// Batched solves: each block gathers the per-instance minima (minD and thr
+// candidates) and statistics of a phase in LDS and adds them to the global
+// per-instance words once per touched instance at the phase end, instead of
+// one device atomic per candidate on a handful of hot addresses.  Batches
+// with more instances than kLdsInst use the device atomics directly.
+constexpr int kLdsInst = 2048;
+
+template <bool BATCH>
+struct BatchLds {};
+
+template <>
+struct BatchLds<true> {
+  int32_t mn[kLdsInst];
+  int32_t th[kLdsInst];
+  uint32_t scan[kLdsInst];
+  uint32_t visit[kLdsInst];
+};
+
+template <class V>
+__device__ void batch_lds_reset(BatchLds<true> &bl, int I) {
+  for (int i = threadIdx.x; i < I && i < kLdsInst; i += RBS) {
+    bl.mn[i] = V::INF;
+    bl.th[i] = V::INF;
+    bl.scan[i] = 0u;
+    bl.visit[i] = 0u;
+  }
+}
+
+// Offer (v, t) to instance ins's minD / thr candidates of slot `slot`.  One
+// LDS atomic per wave when every offering lane of the wave has the same
+// instance (the usual case: lanes walk the edges of neighbouring items).
+template <class V>
+__device__ __forceinline__ void batch_offer(BatchLds<true> &bl, const RoundArgs &a, int slot,
+                                            bool on, int ins, int32_t v, int32_t t) {
+  const int I = a.num_inst;
+  if (I > kLdsInst) {
+    if (on) {
+      atomicMin(&a.imin[slot * I + ins], v);
+      atomicMin(&a.ithr[slot * I + ins], t);
+    }
+    return;
+  }
+  const uint64_t act = __ballot(on);
+  if (!act) return;
+  const int lead = __ffsll((unsigned long long)act) - 1;
+  const int i0 = __shfl(ins, lead, SSSP_WAVE);
+  if (__ballot(on && ins == i0) == act) {
+    const int32_t wv = wave_min(on ? v : V::INF);
+    const int32_t wt = wave_min(on ? t : V::INF);
+    if (lane_id() == lead) {
+      atomicMin(&bl.mn[i0], wv);
+      atomicMin(&bl.th[i0], wt);
+    }
+  } else if (on) {
+    atomicMin(&bl.mn[ins], v);
+    atomicMin(&bl.th[ins], t);
+  }
+}
+
+// After a barrier: the block's per-instance minima and counts into the
+// global words (slot < 0: no minima this phase).
+template <class V>
+__device__ void batch_lds_flush(BatchLds<true> &bl, const RoundArgs &a, int slot) {
+  const int I = a.num_inst;
+  for (int i = threadIdx.x; i < I && i < kLdsInst; i += RBS) {
+    if (slot >= 0) {
+      if (bl.mn[i] != V::INF) atomicMin(&a.imin[slot * I + i], bl.mn[i]);
+      if (bl.th[i] != V::INF) atomicMin(&a.ithr[slot * I + i], bl.th[i]);
+    }
+    if (bl.visit[i]) {
+      atomicAdd(&a.iscanned[2 * i], (unsigned long long)bl.scan[i]);
+      atomicAdd(&a.iscanned[2 * i + 1], (unsigned long long)bl.visit[i]);
+    }
+  }
+}
+
 // The portion of the grid a phase runs on: all blocks, or block 0 alone.
 struct PhaseCtx {
   uint32_t vnb, vbid;
@@ -312,8 +388,9 @@ __device__ __forceinline__ int32_t useful_in_edges(const GraphDev &G, int32_t y,
 // md_prev: a minD of an earlier round (0 before the first), a lower bound of
 // this round's minD for the work counts of newly discovered vertices.
 template <class V, bool BATCH>
-__device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NF,
-                            uint32_t EF, int32_t md_prev, PhaseWork &pw) {
+__device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
+                            const PhaseCtx &pc, int r, int NF, uint32_t EF, int32_t md_prev,
+                            PhaseWork &pw) {
   const int tid = threadIdx.x;
   const int cur = r & 1, s_now = r % 3;
   const int I = a.num_inst;
@@ -334,6 +411,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
     S.st.cnt = 0;
     S.st.deg = 0;
   }
+  if constexpr (BATCH) batch_lds_reset<V>(bl, I);
   __syncthreads();
   const uint32_t WT = EF + CW_RELAX * (uint32_t)NF;
   const uint32_t chunk = chunk_of(WT, pc.vnb);
@@ -434,17 +512,22 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           nv[j] = nd[j] = ni[j] = 0;
-          if ((smask >> j) & 1u) {
+          const bool sj = (smask >> j) & 1u;
+          int32_t th = V::INF;
+          if (sj) {
             // this candidate lowered D[y]: offer it to minD and thr
             const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-            const int32_t th = V::add(cand[j], G.out_wmin[y[j]]);
-            if constexpr (BATCH) {
-              atomicMin(&a.imin[s_now * I + S.inst[it[j]]], cand[j]);
-              atomicMin(&a.ithr[s_now * I + S.inst[it[j]]], th);
-            } else {
+            th = V::add(cand[j], G.out_wmin[y[j]]);
+            if constexpr (!BATCH) {
               lmin = kmin(lmin, cand[j]);
               ltmin = kmin(ltmin, th);
             }
+          }
+          if constexpr (BATCH)
+            batch_offer<V>(bl, a, s_now, sj, sj ? S.inst[it[j]] : 0, sj ? cand[j] : V::INF,
+                           th);
+          if (sj) {
+            const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
             if ((nmask >> j) & 1u) {
               // queued for this round's bound step; D[y] can only drop
               // below cand before it runs
@@ -477,6 +560,9 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
     const int32_t bt = block_min<RBS>(ltmin, sm.red);
     put_part<V>(a, P_CAND0 + cur, bm, pc);
     put_part<V>(a, P_TCAND0 + cur, bt, pc);
+  } else {
+    __syncthreads();
+    batch_lds_flush<V>(bl, a, s_now);
   }
 }
 
@@ -486,7 +572,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
 template <class V, bool BATCH>
 __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NO,
                             uint32_t EO, int32_t mind_all, int32_t thr_all,
-                            long long &scanned, PhaseWork &pw) {
+                            long long &scanned, BatchLds<BATCH> &bl, PhaseWork &pw) {
   const int tid = threadIdx.x;
   const int cur = r & 1, s_now = r % 3, s_next = (r + 1) % 3;
   const int I = a.num_inst;
@@ -506,6 +592,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
     S.op.cnt = 0;
     S.op.deg = 0;
   }
+  if constexpr (BATCH) batch_lds_reset<V>(bl, I);
   __syncthreads();
   int32_t lnext = V::INF, ltnext = V::INF;
   const uint32_t WT = EO + CW_FUSED * (uint32_t)NO;
@@ -603,6 +690,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       // finish the window's items: thread tid handles window item tid
       bool hf = false, ho = false;
       int32_t gy = 0, fd = 0, od = 0, ins = 0;
+      int32_t sv = V::INF, st = V::INF;  // a survivor's offers to the next minD / thr
       if (idx < NO) {
         const uint32_t p0 = (uint32_t)S.pfx[tid], p1 = (uint32_t)S.pfx[tid + 1];
         const uint32_t fb = p0 / chunk, lb = (p1 - 1) / chunk;  // p1 > p0 always
@@ -639,8 +727,15 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             // the method's count: every in-edge of an open vertex is covered
             const long long deg = G.in_off[yl + 1] - G.in_off[yl];
             if constexpr (BATCH) {
-              atomicAdd(&a.iscanned[2 * ins], (unsigned long long)deg);
-              atomicAdd(&a.iscanned[2 * ins + 1], 1ull);
+              if (a.istat) {  // statistics requested
+                if (I > kLdsInst) {
+                  atomicAdd(&a.iscanned[2 * ins], (unsigned long long)deg);
+                  atomicAdd(&a.iscanned[2 * ins + 1], 1ull);
+                } else {
+                  atomicAdd(&bl.scan[ins], (uint32_t)deg);
+                  atomicAdd(&bl.visit[ins], 1u);
+                }
+              }
             } else {
               scanned += deg;
             }
@@ -654,10 +749,9 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
               od = useful_in_edges<V>(G, yl, md, Dy);
               ho = true;
               const int32_t tn = V::add(Dy, G.out_wmin[yl]);
-              if constexpr (BATCH) {
-                atomicMin(&a.imin[s_next * I + ins], Dy);
-                atomicMin(&a.ithr[s_next * I + ins], tn);
-              } else {
+              sv = Dy;
+              st = tn;
+              if constexpr (!BATCH) {
                 lnext = kmin(lnext, Dy);
                 ltnext = kmin(ltnext, tn);
               }
@@ -665,6 +759,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           }
         }
       }
+      if constexpr (BATCH) batch_offer<V>(bl, a, s_next, ho, ins, sv, st);
       stage_push2(S.fr, hf, gy, fd, ins, front, S.op, ho, gy, od, ins, next_open, BATCH, sm);
       k = wend;
       i += WIN;
@@ -678,6 +773,9 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
     const int32_t bt = block_min<RBS>(ltnext, sm.red);
     put_part<V>(a, P_SURV0 + (cur ^ 1), bm, pc);
     put_part<V>(a, P_TSURV0 + (cur ^ 1), bt, pc);
+  } else {
+    __syncthreads();
+    batch_lds_flush<V>(bl, a, s_next);
   }
 }
 
@@ -723,6 +821,7 @@ __device__ bool park(Ctl *ctl, unsigned int &epoch, int &r, int &phase, SmemAll 
 template <class V, bool BATCH>
 __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   __shared__ SmemAll sm;
+  __shared__ BatchLds<BATCH> bl;
   const int tid = threadIdx.x;
   const uint32_t nb = gridDim.x, bid = blockIdx.x;
   Ctl *ctl = a.ctl;
@@ -804,7 +903,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     }
     PhaseWork pw;
     if (phase == 0) {
-      relax_phase<V, BATCH>(a, sm, pc, r, N, E, md_prev, pw);
+      relax_phase<V, BATCH>(a, sm, bl, pc, r, N, E, md_prev, pw);
     } else {
       int32_t mind_all = V::INF, thr_all = V::INF;
       if constexpr (!BATCH) {
@@ -812,7 +911,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
         thr_all = reduce_parts<V>(part_slot(a, P_TSURV0 + cur), part_slot(a, P_TCAND0 + cur), sm);
         if (mind_all != V::INF) md_prev = mind_all;  // minD never decreases over rounds
       }
-      fused_phase<V, BATCH>(a, sm, pc, r, N, E, mind_all, thr_all, scanned, pw);
+      fused_phase<V, BATCH>(a, sm, pc, r, N, E, mind_all, thr_all, scanned, bl, pw);
     }
     if (tb && tid == 0) {
       tb[0] = (long long)wall_clock64();

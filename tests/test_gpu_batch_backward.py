@@ -90,6 +90,39 @@ def test_batch_int32(sp):
                 "i32-mix")
 
 
+def test_batch_more_instances_than_lds_slots(sp):
+    # 2100 instances: more than the per-block LDS slots (2048), so the
+    # per-instance minima go straight to device atomics
+    rng = np.random.default_rng(41)
+    glist = []
+    for k in range(3):
+        n = int(rng.integers(20, 60))
+        m = 4 * n
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        w = rng.integers(1, 30, m).astype(np.int32)
+        glist.append(gen.Graph("s%d" % k, n, src, dst, w, 0))
+    graphs = [sp.Graph(g.n, g.src, g.dst, g.w) for g in glist]
+    inst_graph = [int(x) for x in rng.integers(0, 3, 2100)]
+    inst_source = [int(rng.integers(0, glist[g].n)) for g in inst_graph]
+    cost, pred, stats = sp.solve_batch(graphs, inst_graph, inst_source, with_pred=True,
+                                       with_stats=True)
+    sync()
+    bases, _ = sp.batch_layout(graphs, inst_graph)
+    c, p = to_np(cost), to_np(pred).astype(np.int64)
+    refs = {}
+    for i, (gi, s) in enumerate(zip(inst_graph, inst_source)):
+        if (gi, s) not in refs:
+            g = glist[gi]
+            refs[(gi, s)] = oracle_solution(g.n, g.src, g.dst, g.w, s)
+        ref = refs[(gi, s)]
+        sl = slice(bases[i], bases[i] + glist[gi].n)
+        assert np.array_equal(c[sl], ref["cost"]), i
+        assert np.array_equal(p[sl], ref["pred"]), i
+        assert stats[i]["rounds"] == ref["rounds"], i
+        assert stats[i]["scanned_in_edges"] == ref["scanned"], i
+
+
 def grad_reference(glist, graphs_np_csr, inst_graph, inst_source, preds, gco, bases):
     out = []
     for gi, g in enumerate(glist):
