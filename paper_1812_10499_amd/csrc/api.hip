@@ -291,11 +291,14 @@ sssp_status trace_begin(DevWS &w, RoundArgs &a, hipStream_t stream) {
   sssp_status s;
   const size_t cnt = (size_t)kTraceRounds * kTraceFields;
   const size_t bcnt = (size_t)kTraceBlkRounds * 2 * kMaxBlocks * kBlkFields;
-  if ((s = ws_arr(w, S_TRACE, cnt + bcnt, &a.trace))) return s;
+  const size_t mcnt = (size_t)kTraceRounds * 2 * kMarks;
+  if ((s = ws_arr(w, S_TRACE, cnt + bcnt + mcnt, &a.trace))) return s;
   a.trace_rounds = kTraceRounds;
   a.trace_blk = a.trace + cnt;
   a.trace_blk_rounds = kTraceBlkRounds;
-  HIPCHK(hipMemsetAsync(a.trace, 0, (cnt + bcnt) * sizeof(long long), stream));
+  a.marks = a.trace + cnt + bcnt;
+  a.mark_rounds = kTraceRounds;
+  HIPCHK(hipMemsetAsync(a.trace, 0, (cnt + bcnt + mcnt) * sizeof(long long), stream));
   return SSSP_OK;
 }
 
@@ -317,6 +320,23 @@ sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
     fprintf(f, "\n");
   }
   fclose(f);
+  // checkpoints: <path>.marks, one line per (round, phase): round,phase,m0..
+  {
+    std::vector<long long> hm((size_t)nr * 2 * kMarks);
+    HIPCHK(hipMemcpy(hm.data(), a.marks, hm.size() * sizeof(long long),
+                     hipMemcpyDeviceToHost));
+    std::string mp = std::string(path) + ".marks";
+    FILE *fm = fopen(mp.c_str(), "a");
+    if (!fm) return SSSP_ERR_ARG;
+    for (int r = 0; r < nr; ++r)
+      for (int ph = 0; ph < 2; ++ph) {
+        fprintf(fm, "%d,%d", r + 1, ph);
+        for (int k = 0; k < kMarks; ++k)
+          fprintf(fm, ",%lld", hm[((size_t)r * 2 + ph) * kMarks + k]);
+        fprintf(fm, "\n");
+      }
+    fclose(fm);
+  }
   // per-block records: <path>.blk, one line per (round, phase, block):
   // round,phase,block,end,windows,first_item,units
   const int nbr = nr < kTraceBlkRounds ? nr : kTraceBlkRounds;
@@ -574,6 +594,7 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
   a.max_rounds = g->n + 1;
   a.D = (int32_t *)cost;
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
+  a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
   if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
   LaunchGeom geo;
   if ((s = geometry(ws, f32, false, &geo))) return s;
@@ -639,6 +660,7 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   a.max_rounds = max_n + 1;
   a.D = (int32_t *)cost;
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
+  a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
   if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
   GraphDev *dg;
   InstDev *di;

@@ -32,10 +32,12 @@
 // the last block to arrive (per-item arrival counter), so bound-and-fix
 // needs no barrier of its own: two grid barriers per round.
 //
-// A phase with at most `solo_edges` edges runs on block 0 alone, with block
-// barriers instead of grid barriers, while the other blocks park; block 0
-// hands the grid back when a phase grows.  This keeps long tails of small
-// rounds (grids, the end of every solve) off the grid-barrier latency.
+// A phase runs on as many blocks as its work needs: block 0 alone (block
+// barriers only) for at most `solo_edges` edges, else a power of two near
+// work / block_units; the other blocks park and block 0 wakes them when a
+// phase grows.  A barrier among k blocks costs far less than one across
+// the whole grid, which matters for the long tails of small rounds (grids,
+// the end of every solve).
 #include "sssp_dev.h"
 #include "sssp_kernels.h"
 
@@ -71,8 +73,13 @@ struct SmemRelax {
 };
 
 struct SmemFused {
-  int32_t pfx[WIN + 1];
+  int32_t pfx[WIN + 1];  // work-unit prefix of the window's items (balancing)
+  int32_t epfx[WIN];     // edge prefix of the window's in-chunk edge segments
+  int32_t eoff[WIN];     // where an item's segment starts in its in-list
   int32_t base[WIN];
+  int32_t ideg[WIN];     // in-degree (statistics), out-degree, out_wmin of each item
+  int32_t odeg[WIN];
+  int32_t owm[WIN];
   int32_t acc[WIN];
   int32_t dy[WIN];
   int32_t cy[WIN];
@@ -91,10 +98,16 @@ struct SmemAll {
     SmemFused f;
   } u;
   uint64_t scan[2 * (RBS / SSSP_WAVE + 1)];
-  int32_t red[RBS / SSSP_WAVE];
+  int32_t red[2 * (RBS / SSSP_WAVE)];
   int32_t tmax;
-  int32_t res_round, res_phase, res_done;
-  unsigned int res_go;
+  // block 0, thread 0: the solve's counters, written out at the end
+  long long n_settled, n_relaxed, n_open, n_solo;
+  unsigned long long n_scanned;  // this block's share of the scanned in-edge count
+  // single solve: minima a one-block phase produced, and their rounds
+  int32_t solo_cand_min, solo_cand_thr, solo_surv_min, solo_surv_thr;
+  int32_t solo_cand_r, solo_surv_r;
+  int32_t res_round, res_phase, res_done, res_act;
+  unsigned int res_go, res_aep;
 };
 
 // Batched solves: each block gathers the per-instance minima (minD and thr
@@ -173,6 +186,18 @@ __device__ void batch_lds_flush(BatchLds<true> &bl, const RoundArgs &a, int slot
   }
 }
 
+// A value every lane of the block holds alike, moved to a scalar register.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v);
+}
+
+// Round-trace checkpoint k of a phase: block 0's wall-clock (when enabled).
+__device__ __forceinline__ void mark(const RoundArgs &a, int r, int phase, int k) {
+  if (a.marks && blockIdx.x == 0 && threadIdx.x == 0 && r <= a.mark_rounds)
+    a.marks[((size_t)(r - 1) * 2 + phase) * kMarks + k] = (long long)wall_clock64();
+}
+
 // The portion of the grid a phase runs on: all blocks, or block 0 alone.
 struct PhaseCtx {
   uint32_t vnb, vbid;
@@ -184,6 +209,7 @@ struct PhaseWork {
   int windows = 0;
   int first_item = -1;
   uint32_t units = 0;
+  int32_t bmin = 0, bthr = 0;  // single solve: the block's minD / thr offers
 };
 
 __device__ __forceinline__ int32_t *part_slot(const RoundArgs &a, int k) {
@@ -198,15 +224,15 @@ __device__ int32_t reduce_parts(const int32_t *p0, const int32_t *p1, SmemAll &s
   return block_min<RBS>(m, sm.red);
 }
 
-// A block's partial; a one-block phase owns every slot (the others get INF).
+// A block's partial.  With k active blocks, block b also clears the slots
+// b + k, b + 2k, ... of the parked blocks, so readers can reduce all slots.
 template <class V>
 __device__ void put_part(const RoundArgs &a, int k, int32_t v, const PhaseCtx &pc) {
   int32_t *p = part_slot(a, k);
-  if (!pc.solo) {
-    if (threadIdx.x == 0) p[blockIdx.x] = v;
-  } else {
-    for (uint32_t b = threadIdx.x; b < gridDim.x; b += RBS) p[b] = (b == 0) ? v : V::INF;
-  }
+  const uint32_t b0 = pc.vbid;
+  if (threadIdx.x == 0) p[b0] = v;
+  for (uint32_t b = b0 + pc.vnb * (threadIdx.x + 1); b < gridDim.x; b += pc.vnb * RBS)
+    p[b] = V::INF;
 }
 
 // -------------------------------------------------------------- staging
@@ -329,6 +355,7 @@ __device__ void stage_push2(Stager<CAP_F> &s1, bool h1, int32_t v1, int32_t d1, 
 // Returns the item whose work range contains e0, found by a
 // block-cooperative RBS-ary search (3 steps for millions of items).
 __device__ int find_start_item(const int32_t *lp, int N, uint32_t c, uint32_t e0, SmemAll &sm) {
+  if (e0 == 0) return 0;  // the first chunk (and every one-block phase)
   int lo = 0, hi = N;
   while (hi - lo > 1) {
     const int span = hi - lo;
@@ -371,10 +398,9 @@ __device__ __forceinline__ uint32_t chunk_of(uint32_t E, uint32_t vnb) {
 // the minD of the round that scans y and dy at least that round's D[y],
 // the prefix covers every edge the bound step needs.
 template <class V>
-__device__ __forceinline__ int32_t useful_in_edges(const GraphDev &G, int32_t y, int32_t md,
-                                                   int32_t dy) {
-  const int32_t b = G.in_off[y];
-  int32_t lo = 0, hi = G.in_off[y + 1] - b;
+__device__ __forceinline__ int32_t useful_in_edges_at(const GraphDev &G, int32_t b, int32_t deg,
+                                                      int32_t md, int32_t dy) {
+  int32_t lo = 0, hi = deg;
   if (hi <= 16) return hi;
   while (lo < hi) {
     const int32_t mid = (lo + hi) >> 1;
@@ -382,6 +408,13 @@ __device__ __forceinline__ int32_t useful_in_edges(const GraphDev &G, int32_t y,
     else hi = mid;
   }
   return lo;
+}
+
+template <class V>
+__device__ __forceinline__ int32_t useful_in_edges(const GraphDev &G, int32_t y, int32_t md,
+                                                   int32_t dy) {
+  const int32_t b = G.in_off[y];
+  return useful_in_edges_at<V>(G, b, G.in_off[y + 1] - b, md, dy);
 }
 
 // ================================================================== relax
@@ -413,15 +446,17 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
   }
   if constexpr (BATCH) batch_lds_reset<V>(bl, I);
   __syncthreads();
+  mark(a, r, 0, 2);
   const uint32_t WT = EF + CW_RELAX * (uint32_t)NF;
   const uint32_t chunk = chunk_of(WT, pc.vnb);
   const uint32_t e0 = pc.vbid * chunk;
   const uint32_t e1 = min(WT, e0 + chunk);
   if (e0 < e1) {
-    int i = find_start_item(a.front_p, NF, CW_RELAX, e0, sm);
+    int i = uni(find_start_item(a.front_p, NF, CW_RELAX, e0, sm));
     uint32_t k = e0;
     pw.first_item = i;
     pw.units = e1 - e0;
+    mark(a, r, 0, 3);
     while (k < e1) {
       const int idx = i + tid;
       if (idx < NF) {
@@ -451,11 +486,12 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
                          ? a.front_p[i + WIN] + (int32_t)(CW_RELAX * (uint32_t)(i + WIN))
                          : (int32_t)WT;
       __syncthreads();
-      const uint32_t wend = min((uint32_t)S.pfx[WIN], e1);
+      if (pw.windows == 0) mark(a, r, 0, 4);
+      const uint32_t wend = uni(min((uint32_t)S.pfx[WIN], e1));
       for (uint32_t cb = k; cb < wend; cb += RBS * EPT) {
         // gathers for all EPT edges are issued before any result is used
         int it[EPT];
-        int32_t pos[EPT], y[EPT], wt[EPT], cand[EPT], gy[EPT];
+        int32_t pos[EPT], y[EPT], wt[EPT], cand[EPT], gy[EPT], eid[EPT];
         unsigned long long key[EPT], dk[EPT];
         bool val[EPT];
 #pragma unroll
@@ -470,9 +506,11 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           if (val[j]) {
+            // the edge id is the caller's CSR position (out_eid under a renumbering)
             const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
             y[j] = G.out_dst[pos[j]];
             wt[j] = G.out_w[pos[j]];
+            eid[j] = G.out_eid ? G.out_eid[pos[j]] : pos[j];
           }
         }
 #pragma unroll
@@ -483,18 +521,12 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
             dk[j] = a.D64[gy[j]];  // may be stale: only filters the atomic
           }
         }
-        // Only candidates no worse than the current D need the edge id (the
-        // caller's CSR position, through out_eid under a renumbering); a
-        // float edge that leaves the cost unchanged (w below half an ulp) is
-        // an equal-cost parent.
+        // A float edge that leaves the cost unchanged (w below half an ulp)
+        // is an equal-cost parent.
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           val[j] = val[j] && cand[j] <= (int32_t)(dk[j] >> 32);
-          if (val[j]) {
-            const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-            const int32_t eid = G.out_eid ? G.out_eid[pos[j]] : pos[j];
-            key[j] = make_key(cand[j], eid, cand[j] == S.dx[it[j]]);
-          }
+          if (val[j]) key[j] = make_key(cand[j], eid[j], cand[j] == S.dx[it[j]]);
         }
         int32_t nv[EPT], nd[EPT], ni[EPT];
         uint32_t nmask = 0, smask = 0;
@@ -548,6 +580,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
         stage_push<CAP_R, EPT>(S.st, nmask, nv, nd, ni, octr, Ov, Op, Oi, BATCH, sm);
       }
       __syncthreads();
+      if (pw.windows == 0) mark(a, r, 0, 5);
       k = wend;
       i += WIN;
       ++pw.windows;
@@ -555,24 +588,25 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
   }
   __syncthreads();
   stage_flush(S.st, octr, Ov, Op, Oi, BATCH);
+  mark(a, r, 0, 6);
   if constexpr (!BATCH) {
-    const int32_t bm = block_min<RBS>(lmin, sm.red);
-    const int32_t bt = block_min<RBS>(ltmin, sm.red);
-    put_part<V>(a, P_CAND0 + cur, bm, pc);
-    put_part<V>(a, P_TCAND0 + cur, bt, pc);
+    block_min2<RBS>(lmin, ltmin, sm.red);
+    put_part<V>(a, P_CAND0 + cur, lmin, pc);
+    put_part<V>(a, P_TCAND0 + cur, ltmin, pc);
+    pw.bmin = lmin;
+    pw.bthr = ltmin;
   } else {
     __syncthreads();
     batch_lds_flush<V>(bl, a, s_now);
   }
+  mark(a, r, 0, 7);
 }
 
 // ========================================================== bound-and-fix
-// scanned: the thread's running sum of the in-degrees of the open items it
-// finished (single solve; batches count per instance)
 template <class V, bool BATCH>
 __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NO,
                             uint32_t EO, int32_t mind_all, int32_t thr_all,
-                            long long &scanned, BatchLds<BATCH> &bl, PhaseWork &pw) {
+                            BatchLds<BATCH> &bl, PhaseWork &pw) {
   const int tid = threadIdx.x;
   const int cur = r & 1, s_now = r % 3, s_next = (r + 1) % 3;
   const int I = a.num_inst;
@@ -594,16 +628,18 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
   }
   if constexpr (BATCH) batch_lds_reset<V>(bl, I);
   __syncthreads();
+  mark(a, r, 1, 3);
   int32_t lnext = V::INF, ltnext = V::INF;
   const uint32_t WT = EO + CW_FUSED * (uint32_t)NO;
   const uint32_t chunk = chunk_of(WT, pc.vnb);
   const uint32_t e0 = pc.vbid * chunk;
   const uint32_t e1 = min(WT, e0 + chunk);
   if (e0 < e1) {
-    int i = find_start_item(Op, NO, CW_FUSED, e0, sm);
+    int i = uni(find_start_item(Op, NO, CW_FUSED, e0, sm));
     uint32_t k = e0;
     pw.first_item = i;
     pw.units = e1 - e0;
+    mark(a, r, 1, 4);
     while (k < e1) {
       const int idx = i + tid;
       S.acc[tid] = V::INF;
@@ -620,7 +656,13 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           S.thr[tid] = ld_relaxed(&a.ithr[s_now * I + ins]);
         }
         const GraphDev &G = graph_of<BATCH>(a, gi);
-        S.base[tid] = G.in_off[gy - sb];
+        // everything the item's finish needs is fetched here, in one step
+        const int32_t yl = gy - sb;
+        const int32_t b0 = G.in_off[yl];
+        S.base[tid] = b0;
+        S.ideg[tid] = G.in_off[yl + 1] - b0;
+        S.odeg[tid] = G.out_off[yl + 1] - G.out_off[yl];
+        S.owm[tid] = G.out_wmin[yl];
         S.dy[tid] = ld_relaxed(key_d(&a.D64[gy]));
         S.cy[tid] = Cold[gy];
         S.sb[tid] = sb;
@@ -633,19 +675,35 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
         S.pfx[WIN] = (i + WIN < NO) ? Op[i + WIN] + (int32_t)(CW_FUSED * (uint32_t)(i + WIN))
                                     : (int32_t)WT;
       __syncthreads();
-      const uint32_t wend = min((uint32_t)S.pfx[WIN], e1);
-      for (uint32_t cb = k; cb < wend; cb += RBS * EPT) {
+      if (pw.windows == 0) mark(a, r, 1, 5);
+      const uint32_t wend = uni(min((uint32_t)S.pfx[WIN], e1));
+      // The units of an item are CW_FUSED of bookkeeping and then its
+      // edges; lanes walk only the edges that fall in [k, wend).
+      uint64_t etot;
+      {
+        uint32_t ecnt = 0;
+        if (idx < NO) {
+          const uint32_t p0 = (uint32_t)S.pfx[tid] + CW_FUSED, p1 = (uint32_t)S.pfx[tid + 1];
+          const uint32_t lo = max(p0, k), hi = min(p1, wend);
+          if (hi > lo) {
+            ecnt = hi - lo;
+            S.eoff[tid] = (int32_t)(lo - p0);
+          }
+        }
+        S.epfx[tid] = (int32_t)block_excl_scan64<RBS>((uint64_t)ecnt, sm.scan, &etot);
+        __syncthreads();
+      }
+      const uint32_t ET = uni((uint32_t)etot);
+      for (uint32_t cb = 0; cb < ET; cb += RBS * EPT) {
         int it[EPT];
         int32_t pos[EPT], v[EPT], wt[EPT], cv[EPT];
         bool val[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           const uint32_t q = cb + (uint32_t)(j * RBS + tid);
-          const bool inr = q < wend;
-          it[j] = inr ? window_item(S.pfx, q) : 0;
-          const int32_t off = (int32_t)(q - (uint32_t)S.pfx[it[j]]) - (int32_t)CW_FUSED;
-          val[j] = inr && off >= 0;  // the first CW_FUSED units of an item carry no edge
-          pos[j] = S.base[it[j]] + off;
+          val[j] = q < ET;
+          it[j] = val[j] ? window_item(S.epfx, q) : 0;
+          pos[j] = S.base[it[j]] + S.eoff[it[j]] + (int32_t)(q - (uint32_t)S.epfx[it[j]]);
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -687,10 +745,12 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
         }
       }
       __syncthreads();
+      if (pw.windows == 0) mark(a, r, 1, 6);
       // finish the window's items: thread tid handles window item tid
       bool hf = false, ho = false;
       int32_t gy = 0, fd = 0, od = 0, ins = 0;
       int32_t sv = V::INF, st = V::INF;  // a survivor's offers to the next minD / thr
+      int32_t sdeg = 0;                  // in-degree of a finished item (statistics)
       if (idx < NO) {
         const uint32_t p0 = (uint32_t)S.pfx[tid], p1 = (uint32_t)S.pfx[tid + 1];
         const uint32_t fb = p0 / chunk, lb = (p1 - 1) / chunk;  // p1 > p0 always
@@ -723,9 +783,8 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             const int32_t Dy = S.dy[tid], Cy = S.cy[tid];
             const int32_t Cn = kmax(kmax(Cy, md), kmin(Dy, m));
             const GraphDev &G = graph_of<BATCH>(a, S.gi[tid]);
-            const int32_t yl = gy - S.sb[tid];
             // the method's count: every in-edge of an open vertex is covered
-            const long long deg = G.in_off[yl + 1] - G.in_off[yl];
+            const long long deg = S.ideg[tid];
             if constexpr (BATCH) {
               if (a.istat) {  // statistics requested
                 if (I > kLdsInst) {
@@ -737,18 +796,18 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
                 }
               }
             } else {
-              scanned += deg;
+              sdeg = (int32_t)deg;
             }
             if (Cn >= Dy || Dy <= th) {
               Cnew[gy] = V::INF;  // fixed: drops out of every later bound step
-              fd = G.out_off[yl + 1] - G.out_off[yl];
+              fd = S.odeg[tid];
               hf = true;
             } else {
               Cnew[gy] = Cn;
               // next round: minD >= md and D[y] <= Dy
-              od = useful_in_edges<V>(G, yl, md, Dy);
+              od = useful_in_edges_at<V>(G, S.base[tid], S.ideg[tid], md, Dy);
               ho = true;
-              const int32_t tn = V::add(Dy, G.out_wmin[yl]);
+              const int32_t tn = V::add(Dy, S.owm[tid]);
               sv = Dy;
               st = tn;
               if constexpr (!BATCH) {
@@ -759,8 +818,14 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           }
         }
       }
-      if constexpr (BATCH) batch_offer<V>(bl, a, s_next, ho, ins, sv, st);
+      if constexpr (BATCH) {
+        batch_offer<V>(bl, a, s_next, ho, ins, sv, st);
+      } else {
+        const long long ws = wave_sum64(sdeg);
+        if (lane_id() == 0 && ws) atomicAdd(&sm.n_scanned, (unsigned long long)ws);
+      }
       stage_push2(S.fr, hf, gy, fd, ins, front, S.op, ho, gy, od, ins, next_open, BATCH, sm);
+      if (pw.windows == 0) mark(a, r, 1, 7);
       k = wend;
       i += WIN;
       ++pw.windows;
@@ -768,27 +833,48 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
   }
   stage_flush(S.fr, front.ctr, front.v, front.p, front.i, BATCH);
   stage_flush(S.op, next_open.ctr, next_open.v, next_open.p, next_open.i, BATCH);
+  mark(a, r, 1, 8);
   if constexpr (!BATCH) {
-    const int32_t bm = block_min<RBS>(lnext, sm.red);
-    const int32_t bt = block_min<RBS>(ltnext, sm.red);
-    put_part<V>(a, P_SURV0 + (cur ^ 1), bm, pc);
-    put_part<V>(a, P_TSURV0 + (cur ^ 1), bt, pc);
+    block_min2<RBS>(lnext, ltnext, sm.red);
+    put_part<V>(a, P_SURV0 + (cur ^ 1), lnext, pc);
+    put_part<V>(a, P_TSURV0 + (cur ^ 1), ltnext, pc);
+    pw.bmin = lnext;
+    pw.bthr = ltnext;
   } else {
     __syncthreads();
     batch_lds_flush<V>(bl, a, s_next);
   }
+  mark(a, r, 1, 9);
 }
 
-// ------------------------------------------------- one-block hand-over
-// Block 0 gives the grid back: its stores become visible (L2 write-back),
-// the resume point is published, and `go` moves one epoch on.
-__device__ void release_grid(Ctl *ctl, unsigned int &epoch, int r, int phase, int done) {
+// ------------------------------------------------ active blocks, parking
+// A phase runs on blocks [0, k): k = 1 for phases of at most `solo_edges`
+// edges (block barriers only), else a power of two near work / block_units,
+// at most the grid.  Every active block derives the same k from the list
+// counter.  Blocks outside the active set park on `go`; block 0 wakes them
+// when the set grows.  All blocks count `go` bumps (epoch) and active
+// barriers (aep) alike, so a parked block adopts both on waking.
+__device__ __forceinline__ uint32_t active_for(const RoundArgs &a, uint32_t E, uint32_t WT,
+                                               uint32_t nb) {
+  if (a.solo_edges > 0 && E <= (uint32_t)a.solo_edges) return 1u;
+  const uint32_t u = a.block_units > 0 ? (uint32_t)a.block_units : 1u;
+  const uint32_t want = (WT + u - 1) / u;
+  uint32_t k = 2;
+  while (k < want && k < nb) k <<= 1;
+  return k < nb ? k : nb;
+}
+
+// Block 0 publishes the resume point and moves `go` one epoch on.
+__device__ void wake_parked(Ctl *ctl, unsigned int &epoch, int r, int phase, int done,
+                            uint32_t act, unsigned int aep) {
   wait_own_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
     ctl->resume_round = r;
     ctl->resume_phase = phase;
     ctl->done = done;
+    ctl->resume_act = (int32_t)act;
+    ctl->resume_aep = aep;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&ctl->go, epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -796,25 +882,33 @@ __device__ void release_grid(Ctl *ctl, unsigned int &epoch, int r, int phase, in
   __syncthreads();
 }
 
-// A parked block waits for the hand-over and adopts its resume point.
-// Returns true when the solve has finished.
-__device__ bool park(Ctl *ctl, unsigned int &epoch, int &r, int &phase, SmemAll &sm) {
-  if (threadIdx.x == 0) {
-    unsigned int g;
-    while ((int)((g = ld_flag(&ctl->go)) - epoch) <= 0) __builtin_amdgcn_s_sleep(2);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    sm.res_go = g;
-    sm.res_round = ld_relaxed(&ctl->resume_round);
-    sm.res_phase = ld_relaxed(&ctl->resume_phase);
-    sm.res_done = ld_relaxed(&ctl->done);
+// A parked block sleeps until a hand-over names it active (or the solve
+// ends) and adopts the resume point.  Returns true when the solve is done.
+__device__ bool park(Ctl *ctl, unsigned int &epoch, unsigned int &aep, int &r, int &phase,
+                     uint32_t &act, SmemAll &sm) {
+  for (;;) {
+    if (threadIdx.x == 0) {
+      unsigned int g;
+      while ((int)((g = ld_flag(&ctl->go)) - epoch) <= 0) __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      sm.res_go = g;
+      sm.res_round = ld_relaxed(&ctl->resume_round);
+      sm.res_phase = ld_relaxed(&ctl->resume_phase);
+      sm.res_done = ld_relaxed(&ctl->done);
+      sm.res_act = ld_relaxed(&ctl->resume_act);
+      sm.res_aep = (unsigned int)ld_relaxed((const int32_t *)&ctl->resume_aep);
+    }
+    __syncthreads();
+    epoch = sm.res_go;
+    r = sm.res_round;
+    phase = sm.res_phase;
+    act = (uint32_t)sm.res_act;
+    aep = sm.res_aep;
+    const bool done = sm.res_done != 0;
+    __syncthreads();
+    if (done) return true;
+    if (blockIdx.x < act) return false;
   }
-  __syncthreads();
-  epoch = sm.res_go;
-  r = sm.res_round;
-  phase = sm.res_phase;
-  const bool done = sm.res_done != 0;
-  __syncthreads();
-  return done;
 }
 
 // ------------------------------------------------------------ the kernel
@@ -826,18 +920,26 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   const uint32_t nb = gridDim.x, bid = blockIdx.x;
   Ctl *ctl = a.ctl;
   const int I = a.num_inst;
-  unsigned int epoch = 0;
-  int r = 1, phase = 0;  // phase 0: relax, 1: bound-and-fix
-  bool solo = false;
+  unsigned int epoch = 0;  // hand-overs so far (bumps of ctl->go)
+  unsigned int aep = 0;    // barriers of the active blocks so far
+  int r = 1, phase = 0;    // phase 0: relax, 1: bound-and-fix
+  uint32_t act = nb;       // active blocks
   int32_t md_prev = 0;     // the last minD this block computed (0 before round 1)
-  long long scanned = 0;   // this thread's share of the scanned in-edge count
+  if (tid == 0) {
+    sm.n_settled = sm.n_relaxed = sm.n_open = sm.n_solo = 0;
+    sm.n_scanned = 0ull;
+    sm.solo_cand_r = sm.solo_surv_r = -1;
+  }
+  __syncthreads();
 
   for (;;) {
     const int cur = r & 1;
+    mark(a, r, phase, 0);
     const uint64_t ctr =
         ld_relaxed64(phase == 0 ? &ctl->front_ctr[cur] : &ctl->open_ctr[cur]);
-    const int N = (int)(ctr >> 32);
-    const uint32_t E = (uint32_t)(ctr & 0xffffffffull);
+    const int N = uni((int)(ctr >> 32));
+    const uint32_t E = uni((uint32_t)(ctr & 0xffffffffull));
+    if (N >= 0) mark(a, r, phase, 1);  // the counter has arrived
     // termination: the relax left nothing open, or the watchdog (rounds
     // never exceed the reachable count)
     const bool watchdog = phase == 0 && r > a.max_rounds;
@@ -846,21 +948,24 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
         if (watchdog) ctl->status = 7;
         ctl->rounds = watchdog ? a.max_rounds : r;
       }
-      if (solo) release_grid(ctl, epoch, r, phase, 1);
+      if (act < nb && bid == 0) wake_parked(ctl, epoch, r, phase, 1, act, aep);
       break;
     }
-    const bool want_solo = a.solo_edges > 0 && E <= (uint32_t)a.solo_edges;
-    if (!solo && want_solo) {
-      if (bid != 0) {
-        if (park(ctl, epoch, r, phase, sm)) break;
-        continue;
+    const uint32_t WT = E + (phase == 0 ? CW_RELAX : CW_FUSED) * (uint32_t)N;
+    const uint32_t want = active_for(a, E, WT, nb);
+    if (want < act) {
+      if (bid >= want) {
+        if (park(ctl, epoch, aep, r, phase, act, sm)) break;
+        continue;  // resume where block 0 left off
       }
-      solo = true;
-    } else if (solo && !want_solo) {
-      release_grid(ctl, epoch, r, phase, 0);
-      solo = false;
+      act = want;
+    } else if (want > act) {
+      if (bid == 0) wake_parked(ctl, epoch, r, phase, 0, want, aep);
+      else epoch += 1u;
+      act = want;
     }
-    const PhaseCtx pc = {solo ? 1u : nb, solo ? 0u : bid, solo};
+    const bool solo = act == 1;
+    const PhaseCtx pc = {act, bid, solo};
     long long *tr = (a.trace && r <= a.trace_rounds) ? a.trace + (size_t)(r - 1) * kTraceFields
                                                       : nullptr;
     long long *tb = (a.trace_blk && r <= a.trace_blk_rounds)
@@ -873,12 +978,12 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           // counters the coming bound-and-fix appends to (last read a round ago)
           ctl->open_ctr[cur ^ 1] = 0ull;
           ctl->front_ctr[cur ^ 1] = 0ull;
-          ctl->settled += N;
-          ctl->relaxed += E;
+          sm.n_settled += N;
+          sm.n_relaxed += E;
         } else {
-          ctl->open_visits += N;
+          sm.n_open += N;
         }
-        if (solo) ctl->solo_phases += 1;
+        if (solo) sm.n_solo += 1;
         if (tr) {
           if (phase == 0) {
             tr[TR_START] = (long long)wall_clock64();
@@ -888,7 +993,8 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
             tr[TR_NO] = N;
             tr[TR_EO] = E;
           }
-          tr[TR_MODE] |= (long long)(solo ? (1 << phase) : 0);
+          // active blocks of the relax (low half) and bound-and-fix phases
+          tr[TR_MODE] |= (long long)act << (16 * phase);
         }
       }
       if constexpr (BATCH) {
@@ -904,14 +1010,36 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     PhaseWork pw;
     if (phase == 0) {
       relax_phase<V, BATCH>(a, sm, bl, pc, r, N, E, md_prev, pw);
+      if (!BATCH && solo && tid == 0) {
+        // block 0 alone wrote every partial slot: keep the values
+        sm.solo_cand_min = pw.bmin;
+        sm.solo_cand_thr = pw.bthr;
+        sm.solo_cand_r = r;
+      }
     } else {
       int32_t mind_all = V::INF, thr_all = V::INF;
       if constexpr (!BATCH) {
-        mind_all = reduce_parts<V>(part_slot(a, P_SURV0 + cur), part_slot(a, P_CAND0 + cur), sm);
-        thr_all = reduce_parts<V>(part_slot(a, P_TSURV0 + cur), part_slot(a, P_TCAND0 + cur), sm);
+        if (solo && sm.solo_cand_r == r && sm.solo_surv_r == r - 1) {
+          // both halves of this round's minima came from block 0 alone
+          mind_all = kmin(sm.solo_cand_min, sm.solo_surv_min);
+          thr_all = kmin(sm.solo_cand_thr, sm.solo_surv_thr);
+        } else {
+          mind_all = reduce_parts<V>(part_slot(a, P_SURV0 + cur), part_slot(a, P_CAND0 + cur),
+                                     sm);
+          thr_all = reduce_parts<V>(part_slot(a, P_TSURV0 + cur),
+                                    part_slot(a, P_TCAND0 + cur), sm);
+        }
+        mind_all = uni(mind_all);
+        thr_all = uni(thr_all);
         if (mind_all != V::INF) md_prev = mind_all;  // minD never decreases over rounds
       }
-      fused_phase<V, BATCH>(a, sm, pc, r, N, E, mind_all, thr_all, scanned, bl, pw);
+      mark(a, r, 1, 2);
+      fused_phase<V, BATCH>(a, sm, pc, r, N, E, mind_all, thr_all, bl, pw);
+      if (!BATCH && solo && tid == 0) {
+        sm.solo_surv_min = pw.bmin;
+        sm.solo_surv_thr = pw.bthr;
+        sm.solo_surv_r = r;
+      }
     }
     if (tb && tid == 0) {
       tb[0] = (long long)wall_clock64();
@@ -924,9 +1052,10 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
       wait_own_stores();
       __syncthreads();
     } else {
-      grid_barrier(a.flags, &ctl->go, epoch);
+      grid_barrier(a.flags, &ctl->go_a, aep, act);
     }
     if (tr && bid == 0 && tid == 0) tr[phase == 0 ? TR_END_RELAX : TR_END_FUSED] = (long long)wall_clock64();
+    mark(a, r, phase, 10);
     if (phase == 0) {
       phase = 1;
     } else {
@@ -934,10 +1063,14 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
       ++r;
     }
   }
-  if constexpr (!BATCH) {
-    uint64_t tot;
-    block_excl_scan64<RBS>((uint64_t)scanned, sm.scan, &tot);
-    if (tid == 0 && tot) atomicAdd((unsigned long long *)&ctl->scanned, (unsigned long long)tot);
+  __syncthreads();
+  if (!BATCH && tid == 0 && sm.n_scanned)
+    atomicAdd((unsigned long long *)&ctl->scanned, sm.n_scanned);
+  if (bid == 0 && tid == 0) {
+    ctl->settled = sm.n_settled;
+    ctl->relaxed = sm.n_relaxed;
+    ctl->open_visits = sm.n_open;
+    ctl->solo_phases = sm.n_solo;
   }
 }
 
@@ -1017,6 +1150,9 @@ __global__ void init_seed_kernel(RoundArgs a) {
     c->open_ctr[0] = 0ull;
     c->open_ctr[1] = 0ull;
     c->go = 0u;
+    c->go_a = 0u;
+    c->resume_act = 0;
+    c->resume_aep = 0u;
     c->status = 0;
     c->rounds = 0;
     c->deg_count = 0;

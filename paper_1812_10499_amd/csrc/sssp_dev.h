@@ -171,6 +171,29 @@ __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *scratch) {
   return r;
 }
 
+// Two block-wide minima in one pass; results valid in all threads.
+// scratch: 2 * BS/64 entries.
+template <int BS>
+__device__ __forceinline__ void block_min2(int32_t &a, int32_t &b, int32_t *scratch) {
+  constexpr int NW = BS / SSSP_WAVE;
+  const int w = threadIdx.x / SSSP_WAVE;
+  a = wave_min(a);
+  b = wave_min(b);
+  if (lane_id() == 0) {
+    scratch[w] = a;
+    scratch[NW + w] = b;
+  }
+  __syncthreads();
+  a = scratch[0];
+  b = scratch[NW];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) {
+    a = kmin(a, scratch[i]);
+    b = kmin(b, scratch[NW + i]);
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------- grid barrier
 // Barrier for a cooperative launch (all blocks co-resident) that uses no
 // same-address atomics: 512 blocks incrementing one counter serialize at
@@ -197,8 +220,11 @@ __device__ __forceinline__ unsigned int ld_flag(const unsigned int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// nblocks: the participants are blocks [0, nblocks) (the whole grid by
+// default); the others must not call it for this epoch.
 __device__ __forceinline__ void grid_barrier(unsigned int *flags, unsigned int *go,
-                                             unsigned int &epoch) {
+                                             unsigned int &epoch, unsigned int nblocks = 0) {
+  if (nblocks == 0) nblocks = gridDim.x;
   wait_own_stores();
   __syncthreads();
   epoch += 1;
@@ -209,7 +235,7 @@ __device__ __forceinline__ void grid_barrier(unsigned int *flags, unsigned int *
                        __HIP_MEMORY_SCOPE_AGENT);
   }
   if (blockIdx.x == 0) {
-    for (unsigned int b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+    for (unsigned int b = threadIdx.x; b < nblocks; b += blockDim.x)
       while ((int)(ld_flag(&flags[b * kFlagStride]) - ep) < 0) __builtin_amdgcn_s_sleep(1);
     __syncthreads();
     if (threadIdx.x == 0) {

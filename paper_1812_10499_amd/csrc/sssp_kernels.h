@@ -34,12 +34,16 @@ enum PartSlot {
 struct Ctl {
   unsigned long long front_ctr[2];  // by round parity: (items << 32) | out-degree sum
   unsigned long long open_ctr[2];   // by round parity: (items << 32) | in-degree sum
-  unsigned int go;                  // grid barrier / hand-over release word
+  unsigned int go;                  // hand-over word: parked blocks wait on it
+  unsigned int go_a;                // barrier release word of the active blocks
   int32_t status;                   // 0, or an sssp_status code set on the device
   int32_t rounds;
   int32_t deg_count;    // pred: vertices queued for the equal-cost pass
   int32_t heavy_count;  // pred: vertices queued for the wave-per-vertex pass
-  int32_t resume_round, resume_phase, done;  // hand-over from a one-block stretch
+  // hand-over to parked blocks: where to resume, how many blocks are active
+  // from there, and the active barrier's epoch
+  int32_t resume_round, resume_phase, done, resume_act;
+  unsigned int resume_aep;
   long long settled, relaxed, scanned, open_visits;
   long long solo_phases;  // phases run by block 0 alone
 };
@@ -82,9 +86,14 @@ struct RoundArgs {
   // its phase end, the list windows it walked, its first list item and the
   // work units of its chunk
   long long *trace_blk;
+  // optional checkpoints: block 0's wall-clock at fixed points inside each
+  // phase, [round][2 phases][kMarks]
+  long long *marks;
+  int32_t mark_rounds;
   unsigned int *flags;       // grid barrier flags, kMaxBlocks * kFlagStride
   int32_t *part;             // per-block partial minima, kParts * kMaxBlocks
   int32_t solo_edges;        // phases with at most this many edges run on block 0 alone
+  int32_t block_units;       // otherwise: about this many work units per active block
 };
 
 // Trace record of one round: wall-clock (100 MHz) at the relax start, block
@@ -96,6 +105,7 @@ enum TraceField {
 };
 
 constexpr int kBlkFields = 4;
+constexpr int kMarks = 12;
 
 struct LaunchGeom {
   int blocks;  // persistent grid size (co-resident)
