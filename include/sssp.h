@@ -95,6 +95,9 @@ typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 
  *   s_out_off[n+1], s_out_dst[m] (solver ids), s_out_w[m], s_out_eid[m]
  *       each out-list ascending by (head solver id, edge id)
  *   s_out_wmin[n]  out_wmin by solver id
+ * Always, too: s_vrec[8n], one 32-byte record per solver vertex,
+ *   {out_off, out_degree, in_off, in_degree, out_wmin, 0, 0, 0}, so that a
+ *   round reads a vertex's offsets and out_wmin from one cache line.
  * With SSSP_ORDER_INPUT, solver ids are vertex ids: vid, rank and
  * s_out_eid are NULL and s_out_off/dst/w/wmin alias the CSR arrays.
  * These arrays are library-internal; callers only keep them valid.
@@ -124,6 +127,7 @@ typedef struct {
   const int32_t *s_in_eid;
   const void *s_in_w;
   const void *s_out_wmin;
+  const int32_t *s_vrec;
 } sssp_csr;
 
 /* Per-solve counters (host struct). */

@@ -23,7 +23,7 @@ enum Slot {
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
-  S_TRACE, S_FLAGS, S_PART, S_D64,
+  S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1,
   NSLOTS
 };
 
@@ -148,7 +148,7 @@ sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
 bool csr_ok(const sssp_csr *g) {
   if (!(g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
         g->out_off && g->in_off && g->out_wmin && g->s_out_off && g->s_in_off &&
-        g->s_out_wmin &&
+        g->s_out_wmin && g->s_vrec &&
         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
                        g->s_out_dst && g->s_out_w && g->s_in_src && g->s_in_eid && g->s_in_w))))
     return false;
@@ -173,6 +173,7 @@ GraphDev graph_dev(const sssp_csr *g) {
   d.in_src = g->s_in_src;
   d.in_w = (const int32_t *)g->s_in_w;
   d.out_wmin = (const int32_t *)g->s_out_wmin;
+  d.vrec = (const int4 *)g->s_vrec;
   d.vid = g->vid;
   d.rank = g->rank;
   d.u_out_off = g->out_off;
@@ -190,7 +191,7 @@ GraphDev graph_dev(const sssp_csr *g) {
 // weight-ordered in-lists, then (degree order) the renumbered CSR.
 enum BufArr {
   B_OUT_OFF, B_OUT_DST, B_OUT_W, B_IN_OFF, B_IN_SRC, B_IN_EID, B_IN_W, B_OUT_WMIN,
-  B_S_IN_OFF, B_S_IN_SRC, B_S_IN_EID, B_S_IN_W,
+  B_S_IN_OFF, B_S_IN_SRC, B_S_IN_EID, B_S_IN_W, B_S_VREC,
   B_VID, B_RANK, B_S_OUT_OFF, B_S_OUT_DST, B_S_OUT_W, B_S_OUT_EID, B_S_OUT_WMIN, B_COUNT
 };
 
@@ -203,7 +204,7 @@ Layout build_layout(int32_t n, int32_t m, bool renumber) {
   Layout L;
   size_t o = 0;
   const size_t N = (size_t)n, M = (size_t)m;
-  const size_t count[B_COUNT] = {N + 1, M, M, N + 1, M, M, M, N, N + 1, M, M, M,
+  const size_t count[B_COUNT] = {N + 1, M, M, N + 1, M, M, M, N, N + 1, M, M, M, 8 * N,
                                  N,     N, N + 1, M, M, M, N};
   const int narr = renumber ? B_COUNT : B_VID;
   for (int i = 0; i < B_COUNT; ++i) {
@@ -228,6 +229,7 @@ SolverCopy solver_copy(const sssp_csr *g) {
   c.in_eid = (int32_t *)g->s_in_eid;
   c.in_w = (int32_t *)g->s_in_w;
   c.out_wmin = (int32_t *)g->s_out_wmin;
+  c.vrec = (int32_t *)g->s_vrec;
   return c;
 }
 
@@ -261,6 +263,18 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
   if ((s = ws_arr(w, S_OP1, T, &a.open_p1))) return s;
   if ((s = ws_arr(w, S_FV, T, &a.front_v))) return s;
   if ((s = ws_arr(w, S_FP, T, &a.front_p))) return s;
+  {
+    // list payload words: kFX per frontier entry, kOX per open entry and parity
+    int32_t *fx, *ox0, *ox1;
+    if ((s = ws_arr(w, S_FX, kFX * T, &fx))) return s;
+    if ((s = ws_arr(w, S_OX0, kOX * T, &ox0))) return s;
+    if ((s = ws_arr(w, S_OX1, kOX * T, &ox1))) return s;
+    for (int k = 0; k < kFX; ++k) a.front_x[k] = fx + (size_t)k * T;
+    for (int k = 0; k < kOX; ++k) {
+      a.open_x0[k] = ox0 + (size_t)k * T;
+      a.open_x1[k] = ox1 + (size_t)k * T;
+    }
+  }
   if ((s = ws_arr(w, S_CTL, 1, &a.ctl))) return s;
   if ((s = ws_arr(w, S_FLAGS, (size_t)kMaxBlocks * kFlagStride, &a.flags))) return s;
   if ((s = ws_arr(w, S_PART, (size_t)kParts * kMaxBlocks, &a.part))) return s;
@@ -491,6 +505,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   c.in_src = arr(B_S_IN_SRC);
   c.in_eid = arr(B_S_IN_EID);
   c.in_w = arr(B_S_IN_W);
+  c.vrec = arr(B_S_VREC);
   if (order != SSSP_ORDER_INPUT && m > 0) {
     HIPCHK(launch_degree(n, out_off, in_off, t, stream));
     HIPCHK(hipMemcpyAsync(hs, t.status, sizeof(hs), hipMemcpyDeviceToHost, stream));
@@ -511,6 +526,8 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
     }
   }
   HIPCHK(launch_in_lists(n, m, wkey_max, out_off, out_dst, out_w, c, t, stream));
+  HIPCHK(launch_vrec(n, c, stream));
+  out->s_vrec = c.vrec;
   out->vid = c.vid;
   out->rank = c.rank;
   out->s_out_off = c.out_off;
@@ -568,6 +585,7 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
                             stream));
   HIPCHK(launch_in_lists(g->n, g->m, hs[1], g->out_off, g->out_dst, (const int32_t *)g->out_w,
                          c, t, stream));
+  HIPCHK(launch_vrec(g->n, c, stream));  // out_wmin changed
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));
   g->w_max = w_max;

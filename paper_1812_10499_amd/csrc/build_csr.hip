@@ -462,6 +462,21 @@ hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t
   return hipGetLastError();
 }
 
+__global__ void vrec_kernel(int32_t n, const int32_t *out_off, const int32_t *in_off,
+                            const int32_t *out_wmin, int4 *vrec) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int32_t o = out_off[v], i = in_off[v];
+    vrec[2 * v] = make_int4(o, out_off[v + 1] - o, i, in_off[v + 1] - i);
+    vrec[2 * v + 1] = make_int4(out_wmin[v], 0, 0, 0);
+  }
+}
+
+hipError_t launch_vrec(int32_t n, const SolverCopy &c, hipStream_t stream) {
+  hipLaunchKernelGGL(vrec_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, c.out_off,
+                     c.in_off, c.out_wmin, (int4 *)c.vrec);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------- reweighting
 __global__ void set_weights_kernel(const int32_t *w, const int32_t *in_eid, int32_t m,
                                    int32_t *out_w, int32_t *in_w, const int32_t *s_out_eid,

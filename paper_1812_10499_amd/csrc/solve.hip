@@ -52,15 +52,20 @@ constexpr uint32_t CW_RELAX = 4;  // work units per frontier item (its loads and
 constexpr uint32_t CW_FUSED = 8;  // work units per open item (loads, decision, list entry)
 
 // ----------------------------------------------------------- LDS layouts
-template <int CAP>
+// LDS staging of list appends: vertex, local exclusive work prefix,
+// instance, and NX payload words per item.
+template <int CAP, int NX>
 struct Stager {
   int32_t v[CAP];
   int32_t d[CAP];  // local exclusive degree prefix
   int32_t inst[CAP];
+  int32_t x[NX > 0 ? NX : 1][NX > 0 ? CAP : 1];
   int32_t cnt;
   uint32_t deg;
   unsigned long long base;
 };
+
+
 
 struct SmemRelax {
   int32_t pfx[WIN + 1];
@@ -69,7 +74,7 @@ struct SmemRelax {
   int32_t sb[WIN];
   int32_t gi[WIN];
   int32_t inst[WIN];
-  Stager<CAP_R> st;
+  Stager<CAP_R, 0> st;
 };
 
 struct SmemFused {
@@ -77,7 +82,8 @@ struct SmemFused {
   int32_t epfx[WIN];     // edge prefix of the window's in-chunk edge segments
   int32_t eoff[WIN];     // where an item's segment starts in its in-list
   int32_t base[WIN];
-  int32_t ideg[WIN];     // in-degree (statistics), out-degree, out_wmin of each item
+  int32_t ideg[WIN];     // in-degree (statistics), out-offset, out-degree, out_wmin
+  int32_t ooff[WIN];
   int32_t odeg[WIN];
   int32_t owm[WIN];
   int32_t acc[WIN];
@@ -88,8 +94,8 @@ struct SmemFused {
   int32_t sb[WIN];
   int32_t gi[WIN];
   int32_t inst[WIN];
-  Stager<CAP_F> fr;
-  Stager<CAP_F> op;
+  Stager<CAP_F, kFX> fr;
+  Stager<CAP_F, kOX> op;
 };
 
 struct SmemAll {
@@ -236,26 +242,40 @@ __device__ void put_part(const RoundArgs &a, int k, int32_t v, const PhaseCtx &p
 }
 
 // -------------------------------------------------------------- staging
+// A global list: its append counter ((items << 32) | work units) and its
+// arrays.  x[k] receives payload word k; a list fed by a payload-free
+// stager gets -1 in x[0] when x[0] is set (the "no payload" mark).
+struct ListRef {
+  unsigned long long *ctr;
+  int32_t *v, *p, *i;
+  int32_t *x[kOX];
+};
+
 // Block-collective flush of an LDS stager into the global list: one 64-bit
 // atomicAdd reserves (slots, degree range).  All threads call, after a
 // barrier that made st.cnt current.
-template <int CAP>
-__device__ void stage_flush(Stager<CAP> &st, unsigned long long *ctr, int32_t *lv, int32_t *lp,
-                            int32_t *li, bool batch) {
+template <int CAP, int NX>
+__device__ void stage_flush(Stager<CAP, NX> &st, const ListRef &l, bool batch) {
   const int cnt = st.cnt;
   if (cnt == 0) return;
   if (threadIdx.x == 0) {
     unsigned long long inc = ((unsigned long long)cnt << 32) | (unsigned long long)st.deg;
-    st.base = atomicAdd(ctr, inc);
+    st.base = atomicAdd(l.ctr, inc);
   }
   __syncthreads();
   const unsigned long long b = st.base;
   const int32_t bc = (int32_t)(b >> 32);
   const int32_t bd = (int32_t)(uint32_t)(b & 0xffffffffull);
   for (int j = threadIdx.x; j < cnt; j += RBS) {
-    lv[bc + j] = st.v[j];
-    lp[bc + j] = bd + st.d[j];
-    if (batch) li[bc + j] = st.inst[j];
+    l.v[bc + j] = st.v[j];
+    l.p[bc + j] = bd + st.d[j];
+    if (batch) l.i[bc + j] = st.inst[j];
+    if constexpr (NX > 0) {
+#pragma unroll
+      for (int k = 0; k < NX; ++k) l.x[k][bc + j] = st.x[k][j];
+    } else {
+      if (l.x[0]) l.x[0][bc + j] = -1;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -269,9 +289,8 @@ __device__ void stage_flush(Stager<CAP> &st, unsigned long long *ctr, int32_t *l
 // iff bit j of `mask` is set (arrays are indexed by compile-time j only, so
 // they stay in VGPRs).  Flushes first when the stager would overflow.
 template <int CAP, int K>
-__device__ void stage_push(Stager<CAP> &st, uint32_t mask, const int32_t (&v)[K],
-                           const int32_t (&d)[K], const int32_t (&ins)[K],
-                           unsigned long long *ctr, int32_t *lv, int32_t *lp, int32_t *li,
+__device__ void stage_push(Stager<CAP, 0> &st, uint32_t mask, const int32_t (&v)[K],
+                           const int32_t (&d)[K], const int32_t (&ins)[K], const ListRef &l,
                            bool batch, SmemAll &sm) {
   uint32_t dsum = 0;
   int n_local = 0;
@@ -285,7 +304,7 @@ __device__ void stage_push(Stager<CAP> &st, uint32_t mask, const int32_t (&v)[K]
   const uint64_t ex = block_excl_scan64<RBS>(((uint64_t)n_local << 32) | dsum, sm.scan, &tot);
   const int tcnt = (int)(tot >> 32);
   if (tcnt == 0) return;  // uniform
-  if (st.cnt + tcnt > CAP) stage_flush(st, ctr, lv, lp, li, batch);
+  if (st.cnt + tcnt > CAP) stage_flush(st, l, batch);
   int pos = st.cnt + (int)(ex >> 32);
   uint32_t dpos = st.deg + (uint32_t)(ex & 0xffffffffull);
 #pragma unroll
@@ -306,34 +325,35 @@ __device__ void stage_push(Stager<CAP> &st, uint32_t mask, const int32_t (&v)[K]
   __syncthreads();
 }
 
-// One item per thread into each of two stagers, with a single scan.
-struct ListRef {
-  unsigned long long *ctr;
-  int32_t *v, *p, *i;
-};
-
-__device__ void stage_push2(Stager<CAP_F> &s1, bool h1, int32_t v1, int32_t d1, int32_t i1,
-                            const ListRef &l1, Stager<CAP_F> &s2, bool h2, int32_t v2,
-                            int32_t d2, int32_t i2, const ListRef &l2, bool batch,
+// One item per thread into each of two payload stagers, with a single scan.
+template <int N1, int N2>
+__device__ void stage_push2(Stager<CAP_F, N1> &s1, bool h1, int32_t v1, int32_t d1, int32_t i1,
+                            const int32_t (&x1)[N1], const ListRef &l1,
+                            Stager<CAP_F, N2> &s2, bool h2, int32_t v2, int32_t d2, int32_t i2,
+                            const int32_t (&x2)[N2], const ListRef &l2, bool batch,
                             SmemAll &sm) {
   const uint64_t m1 = h1 ? ((1ull << 32) | (uint32_t)d1) : 0ull;
   const uint64_t m2 = h2 ? ((1ull << 32) | (uint32_t)d2) : 0ull;
   uint64_t ex1, ex2, t1, t2;
   block_excl_scan64x2<RBS>(m1, m2, sm.scan, &ex1, &ex2, &t1, &t2);
   const int c1 = (int)(t1 >> 32), c2 = (int)(t2 >> 32);
-  if (c1 && s1.cnt + c1 > CAP_F) stage_flush(s1, l1.ctr, l1.v, l1.p, l1.i, batch);
-  if (c2 && s2.cnt + c2 > CAP_F) stage_flush(s2, l2.ctr, l2.v, l2.p, l2.i, batch);
+  if (c1 && s1.cnt + c1 > CAP_F) stage_flush(s1, l1, batch);
+  if (c2 && s2.cnt + c2 > CAP_F) stage_flush(s2, l2, batch);
   if (h1) {
     const int pos = s1.cnt + (int)(ex1 >> 32);
     s1.v[pos] = v1;
     s1.d[pos] = (int32_t)(s1.deg + (uint32_t)(ex1 & 0xffffffffull));
     s1.inst[pos] = i1;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) s1.x[k][pos] = x1[k];
   }
   if (h2) {
     const int pos = s2.cnt + (int)(ex2 >> 32);
     s2.v[pos] = v2;
     s2.d[pos] = (int32_t)(s2.deg + (uint32_t)(ex2 & 0xffffffffull));
     s2.inst[pos] = i2;
+#pragma unroll
+    for (int k = 0; k < N2; ++k) s2.x[k][pos] = x2[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -428,11 +448,11 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
   const int cur = r & 1, s_now = r % 3;
   const int I = a.num_inst;
   Ctl *ctl = a.ctl;
-  int32_t *Ov = cur ? a.open_v1 : a.open_v0;
-  int32_t *Op = cur ? a.open_p1 : a.open_p0;
-  int32_t *Oi = cur ? a.open_i1 : a.open_i0;
+  // first discoveries go to this round's open list, marked "no payload"
+  const ListRef olist = {&ctl->open_ctr[cur], cur ? a.open_v1 : a.open_v0,
+                         cur ? a.open_p1 : a.open_p0, cur ? a.open_i1 : a.open_i0,
+                         {cur ? a.open_x1[OX_BASE] : a.open_x0[OX_BASE]}};
   int32_t *Cnew = cur ? a.C0 : a.C1;
-  unsigned long long *octr = &ctl->open_ctr[cur];
   if constexpr (BATCH) {
     // per-instance round count: the last round with a non-empty frontier
     for (int i = (int)(pc.vbid * RBS) + tid; i < NF; i += (int)(pc.vnb * RBS))
@@ -469,9 +489,9 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
           sb = id.sbase;
           gi = id.graph;
         }
-        const GraphDev &G = graph_of<BATCH>(a, gi);
-        S.base[tid] = G.out_off[gx - sb];
-        S.dx[tid] = ld_relaxed(key_d(&a.D64[gx]));
+        // out-offset and final D travel with the frontier entry
+        S.base[tid] = a.front_x[FX_OOFF][idx];
+        S.dx[tid] = a.front_x[FX_D][idx];
         S.sb[tid] = sb;
         S.gi[tid] = gi;
         S.inst[tid] = ins;
@@ -577,7 +597,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
             }
           }
         }
-        stage_push<CAP_R, EPT>(S.st, nmask, nv, nd, ni, octr, Ov, Op, Oi, BATCH, sm);
+        stage_push<CAP_R, EPT>(S.st, nmask, nv, nd, ni, olist, BATCH, sm);
       }
       __syncthreads();
       if (pw.windows == 0) mark(a, r, 0, 5);
@@ -587,7 +607,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
     }
   }
   __syncthreads();
-  stage_flush(S.st, octr, Ov, Op, Oi, BATCH);
+  stage_flush(S.st, olist, BATCH);
   mark(a, r, 0, 6);
   if constexpr (!BATCH) {
     block_min2<RBS>(lmin, ltmin, sm.red);
@@ -616,9 +636,13 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
   const int32_t *Oi = cur ? a.open_i1 : a.open_i0;
   const int32_t *Cold = cur ? a.C1 : a.C0;
   int32_t *Cnew = cur ? a.C0 : a.C1;
+  int32_t *const *Ox = cur ? a.open_x1 : a.open_x0;
+  int32_t *const *Nx = cur ? a.open_x0 : a.open_x1;
   const ListRef next_open = {&ctl->open_ctr[cur ^ 1], cur ? a.open_v0 : a.open_v1,
-                             cur ? a.open_p0 : a.open_p1, cur ? a.open_i0 : a.open_i1};
-  const ListRef front = {&ctl->front_ctr[cur ^ 1], a.front_v, a.front_p, a.front_i};
+                             cur ? a.open_p0 : a.open_p1, cur ? a.open_i0 : a.open_i1,
+                             {Nx[0], Nx[1], Nx[2], Nx[3], Nx[4], Nx[5]}};
+  const ListRef front = {&ctl->front_ctr[cur ^ 1], a.front_v, a.front_p, a.front_i,
+                         {a.front_x[FX_OOFF], a.front_x[FX_D]}};
   SmemFused &S = sm.u.f;
   if (tid == 0) {
     S.fr.cnt = 0;
@@ -656,15 +680,28 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           S.thr[tid] = ld_relaxed(&a.ithr[s_now * I + ins]);
         }
         const GraphDev &G = graph_of<BATCH>(a, gi);
-        // everything the item's finish needs is fetched here, in one step
-        const int32_t yl = gy - sb;
-        const int32_t b0 = G.in_off[yl];
-        S.base[tid] = b0;
-        S.ideg[tid] = G.in_off[yl + 1] - b0;
-        S.odeg[tid] = G.out_off[yl + 1] - G.out_off[yl];
-        S.owm[tid] = G.out_wmin[yl];
+        // everything the item's finish needs: carried by a survivor's entry,
+        // or (first discovery, no payload) one vertex record with C = 0
+        int32_t xv[kOX];
+#pragma unroll
+        for (int k = 0; k < kOX; ++k) xv[k] = Ox[k][idx];
+        if (xv[OX_BASE] < 0) {
+          const int32_t yl = gy - sb;
+          const int4 rec = G.vrec[2 * yl];  // out_off, out_degree, in_off, in_degree
+          xv[OX_BASE] = rec.z;
+          xv[OX_IDEG] = rec.w;
+          xv[OX_OOFF] = rec.x;
+          xv[OX_ODEG] = rec.y;
+          xv[OX_OWM] = G.vrec[2 * yl + 1].x;
+          xv[OX_C] = 0;
+        }
+        S.base[tid] = xv[OX_BASE];
+        S.ideg[tid] = xv[OX_IDEG];
+        S.ooff[tid] = xv[OX_OOFF];
+        S.odeg[tid] = xv[OX_ODEG];
+        S.owm[tid] = xv[OX_OWM];
+        S.cy[tid] = xv[OX_C];
         S.dy[tid] = ld_relaxed(key_d(&a.D64[gy]));
-        S.cy[tid] = Cold[gy];
         S.sb[tid] = sb;
         S.gi[tid] = gi;
         S.inst[tid] = ins;
@@ -751,6 +788,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       int32_t gy = 0, fd = 0, od = 0, ins = 0;
       int32_t sv = V::INF, st = V::INF;  // a survivor's offers to the next minD / thr
       int32_t sdeg = 0;                  // in-degree of a finished item (statistics)
+      int32_t fx[kFX] = {0, 0}, ox[kOX] = {0, 0, 0, 0, 0, 0};  // payloads of the pushes
       if (idx < NO) {
         const uint32_t p0 = (uint32_t)S.pfx[tid], p1 = (uint32_t)S.pfx[tid + 1];
         const uint32_t fb = p0 / chunk, lb = (p1 - 1) / chunk;  // p1 > p0 always
@@ -802,11 +840,19 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
               Cnew[gy] = V::INF;  // fixed: drops out of every later bound step
               fd = S.odeg[tid];
               hf = true;
+              fx[FX_OOFF] = S.ooff[tid];
+              fx[FX_D] = Dy;
             } else {
               Cnew[gy] = Cn;
               // next round: minD >= md and D[y] <= Dy
               od = useful_in_edges_at<V>(G, S.base[tid], S.ideg[tid], md, Dy);
               ho = true;
+              ox[OX_BASE] = S.base[tid];
+              ox[OX_IDEG] = S.ideg[tid];
+              ox[OX_OOFF] = S.ooff[tid];
+              ox[OX_ODEG] = S.odeg[tid];
+              ox[OX_OWM] = S.owm[tid];
+              ox[OX_C] = Cn;
               const int32_t tn = V::add(Dy, S.owm[tid]);
               sv = Dy;
               st = tn;
@@ -824,15 +870,16 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
         const long long ws = wave_sum64(sdeg);
         if (lane_id() == 0 && ws) atomicAdd(&sm.n_scanned, (unsigned long long)ws);
       }
-      stage_push2(S.fr, hf, gy, fd, ins, front, S.op, ho, gy, od, ins, next_open, BATCH, sm);
+      stage_push2(S.fr, hf, gy, fd, ins, fx, front, S.op, ho, gy, od, ins, ox, next_open, BATCH,
+                  sm);
       if (pw.windows == 0) mark(a, r, 1, 7);
       k = wend;
       i += WIN;
       ++pw.windows;
     }
   }
-  stage_flush(S.fr, front.ctr, front.v, front.p, front.i, BATCH);
-  stage_flush(S.op, next_open.ctr, next_open.v, next_open.p, next_open.i, BATCH);
+  stage_flush(S.fr, front, BATCH);
+  stage_flush(S.op, next_open, BATCH);
   mark(a, r, 1, 8);
   if constexpr (!BATCH) {
     block_min2<RBS>(lnext, ltnext, sm.red);
@@ -1102,7 +1149,7 @@ __global__ void init_seed_kernel(RoundArgs a) {
   for (int b0 = 0; b0 < I; b0 += RBS) {
     const int i = b0 + threadIdx.x;
     uint32_t deg = 0;
-    int32_t gs = 0;
+    int32_t gs = 0, ooff = 0;
     if (i < I) {
       int32_t sb = 0, gi = 0, s = a.source;
       if constexpr (BATCH) {
@@ -1114,7 +1161,8 @@ __global__ void init_seed_kernel(RoundArgs a) {
       const GraphDev &G = graph_of<BATCH>(a, gi);
       if (G.rank) s = G.rank[s];  // the solver's id of the source
       gs = sb + s;
-      deg = (uint32_t)(G.out_off[s + 1] - G.out_off[s]);
+      ooff = G.out_off[s];
+      deg = (uint32_t)(G.out_off[s + 1] - ooff);
       a.D64[gs] = make_key(0, -1, false);
       a.C0[gs] = V::INF;
       a.C1[gs] = V::INF;
@@ -1124,6 +1172,8 @@ __global__ void init_seed_kernel(RoundArgs a) {
     if (i < I) {
       a.front_v[i] = gs;
       a.front_p[i] = (int32_t)(run + ex);
+      a.front_x[FX_OOFF][i] = ooff;
+      a.front_x[FX_D][i] = 0;
       if constexpr (BATCH) {
         a.front_i[i] = i;
         for (int s = 0; s < 3; ++s) {

@@ -45,10 +45,13 @@ __device__ __forceinline__ int32_t kmax(int32_t a, int32_t b) { return a > b ? a
 // vertex to the caller's vertex id, rank the reverse (all three null when
 // the numberings coincide).  The u_ arrays are the caller-numbered CSR/CSC
 // that the parent tie pass and the backward pass walk.
+// vrec: per solver vertex {out_off, out_degree, in_off, in_degree,
+// out_wmin, 0, 0, 0} (one 32-byte record).
 struct GraphDev {
   const int32_t *out_off, *out_dst, *out_w, *out_eid;
   const int32_t *in_off, *in_src, *in_w;
   const int32_t *out_wmin;
+  const int4 *vrec;
   const int32_t *vid, *rank;
   const int32_t *u_out_off, *u_out_dst;
   const int32_t *u_in_off, *u_in_src, *u_in_eid, *u_in_w;

@@ -30,6 +30,15 @@ enum PartSlot {
   kParts
 };
 
+// Payload words carried by the lists.  A frontier item (fixed last round)
+// carries its out-offset and final D; an open item pushed as a survivor
+// carries what its next bound step needs, so neither phase gathers them.
+// An open item pushed by relax (a first discovery) carries OX_BASE = -1:
+// the bound step then reads the vertex record, and its C is still 0 (C is
+// only ever raised on open vertices).
+enum { FX_OOFF = 0, FX_D, kFX };
+enum { OX_BASE = 0, OX_IDEG, OX_OOFF, OX_ODEG, OX_OWM, OX_C, kOX };
+
 // Control block of one persistent solve, in device memory.
 struct Ctl {
   unsigned long long front_ctr[2];  // by round parity: (items << 32) | out-degree sum
@@ -73,6 +82,8 @@ struct RoundArgs {
   int32_t *open_v0, *open_p0, *open_i0;
   int32_t *open_v1, *open_p1, *open_i1;
   int32_t *front_v, *front_p, *front_i;
+  int32_t *front_x[kFX];              // frontier payload words
+  int32_t *open_x0[kOX], *open_x1[kOX];  // open-list payload words, by parity
   Ctl *ctl;
   int32_t *imin, *ithr, *irounds;  // batch: [3][I], [3][I], [I]
   unsigned long long *iscanned;    // batch: [I][2] scanned in-edges, open visits
@@ -156,6 +167,7 @@ struct SolverCopy {
   int32_t *out_off, *out_dst, *out_w, *out_eid;
   int32_t *in_off, *in_src, *in_eid, *in_w;
   int32_t *out_wmin;
+  int32_t *vrec;  // 8 ints per vertex
 };
 size_t build_hist_entries(int32_t m);
 hipError_t launch_validate(int32_t n, int32_t m, bool f32, const int32_t *src,
@@ -179,6 +191,8 @@ hipError_t launch_renumber(int32_t n, int32_t m, int32_t dmax, const int32_t *ou
 hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t *out_off,
                            const int32_t *out_dst, const int32_t *out_w, const SolverCopy &c,
                            const BuildTemps &t, hipStream_t stream);
+// the per-vertex records of the copy (after its offsets and out_wmin)
+hipError_t launch_vrec(int32_t n, const SolverCopy &c, hipStream_t stream);
 // new weights (validated by the caller) into the CSR/CSC, out_wmin and the
 // copy's out-lists; the copy's in-lists are rebuilt by launch_in_lists
 hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,

@@ -97,7 +97,8 @@ class Graph:
         and in degree order also vid, rank and the renumbered out-lists."""
         c, n, m, vt = self.csr, self.n, self.m, self.value_dtype
         out = dict(in_off=self._view(c.s_in_off, n + 1), in_src=self._view(c.s_in_src, m),
-                   in_eid=self._view(c.s_in_eid, m), in_w=self._view(c.s_in_w, m, vt))
+                   in_eid=self._view(c.s_in_eid, m), in_w=self._view(c.s_in_w, m, vt),
+                   vrec=self._view(c.s_vrec, 8 * n).view(n, 8))
         if self.csr.order == SSSP_ORDER_DEGREE:
             out.update(vid=self._view(c.vid, n), rank=self._view(c.rank, n),
                        out_off=self._view(c.s_out_off, n + 1),

@@ -79,6 +79,15 @@ def check_solver_copy(G, n, src, dst, w):
         assert np.array_equal(S["vid"], vid) and np.array_equal(S["rank"], rank)
         sides["out"] = np.lexsort((eid, rank[head], rank[tail]))
         assert np.array_equal(bits(S["out_wmin"]), bits(wmin[vid]))
+    # vertex records: out offset and degree, in offset and degree, out_wmin
+    so = S["out_off"] if G.order == "degree" else O.out_off
+    vr = S["vrec"]
+    wmin_s = wmin[vid]
+    assert np.array_equal(vr[:, 0], so[:-1]) and np.array_equal(vr[:, 1], np.diff(so))
+    in_off_s = np.concatenate([[0], np.cumsum(np.bincount(rank[head], minlength=n))])
+    assert np.array_equal(vr[:, 2], in_off_s[:-1]) and np.array_equal(vr[:, 3], np.diff(in_off_s))
+    assert np.array_equal(vr[:, 4], bits(np.ascontiguousarray(wmin_s)))
+    assert not vr[:, 5:].any()
     for side, order in sides.items():
         key = rank[tail] if side == "out" else rank[head]
         nbr = rank[head] if side == "out" else rank[tail]

@@ -54,8 +54,8 @@ def test_strerror_and_sizes(sp):
     assert sp.sssp_build_csr_bytes(10, 10, sp.SSSP_I32, 3) == 0
     b = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, I)
     # CSR/CSC (2 offset arrays, 5 edge arrays, out_wmin) + the weight-ordered
-    # in-lists of the working copy (offsets, 3 edge arrays)
-    assert b >= 4 * (3 * 1001 + 8 * 5000 + 1000)
+    # in-lists of the working copy (offsets, 3 edge arrays) + 32-byte vertex records
+    assert b >= 4 * (3 * 1001 + 8 * 5000 + 1000) + 32 * 1000
     # degree order adds vid, rank, out_wmin (n), offsets (n+1), 3 edge arrays
     bd = sp.sssp_build_csr_bytes(1000, 5000, sp.SSSP_F32, D)
     assert bd >= b + 4 * (3 * 1000 + 1001 + 3 * 5000)
@@ -67,7 +67,7 @@ def _fake_csr(sp, n=10, m=20, dtype=0, w_max=5.0):
     c.n, c.m, c.dtype, c.w_max, c.order = n, m, dtype, w_max, sp.SSSP_ORDER_INPUT
     for f in ("out_off", "out_dst", "out_w", "in_off", "in_src", "in_eid", "in_w", "out_wmin",
               "s_out_off", "s_out_dst", "s_out_w", "s_in_off", "s_in_src", "s_in_eid", "s_in_w",
-              "s_out_wmin"):
+              "s_out_wmin", "s_vrec"):
         setattr(c, f, 0x1000)  # never dereferenced: every call below fails its host checks
     return c
 
