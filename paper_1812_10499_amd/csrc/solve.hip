@@ -49,7 +49,7 @@ constexpr int WIN = RBS;          // list items per window
 constexpr int CAP_R = RBS * EPT;  // relax staging capacity (>= one sub-chunk)
 constexpr int CAP_F = RBS;        // bound-and-fix staging capacity per list (>= one window)
 constexpr uint32_t CW_RELAX = 4;  // work units per frontier item (its loads and list entry)
-constexpr uint32_t CW_FUSED = 8;  // work units per open item (loads, decision, list entry)
+constexpr uint32_t CW_FUSED = 16; // work units per open item (loads, decision, list entry)
 
 // ----------------------------------------------------------- LDS layouts
 // LDS staging of list appends: vertex, local exclusive work prefix,
@@ -69,6 +69,8 @@ struct Stager {
 
 struct SmemRelax {
   int32_t pfx[WIN + 1];
+  int32_t epfx[WIN];  // edge prefix of the window's edge sub-ranges
+  int32_t epos[WIN];  // CSR position where an item's sub-range starts
   int32_t base[WIN];
   int32_t dx[WIN];
   int32_t sb[WIN];
@@ -508,7 +510,24 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
       __syncthreads();
       if (pw.windows == 0) mark(a, r, 0, 4);
       const uint32_t wend = uni(min((uint32_t)S.pfx[WIN], e1));
-      for (uint32_t cb = k; cb < wend; cb += RBS * EPT) {
+      // Each item's units are CW_RELAX of bookkeeping, then one per
+      // out-edge; lanes walk only the edges that fall in [k, wend).
+      uint64_t etot;
+      {
+        uint32_t ecnt = 0;
+        if (idx < NF) {
+          const uint32_t p0 = (uint32_t)S.pfx[tid] + CW_RELAX, p1 = (uint32_t)S.pfx[tid + 1];
+          const uint32_t lo = max(p0, k), hi = min(p1, wend);
+          if (hi > lo) {
+            ecnt = hi - lo;
+            S.epos[tid] = S.base[tid] + (int32_t)(lo - p0);
+          }
+        }
+        S.epfx[tid] = (int32_t)block_excl_scan64<RBS>((uint64_t)ecnt, sm.scan, &etot);
+        __syncthreads();
+      }
+      const uint32_t ET = uni((uint32_t)etot);
+      for (uint32_t cb = 0; cb < ET; cb += RBS * EPT) {
         // gathers for all EPT edges are issued before any result is used
         int it[EPT];
         int32_t pos[EPT], y[EPT], wt[EPT], cand[EPT], gy[EPT], eid[EPT];
@@ -517,11 +536,9 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           const uint32_t q = cb + (uint32_t)(j * RBS + tid);
-          const bool inr = q < wend;
-          it[j] = inr ? window_item(S.pfx, q) : 0;
-          const int32_t off = (int32_t)(q - (uint32_t)S.pfx[it[j]]) - (int32_t)CW_RELAX;
-          val[j] = inr && off >= 0;  // the first CW_RELAX units of an item carry no edge
-          pos[j] = S.base[it[j]] + off;
+          val[j] = q < ET;
+          it[j] = val[j] ? window_item(S.epfx, q) : 0;
+          pos[j] = S.epos[it[j]] + (int32_t)(q - (uint32_t)S.epfx[it[j]]);
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
