@@ -312,6 +312,7 @@ sssp_status trace_begin(DevWS &w, RoundArgs &a, hipStream_t stream) {
   a.trace_blk_rounds = kTraceBlkRounds;
   a.marks = a.trace + cnt + bcnt;
   a.mark_rounds = kTraceRounds;
+  a.mark_block = env_flag("SSSP_MARK_BLOCK", 0);
   HIPCHK(hipMemsetAsync(a.trace, 0, (cnt + bcnt + mcnt) * sizeof(long long), stream));
   return SSSP_OK;
 }

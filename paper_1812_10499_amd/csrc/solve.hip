@@ -200,9 +200,10 @@ __device__ __forceinline__ uint32_t uni(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v);
 }
 
-// Round-trace checkpoint k of a phase: block 0's wall-clock (when enabled).
+// Round-trace checkpoint k of a phase: one chosen block's wall-clock (when
+// enabled).
 __device__ __forceinline__ void mark(const RoundArgs &a, int r, int phase, int k) {
-  if (a.marks && blockIdx.x == 0 && threadIdx.x == 0 && r <= a.mark_rounds)
+  if (a.marks && blockIdx.x == (uint32_t)a.mark_block && threadIdx.x == 0 && r <= a.mark_rounds)
     a.marks[((size_t)(r - 1) * 2 + phase) * kMarks + k] = (long long)wall_clock64();
 }
 
@@ -224,12 +225,21 @@ __device__ __forceinline__ int32_t *part_slot(const RoundArgs &a, int k) {
   return a.part + (size_t)k * kMaxBlocks;
 }
 
-// min over all per-block partial slots of p0 and p1
+// This round's minD and thr: minima over all per-block partial slots of the
+// survivors (last bound step) and the candidates (this relax), in one pass.
 template <class V>
-__device__ int32_t reduce_parts(const int32_t *p0, const int32_t *p1, SmemAll &sm) {
-  int32_t m = V::INF;
-  for (uint32_t b = threadIdx.x; b < gridDim.x; b += RBS) m = kmin(m, kmin(p0[b], p1[b]));
-  return block_min<RBS>(m, sm.red);
+__device__ void reduce_parts(const RoundArgs &a, int cur, int32_t &mind, int32_t &thr,
+                             SmemAll &sm) {
+  const int32_t *s0 = part_slot(a, P_SURV0 + cur), *c0 = part_slot(a, P_CAND0 + cur);
+  const int32_t *s1 = part_slot(a, P_TSURV0 + cur), *c1 = part_slot(a, P_TCAND0 + cur);
+  int32_t m = V::INF, t = V::INF;
+  for (uint32_t b = threadIdx.x; b < gridDim.x; b += RBS) {
+    m = kmin(m, kmin(s0[b], c0[b]));
+    t = kmin(t, kmin(s1[b], c1[b]));
+  }
+  block_min2<RBS>(m, t, sm.red);
+  mind = m;
+  thr = t;
 }
 
 // A block's partial.  With k active blocks, block b also clears the slots
@@ -432,11 +442,43 @@ __device__ __forceinline__ int32_t useful_in_edges_at(const GraphDev &G, int32_t
   return lo;
 }
 
+// Work of a vertex y first discovered in this round's relax step: the
+// weight prefix above, cut after the first of y's kProbe lightest in-edges
+// whose tail v has C[v] <= md in the C the bound step will read (so v is not
+// fixed: fixed vertices carry C = INF).  With minD >= md that edge's term
+// max(C[v], minD) + w is minD + w, and every later edge of the list is at
+// least as heavy, so its term is no smaller: m_y is decided by the edges up
+// to the probe hit, and the probe's own weights give the prefix among them
+// (no search).  Cold must be stable for the whole relax step (the bound step
+// writes the other C buffer).
+constexpr int kProbe = 8;
+
 template <class V>
-__device__ __forceinline__ int32_t useful_in_edges(const GraphDev &G, int32_t y, int32_t md,
-                                                   int32_t dy) {
+__device__ __forceinline__ int32_t discovery_in_edges(const GraphDev &G, const int32_t *Cold,
+                                                      int32_t y, int32_t md, int32_t dy) {
   const int32_t b = G.in_off[y];
-  return useful_in_edges_at<V>(G, b, G.in_off[y + 1] - b, md, dy);
+  const int32_t deg = G.in_off[y + 1] - b;
+  if (deg <= 16) return deg;
+  int32_t c[kProbe], wv[kProbe];
+#pragma unroll
+  for (int l = 0; l < kProbe; ++l) {
+    c[l] = G.in_src[b + l];
+    wv[l] = G.in_w[b + l];
+  }
+#pragma unroll
+  for (int l = 0; l < kProbe; ++l) c[l] = Cold[c[l]];
+  int hit = kProbe;
+#pragma unroll
+  for (int l = kProbe - 1; l >= 0; --l)
+    if (c[l] <= md) hit = l;
+  if (hit < kProbe) {
+    // the edges that pass the weight test form a prefix of the list
+    int32_t p = 0;
+#pragma unroll
+    for (int l = 0; l < kProbe; ++l) p += (l <= hit && V::add(md, wv[l]) < dy) ? 1 : 0;
+    return p;
+  }
+  return useful_in_edges_at<V>(G, b, deg, md, dy);
 }
 
 // ================================================================== relax
@@ -455,6 +497,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
                          cur ? a.open_p1 : a.open_p0, cur ? a.open_i1 : a.open_i0,
                          {cur ? a.open_x1[OX_BASE] : a.open_x0[OX_BASE]}};
   int32_t *Cnew = cur ? a.C0 : a.C1;
+  const int32_t *Cold = cur ? a.C1 : a.C0;  // what this round's bound step reads
   if constexpr (BATCH) {
     // per-instance round count: the last round with a non-empty frontier
     for (int i = (int)(pc.vbid * RBS) + tid; i < NF; i += (int)(pc.vnb * RBS))
@@ -609,7 +652,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
                 }
               }
               nv[j] = gy[j];
-              nd[j] = useful_in_edges<V>(G, y[j], md, cand[j]);
+              nd[j] = discovery_in_edges<V>(G, Cold + S.sb[it[j]], y[j], md, cand[j]);
               ni[j] = S.inst[it[j]];
             }
           }
@@ -1088,10 +1131,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           mind_all = kmin(sm.solo_cand_min, sm.solo_surv_min);
           thr_all = kmin(sm.solo_cand_thr, sm.solo_surv_thr);
         } else {
-          mind_all = reduce_parts<V>(part_slot(a, P_SURV0 + cur), part_slot(a, P_CAND0 + cur),
-                                     sm);
-          thr_all = reduce_parts<V>(part_slot(a, P_TSURV0 + cur),
-                                    part_slot(a, P_TCAND0 + cur), sm);
+          reduce_parts<V>(a, cur, mind_all, thr_all, sm);
         }
         mind_all = uni(mind_all);
         thr_all = uni(thr_all);

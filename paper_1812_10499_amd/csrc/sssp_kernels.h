@@ -101,6 +101,7 @@ struct RoundArgs {
   // phase, [round][2 phases][kMarks]
   long long *marks;
   int32_t mark_rounds;
+  int32_t mark_block;  // the block whose checkpoints are recorded
   unsigned int *flags;       // grid barrier flags, kMaxBlocks * kFlagStride
   int32_t *part;             // per-block partial minima, kParts * kMaxBlocks
   int32_t solo_edges;        // phases with at most this many edges run on block 0 alone
