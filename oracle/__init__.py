@@ -84,14 +84,18 @@ def _call(name, *args):
     return f(*args)
 
 
-def dijkstra(n, src, dst, w, source):
-    """Return (cost, settles): binary-heap Dijkstra (Fig. 1)."""
+def dijkstra(n, src, dst, w, source, target=None):
+    """Return (cost, settles): binary-heap Dijkstra (Fig. 1).  With a target,
+    it stops once the target leaves the heap; settles counts the removals up
+    to and including it."""
     k, w = _kind(w)
     src, dst = _i32(src), _i32(dst)
     cost = np.empty(n, dtype=w.dtype)
     settles = ctypes.c_int64(0)
-    rc = _call("oracle_dijkstra_" + k, ctypes.c_int32(n), ctypes.c_int64(len(src)), _p(src),
-               _p(dst), _p(w), ctypes.c_int32(source), _p(cost), ctypes.byref(settles))
+    t = -1 if target is None else int(target)
+    rc = _call("oracle_dijkstra_target_" + k, ctypes.c_int32(n), ctypes.c_int64(len(src)),
+               _p(src), _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int32(t), _p(cost),
+               ctypes.byref(settles))
     if rc != 0:
         raise ValueError("oracle_dijkstra failed: %d" % rc)
     return cost, settles.value
@@ -184,22 +188,25 @@ def pred(g: CSR, w, source, cost):
 MODE_ADOPTED, MODE_SCOPE_ALL, MODE_LITERAL_FIG5 = 0, 1, 2
 
 
-def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None):
+def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=None):
     """Run the round simulator.  Returns dict(cost, rounds, fixed_per_round,
-    relaxed_edges, scanned_in_edges, violations)."""
+    relaxed_edges, scanned_in_edges, settled, violations).  With a target
+    (modes 0 and 1) the rounds stop once the target is fixed."""
     k, w = _kind(w)
     src, dst = _i32(src), _i32(dst)
     cost = np.empty(n, dtype=w.dtype)
     cap = 4 * n + 8
     fpr = np.zeros(cap, dtype=np.int64)
-    stats = np.zeros(2, dtype=np.int64)
+    stats = np.zeros(3, dtype=np.int64)
+    t = -1 if target is None else int(target)
     rounds = ctypes.c_int64(0)
     viol = ctypes.c_int64(0)
     tc = None
     if true_cost is not None:
         tc = np.ascontiguousarray(true_cost, dtype=w.dtype)
     rc = _call("oracle_round_sim_" + k, ctypes.c_int32(n), ctypes.c_int64(len(src)), _p(src),
-               _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int(mode), _p(cost),
+               _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int32(t), ctypes.c_int(mode),
+               _p(cost),
                ctypes.byref(rounds), _p(fpr), ctypes.c_int64(cap), _p(stats),
                _p(tc) if tc is not None else None, ctypes.byref(viol))
     if rc != 0:
@@ -207,7 +214,7 @@ def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None):
     r = rounds.value
     return dict(cost=cost, rounds=r, fixed_per_round=fpr[:r].copy(),
                 relaxed_edges=int(stats[0]), scanned_in_edges=int(stats[1]),
-                violations=viol.value)
+                settled=int(stats[2]), violations=viol.value)
 
 
 def grad(g: CSR, sources, preds, gcoef):

@@ -436,3 +436,55 @@ def test_generators_deterministic_and_in_range():
     assert len(set(d.sources.tolist())) == 5 and gco.shape == (5, 256)
     assert d.w.min() >= 0.5 and d.w.max() <= 1.5
     assert abs(float(gen.normal_f32(1, 100000).std()) - 1.0) < 0.02
+
+
+def test_target_closed_forms():
+    """Single-destination stop (Section I).  On a path 0 -> 1 -> ... -> k,
+    vertex j is fixed in round j, so the rounds stop after j of them with
+    0..j exact and j + 1 still undiscovered; the source as target stops
+    before round 1.  Dijkstra removes 0..j from its heap."""
+    k = 12
+    src = np.arange(k, dtype=np.int32)
+    dst = src + 1
+    w = np.full(k, 5, np.int32)
+    for j in range(k + 1):
+        r = oracle.round_sim(k + 1, src, dst, w, 0, target=j)
+        assert r["rounds"] == j and r["settled"] == j + 1 and r["relaxed_edges"] == j
+        assert r["cost"][: j + 1].tolist() == [5 * i for i in range(j + 1)]
+        assert all(x == I32_INF for x in r["cost"][j + 1:])
+        c, pops = oracle.dijkstra(k + 1, src, dst, w, 0, target=j)
+        assert pops == j + 1 and c[j] == 5 * j
+    # star: every leaf is fixed in round 1
+    src = np.zeros(9, np.int32)
+    dst = np.arange(1, 10, dtype=np.int32)
+    r = oracle.round_sim(10, src, dst, np.arange(9, 0, -1).astype(np.int32), 0, target=4)
+    assert r["rounds"] == 1 and r["settled"] == 10
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_target_stop_against_full_solve(dtype):
+    """The stopped rounds are a prefix of the full ones; the target's cost is
+    exact and every other entry is an upper bound; an unreachable target
+    runs the whole solve."""
+    rng = np.random.default_rng(16)
+    inf = _inf(dtype)
+    for _ in range(300):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 30)))
+        c, settles = oracle.dijkstra(n, src, dst, w, s)
+        full = oracle.round_sim(n, src, dst, w, s)
+        t = int(rng.integers(0, n))
+        r = oracle.round_sim(n, src, dst, w, s, target=t)
+        ct, pops = oracle.dijkstra(n, src, dst, w, s, target=t)
+        assert r["cost"][t] == c[t] and ct[t] == c[t]
+        assert np.all(r["cost"] >= c)
+        assert pops <= settles
+        if c[t] == inf:
+            assert r["rounds"] == full["rounds"] and np.array_equal(r["cost"], full["cost"])
+            assert r["settled"] == full["settled"] == settles
+            continue
+        assert (r["rounds"] == 0) == (t == s)
+        assert r["rounds"] <= full["rounds"]
+        assert r["fixed_per_round"].tolist() == full["fixed_per_round"][: r["rounds"]].tolist()
+        assert r["settled"] == 1 + sum(r["fixed_per_round"])
+        assert np.count_nonzero((r["cost"] == c) & (c != inf)) >= r["settled"]
+        assert r["relaxed_edges"] <= full["relaxed_edges"]
