@@ -199,6 +199,27 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
                        sssp_stats *stats, void *stream);
 
 /*
+ * Single-target early exit (Section I: a shortest path to one destination
+ * can be known as soon as that vertex's bounds meet, before Dijkstra's
+ * algorithm would settle it).  The rounds of sssp_solve run until the round
+ * whose step (D) fixes `target` (or, if the target is unreachable, to the
+ * end); the frontier that round produced is not relaxed.
+ *   target in [0, n) (caller's id); target == source stops before round 1.
+ *   cost[n] (device): D when the rounds stop: the exact cost for every
+ *           vertex fixed by then (the target among them), an upper bound
+ *           for the other discovered vertices, INF for the rest.
+ *   stats (host, nullable, synchronizes): rounds = rounds to the target,
+ *           settled = vertices fixed when the rounds stop, relaxed_edges and
+ *           scanned_in_edges = the work of those rounds.
+ * No parent pointers: the parent rule needs every in-edge of a vertex
+ * offered from a fixed tail, which a stopped solve has not done (call
+ * sssp_solve for them).  Errors as for sssp_solve; a target outside [0, n)
+ * is SSSP_ERR_ARG.
+ */
+sssp_status sssp_solve_target(const sssp_csr *g, int32_t source, int32_t target, void *cost,
+                              sssp_stats *stats, void *stream);
+
+/*
  * Many independent solves in one persistent launch.
  *   graphs[num_graphs] (host array of built graphs, all of one dtype)
  *   inst_graph[num_inst], inst_source[num_inst] (host): instance i solves

@@ -12,6 +12,7 @@ from ._abi import (  # noqa: F401
     SSSP_ORDER_AUTO, SSSP_ORDER_DEGREE, SSSP_ORDER_INPUT, Csr,
     SSSPError, Stats, lib, sssp_backward, sssp_profile_enable, sssp_profile_read,
     sssp_build_csr, sssp_build_csr_bytes, sssp_release_workspace, sssp_set_weights, sssp_solve,
-    sssp_solve_batch, sssp_strerror)
+    sssp_solve_batch, sssp_solve_target, sssp_strerror)
 from .graph import (  # noqa: F401
-    I32_INF, Graph, SSSPFunction, backward, batch_layout, shortest_paths, solve, solve_batch)
+    I32_INF, Graph, SSSPFunction, backward, batch_layout, shortest_paths, solve, solve_batch,
+    solve_target)

@@ -22,7 +22,7 @@ SSSP_ORDER_AUTO, SSSP_ORDER_INPUT, SSSP_ORDER_DEGREE = 0, 1, 2
  SSSP_ERR_HIP, SSSP_ERR_INTERNAL) = range(8)
 
 EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_solve",
-           "sssp_solve_batch", "sssp_backward", "sssp_release_workspace", "sssp_strerror",
+           "sssp_solve_target", "sssp_solve_batch", "sssp_backward", "sssp_release_workspace", "sssp_strerror",
            "sssp_profile_enable", "sssp_profile_read")
 
 
@@ -78,6 +78,9 @@ def lib():
         L.sssp_set_weights.restype = ctypes.c_int
         L.sssp_solve.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, ctypes.POINTER(Stats), vp]
         L.sssp_solve.restype = ctypes.c_int
+        L.sssp_solve_target.argtypes = [ctypes.POINTER(Csr), i32, i32, vp,
+                                        ctypes.POINTER(Stats), vp]
+        L.sssp_solve_target.restype = ctypes.c_int
         L.sssp_solve_batch.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, i32, vp, vp,
                                        ctypes.POINTER(Stats), vp]
         L.sssp_solve_batch.restype = ctypes.c_int
@@ -129,6 +132,12 @@ def sssp_solve(g: Csr, source, cost, pred, stats, stream):
     _check(lib().sssp_solve(ctypes.byref(g), source, cost, pred,
                             ctypes.byref(stats) if stats is not None else None, stream),
            "sssp_solve")
+
+
+def sssp_solve_target(g: Csr, source, target, cost, stats, stream):
+    _check(lib().sssp_solve_target(ctypes.byref(g), source, target, cost,
+                                   ctypes.byref(stats) if stats is not None else None, stream),
+           "sssp_solve_target")
 
 
 def sssp_solve_batch(graphs, inst_graph, inst_source, cost, pred, stats, stream):

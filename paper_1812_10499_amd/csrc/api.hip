@@ -593,9 +593,14 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
   return SSSP_OK;
 }
 
-sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
-                       sssp_stats *stats, void *stream_) {
+}  // extern "C"
+
+// One solve from `source`; with target >= 0 the rounds stop once the target
+// is fixed (no parent pointers then).
+static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, void *cost,
+                             int32_t *pred, sssp_stats *stats, void *stream_) {
   if (!csr_ok(g) || !cost || source < 0 || source >= g->n) return SSSP_ERR_ARG;
+  if (target >= g->n || (target >= 0 && pred)) return SSSP_ERR_ARG;
   if (overflow_risk(g)) return SSSP_ERR_OVERFLOW;
   hipStream_t stream = (hipStream_t)stream_;
   const bool f32 = g->dtype == SSSP_F32;
@@ -614,6 +619,7 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
   a.D = (int32_t *)cost;
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
+  a.target = target;
   if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
   LaunchGeom geo;
   if ((s = geometry(ws, f32, false, &geo))) return s;
@@ -641,6 +647,19 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
   }
   HIPCHK(hipEventRecord(ws.last, stream));
   return SSSP_OK;
+}
+
+extern "C" {
+
+sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
+                       sssp_stats *stats, void *stream) {
+  return solve_one(g, source, -1, cost, pred, stats, stream);
+}
+
+sssp_status sssp_solve_target(const sssp_csr *g, int32_t source, int32_t target, void *cost,
+                              sssp_stats *stats, void *stream) {
+  if (target < 0) return SSSP_ERR_ARG;
+  return solve_one(g, source, target, cost, nullptr, stats, stream);
 }
 
 sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
@@ -677,6 +696,7 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   a.num_inst = num_inst;
   a.total = (int32_t)total;
   a.max_rounds = max_n + 1;
+  a.target = -1;
   a.D = (int32_t *)cost;
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);

@@ -211,6 +211,7 @@ __device__ __forceinline__ void mark(const RoundArgs &a, int r, int phase, int k
 struct PhaseCtx {
   uint32_t vnb, vbid;
   bool solo;
+  int32_t target;  // single-target solve: the target's solver id, else -1
 };
 
 // What a block's share of a phase was (for the round trace).
@@ -898,6 +899,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             }
             if (Cn >= Dy || Dy <= th) {
               Cnew[gy] = V::INF;  // fixed: drops out of every later bound step
+              if (gy == pc.target) ctl->target_hit = 1;
               fd = S.odeg[tid];
               hf = true;
               fx[FX_OOFF] = S.ooff[tid];
@@ -1032,6 +1034,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   int r = 1, phase = 0;    // phase 0: relax, 1: bound-and-fix
   uint32_t act = nb;       // active blocks
   int32_t md_prev = 0;     // the last minD this block computed (0 before round 1)
+  const int32_t tgt = (!BATCH && a.target >= 0) ? uni(ld_relaxed(&ctl->target_id)) : -1;
   if (tid == 0) {
     sm.n_settled = sm.n_relaxed = sm.n_open = sm.n_solo = 0;
     sm.n_scanned = 0ull;
@@ -1047,13 +1050,16 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     const int N = uni((int)(ctr >> 32));
     const uint32_t E = uni((uint32_t)(ctr & 0xffffffffull));
     if (N >= 0) mark(a, r, phase, 1);  // the counter has arrived
-    // termination: the relax left nothing open, or the watchdog (rounds
-    // never exceed the reachable count)
+    // termination: the relax left nothing open, the target has been fixed
+    // (single-target solve: the frontier it joined is not relaxed), or the
+    // watchdog (rounds never exceed the reachable count)
     const bool watchdog = phase == 0 && r > a.max_rounds;
-    if (watchdog || (phase == 1 && N == 0)) {
+    const bool reached = phase == 0 && tgt >= 0 && uni(ld_relaxed(&ctl->target_hit)) != 0;
+    if (watchdog || reached || (phase == 1 && N == 0)) {
       if (bid == 0 && tid == 0) {
         if (watchdog) ctl->status = 7;
-        ctl->rounds = watchdog ? a.max_rounds : r;
+        if (reached) sm.n_settled += N;  // the last frontier is fixed too
+        ctl->rounds = watchdog ? a.max_rounds : (reached ? r - 1 : r);
       }
       if (act < nb && bid == 0) wake_parked(ctl, epoch, r, phase, 1, act, aep);
       break;
@@ -1072,7 +1078,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
       act = want;
     }
     const bool solo = act == 1;
-    const PhaseCtx pc = {act, bid, solo};
+    const PhaseCtx pc = {act, bid, solo, tgt};
     long long *tr = (a.trace && r <= a.trace_rounds) ? a.trace + (size_t)(r - 1) * kTraceFields
                                                       : nullptr;
     long long *tb = (a.trace_blk && r <= a.trace_blk_rounds)
@@ -1218,6 +1224,12 @@ __global__ void init_seed_kernel(RoundArgs a) {
       const GraphDev &G = graph_of<BATCH>(a, gi);
       if (G.rank) s = G.rank[s];  // the solver's id of the source
       gs = sb + s;
+      if constexpr (!BATCH) {
+        int32_t t = a.target;
+        if (t >= 0 && G.rank) t = G.rank[t];
+        a.ctl->target_id = t;
+        a.ctl->target_hit = (t >= 0 && t == s) ? 1 : 0;  // the source is fixed at the start
+      }
       ooff = G.out_off[s];
       deg = (uint32_t)(G.out_off[s + 1] - ooff);
       a.D64[gs] = make_key(0, -1, false);

@@ -55,6 +55,9 @@ struct Ctl {
   unsigned int resume_aep;
   long long settled, relaxed, scanned, open_visits;
   long long solo_phases;  // phases run by block 0 alone
+  // single-target solve: the target's solver id (-1: none) and whether a
+  // bound step (or the seed) has fixed it
+  int32_t target_id, target_hit;
 };
 
 // Optional event pair recorded around the persistent kernel launch.
@@ -97,7 +100,7 @@ struct RoundArgs {
   // its phase end, the list windows it walked, its first list item and the
   // work units of its chunk
   long long *trace_blk;
-  // optional checkpoints: block 0's wall-clock at fixed points inside each
+  // optional checkpoints: one block's wall-clock at fixed points inside each
   // phase, [round][2 phases][kMarks]
   long long *marks;
   int32_t mark_rounds;
@@ -106,6 +109,7 @@ struct RoundArgs {
   int32_t *part;             // per-block partial minima, kParts * kMaxBlocks
   int32_t solo_edges;        // phases with at most this many edges run on block 0 alone
   int32_t block_units;       // otherwise: about this many work units per active block
+  int32_t target;            // single solve: stop once this vertex (caller's id) is fixed, or -1
 };
 
 // Trace record of one round: wall-clock (100 MHz) at the relax start, block

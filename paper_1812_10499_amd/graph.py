@@ -125,6 +125,15 @@ def solve(g: Graph, source: int, with_pred: bool = True, with_stats: bool = Fals
     return cost, pred, (st.as_dict() if st is not None else None)
 
 
+def solve_target(g: Graph, source: int, target: int, with_stats: bool = False):
+    """Rounds until `target` is fixed.  Returns (cost[n], stats dict or None):
+    cost is exact for every vertex fixed by then, the target among them."""
+    cost = torch.empty(g.n, dtype=g.value_dtype, device=g.device)
+    st = Stats() if with_stats else None
+    _abi.sssp_solve_target(g.csr, int(source), int(target), cost.data_ptr(), st, _stream())
+    return cost, (st.as_dict() if st is not None else None)
+
+
 def batch_layout(graphs: Sequence[Graph], inst_graph: Sequence[int]):
     bases, b = [], 0
     for gi in inst_graph:

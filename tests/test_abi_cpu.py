@@ -31,7 +31,8 @@ def declared_functions():
 def test_header_declares_the_abi():
     names = declared_functions()
     assert names == sorted(["sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights",
-                            "sssp_solve", "sssp_solve_batch", "sssp_backward",
+                            "sssp_solve", "sssp_solve_target", "sssp_solve_batch",
+                            "sssp_backward",
                             "sssp_release_workspace", "sssp_strerror",
                             "sssp_profile_enable", "sssp_profile_read"])
 
