@@ -74,6 +74,24 @@ typedef enum {
 typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 } sssp_order;
 
 /*
+ * Scope of the lower-bound step (C) of a round: the non-fixed vertices
+ * whose C it raises.  No result changes (costs, parents); the number of
+ * rounds and the work per round do.
+ *   SSSP_SCOPE_OPEN  the discovered vertices only (D < INF); undiscovered
+ *                    vertices keep C = 0
+ *   SSSP_SCOPE_ALL   every non-fixed vertex, as step 4 of SP_4 (Section VI,
+ *                    Fig. 6) reads: an undiscovered y gets
+ *                    C'[y] = max(C[y], minD, m_y), m_y over all its
+ *                    in-edges; unreachable vertices reach C = INF and stop
+ *                    holding their out-neighbours' bounds down
+ *   SSSP_SCOPE_AUTO  ALL for graphs in degree order (skewed degrees), else
+ *                    OPEN
+ * Single solves (sssp_solve, sssp_solve_target) honour the graph's scope;
+ * sssp_solve_batch always runs OPEN.
+ */
+typedef enum { SSSP_SCOPE_AUTO = 0, SSSP_SCOPE_OPEN = 1, SSSP_SCOPE_ALL = 2 } sssp_scope;
+
+/*
  * A built graph: CSR by tail plus CSC by head (the incoming-edge access the
  * method assumes, Section I).  All arrays are device arrays in the caller's
  * build buffer.
@@ -85,6 +103,8 @@ typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 
  *                 outWeight array of SP_3 and SP_4, Figs. 5 and 6)
  *   w_max         largest weight (filled by the builder; used for the
  *                 int32 overflow precondition)
+ *   scope         sssp_scope of the single solves on this graph (the
+ *                 builder sets SSSP_SCOPE_AUTO; the caller may change it)
  * The solver's working copy.  Always: in-lists ordered by weight, so that
  * the in-edges a lower-bound step needs (minD + w < D[y]) form a prefix:
  *   s_in_off[n+1], s_in_src[m] (solver ids), s_in_eid[m], s_in_w[m]
@@ -107,6 +127,7 @@ typedef struct {
   int32_t m;
   int32_t dtype; /* sssp_dtype */
   int32_t order; /* sssp_order the builder applied: INPUT or DEGREE */
+  int32_t scope; /* sssp_scope of single solves */
   const int32_t *out_off;
   const int32_t *out_dst;
   const void *out_w;

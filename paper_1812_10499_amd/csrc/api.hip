@@ -23,7 +23,7 @@ enum Slot {
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
-  S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1,
+  S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1, S_LV0, S_LV1,
   NSLOTS
 };
 
@@ -147,6 +147,7 @@ sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
 
 bool csr_ok(const sssp_csr *g) {
   if (!(g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
+        g->scope >= SSSP_SCOPE_AUTO && g->scope <= SSSP_SCOPE_ALL &&
         g->out_off && g->in_off && g->out_wmin && g->s_out_off && g->s_in_off &&
         g->s_out_wmin && g->s_vrec &&
         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
@@ -155,6 +156,9 @@ bool csr_ok(const sssp_csr *g) {
   if (g->order == SSSP_ORDER_INPUT) return true;
   return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && (g->m == 0 || g->s_out_eid);
 }
+
+// SSSP_SCOPE_AUTO: scope ALL on graphs the builder put in degree order.
+bool effective_auto_all(const sssp_csr *g) { return g->order == SSSP_ORDER_DEGREE; }
 
 bool overflow_risk(const sssp_csr *g) {
   if (g->dtype != SSSP_I32) return false;
@@ -282,6 +286,10 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
   if ((s = ws_arr(w, S_DEGEN, 2 * T, &a.degen))) return s;
   if ((s = ws_arr(w, S_LVL, T, &a.lvl))) return s;
   if ((s = ws_arr(w, S_FLAG, T, &a.flag))) return s;
+  if (a.scope_all) {
+    if ((s = ws_arr(w, S_LV0, T, &a.live_v0))) return s;
+    if ((s = ws_arr(w, S_LV1, T, &a.live_v1))) return s;
+  }
   if (batch) {
     if ((s = ws_arr(w, S_OI0, T, &a.open_i0))) return s;
     if ((s = ws_arr(w, S_OI1, T, &a.open_i1))) return s;
@@ -478,6 +486,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->m = m;
   out->dtype = dtype;
   out->order = SSSP_ORDER_INPUT;
+  out->scope = SSSP_SCOPE_AUTO;
   out->out_off = out_off;
   out->out_dst = out_dst;
   out->out_w = out_w;
@@ -620,6 +629,8 @@ static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, 
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
   a.target = target;
+  a.scope_all = g->scope == SSSP_SCOPE_ALL ||
+                (g->scope == SSSP_SCOPE_AUTO && effective_auto_all(g));
   if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
   LaunchGeom geo;
   if ((s = geometry(ws, f32, false, &geo))) return s;

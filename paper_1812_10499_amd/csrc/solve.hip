@@ -50,6 +50,8 @@ constexpr int CAP_R = RBS * EPT;  // relax staging capacity (>= one sub-chunk)
 constexpr int CAP_F = RBS;        // bound-and-fix staging capacity per list (>= one window)
 constexpr uint32_t CW_RELAX = 4;  // work units per frontier item (its loads and list entry)
 constexpr uint32_t CW_FUSED = 16; // work units per open item (loads, decision, list entry)
+constexpr uint32_t CW_LIVE = 8;   // work units per live undiscovered vertex (scope ALL)
+constexpr int CAP_L = 8 * RBS;    // live-list staging capacity
 
 // ----------------------------------------------------------- LDS layouts
 // LDS staging of list appends: vertex, local exclusive work prefix,
@@ -100,16 +102,25 @@ struct SmemFused {
   Stager<CAP_F, kOX> op;
 };
 
+// The live pass of a bound step runs after the open items' stagers are
+// flushed, so it reuses their LDS.
+struct SmemLive {
+  int32_t v[CAP_L];  // staged survivors
+  int32_t cnt;
+  int32_t base;
+};
+
 struct SmemAll {
   union {
     SmemRelax r;
     SmemFused f;
+    SmemLive l;
   } u;
   uint64_t scan[2 * (RBS / SSSP_WAVE + 1)];
   int32_t red[2 * (RBS / SSSP_WAVE)];
   int32_t tmax;
   // block 0, thread 0: the solve's counters, written out at the end
-  long long n_settled, n_relaxed, n_open, n_solo;
+  long long n_settled, n_relaxed, n_open, n_solo, n_bound;
   unsigned long long n_scanned;  // this block's share of the scanned in-edge count
   // single solve: minima a one-block phase produced, and their rounds
   int32_t solo_cand_min, solo_cand_thr, solo_surv_min, solo_surv_thr;
@@ -683,10 +694,120 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
   mark(a, r, 0, 7);
 }
 
+// ================================================ live pass (C scope ALL)
+// Step (C) for the undiscovered vertices (SP_4's step-4 scope, Section VI):
+// C'[y] = max(C[y], minD, m_y), m_y over all in-edges (no in-neighbour of
+// an undiscovered vertex is fixed: fixed tails were relaxed), reading the C
+// of the round start (Cold) and writing Cnew.  The round's live list holds
+// the undiscovered vertices whose C may still be finite (round 1: every
+// vertex, by index).  Each thread takes one vertex:
+//   discovered since (D < INF): dropped, it is an open item now;
+//   C = INF: C' = INF, dropped (it was kept one round so that both C
+//     buffers hold INF; an undiscovered vertex with C = INF is unreachable);
+//   else its weight-ordered in-list is scanned four edges at a time until
+//     minD + w of the last edge read reaches the running minimum (no later,
+//     heavier edge can lower it), and the vertex is kept.
+// The method's scanned count takes every undiscovered vertex's whole
+// in-degree each round; dropped unreachable ones are settled at the end
+// from dead_deg and dead_deg_r.
+template <class V>
+__device__ void live_pass(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NL,
+                          int32_t md, const int32_t *Cold, int32_t *Cnew) {
+  const int tid = threadIdx.x;
+  const int cur = r & 1;
+  SmemLive &L = sm.u.l;
+  const int32_t *Lv = cur ? a.live_v1 : a.live_v0;
+  int32_t *Ln = cur ? a.live_v0 : a.live_v1;
+  unsigned long long *lctr = &a.ctl->live_ctr[cur ^ 1];
+  const GraphDev &G = a.g;
+  if (tid == 0) L.cnt = 0;
+  __syncthreads();
+  const uint32_t chunk = chunk_of((uint32_t)NL, pc.vnb);
+  const uint32_t l0 = pc.vbid * chunk;
+  const uint32_t l1 = min((uint32_t)NL, l0 + chunk);
+  long long scanned = 0, ddeg = 0, ddeg_r = 0;
+  for (uint32_t b0 = l0; b0 < l1; b0 += RBS) {
+    const uint32_t i = b0 + (uint32_t)tid;
+    bool keep = false;
+    int32_t y = 0;
+    if (i < l1) {
+      y = (r == 1) ? (int32_t)i : Lv[i];
+      if ((int32_t)(a.D64[y] >> 32) == V::INF) {
+        const int32_t c = Cold[y];
+        const int4 rec = G.vrec[2 * y];  // out_off, out_degree, in_off, in_degree
+        const int32_t b = rec.z, deg = rec.w;
+        scanned += deg;
+        if (c == V::INF) {
+          Cnew[y] = V::INF;
+          ddeg += deg;
+          ddeg_r += (long long)deg * r;
+        } else {
+          int32_t m = V::INF;
+          for (int32_t j = 0; j < deg; j += 4) {
+            int32_t vs[4], ws[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const bool ok = j + q < deg;
+              vs[q] = ok ? G.in_src[b + j + q] : 0;
+              ws[q] = ok ? G.in_w[b + j + q] : 0;
+            }
+            int32_t cs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cs[q] = (j + q < deg) ? Cold[vs[q]] : V::INF;
+            int32_t wl = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (j + q < deg) {
+                if (cs[q] != V::INF) m = kmin(m, V::add(kmax(cs[q], md), ws[q]));
+                wl = ws[q];
+              }
+            }
+            if (V::add(md, wl) >= m) break;
+          }
+          Cnew[y] = kmax(kmax(c, md), m);
+          keep = true;
+        }
+      }
+    }
+    // stage the kept vertices; flush to the next live list when full
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan64<RBS>(keep ? 1ull : 0ull, sm.scan, &tot);
+    const int tcnt = (int)tot;
+    if (L.cnt + tcnt > CAP_L) {
+      const int cnt = L.cnt;
+      if (tid == 0) L.base = (int32_t)atomicAdd(lctr, (unsigned long long)cnt);
+      __syncthreads();
+      for (int j = tid; j < cnt; j += RBS) Ln[L.base + j] = L.v[j];
+      __syncthreads();
+      if (tid == 0) L.cnt = 0;
+      __syncthreads();
+    }
+    if (keep) L.v[L.cnt + (int)ex] = y;
+    __syncthreads();
+    if (tid == 0) L.cnt += tcnt;
+    __syncthreads();
+  }
+  {
+    const int cnt = L.cnt;
+    if (cnt > 0) {
+      if (tid == 0) L.base = (int32_t)atomicAdd(lctr, (unsigned long long)cnt);
+      __syncthreads();
+      for (int j = tid; j < cnt; j += RBS) Ln[L.base + j] = L.v[j];
+    }
+  }
+  const long long s1 = wave_sum64(scanned), s2 = wave_sum64(ddeg), s3 = wave_sum64(ddeg_r);
+  if (lane_id() == 0) {
+    if (s1) atomicAdd(&sm.n_scanned, (unsigned long long)s1);
+    if (s2) atomicAdd(&a.ctl->dead_deg, (unsigned long long)s2);
+    if (s3) atomicAdd(&a.ctl->dead_deg_r, (unsigned long long)s3);
+  }
+  __syncthreads();
+}
+
 // ========================================================== bound-and-fix
 template <class V, bool BATCH>
 __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NO,
-                            uint32_t EO, int32_t mind_all, int32_t thr_all,
+                            uint32_t EO, int NL, int32_t mind_all, int32_t thr_all,
                             BatchLds<BATCH> &bl, PhaseWork &pw) {
   const int tid = threadIdx.x;
   const int cur = r & 1, s_now = r % 3, s_next = (r + 1) % 3;
@@ -754,7 +875,9 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           xv[OX_OOFF] = rec.x;
           xv[OX_ODEG] = rec.y;
           xv[OX_OWM] = G.vrec[2 * yl + 1].x;
-          xv[OX_C] = 0;
+          // C of an undiscovered vertex: 0, or under scope ALL what the
+          // live pass raised it to
+          xv[OX_C] = a.scope_all ? Cold[gy] : 0;
         }
         S.base[tid] = xv[OX_BASE];
         S.ideg[tid] = xv[OX_IDEG];
@@ -942,6 +1065,12 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
   }
   stage_flush(S.fr, front, BATCH);
   stage_flush(S.op, next_open, BATCH);
+  if constexpr (!BATCH) {
+    if (NL > 0) {
+      __syncthreads();  // the live pass reuses the stagers' LDS
+      live_pass<V>(a, sm, pc, r, NL, mind_all, Cold, Cnew);
+    }
+  }
   mark(a, r, 1, 8);
   if constexpr (!BATCH) {
     block_min2<RBS>(lnext, ltnext, sm.red);
@@ -1036,7 +1165,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   int32_t md_prev = 0;     // the last minD this block computed (0 before round 1)
   const int32_t tgt = (!BATCH && a.target >= 0) ? uni(ld_relaxed(&ctl->target_id)) : -1;
   if (tid == 0) {
-    sm.n_settled = sm.n_relaxed = sm.n_open = sm.n_solo = 0;
+    sm.n_settled = sm.n_relaxed = sm.n_open = sm.n_solo = sm.n_bound = 0;
     sm.n_scanned = 0ull;
     sm.solo_cand_r = sm.solo_surv_r = -1;
   }
@@ -1064,8 +1193,13 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
       if (act < nb && bid == 0) wake_parked(ctl, epoch, r, phase, 1, act, aep);
       break;
     }
-    const uint32_t WT = E + (phase == 0 ? CW_RELAX : CW_FUSED) * (uint32_t)N;
-    const uint32_t want = active_for(a, E, WT, nb);
+    // scope ALL: the bound step also walks the live list (round 1: all n)
+    const int NL = (phase == 1 && a.scope_all)
+                       ? (r == 1 ? a.g.n : uni((int)ld_relaxed64(&ctl->live_ctr[cur])))
+                       : 0;
+    const uint32_t WL = CW_LIVE * (uint32_t)NL;
+    const uint32_t WT = E + (phase == 0 ? CW_RELAX : CW_FUSED) * (uint32_t)N + WL;
+    const uint32_t want = active_for(a, E + WL, WT, nb);
     if (want < act) {
       if (bid >= want) {
         if (park(ctl, epoch, aep, r, phase, act, sm)) break;
@@ -1091,10 +1225,12 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           // counters the coming bound-and-fix appends to (last read a round ago)
           ctl->open_ctr[cur ^ 1] = 0ull;
           ctl->front_ctr[cur ^ 1] = 0ull;
+          ctl->live_ctr[cur ^ 1] = 0ull;
           sm.n_settled += N;
           sm.n_relaxed += E;
         } else {
           sm.n_open += N;
+          sm.n_bound += 1;
         }
         if (solo) sm.n_solo += 1;
         if (tr) {
@@ -1144,7 +1280,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
         if (mind_all != V::INF) md_prev = mind_all;  // minD never decreases over rounds
       }
       mark(a, r, 1, 2);
-      fused_phase<V, BATCH>(a, sm, pc, r, N, E, mind_all, thr_all, bl, pw);
+      fused_phase<V, BATCH>(a, sm, pc, r, N, E, NL, mind_all, thr_all, bl, pw);
       if (!BATCH && solo && tid == 0) {
         sm.solo_surv_min = pw.bmin;
         sm.solo_surv_thr = pw.bthr;
@@ -1174,6 +1310,13 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     }
   }
   __syncthreads();
+  if (!BATCH && a.scope_all && bid == 0 && tid == 0) {
+    // unreachable vertices dropped from the live list in round r_d are
+    // still scanned in every later round with a bound step
+    const unsigned long long dd = ld_relaxed64(&ctl->dead_deg);
+    const unsigned long long ddr = ld_relaxed64(&ctl->dead_deg_r);
+    sm.n_scanned += dd * (unsigned long long)sm.n_bound - ddr;
+  }
   if (!BATCH && tid == 0 && sm.n_scanned)
     atomicAdd((unsigned long long *)&ctl->scanned, sm.n_scanned);
   if (bid == 0 && tid == 0) {
@@ -1281,6 +1424,8 @@ __global__ void init_seed_kernel(RoundArgs a) {
     c->done = 0;
     c->settled = c->relaxed = c->scanned = c->open_visits = 0;
     c->solo_phases = 0;
+    c->live_ctr[0] = c->live_ctr[1] = 0ull;
+    c->dead_deg = c->dead_deg_r = 0ull;
   }
 }
 

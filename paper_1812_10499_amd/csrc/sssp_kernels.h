@@ -58,6 +58,11 @@ struct Ctl {
   // single-target solve: the target's solver id (-1: none) and whether a
   // bound step (or the seed) has fixed it
   int32_t target_id, target_hit;
+  // C scope ALL: live-list sizes by round parity, and the in-degree sums
+  // (plain and times the drop round) of undiscovered vertices dropped with
+  // C = INF, for the scanned-edge count of the rounds after their drop
+  unsigned long long live_ctr[2];
+  unsigned long long dead_deg, dead_deg_r;
 };
 
 // Optional event pair recorded around the persistent kernel launch.
@@ -110,6 +115,10 @@ struct RoundArgs {
   int32_t solo_edges;        // phases with at most this many edges run on block 0 alone
   int32_t block_units;       // otherwise: about this many work units per active block
   int32_t target;            // single solve: stop once this vertex (caller's id) is fixed, or -1
+  // single solve, C scope ALL: the bound step also raises C of undiscovered
+  // vertices; live lists (by round parity) hold those whose C is finite
+  int32_t scope_all;
+  int32_t *live_v0, *live_v1;
 };
 
 // Trace record of one round: wall-clock (100 MHz) at the relax start, block

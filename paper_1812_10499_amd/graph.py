@@ -14,10 +14,12 @@ import torch
 
 from . import _abi
 from ._abi import (Csr, SSSP_F32, SSSP_I32, SSSP_ORDER_AUTO, SSSP_ORDER_DEGREE,
+                   SSSP_SCOPE_ALL, SSSP_SCOPE_AUTO, SSSP_SCOPE_OPEN,
                    SSSP_ORDER_INPUT, Stats)
 
 I32_INF = 2**31 - 1
 ORDERS = {"auto": SSSP_ORDER_AUTO, "input": SSSP_ORDER_INPUT, "degree": SSSP_ORDER_DEGREE}
+SCOPES = {"auto": SSSP_SCOPE_AUTO, "open": SSSP_SCOPE_OPEN, "all": SSSP_SCOPE_ALL}
 
 
 def _stream() -> int:
@@ -36,10 +38,12 @@ class Graph:
     Edge ids are positions in the CSR; ``perm[k]`` is the input (COO) index
     of edge id ``k``.  Weights are int32 (>= 1) or float32 (> 0).  ``order``
     picks the vertex numbering of the solver's working copy ("auto",
-    "input" or "degree"); results never depend on it.
+    "input" or "degree"); ``scope`` the C scope of single solves ("auto",
+    "open" or "all"; see :attr:`scope`).  Results never depend on either.
     """
 
-    def __init__(self, n: int, src, dst, w, device="cuda", order: str = "auto"):
+    def __init__(self, n: int, src, dst, w, device="cuda", order: str = "auto",
+                 scope: str = "auto"):
         device = torch.device(device)
         if isinstance(w, torch.Tensor):
             wt = w.to(device).contiguous()
@@ -69,6 +73,25 @@ class Graph:
                             wt.data_ptr(), self.buffer.data_ptr(), nbytes, self.csr,
                             self.perm.data_ptr(), _stream())
         self.perm = self.perm[:m]
+        self.scope = scope
+
+    @property
+    def scope(self) -> str:
+        """C scope of single solves as set: "auto", "open" or "all"."""
+        return {v: k for k, v in SCOPES.items()}[self.csr.scope]
+
+    @scope.setter
+    def scope(self, value: str):
+        if value not in SCOPES:
+            raise ValueError("scope must be one of %s" % sorted(SCOPES))
+        self.csr.scope = SCOPES[value]
+
+    @property
+    def effective_scope(self) -> str:
+        """The scope single solves run: "auto" is "all" in degree order."""
+        if self.csr.scope == SSSP_SCOPE_AUTO:
+            return "all" if self.csr.order == SSSP_ORDER_DEGREE else "open"
+        return "all" if self.csr.scope == SSSP_SCOPE_ALL else "open"
 
     @property
     def order(self) -> str:

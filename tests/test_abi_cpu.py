@@ -103,6 +103,12 @@ def test_host_argument_errors(sp):
     bad = _fake_csr(sp)
     bad.s_in_w = None  # the in-list copy is required in every order
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    bad = _fake_csr(sp)
+    bad.scope = 3  # not an sssp_scope
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    # single-target solve: the target must be a vertex
+    assert _status(lambda: sp.sssp_solve_target(c, 0, -1, 0x1000, None, None)) == S
+    assert _status(lambda: sp.sssp_solve_target(c, 0, 10, 0x1000, None, None)) == S
     # int32 overflow precondition: (n-1) * w_max >= INT32_MAX
     big = _fake_csr(sp, n=1 << 22, w_max=1000.0)
     assert _status(lambda: sp.sssp_solve(big, 0, 0x1000, None, None, None)) == \

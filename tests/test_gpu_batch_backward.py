@@ -43,9 +43,13 @@ def check_batch(sp, graphs, glist, inst_graph, inst_source, label):
         assert st["settled"] == ref["settles"], (label, i)
         assert st["relaxed_edges"] == ref["relaxed"], (label, i)
         assert st["scanned_in_edges"] == ref["scanned"], (label, i)
-        # identical to the single solve of the same instance
+        # identical to the single solve of the same instance (batches run
+        # C scope OPEN)
+        prev = graphs[gi].scope
+        graphs[gi].scope = "open"
         c1, p1, st1 = sp.solve(graphs[gi], s, with_pred=True, with_stats=True)
         sync()
+        graphs[gi].scope = prev
         assert np.array_equal(to_np(c1), c[sl]) and np.array_equal(to_np(p1), to_np(pred)[sl])
         assert st1["rounds"] == st["rounds"] and st1["open_visits"] == st["open_visits"]
     return cost, pred

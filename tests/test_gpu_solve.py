@@ -24,8 +24,8 @@ def sp():
     return sp
 
 
-def check_build(sp, n, src, dst, w, order="auto"):
-    G = sp.Graph(n, src, dst, w, order=order)
+def check_build(sp, n, src, dst, w, order="auto", scope="auto"):
+    G = sp.Graph(n, src, dst, w, order=order, scope=scope)
     want = expected_order(n, src, dst) if order == "auto" else order
     assert G.order == (want if len(src) else "input"), (G.order, want)
     check_solver_copy(G, n, src, dst, w)
@@ -49,12 +49,12 @@ def check_build(sp, n, src, dst, w, order="auto"):
     return G
 
 
-def run_case(sp, n, src, dst, w, source, label, order="auto"):
-    print("case", label, "n=%d m=%d order=%s" % (n, len(src), order), flush=True)
-    G = check_build(sp, n, src, dst, w, order)
+def run_case(sp, n, src, dst, w, source, label, order="auto", scope="auto"):
+    print("case", label, "n=%d m=%d order=%s scope=%s" % (n, len(src), order, scope), flush=True)
+    G = check_build(sp, n, src, dst, w, order, scope)
     cost, pred, st = sp.solve(G, source, with_pred=True, with_stats=True)
     sync()
-    ref = oracle_solution(n, src, dst, w, source)
+    ref = oracle_solution(n, src, dst, w, source, G.effective_scope)
     assert_same_solution(cost, pred, st, ref, label)
     # a second solve on the same graph reuses the workspace
     cost2, pred2, _ = sp.solve(G, source, with_pred=True)
@@ -158,6 +158,40 @@ def test_rmat_scaled(sp, scale, order):
         assert G.order == "degree"
 
 
+@pytest.mark.parametrize("scope", ["open", "all"])
+def test_scope_both_ways(sp, scope):
+    """Each C scope against the round simulator in the same scope, on every
+    workload family and the degenerate shapes."""
+    rng = np.random.default_rng(23)
+    for trial in range(12):
+        n = int(rng.integers(1, 400))
+        m = int(rng.integers(0, 6 * n))
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        if trial % 2:
+            w = rng.integers(1, 50, m).astype(np.int32)
+        else:
+            w = (rng.integers(1, 2**24, m) * 2.0 ** -24).astype(np.float32)
+        run_case(sp, n, src, dst, w, int(rng.integers(0, n)), "scope-rand-%d" % trial,
+                 ["input", "degree"][trial % 3 == 0], scope)
+    for order in ("input", "degree"):
+        g = gen.rmat_workload(scale=14)
+        run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-rmat14-" + order, order, scope)
+    g = gen.grid_workload(side=48)
+    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-grid48", "auto", scope)
+    run_case(sp, g.n, g.src, g.dst, np.ones(g.m, np.int32), g.source, "scope-grid48-unit",
+             "auto", scope)
+    for g in gen.batch_workload(count=2, nmin=1000, nmax=20000):
+        run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-" + g.name, "auto", scope)
+    # one vertex; no edges; a source with no out-edges; unreachable cycles
+    run_case(sp, 1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32), 0,
+             "scope-single", "auto", scope)
+    src = np.array([1, 2, 3, 4, 0], np.int32)
+    dst = np.array([2, 3, 1, 0, 5], np.int32)
+    run_case(sp, 6, src, dst, np.array([3, 4, 5, 6, 7], np.int32), 0, "scope-cycle", "auto",
+             scope)
+
+
 @pytest.mark.parametrize("side", [32, 128])
 def test_grid_scaled(sp, side):
     g = gen.grid_workload(side=side)
@@ -184,8 +218,8 @@ def test_set_weights_then_solve(sp, order):
     check_solver_copy(G, g.n, g.src, g.dst, w2)
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
-    assert_same_solution(cost, pred, st, oracle_solution(g.n, g.src, g.dst, w2, g.source),
-                         "rmat12-reweighted-" + order)
+    ref = oracle_solution(g.n, g.src, g.dst, w2, g.source, G.effective_scope)
+    assert_same_solution(cost, pred, st, ref, "rmat12-reweighted-" + order)
     # invalid weights are refused before anything is written
     bad = torch.from_numpy(w2[to_np(G.perm)]).cuda()
     bad[g.m // 2] = 0
@@ -229,6 +263,6 @@ def test_workload_rmat22_full(sp):
     assert G.order == "degree"
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
-    ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source)
+    ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source, G.effective_scope)
     assert_same_solution(cost, pred, st, ref, "rmat22")
     print("rmat22 rounds", st, flush=True)

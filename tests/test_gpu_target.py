@@ -12,7 +12,7 @@ import torch
 
 import gen
 import oracle
-from gpu_util import sync, to_np
+from gpu_util import oracle_mode, sync, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,8 @@ def check_target(sp, G, n, src, dst, w, source, target, label):
           flush=True)
     cost, st = sp.solve_target(G, source, target, with_stats=True)
     sync()
-    ref = oracle.round_sim(n, src, dst, w, source, target=target)
+    ref = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(G.effective_scope),
+                           target=target)
     full, _ = oracle.dijkstra(n, src, dst, w, source)
     c = to_np(cost)
     bad = np.nonzero(c != ref["cost"])[0]
@@ -79,9 +80,10 @@ def test_target_random_small(sp, dtype, order):
             check_target(sp, G, n, src, dst, w, s, t, "%s-%s-%d-t%d" % (dtype, order, it, t))
 
 
-def test_target_rmat_and_grid(sp):
+@pytest.mark.parametrize("scope", ["open", "all"])
+def test_target_rmat_and_grid(sp, scope):
     g = gen.rmat_workload(scale=14)
-    G = sp.Graph(g.n, g.src, g.dst, g.w)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, scope=scope)
     full, _ = oracle.dijkstra(g.n, g.src, g.dst, g.w, g.source)
     reach = np.nonzero(full != np.int32(2**31 - 1))[0]
     order = reach[np.argsort(full[reach], kind="stable")]
@@ -89,7 +91,7 @@ def test_target_rmat_and_grid(sp):
     for t in (int(order[1]), int(order[len(order) // 2]), int(order[-1]), int(unreach[0])):
         check_target(sp, G, g.n, g.src, g.dst, g.w, g.source, t, "rmat14-t%d" % t)
     g = gen.grid_workload(side=64)
-    G = sp.Graph(g.n, g.src, g.dst, g.w)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, scope=scope)
     for t in (0, g.n - 1, g.source + 1):
         check_target(sp, G, g.n, g.src, g.dst, g.w, g.source, t, "grid64-t%d" % t)
 
