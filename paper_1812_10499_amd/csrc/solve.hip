@@ -38,6 +38,8 @@
 // phase grows.  A barrier among k blocks costs far less than one across
 // the whole grid, which matters for the long tails of small rounds (grids,
 // the end of every solve).
+#include <type_traits>
+
 #include "sssp_dev.h"
 #include "sssp_kernels.h"
 
@@ -490,6 +492,38 @@ __device__ __forceinline__ int32_t discovery_in_edges(const GraphDev &G, const i
     for (int l = 0; l < kProbe; ++l) p += (l <= hit && V::add(md, wv[l]) < dy) ? 1 : 0;
     return p;
   }
+  if constexpr (std::is_same<V, KeyI32>::value) {
+    // Integer weights: a probed tail j with C[j] > md still bounds the scan.
+    // For every minD >= md its term max(C[j], minD) + w_j is at most
+    // minD + w_j + (C[j] - md), so each edge k with w_k >= W* =
+    // min_j (w_j + C[j] - md) has minD + w_k >= that term: only the edges
+    // lighter than W*, and the probe edge j* that attains it, can set m_y.
+    long long ws = (long long)V::INF + V::INF;
+    int js = -1;
+#pragma unroll
+    for (int l = 0; l < kProbe; ++l) {
+      if (c[l] != V::INF) {
+        const long long t = (long long)wv[l] + (c[l] - md);
+        if (t < ws) {
+          ws = t;
+          js = l;
+        }
+      }
+    }
+    if (js >= 0) {
+      // One search for the weight bound min(dy - md, W*): md + w < dy is
+      // w < dy - md (dy <= INF, so the saturating add hides nothing), and
+      // j* itself lies below W* (C[j*] > md here), so the count keeps it.
+      const long long lim = ws < (long long)dy - md ? ws : (long long)dy - md;
+      int32_t lo = 0, hi = deg;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((long long)G.in_w[b + mid] < lim) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    }
+  }
   return useful_in_edges_at<V>(G, b, deg, md, dy);
 }
 
@@ -704,9 +738,10 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
 //   discovered since (D < INF): dropped, it is an open item now;
 //   C = INF: C' = INF, dropped (it was kept one round so that both C
 //     buffers hold INF; an undiscovered vertex with C = INF is unreachable);
-//   else its weight-ordered in-list is scanned four edges at a time until
-//     minD + w of the last edge read reaches the running minimum (no later,
-//     heavier edge can lower it), and the vertex is kept.
+//   else its weight-ordered in-list is scanned, the lightest edge alone and
+//     then four edges at a time, until minD + w of the last edge read
+//     reaches the running minimum (no later, heavier edge can lower it),
+//     and the vertex is kept.
 // The method's scanned count takes every undiscovered vertex's whole
 // in-degree each round; dropped unreachable ones are settled at the end
 // from dead_deg and dead_deg_r.
@@ -722,15 +757,14 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, i
   const GraphDev &G = a.g;
   if (tid == 0) L.cnt = 0;
   __syncthreads();
-  const uint32_t chunk = chunk_of((uint32_t)NL, pc.vnb);
-  const uint32_t l0 = pc.vbid * chunk;
-  const uint32_t l1 = min((uint32_t)NL, l0 + chunk);
+  // tiles of RBS list entries go round-robin to the blocks: the lists keep
+  // solver order, and under degree order the costly vertices come first
   long long scanned = 0, ddeg = 0, ddeg_r = 0;
-  for (uint32_t b0 = l0; b0 < l1; b0 += RBS) {
+  for (uint32_t b0 = pc.vbid * RBS; b0 < (uint32_t)NL; b0 += pc.vnb * RBS) {
     const uint32_t i = b0 + (uint32_t)tid;
     bool keep = false;
     int32_t y = 0;
-    if (i < l1) {
+    if (i < (uint32_t)NL) {
       y = (r == 1) ? (int32_t)i : Lv[i];
       if ((int32_t)(a.D64[y] >> 32) == V::INF) {
         const int32_t c = Cold[y];
@@ -743,7 +777,15 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, i
           ddeg_r += (long long)deg * r;
         } else {
           int32_t m = V::INF;
-          for (int32_t j = 0; j < deg; j += 4) {
+          int32_t j = 0;
+          if (deg > 0) {
+            // the lightest in-edge alone first: its tail usually decides m
+            const int32_t v0 = G.in_src[b], w0 = G.in_w[b];
+            const int32_t c0 = Cold[v0];
+            if (c0 != V::INF) m = V::add(kmax(c0, md), w0);
+            j = (V::add(md, w0) >= m) ? deg : 1;
+          }
+          for (; j < deg; j += 4) {
             int32_t vs[4], ws[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
