@@ -19,7 +19,8 @@ Functions and the passages they follow:
 * :func:`pred` -- parent pointers (Section I) under the smallest-tight-edge
   tie rule, with the equal-cost level rule for float ties.
 * :func:`round_sim` -- the method's rounds (Eq. 1, Lemmas crule2 and crauser,
-  Fig. 6's steps in the adopted sound order; mode 2 is Fig. 6 as printed).
+  Fig. 6's steps in the adopted sound order; mode 2 is Fig. 6 as printed;
+  MODE_LC relaxes every discovered vertex whose D fell, as Fig. 6's step 3).
 * :func:`grad` -- fp64 subtree-sum gradient of ``sum g * cost`` over the
   pred tree.
 """
@@ -186,6 +187,7 @@ def pred(g: CSR, w, source, cost):
 
 
 MODE_ADOPTED, MODE_SCOPE_ALL, MODE_LITERAL_FIG5 = 0, 1, 2
+MODE_LC = 4  # or-ed with MODE_ADOPTED / MODE_SCOPE_ALL: label-correcting relax
 
 
 def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=None):

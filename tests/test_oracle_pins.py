@@ -488,3 +488,44 @@ def test_target_stop_against_full_solve(dtype):
         assert r["settled"] == 1 + sum(r["fixed_per_round"])
         assert np.count_nonzero((r["cost"] == c) & (c != inf)) >= r["settled"]
         assert r["relaxed_edges"] <= full["relaxed_edges"]
+
+
+def test_label_correcting_closed_forms():
+    """Label-correcting relax (Fig. 6's step 3 explores every discovered
+    vertex).  Worked by hand on 0->1 (10), 0->2 (1), 2->1 (1), 1->3 (1): round
+    1 relaxes 0 and fixes 2; round 2 relaxes 2 and, from its tentative D = 10,
+    also 1, so D[1] = 2 and D[3] = 11, and 1 is fixed; round 3 relaxes 1 again
+    (D fell to 2) and fixes 3; round 4 finds nothing open.  Label-setting
+    relaxes each of the four edges once in the same four rounds."""
+    src = np.array([0, 0, 2, 1], np.int32)
+    dst = np.array([1, 2, 1, 3], np.int32)
+    w = np.array([10, 1, 1, 1], np.int32)
+    for scope in (oracle.MODE_ADOPTED, oracle.MODE_SCOPE_ALL):
+        ls = oracle.round_sim(4, src, dst, w, 0, mode=scope)
+        lc = oracle.round_sim(4, src, dst, w, 0, mode=scope | oracle.MODE_LC)
+        assert ls["cost"].tolist() == lc["cost"].tolist() == [0, 2, 1, 3]
+        assert ls["rounds"] == lc["rounds"] == 4
+        assert ls["fixed_per_round"].tolist() == lc["fixed_per_round"].tolist() == [1, 1, 1, 0]
+        assert ls["relaxed_edges"] == 4 and lc["relaxed_edges"] == 5
+    # a path: every D is final when discovered, so nothing is relaxed twice
+    for k in (1, 7, 30):
+        src = np.arange(k, dtype=np.int32)
+        r = oracle.round_sim(k + 1, src, src + 1, np.full(k, 3, np.int32), 0,
+                             mode=oracle.MODE_LC)
+        assert r["rounds"] == k + 1 and r["relaxed_edges"] == k
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_label_correcting_costs_and_invariants(dtype):
+    rng = np.random.default_rng(17)
+    for _ in range(300):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 30)))
+        c, settles = oracle.dijkstra(n, src, dst, w, s)
+        for mode in (oracle.MODE_ADOPTED, oracle.MODE_SCOPE_ALL):
+            ls = oracle.round_sim(n, src, dst, w, s, mode=mode)
+            r = oracle.round_sim(n, src, dst, w, s, mode=mode | oracle.MODE_LC, true_cost=c)
+            assert np.array_equal(r["cost"], c)
+            assert r["violations"] == 0
+            assert 1 <= r["rounds"] <= settles
+            assert r["settled"] == settles
+            assert r["relaxed_edges"] >= ls["relaxed_edges"]
