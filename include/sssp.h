@@ -92,6 +92,22 @@ typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 
 typedef enum { SSSP_SCOPE_AUTO = 0, SSSP_SCOPE_OPEN = 1, SSSP_SCOPE_ALL = 2 } sssp_scope;
 
 /*
+ * Relax step (A) of a round.  No result changes; rounds and relax work do.
+ *   SSSP_RELAX_SETTING     label-setting: the out-edges of the vertices the
+ *                          previous round fixed, each once per solve
+ *   SSSP_RELAX_CORRECTING  label-correcting, as step 3 of SP_4 (Section VI,
+ *                          Fig. 6) explores every discovered vertex: also the
+ *                          open vertices whose D fell since their last relax,
+ *                          each from its D at the start of the step; a fixed
+ *                          vertex already relaxed at its final D is skipped
+ *   SSSP_RELAX_AUTO        the mode the graph's vertex order suggests (see
+ *                          the definition in the library: SETTING for now
+ *                          on every graph)
+ * Honoured per graph by single and batched solves.
+ */
+typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTING = 2 } sssp_relax;
+
+/*
  * A built graph: CSR by tail plus CSC by head (the incoming-edge access the
  * method assumes, Section I).  All arrays are device arrays in the caller's
  * build buffer.
@@ -105,6 +121,7 @@ typedef enum { SSSP_SCOPE_AUTO = 0, SSSP_SCOPE_OPEN = 1, SSSP_SCOPE_ALL = 2 } ss
  *                 int32 overflow precondition)
  *   scope         sssp_scope of the single solves on this graph (the
  *                 builder sets SSSP_SCOPE_AUTO; the caller may change it)
+ *   relax         sssp_relax of the solves on this graph (likewise AUTO)
  * The solver's working copy.  Always: in-lists ordered by weight, so that
  * the in-edges a lower-bound step needs (minD + w < D[y]) form a prefix:
  *   s_in_off[n+1], s_in_src[m] (solver ids), s_in_eid[m], s_in_w[m]
@@ -128,6 +145,7 @@ typedef struct {
   int32_t dtype; /* sssp_dtype */
   int32_t order; /* sssp_order the builder applied: INPUT or DEGREE */
   int32_t scope; /* sssp_scope of single solves */
+  int32_t relax; /* sssp_relax of every solve on this graph */
   const int32_t *out_off;
   const int32_t *out_dst;
   const void *out_w;

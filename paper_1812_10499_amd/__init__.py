@@ -9,7 +9,8 @@ include/sssp.h; this package is its Python binding.
 from ._abi import (  # noqa: F401
     EXPORTS, LIB_PATH, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_HIP, SSSP_ERR_INTERNAL,
     SSSP_ERR_NOMEM, SSSP_ERR_OVERFLOW, SSSP_ERR_WEIGHT, SSSP_F32, SSSP_I32, SSSP_OK,
-    SSSP_ORDER_AUTO, SSSP_ORDER_DEGREE, SSSP_ORDER_INPUT, SSSP_SCOPE_ALL, SSSP_SCOPE_AUTO,
+    SSSP_ORDER_AUTO, SSSP_ORDER_DEGREE, SSSP_ORDER_INPUT, SSSP_RELAX_AUTO,
+    SSSP_RELAX_CORRECTING, SSSP_RELAX_SETTING, SSSP_SCOPE_ALL, SSSP_SCOPE_AUTO,
     SSSP_SCOPE_OPEN, Csr,
     SSSPError, Stats, lib, sssp_backward, sssp_profile_enable, sssp_profile_read,
     sssp_build_csr, sssp_build_csr_bytes, sssp_release_workspace, sssp_set_weights, sssp_solve,

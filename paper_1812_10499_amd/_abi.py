@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("SSSP_LIBRARY") or os.path.join(_HERE, "libsssp.so")
 SSSP_I32, SSSP_F32 = 0, 1
 SSSP_ORDER_AUTO, SSSP_ORDER_INPUT, SSSP_ORDER_DEGREE = 0, 1, 2
 SSSP_SCOPE_AUTO, SSSP_SCOPE_OPEN, SSSP_SCOPE_ALL = 0, 1, 2
+SSSP_RELAX_AUTO, SSSP_RELAX_SETTING, SSSP_RELAX_CORRECTING = 0, 1, 2
 (SSSP_OK, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_WEIGHT, SSSP_ERR_OVERFLOW, SSSP_ERR_NOMEM,
  SSSP_ERR_HIP, SSSP_ERR_INTERNAL) = range(8)
 
@@ -30,6 +31,7 @@ EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_s
 class Csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("scope", ctypes.c_int32),
+                ("relax", ctypes.c_int32),
                 ("out_off", ctypes.c_void_p), ("out_dst", ctypes.c_void_p),
                 ("out_w", ctypes.c_void_p), ("in_off", ctypes.c_void_p),
                 ("in_src", ctypes.c_void_p), ("in_eid", ctypes.c_void_p),

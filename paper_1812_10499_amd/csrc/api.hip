@@ -23,7 +23,7 @@ enum Slot {
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
-  S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1, S_LV0, S_LV1,
+  S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1, S_LV0, S_LV1, S_DR,
   NSLOTS
 };
 
@@ -148,6 +148,7 @@ sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
 bool csr_ok(const sssp_csr *g) {
   if (!(g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
         g->scope >= SSSP_SCOPE_AUTO && g->scope <= SSSP_SCOPE_ALL &&
+        g->relax >= SSSP_RELAX_AUTO && g->relax <= SSSP_RELAX_CORRECTING &&
         g->out_off && g->in_off && g->out_wmin && g->s_out_off && g->s_in_off &&
         g->s_out_wmin && g->s_vrec &&
         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
@@ -159,6 +160,9 @@ bool csr_ok(const sssp_csr *g) {
 
 // SSSP_SCOPE_AUTO: scope ALL on graphs the builder put in degree order.
 bool effective_auto_all(const sssp_csr *g) { return g->order == SSSP_ORDER_DEGREE; }
+
+// The relax step a graph's solves use (SSSP_RELAX_AUTO: label-setting).
+bool relax_correcting(const sssp_csr *g) { return g->relax == SSSP_RELAX_CORRECTING; }
 
 bool overflow_risk(const sssp_csr *g) {
   if (g->dtype != SSSP_I32) return false;
@@ -188,6 +192,7 @@ GraphDev graph_dev(const sssp_csr *g) {
   d.u_in_w = (const int32_t *)g->in_w;
   d.n = g->n;
   d.m = g->m;
+  d.lc = relax_correcting(g) ? 1 : 0;
   return d;
 }
 
@@ -290,6 +295,7 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
     if ((s = ws_arr(w, S_LV0, T, &a.live_v0))) return s;
     if ((s = ws_arr(w, S_LV1, T, &a.live_v1))) return s;
   }
+  if (a.any_lc && (s = ws_arr(w, S_DR, T, &a.DR))) return s;
   if (batch) {
     if ((s = ws_arr(w, S_OI0, T, &a.open_i0))) return s;
     if ((s = ws_arr(w, S_OI1, T, &a.open_i1))) return s;
@@ -297,7 +303,7 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
     if ((s = ws_arr(w, S_IMIN, 3 * (size_t)num_inst, &a.imin))) return s;
     if ((s = ws_arr(w, S_ITHR, 3 * (size_t)num_inst, &a.ithr))) return s;
     if ((s = ws_arr(w, S_IROUNDS, (size_t)num_inst, &a.irounds))) return s;
-    if ((s = ws_arr(w, S_ISCAN, 2 * (size_t)num_inst, &a.iscanned))) return s;
+    if ((s = ws_arr(w, S_ISCAN, 3 * (size_t)num_inst, &a.iscanned))) return s;
   }
   return SSSP_OK;
 }
@@ -487,6 +493,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->dtype = dtype;
   out->order = SSSP_ORDER_INPUT;
   out->scope = SSSP_SCOPE_AUTO;
+  out->relax = SSSP_RELAX_AUTO;
   out->out_off = out_off;
   out->out_dst = out_dst;
   out->out_w = out_w;
@@ -631,6 +638,7 @@ static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, 
   a.target = target;
   a.scope_all = g->scope == SSSP_SCOPE_ALL ||
                 (g->scope == SSSP_SCOPE_AUTO && effective_auto_all(g));
+  a.any_lc = a.g.lc;
   if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
   LaunchGeom geo;
   if ((s = geometry(ws, f32, false, &geo))) return s;
@@ -711,6 +719,8 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   a.D = (int32_t *)cost;
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
+  for (int32_t i = 0; i < num_inst; ++i)
+    if (relax_correcting(&graphs[inst_graph[i]])) a.any_lc = 1;
   if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
   GraphDev *dg;
   InstDev *di;
@@ -758,17 +768,17 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
     HIPCHK(hipMemcpyAsync(hr, a.irounds, sizeof(int32_t) * num_inst, hipMemcpyDeviceToHost,
                           stream));
     HIPCHK(hipStreamSynchronize(stream));
-    std::vector<unsigned long long> sc(2 * (size_t)num_inst);
-    HIPCHK(hipMemcpy(sc.data(), a.iscanned, sizeof(unsigned long long) * 2 * num_inst,
+    std::vector<unsigned long long> sc(3 * (size_t)num_inst);
+    HIPCHK(hipMemcpy(sc.data(), a.iscanned, sizeof(unsigned long long) * 3 * num_inst,
                      hipMemcpyDeviceToHost));
     Ctl c;
     HIPCHK(hipMemcpy(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     for (int32_t i = 0; i < num_inst; ++i) {
       stats[i].rounds = hr[i];
       stats[i].settled = (int32_t)hst[4 * i + 1];
-      stats[i].relaxed_edges = hst[4 * i + 2];
-      stats[i].scanned_in_edges = (int64_t)sc[2 * i];
-      stats[i].open_visits = (int64_t)sc[2 * i + 1];
+      stats[i].relaxed_edges = (int64_t)sc[3 * i + 2];
+      stats[i].scanned_in_edges = (int64_t)sc[3 * i];
+      stats[i].open_visits = (int64_t)sc[3 * i + 1];
     }
     HIPCHK(hipEventRecord(ws.last, stream));
     if (c.status) return SSSP_ERR_INTERNAL;

@@ -122,7 +122,8 @@ struct SmemAll {
   int32_t red[2 * (RBS / SSSP_WAVE)];
   int32_t tmax;
   // block 0, thread 0: the solve's counters, written out at the end
-  long long n_settled, n_relaxed, n_open, n_solo, n_bound;
+  long long n_relaxed, n_open, n_solo, n_bound;
+  unsigned long long n_fixed;  // this block's fixes (single solve)
   unsigned long long n_scanned;  // this block's share of the scanned in-edge count
   // single solve: minima a one-block phase produced, and their rounds
   int32_t solo_cand_min, solo_cand_thr, solo_surv_min, solo_surv_thr;
@@ -191,18 +192,22 @@ __device__ __forceinline__ void batch_offer(BatchLds<true> &bl, const RoundArgs 
 }
 
 // After a barrier: the block's per-instance minima and counts into the
-// global words (slot < 0: no minima this phase).
+// global words (slot < 0: no minima this phase).  Per instance the counts
+// are iscanned[3i] scanned in-edges and [3i + 1] open visits (bound step),
+// [3i + 2] relaxed edges (relax step, accumulated in `scan`).
 template <class V>
-__device__ void batch_lds_flush(BatchLds<true> &bl, const RoundArgs &a, int slot) {
+__device__ void batch_lds_flush(BatchLds<true> &bl, const RoundArgs &a, int slot, bool relax) {
   const int I = a.num_inst;
   for (int i = threadIdx.x; i < I && i < kLdsInst; i += RBS) {
     if (slot >= 0) {
       if (bl.mn[i] != V::INF) atomicMin(&a.imin[slot * I + i], bl.mn[i]);
       if (bl.th[i] != V::INF) atomicMin(&a.ithr[slot * I + i], bl.th[i]);
     }
-    if (bl.visit[i]) {
-      atomicAdd(&a.iscanned[2 * i], (unsigned long long)bl.scan[i]);
-      atomicAdd(&a.iscanned[2 * i + 1], (unsigned long long)bl.visit[i]);
+    if (relax) {
+      if (bl.scan[i]) atomicAdd(&a.iscanned[3 * i + 2], (unsigned long long)bl.scan[i]);
+    } else if (bl.visit[i]) {
+      atomicAdd(&a.iscanned[3 * i], (unsigned long long)bl.scan[i]);
+      atomicAdd(&a.iscanned[3 * i + 1], (unsigned long long)bl.visit[i]);
     }
   }
 }
@@ -465,7 +470,7 @@ __device__ __forceinline__ int32_t useful_in_edges_at(const GraphDev &G, int32_t
 // to the probe hit, and the probe's own weights give the prefix among them
 // (no search).  Cold must be stable for the whole relax step (the bound step
 // writes the other C buffer).
-constexpr int kProbe = 8;
+constexpr int kProbe = 2;
 
 template <class V>
 __device__ __forceinline__ int32_t discovery_in_edges(const GraphDev &G, const int32_t *Cold,
@@ -580,15 +585,19 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
           sb = id.sbase;
           gi = id.graph;
         }
-        // out-offset and final D travel with the frontier entry
+        // out-offset and relax D travel with the entry (bit 31: x is open)
+        const int32_t dxr = a.front_x[FX_D][idx];
+        const int32_t dx = dxr & 0x7fffffff;
         S.base[tid] = a.front_x[FX_OOFF][idx];
-        S.dx[tid] = a.front_x[FX_D][idx];
+        S.dx[tid] = dx;
         S.sb[tid] = sb;
         S.gi[tid] = gi;
         S.inst[tid] = ins;
-        // x was fixed last round; the buffer the next bound step reads must
-        // say so too (every x with an out-edge is in some block's window)
-        Cnew[gx] = V::INF;
+        // a fixed x was fixed last round; the buffer the next bound step
+        // reads must say so too (every item is in some block's window: each
+        // weighs CW_RELAX units even with no edges)
+        if (dxr >= 0) Cnew[gx] = V::INF;
+        if (graph_of<BATCH>(a, gi).lc) a.DR[gx] = dx;  // relaxed from dx
       } else {
         S.pfx[tid] = (int32_t)WT;
       }
@@ -598,6 +607,18 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
                          : (int32_t)WT;
       __syncthreads();
       if (pw.windows == 0) mark(a, r, 0, 4);
+      if constexpr (BATCH) {
+        // relaxed-edge count per instance: an item's out-degree, counted by
+        // the block whose chunk holds the item's first unit
+        if (idx < NF) {
+          const uint32_t p0 = (uint32_t)S.pfx[tid];
+          const uint32_t deg = (uint32_t)S.pfx[tid + 1] - p0 - CW_RELAX;
+          if (p0 >= e0 && p0 < e1 && deg) {
+            if (I > kLdsInst) atomicAdd(&a.iscanned[3 * S.inst[tid] + 2], (unsigned long long)deg);
+            else atomicAdd(&bl.scan[S.inst[tid]], deg);
+          }
+        }
+      }
       const uint32_t wend = uni(min((uint32_t)S.pfx[WIN], e1));
       // Each item's units are CW_RELAX of bookkeeping, then one per
       // out-edge; lanes walk only the edges that fall in [k, wend).
@@ -723,7 +744,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
     pw.bthr = ltmin;
   } else {
     __syncthreads();
-    batch_lds_flush<V>(bl, a, s_now);
+    batch_lds_flush<V>(bl, a, s_now, true);
   }
   mark(a, r, 0, 7);
 }
@@ -1011,7 +1032,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       if (pw.windows == 0) mark(a, r, 1, 6);
       // finish the window's items: thread tid handles window item tid
       bool hf = false, ho = false;
-      int32_t gy = 0, fd = 0, od = 0, ins = 0;
+      int32_t gy = 0, fd = 0, od = 0, ins = 0, nfix = 0;
       int32_t sv = V::INF, st = V::INF;  // a survivor's offers to the next minD / thr
       int32_t sdeg = 0;                  // in-degree of a finished item (statistics)
       int32_t fx[kFX] = {0, 0}, ox[kOX] = {0, 0, 0, 0, 0, 0};  // payloads of the pushes
@@ -1052,8 +1073,8 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             if constexpr (BATCH) {
               if (a.istat) {  // statistics requested
                 if (I > kLdsInst) {
-                  atomicAdd(&a.iscanned[2 * ins], (unsigned long long)deg);
-                  atomicAdd(&a.iscanned[2 * ins + 1], 1ull);
+                  atomicAdd(&a.iscanned[3 * ins], (unsigned long long)deg);
+                  atomicAdd(&a.iscanned[3 * ins + 1], 1ull);
                 } else {
                   atomicAdd(&bl.scan[ins], (uint32_t)deg);
                   atomicAdd(&bl.visit[ins], 1u);
@@ -1062,11 +1083,16 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             } else {
               sdeg = (int32_t)deg;
             }
+            // label-correcting: the D y was last relaxed with (INF if never)
+            const int32_t dr = G.lc ? a.DR[gy] : V::INF;
             if (Cn >= Dy || Dy <= th) {
               Cnew[gy] = V::INF;  // fixed: drops out of every later bound step
               if (gy == pc.target) ctl->target_hit = 1;
-              fd = S.odeg[tid];
+              // next round's relax list; a vertex already relaxed at its
+              // final D comes with no edges, only to mark its C
+              fd = Dy < dr ? S.odeg[tid] : 0;
               hf = true;
+              nfix = 1;
               fx[FX_OOFF] = S.ooff[tid];
               fx[FX_D] = Dy;
             } else {
@@ -1083,6 +1109,13 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
               const int32_t tn = V::add(Dy, S.owm[tid]);
               sv = Dy;
               st = tn;
+              if (Dy < dr && G.lc) {
+                // label-correcting: relaxed again from its lower D
+                hf = true;
+                fd = S.odeg[tid];
+                fx[FX_OOFF] = S.ooff[tid];
+                fx[FX_D] = Dy | kOpenRelax;
+              }
               if constexpr (!BATCH) {
                 lnext = kmin(lnext, Dy);
                 ltnext = kmin(ltnext, tn);
@@ -1094,8 +1127,9 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       if constexpr (BATCH) {
         batch_offer<V>(bl, a, s_next, ho, ins, sv, st);
       } else {
-        const long long ws = wave_sum64(sdeg);
+        const long long ws = wave_sum64(sdeg), wf = wave_sum64(nfix);
         if (lane_id() == 0 && ws) atomicAdd(&sm.n_scanned, (unsigned long long)ws);
+        if (lane_id() == 0 && wf) atomicAdd(&sm.n_fixed, (unsigned long long)wf);
       }
       stage_push2(S.fr, hf, gy, fd, ins, fx, front, S.op, ho, gy, od, ins, ox, next_open, BATCH,
                   sm);
@@ -1122,7 +1156,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
     pw.bthr = ltnext;
   } else {
     __syncthreads();
-    batch_lds_flush<V>(bl, a, s_next);
+    batch_lds_flush<V>(bl, a, s_next, false);
   }
   mark(a, r, 1, 9);
 }
@@ -1207,7 +1241,8 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   int32_t md_prev = 0;     // the last minD this block computed (0 before round 1)
   const int32_t tgt = (!BATCH && a.target >= 0) ? uni(ld_relaxed(&ctl->target_id)) : -1;
   if (tid == 0) {
-    sm.n_settled = sm.n_relaxed = sm.n_open = sm.n_solo = sm.n_bound = 0;
+    sm.n_relaxed = sm.n_open = sm.n_solo = sm.n_bound = 0;
+    sm.n_fixed = 0ull;
     sm.n_scanned = 0ull;
     sm.solo_cand_r = sm.solo_surv_r = -1;
   }
@@ -1229,7 +1264,6 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     if (watchdog || reached || (phase == 1 && N == 0)) {
       if (bid == 0 && tid == 0) {
         if (watchdog) ctl->status = 7;
-        if (reached) sm.n_settled += N;  // the last frontier is fixed too
         ctl->rounds = watchdog ? a.max_rounds : (reached ? r - 1 : r);
       }
       if (act < nb && bid == 0) wake_parked(ctl, epoch, r, phase, 1, act, aep);
@@ -1268,7 +1302,6 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           ctl->open_ctr[cur ^ 1] = 0ull;
           ctl->front_ctr[cur ^ 1] = 0ull;
           ctl->live_ctr[cur ^ 1] = 0ull;
-          sm.n_settled += N;
           sm.n_relaxed += E;
         } else {
           sm.n_open += N;
@@ -1361,8 +1394,10 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
   }
   if (!BATCH && tid == 0 && sm.n_scanned)
     atomicAdd((unsigned long long *)&ctl->scanned, sm.n_scanned);
+  // settled: the source plus every vertex a bound step fixed
+  if (!BATCH && tid == 0 && (sm.n_fixed || bid == 0))
+    atomicAdd((unsigned long long *)&ctl->settled, sm.n_fixed + (bid == 0 ? 1ull : 0ull));
   if (bid == 0 && tid == 0) {
-    ctl->settled = sm.n_settled;
     ctl->relaxed = sm.n_relaxed;
     ctl->open_visits = sm.n_open;
     ctl->solo_phases = sm.n_solo;
@@ -1370,8 +1405,9 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
 }
 
 // ------------------------------------------------------------------ init
-// D = INF, C = 0 (both buffers), mtmp = INF, arrive = 0 over all state
-// entries; barrier flags and the per-block partial slots are reset.
+// D = INF, C = 0 (both buffers), mtmp = INF, arrive = 0 (and, with
+// label-correcting relax, DR = INF) over all state entries; barrier flags
+// and the per-block partial slots are reset.
 template <class V>
 __global__ void init_fill_kernel(RoundArgs a) {
   const int32_t stride = gridDim.x * blockDim.x;
@@ -1382,6 +1418,7 @@ __global__ void init_fill_kernel(RoundArgs a) {
     a.C1[i] = 0;
     a.mtmp[i] = V::INF;
     a.arrive[i] = 0u;
+    if (a.DR) a.DR[i] = V::INF;
   }
   for (int32_t i = t0; i < kMaxBlocks; i += stride) a.flags[i * kFlagStride] = 0u;
   for (int32_t i = t0; i < kParts * kMaxBlocks; i += stride) a.part[i] = V::INF;
@@ -1435,8 +1472,9 @@ __global__ void init_seed_kernel(RoundArgs a) {
           a.ithr[s * I + i] = V::INF;
         }
         a.irounds[i] = 0;
-        a.iscanned[2 * i] = 0ull;
-        a.iscanned[2 * i + 1] = 0ull;
+        a.iscanned[3 * i] = 0ull;
+        a.iscanned[3 * i + 1] = 0ull;
+        a.iscanned[3 * i + 2] = 0ull;
         if (a.istat) {
           a.istat[4 * i + 0] = 0;
           a.istat[4 * i + 1] = 0;

@@ -30,12 +30,15 @@ enum PartSlot {
   kParts
 };
 
-// Payload words carried by the lists.  A frontier item (fixed last round)
-// carries its out-offset and final D; an open item pushed as a survivor
+// Payload words carried by the lists.  A relax item carries its out-offset
+// and the D it is relaxed from; a fixed vertex carries its final D as is,
+// an open one (label-correcting relax) its D with bit 31 set (D keys are
+// non-negative, so the bit is free).  An open item pushed as a survivor
 // carries what its next bound step needs, so neither phase gathers them.
 // An open item pushed by relax (a first discovery) carries OX_BASE = -1:
-// the bound step then reads the vertex record, and its C is still 0 (C is
-// only ever raised on open vertices).
+// the bound step then reads the vertex record, and C (0, or under scope
+// ALL what the live pass raised it to).
+constexpr int32_t kOpenRelax = (int32_t)0x80000000;
 enum { FX_OOFF = 0, FX_D, kFX };
 enum { OX_BASE = 0, OX_IDEG, OX_OOFF, OX_ODEG, OX_OWM, OX_C, kOX };
 
@@ -94,7 +97,7 @@ struct RoundArgs {
   int32_t *open_x0[kOX], *open_x1[kOX];  // open-list payload words, by parity
   Ctl *ctl;
   int32_t *imin, *ithr, *irounds;  // batch: [3][I], [3][I], [I]
-  unsigned long long *iscanned;    // batch: [I][2] scanned in-edges, open visits
+  unsigned long long *iscanned;    // batch: [I][3] scanned in-edges, open visits, relaxed edges
   int32_t *heavy, *degen, *lvl, *flag, *scratch_pred;
   long long *istat;                // batch stats [4][I], zeroed by the seed kernel
   // optional round trace (SSSP_TRACE): per round kTraceFields entries
@@ -119,6 +122,10 @@ struct RoundArgs {
   // vertices; live lists (by round parity) hold those whose C is finite
   int32_t scope_all;
   int32_t *live_v0, *live_v1;
+  // label-correcting relax: per state entry the D it was last relaxed with
+  // (INF before its first relax)
+  int32_t *DR;
+  int32_t any_lc;  // some graph of the solve relaxes label-correcting
 };
 
 // Trace record of one round: wall-clock (100 MHz) at the relax start, block

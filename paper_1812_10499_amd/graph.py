@@ -14,12 +14,15 @@ import torch
 
 from . import _abi
 from ._abi import (Csr, SSSP_F32, SSSP_I32, SSSP_ORDER_AUTO, SSSP_ORDER_DEGREE,
-                   SSSP_SCOPE_ALL, SSSP_SCOPE_AUTO, SSSP_SCOPE_OPEN,
+                   SSSP_SCOPE_ALL, SSSP_SCOPE_AUTO, SSSP_SCOPE_OPEN, SSSP_RELAX_AUTO,
+                   SSSP_RELAX_CORRECTING, SSSP_RELAX_SETTING,
                    SSSP_ORDER_INPUT, Stats)
 
 I32_INF = 2**31 - 1
 ORDERS = {"auto": SSSP_ORDER_AUTO, "input": SSSP_ORDER_INPUT, "degree": SSSP_ORDER_DEGREE}
 SCOPES = {"auto": SSSP_SCOPE_AUTO, "open": SSSP_SCOPE_OPEN, "all": SSSP_SCOPE_ALL}
+RELAXES = {"auto": SSSP_RELAX_AUTO, "setting": SSSP_RELAX_SETTING,
+           "correcting": SSSP_RELAX_CORRECTING}
 
 
 def _stream() -> int:
@@ -39,11 +42,13 @@ class Graph:
     of edge id ``k``.  Weights are int32 (>= 1) or float32 (> 0).  ``order``
     picks the vertex numbering of the solver's working copy ("auto",
     "input" or "degree"); ``scope`` the C scope of single solves ("auto",
-    "open" or "all"; see :attr:`scope`).  Results never depend on either.
+    "open" or "all"; see :attr:`scope`), ``relax`` the relax step ("auto",
+    "setting" or "correcting"; see :attr:`relax`).  Results never depend on
+    any of them.
     """
 
     def __init__(self, n: int, src, dst, w, device="cuda", order: str = "auto",
-                 scope: str = "auto"):
+                 scope: str = "auto", relax: str = "auto"):
         device = torch.device(device)
         if isinstance(w, torch.Tensor):
             wt = w.to(device).contiguous()
@@ -74,6 +79,7 @@ class Graph:
                             self.perm.data_ptr(), _stream())
         self.perm = self.perm[:m]
         self.scope = scope
+        self.relax = relax
 
     @property
     def scope(self) -> str:
@@ -92,6 +98,22 @@ class Graph:
         if self.csr.scope == SSSP_SCOPE_AUTO:
             return "all" if self.csr.order == SSSP_ORDER_DEGREE else "open"
         return "all" if self.csr.scope == SSSP_SCOPE_ALL else "open"
+
+    @property
+    def relax(self) -> str:
+        """Relax step of every solve as set: "auto", "setting" or "correcting"."""
+        return {v: k for k, v in RELAXES.items()}[self.csr.relax]
+
+    @relax.setter
+    def relax(self, value: str):
+        if value not in RELAXES:
+            raise ValueError("relax must be one of %s" % sorted(RELAXES))
+        self.csr.relax = RELAXES[value]
+
+    @property
+    def effective_relax(self) -> str:
+        """The relax step solves run: "auto" is "setting"."""
+        return "correcting" if self.csr.relax == SSSP_RELAX_CORRECTING else "setting"
 
     @property
     def order(self) -> str:

@@ -10,18 +10,20 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-def oracle_mode(scope):
-    """The round simulator's mode for a solve's C scope ("open" or "all")."""
-    return oracle.MODE_SCOPE_ALL if scope == "all" else oracle.MODE_ADOPTED
+def oracle_mode(scope, relax="setting"):
+    """The round simulator's mode for a solve's C scope ("open" or "all") and
+    relax step ("setting" or "correcting")."""
+    mode = oracle.MODE_SCOPE_ALL if scope == "all" else oracle.MODE_ADOPTED
+    return mode | (oracle.MODE_LC if relax == "correcting" else 0)
 
 
-def oracle_solution(n, src, dst, w, source, scope="open"):
+def oracle_solution(n, src, dst, w, source, scope="open", relax="setting"):
     """(cost, pred (int64), settles, rounds, fixed_per_round, stats) from the
-    oracle, the round counts under the given C scope."""
+    oracle, the round counts under the given C scope and relax step."""
     cost, settles = oracle.dijkstra(n, src, dst, w, source)
     O = oracle.csr(n, src, dst)
     pred, _ = oracle.pred(O, w, source, cost)
-    sim = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(scope))
+    sim = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(scope, relax))
     assert np.array_equal(sim["cost"], cost)
     return dict(cost=cost, pred=pred, settles=settles, rounds=sim["rounds"],
                 relaxed=sim["relaxed_edges"], scanned=sim["scanned_in_edges"], csr=O)

@@ -34,7 +34,8 @@ def check_batch(sp, graphs, glist, inst_graph, inst_source, label):
     c, p = to_np(cost), to_np(pred).astype(np.int64)
     for i, (gi, s) in enumerate(zip(inst_graph, inst_source)):
         g = glist[gi]
-        ref = oracle_solution(g.n, g.src, g.dst, g.w, s)
+        # batches run C scope OPEN and each graph's relax step
+        ref = oracle_solution(g.n, g.src, g.dst, g.w, s, "open", graphs[gi].effective_relax)
         sl = slice(bases[i], bases[i] + g.n)
         assert np.array_equal(c[sl], ref["cost"]), (label, i)
         assert np.array_equal(p[sl], ref["pred"]), (label, i)
@@ -71,6 +72,18 @@ def test_batch_mixed_small(sp):
     inst_graph = [0, 1, 2, 3, 4, 2, 2, 0]
     inst_source = [int(rng.integers(0, glist[g].n)) for g in inst_graph]
     check_batch(sp, graphs, glist, inst_graph, inst_source, "mixed-small")
+
+
+def test_batch_label_correcting(sp):
+    # per-graph relax steps in one launch: label-correcting and label-setting
+    glist = gen.batch_workload(count=6, nmin=1000, nmax=20000)
+    graphs = [sp.Graph(g.n, g.src, g.dst, g.w, relax=("correcting" if k % 3 else "setting"))
+              for k, g in enumerate(glist)]
+    check_batch(sp, graphs, glist, [0, 1, 2, 3, 4, 5, 1, 2], [g.source for g in glist] +
+                [int(glist[1].n // 2), int(glist[2].n // 3)], "batch-lc")
+    d, _ = gen.diff_workload(side=48, num_sources=8)
+    G = sp.Graph(d.n, d.src, d.dst, d.w, relax="correcting")
+    check_batch(sp, [G], [d], [0] * 8, [int(s) for s in d.sources], "grid48x8-lc")
 
 
 def test_batch_workload_shape(sp):

@@ -24,8 +24,8 @@ def sp():
     return sp
 
 
-def check_build(sp, n, src, dst, w, order="auto", scope="auto"):
-    G = sp.Graph(n, src, dst, w, order=order, scope=scope)
+def check_build(sp, n, src, dst, w, order="auto", scope="auto", relax="auto"):
+    G = sp.Graph(n, src, dst, w, order=order, scope=scope, relax=relax)
     want = expected_order(n, src, dst) if order == "auto" else order
     assert G.order == (want if len(src) else "input"), (G.order, want)
     check_solver_copy(G, n, src, dst, w)
@@ -49,12 +49,13 @@ def check_build(sp, n, src, dst, w, order="auto", scope="auto"):
     return G
 
 
-def run_case(sp, n, src, dst, w, source, label, order="auto", scope="auto"):
-    print("case", label, "n=%d m=%d order=%s scope=%s" % (n, len(src), order, scope), flush=True)
-    G = check_build(sp, n, src, dst, w, order, scope)
+def run_case(sp, n, src, dst, w, source, label, order="auto", scope="auto", relax="auto"):
+    print("case", label, "n=%d m=%d order=%s scope=%s relax=%s" % (n, len(src), order, scope,
+                                                                  relax), flush=True)
+    G = check_build(sp, n, src, dst, w, order, scope, relax)
     cost, pred, st = sp.solve(G, source, with_pred=True, with_stats=True)
     sync()
-    ref = oracle_solution(n, src, dst, w, source, G.effective_scope)
+    ref = oracle_solution(n, src, dst, w, source, G.effective_scope, G.effective_relax)
     assert_same_solution(cost, pred, st, ref, label)
     # a second solve on the same graph reuses the workspace
     cost2, pred2, _ = sp.solve(G, source, with_pred=True)
@@ -158,10 +159,11 @@ def test_rmat_scaled(sp, scale, order):
         assert G.order == "degree"
 
 
-@pytest.mark.parametrize("scope", ["open", "all"])
-def test_scope_both_ways(sp, scope):
-    """Each C scope against the round simulator in the same scope, on every
-    workload family and the degenerate shapes."""
+@pytest.mark.parametrize("scope,relax", [("open", "setting"), ("all", "setting"),
+                                         ("open", "correcting"), ("all", "correcting")])
+def test_scope_and_relax_modes(sp, scope, relax):
+    """Each C scope and relax step against the round simulator in the same
+    mode, on every workload family and the degenerate shapes."""
     rng = np.random.default_rng(23)
     for trial in range(12):
         n = int(rng.integers(1, 400))
@@ -173,23 +175,31 @@ def test_scope_both_ways(sp, scope):
         else:
             w = (rng.integers(1, 2**24, m) * 2.0 ** -24).astype(np.float32)
         run_case(sp, n, src, dst, w, int(rng.integers(0, n)), "scope-rand-%d" % trial,
-                 ["input", "degree"][trial % 3 == 0], scope)
+                 ["input", "degree"][trial % 3 == 0], scope, relax)
     for order in ("input", "degree"):
         g = gen.rmat_workload(scale=14)
-        run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-rmat14-" + order, order, scope)
+        run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-rmat14-" + order, order, scope,
+                 relax)
     g = gen.grid_workload(side=48)
-    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-grid48", "auto", scope)
+    run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-grid48", "auto", scope, relax)
     run_case(sp, g.n, g.src, g.dst, np.ones(g.m, np.int32), g.source, "scope-grid48-unit",
-             "auto", scope)
+             "auto", scope, relax)
     for g in gen.batch_workload(count=2, nmin=1000, nmax=20000):
-        run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-" + g.name, "auto", scope)
+        run_case(sp, g.n, g.src, g.dst, g.w, g.source, "scope-" + g.name, "auto", scope, relax)
     # one vertex; no edges; a source with no out-edges; unreachable cycles
     run_case(sp, 1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32), 0,
-             "scope-single", "auto", scope)
+             "scope-single", "auto", scope, relax)
     src = np.array([1, 2, 3, 4, 0], np.int32)
     dst = np.array([2, 3, 1, 0, 5], np.int32)
     run_case(sp, 6, src, dst, np.array([3, 4, 5, 6, 7], np.int32), 0, "scope-cycle", "auto",
-             scope)
+             scope, relax)
+    # a vertex relaxed twice under label-correcting relax (hand-worked in the
+    # oracle's pins): 0->1 (10), 0->2 (1), 2->1 (1), 1->3 (1)
+    src = np.array([0, 0, 2, 1], np.int32)
+    dst = np.array([1, 2, 1, 3], np.int32)
+    G, st = run_case(sp, 4, src, dst, np.array([10, 1, 1, 1], np.int32), 0, "relax-twice",
+                     "auto", scope, relax)
+    assert st["relaxed_edges"] == (5 if relax == "correcting" else 4)
 
 
 @pytest.mark.parametrize("side", [32, 128])
@@ -218,7 +228,8 @@ def test_set_weights_then_solve(sp, order):
     check_solver_copy(G, g.n, g.src, g.dst, w2)
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
-    ref = oracle_solution(g.n, g.src, g.dst, w2, g.source, G.effective_scope)
+    ref = oracle_solution(g.n, g.src, g.dst, w2, g.source, G.effective_scope,
+                          G.effective_relax)
     assert_same_solution(cost, pred, st, ref, "rmat12-reweighted-" + order)
     # invalid weights are refused before anything is written
     bad = torch.from_numpy(w2[to_np(G.perm)]).cuda()
@@ -263,6 +274,7 @@ def test_workload_rmat22_full(sp):
     assert G.order == "degree"
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
-    ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source, G.effective_scope)
+    ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source, G.effective_scope,
+                          G.effective_relax)
     assert_same_solution(cost, pred, st, ref, "rmat22")
     print("rmat22 rounds", st, flush=True)

@@ -29,8 +29,8 @@ def check_target(sp, G, n, src, dst, w, source, target, label):
           flush=True)
     cost, st = sp.solve_target(G, source, target, with_stats=True)
     sync()
-    ref = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(G.effective_scope),
-                           target=target)
+    mode = oracle_mode(G.effective_scope, G.effective_relax)
+    ref = oracle.round_sim(n, src, dst, w, source, mode=mode, target=target)
     full, _ = oracle.dijkstra(n, src, dst, w, source)
     c = to_np(cost)
     bad = np.nonzero(c != ref["cost"])[0]
@@ -80,10 +80,11 @@ def test_target_random_small(sp, dtype, order):
             check_target(sp, G, n, src, dst, w, s, t, "%s-%s-%d-t%d" % (dtype, order, it, t))
 
 
-@pytest.mark.parametrize("scope", ["open", "all"])
-def test_target_rmat_and_grid(sp, scope):
+@pytest.mark.parametrize("scope,relax", [("open", "setting"), ("all", "setting"),
+                                         ("open", "correcting")])
+def test_target_rmat_and_grid(sp, scope, relax):
     g = gen.rmat_workload(scale=14)
-    G = sp.Graph(g.n, g.src, g.dst, g.w, scope=scope)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, scope=scope, relax=relax)
     full, _ = oracle.dijkstra(g.n, g.src, g.dst, g.w, g.source)
     reach = np.nonzero(full != np.int32(2**31 - 1))[0]
     order = reach[np.argsort(full[reach], kind="stable")]
@@ -91,7 +92,7 @@ def test_target_rmat_and_grid(sp, scope):
     for t in (int(order[1]), int(order[len(order) // 2]), int(order[-1]), int(unreach[0])):
         check_target(sp, G, g.n, g.src, g.dst, g.w, g.source, t, "rmat14-t%d" % t)
     g = gen.grid_workload(side=64)
-    G = sp.Graph(g.n, g.src, g.dst, g.w, scope=scope)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, scope=scope, relax=relax)
     for t in (0, g.n - 1, g.source + 1):
         check_target(sp, G, g.n, g.src, g.dst, g.w, g.source, t, "grid64-t%d" % t)
 
