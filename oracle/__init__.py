@@ -10,6 +10,8 @@ Functions and the passages they follow:
 
 * :func:`dijkstra` -- Fig. 1 (binary-heap Dijkstra); the definition of
   ``cost[x]`` in Section I.
+* :func:`sp12` -- SP_1 and SP_2 (Figs. 3 and 4; Sections III and IV), the
+  sequential algorithms, with their heap operations counted.
 * :func:`bellman_ford` -- brute-force relaxation to a fixpoint (tiny graphs).
 * :func:`dag` -- topological-order DP, the O(e) behaviour the SP_1/SP_2
   theorems give on acyclic graphs.
@@ -100,6 +102,22 @@ def dijkstra(n, src, dst, w, source, target=None):
     if rc != 0:
         raise ValueError("oracle_dijkstra failed: %d" % rc)
     return cost, settles.value
+
+
+def sp12(n, src, dst, w, source, variant):
+    """SP_1 (variant 1, Fig. 3) or SP_2 (variant 2, Fig. 4), or Dijkstra in
+    the same framework (variant 0).  Returns (cost, ops) with ops a dict of
+    remove_min, insert, adjust and fixed_by_r counts."""
+    k, w = _kind(w)
+    src, dst = _i32(src), _i32(dst)
+    cost = np.empty(n, dtype=w.dtype)
+    ops = np.zeros(4, dtype=np.int64)
+    rc = _call("oracle_sp12_" + k, ctypes.c_int32(n), ctypes.c_int64(len(src)), _p(src),
+               _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int(variant), _p(cost), _p(ops))
+    if rc != 0:
+        raise ValueError("oracle_sp12 failed: %d" % rc)
+    return cost, dict(remove_min=int(ops[0]), insert=int(ops[1]), adjust=int(ops[2]),
+                      fixed_by_r=int(ops[3]))
 
 
 def bellman_ford(n, src, dst, w, source):

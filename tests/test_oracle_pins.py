@@ -529,3 +529,59 @@ def test_label_correcting_costs_and_invariants(dtype):
             assert 1 <= r["rounds"] <= settles
             assert r["settled"] == settles
             assert r["relaxed_edges"] >= ls["relaxed_edges"]
+
+
+def _heap_ops(o):
+    return o["remove_min"] + o["insert"] + o["adjust"]
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_sp12_costs(dtype):
+    """SP_1 and SP_2 (Figs. 3 and 4) reach Dijkstra's costs; variant 0 is
+    Dijkstra in the same framework and removes each reachable vertex once."""
+    rng = np.random.default_rng(18)
+    for _ in range(400):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 30)))
+        c, settles = oracle.dijkstra(n, src, dst, w, s)
+        c0, o0 = oracle.sp12(n, src, dst, w, s, 0)
+        assert np.array_equal(c0, c) and o0["remove_min"] == settles == o0["insert"]
+        assert o0["fixed_by_r"] == 0
+        for v in (1, 2):
+            cv, ov = oracle.sp12(n, src, dst, w, s, v)
+            assert np.array_equal(cv, c)
+            # every reachable vertex is fixed once: by removeMin or through R
+            assert ov["fixed_by_r"] <= settles - 1
+
+
+def test_sp12_dag_theorem():
+    """On a DAG whose only vertex without in-edges is the source, SP_1 and
+    SP_2 fix every vertex through R: one insertion and one removeMin (the
+    source), no adjustments (the O(e) case of the SP_1 theorem)."""
+    rng = np.random.default_rng(19)
+    for _ in range(100):
+        n = int(rng.integers(2, 80))
+        src, dst = [], []
+        for v in range(1, n):
+            for u in rng.choice(v, size=int(rng.integers(1, min(v, 4) + 1)), replace=False):
+                src.append(u)
+                dst.append(v)
+        src, dst = np.array(src, np.int32), np.array(dst, np.int32)
+        w = rng.integers(1, 100, len(src)).astype(np.int32)
+        c = oracle.dag(n, src, dst, w, 0)
+        for v in (1, 2):
+            cv, ov = oracle.sp12(n, src, dst, w, 0, v)
+            assert np.array_equal(cv, c)
+            assert ov == dict(remove_min=1, insert=1, adjust=0, fixed_by_r=n - 1)
+
+
+def test_sp12_heap_operations_on_workloads():
+    """SP_2 needs no more heap operations than Dijkstra on every workload
+    family (Section I's claim; SP_1 can need one more adjustment on a few
+    graphs, see the readings), and fixes part of each graph through R."""
+    for g in (gen.grid_workload(side=64), gen.rmat_workload(scale=14), gen.random_workload(),
+              gen.batch_workload(count=2, nmin=1000, nmax=5000)[1]):
+        c, _ = oracle.dijkstra(g.n, g.src, g.dst, g.w, g.source)
+        _, o0 = oracle.sp12(g.n, g.src, g.dst, g.w, g.source, 0)
+        _, o2 = oracle.sp12(g.n, g.src, g.dst, g.w, g.source, 2)
+        assert _heap_ops(o2) <= _heap_ops(o0)
+        assert o2["fixed_by_r"] > 0
