@@ -665,7 +665,10 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
           if (val[j]) {
             cand[j] = V::add(S.dx[it[j]], wt[j]);
             gy[j] = S.sb[it[j]] + y[j];
-            dk[j] = a.D64[gy[j]];  // may be stale: only filters the atomic
+            // may be stale: only filters the atomic, against contention on
+            // hot heads in the big rounds; a one-block phase goes straight
+            // to the atomic and saves the dependent load
+            dk[j] = pc.solo ? 0x7fffffffffffffffull : a.D64[gy[j]];
           }
         }
         // A float edge that leaves the cost unchanged (w below half an ulp)
