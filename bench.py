@@ -7,8 +7,9 @@ progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22]
 
 Other workloads: grid1024, random4096, rmatNN (single solves, same fields),
-batch256 (256 instances in one launch against 256 single solves) and
-diff512 (64-source forward, backward and both against 64 single solves).
+batch256 (256 instances in one launch against 256 single solves),
+diff512 (64-source forward, backward and both against 64 single solves) and
+target22 (single-target early exit to eight targets on the RMAT-22 graph).
 
 value = GTEPS = m_reach / t_step (m_reach: edges whose tail is reachable,
 each relaxed exactly once per solve).  roofline.achieved = algorithmic bytes
@@ -229,6 +230,71 @@ def bench_diff(args, sp, torch):
     }
 
 
+def bench_target(args, sp, torch):
+    """Single-target early exit on the R-MAT scale-22 graph: eight reachable
+    targets at the 1/8, 2/8, ..., 8/8 points of the cost order; one step =
+    the eight sssp_solve_target calls.  Rounds to each target are reported
+    beside Dijkstra's heap removals up to the same target (the oracle)."""
+    import numpy as np
+    import gen
+    g = gen.rmat_workload()
+    G = sp.Graph(g.n, g.src, g.dst, g.w, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    cost = torch.empty(g.n, dtype=G.value_dtype, device="cuda:0")
+    st = sp.Stats()
+    sp.sssp_solve(G.csr, g.source, cost.data_ptr(), None, st, stream.cuda_stream)
+    full = st.as_dict()
+    c = cost.cpu().numpy()
+    reach = np.nonzero(c != np.iinfo(np.int32).max)[0]
+    order = reach[np.argsort(c[reach], kind="stable")]
+    targets = [int(order[min(len(order) - 1, (len(order) * k) // 8)]) for k in range(1, 9)]
+    per = []
+    for t in targets:
+        _, s = sp.solve_target(G, g.source, t, with_stats=True)
+        per.append(s)
+
+    def step():
+        for t in targets:
+            sp.sssp_solve_target(G.csr, g.source, t, cost.data_ptr(), None, stream.cuda_stream)
+
+    def full_solve():
+        sp.sssp_solve(G.csr, g.source, cost.data_ptr(), None, None, stream.cuda_stream)
+
+    for _ in range(args.warmup):
+        step()
+        full_solve()
+    t_step = timed(step, args.steps, stream)
+    t_full = timed(full_solve, args.steps, stream)
+    relaxed = sum(s["relaxed_edges"] for s in per)
+    log("8 targets %.3f ms, full solve %.3f ms" % (t_step, t_full))
+    pops, cpu = None, None
+    if not args.no_cpu_baseline:
+        # the CPU leg: Dijkstra stopped at the same targets, timed
+        import oracle
+        pops = []
+        t0 = time.perf_counter()
+        for t in targets:
+            _, p = oracle.dijkstra(g.n, g.src, g.dst, g.w, g.source, target=t)
+            pops.append(int(p))
+        sec = time.perf_counter() - t0
+        cpu = {"value": relaxed / sec / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "Dijkstra stopped at each of the 8 targets, one thread, %.1f s; "
+                         "GTEPS on the edges the GPU rounds relaxed" % sec}
+    return {
+        "value": round(relaxed / (t_step * 1e-3) / 1e9, 4), "ms_per_step": round(t_step, 4),
+        "dtype": "int32",
+        "config": {"workload": "rmat22_ef16_single_target_x8", "n": g.n, "m": g.m,
+                   "source": g.source, "targets": targets, "relaxed_edges": relaxed},
+        "ms_per_target": round(t_step / len(targets), 4),
+        "full_solve_ms": round(t_full, 4),
+        "rounds_to_target": [s["rounds"] for s in per],
+        "dijkstra_pops_to_target": pops,
+        "settled_at_stop": [s["settled"] for s in per],
+        "full_rounds": full["rounds"], "full_settled": full["settled"],
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,8 +315,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.workload in ("batch256", "diff512"):
-        res = (bench_batch if args.workload == "batch256" else bench_diff)(args, sp, torch)
+    if args.workload in ("batch256", "diff512", "target22"):
+        res = {"batch256": bench_batch, "diff512": bench_diff,
+               "target22": bench_target}[args.workload](args, sp, torch)
         out = {"metric": METRIC, "value": res.pop("value"), "unit": "GTEPS", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup,
                "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True,
