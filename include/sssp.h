@@ -84,10 +84,14 @@ typedef enum { SSSP_ORDER_AUTO = 0, SSSP_ORDER_INPUT = 1, SSSP_ORDER_DEGREE = 2 
  *                    C'[y] = max(C[y], minD, m_y), m_y over all its
  *                    in-edges; unreachable vertices reach C = INF and stop
  *                    holding their out-neighbours' bounds down
- *   SSSP_SCOPE_AUTO  ALL for graphs in degree order (skewed degrees), else
- *                    OPEN
- * Single solves (sssp_solve, sssp_solve_target) honour the graph's scope;
- * sssp_solve_batch always runs OPEN.
+ *   SSSP_SCOPE_AUTO  ALL when the largest total degree is at least 3m/n
+ *                    (1.5 times the mean), else OPEN.  Graphs with uniform
+ *                    degrees (grids, road-like networks) have long diameters:
+ *                    their vertices stay undiscovered for many rounds, and
+ *                    raising C on all of them costs more than the rounds it
+ *                    saves; skewed and random graphs finish discovery within
+ *                    a few rounds.
+ * Every solve honours the scope of its graph.
  */
 typedef enum { SSSP_SCOPE_AUTO = 0, SSSP_SCOPE_OPEN = 1, SSSP_SCOPE_ALL = 2 } sssp_scope;
 
@@ -122,6 +126,7 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  *   scope         sssp_scope of the single solves on this graph (the
  *                 builder sets SSSP_SCOPE_AUTO; the caller may change it)
  *   relax         sssp_relax of the solves on this graph (likewise AUTO)
+ *   deg_max       largest out-degree + in-degree (filled by the builder)
  * The solver's working copy.  Always: in-lists ordered by weight, so that
  * the in-edges a lower-bound step needs (minD + w < D[y]) form a prefix:
  *   s_in_off[n+1], s_in_src[m] (solver ids), s_in_eid[m], s_in_w[m]
@@ -146,6 +151,7 @@ typedef struct {
   int32_t order; /* sssp_order the builder applied: INPUT or DEGREE */
   int32_t scope; /* sssp_scope of single solves */
   int32_t relax; /* sssp_relax of every solve on this graph */
+  int32_t deg_max; /* largest total degree */
   const int32_t *out_off;
   const int32_t *out_dst;
   const void *out_w;

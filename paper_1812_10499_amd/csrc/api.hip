@@ -23,7 +23,7 @@ enum Slot {
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
-  S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1, S_LV0, S_LV1, S_DR,
+  S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1, S_LV0, S_LV1, S_DR, S_INSTOF, S_IDEAD,
   NSLOTS
 };
 
@@ -158,8 +158,13 @@ bool csr_ok(const sssp_csr *g) {
   return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && (g->m == 0 || g->s_out_eid);
 }
 
-// SSSP_SCOPE_AUTO: scope ALL on graphs the builder put in degree order.
-bool effective_auto_all(const sssp_csr *g) { return g->order == SSSP_ORDER_DEGREE; }
+// The C scope a graph's solves use (SSSP_SCOPE_AUTO: ALL when the largest
+// total degree is at least 3m/n).
+bool scope_all_of(const sssp_csr *g) {
+  if (g->scope == SSSP_SCOPE_AUTO)
+    return g->m > 0 && (int64_t)g->deg_max * g->n >= 3 * (int64_t)g->m;
+  return g->scope == SSSP_SCOPE_ALL;
+}
 
 // The relax step a graph's solves use (SSSP_RELAX_AUTO: label-setting).
 bool relax_correcting(const sssp_csr *g) { return g->relax == SSSP_RELAX_CORRECTING; }
@@ -193,6 +198,7 @@ GraphDev graph_dev(const sssp_csr *g) {
   d.n = g->n;
   d.m = g->m;
   d.lc = relax_correcting(g) ? 1 : 0;
+  d.all = scope_all_of(g) ? 1 : 0;
   return d;
 }
 
@@ -294,6 +300,10 @@ sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
   if (a.scope_all) {
     if ((s = ws_arr(w, S_LV0, T, &a.live_v0))) return s;
     if ((s = ws_arr(w, S_LV1, T, &a.live_v1))) return s;
+    if (batch) {
+      if ((s = ws_arr(w, S_INSTOF, T, &a.inst_of))) return s;
+      if ((s = ws_arr(w, S_IDEAD, 2 * (size_t)num_inst, &a.idead))) return s;
+    }
   }
   if (a.any_lc && (s = ws_arr(w, S_DR, T, &a.DR))) return s;
   if (batch) {
@@ -494,6 +504,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->order = SSSP_ORDER_INPUT;
   out->scope = SSSP_SCOPE_AUTO;
   out->relax = SSSP_RELAX_AUTO;
+  out->deg_max = 0;
   out->out_off = out_off;
   out->out_dst = out_dst;
   out->out_w = out_w;
@@ -523,11 +534,14 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   c.in_eid = arr(B_S_IN_EID);
   c.in_w = arr(B_S_IN_W);
   c.vrec = arr(B_S_VREC);
-  if (order != SSSP_ORDER_INPUT && m > 0) {
+  if (m > 0) {
     HIPCHK(launch_degree(n, out_off, in_off, t, stream));
     HIPCHK(hipMemcpyAsync(hs, t.status, sizeof(hs), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
-    const int32_t dmax = hs[2];
+    out->deg_max = hs[2];
+  }
+  if (order != SSSP_ORDER_INPUT && m > 0) {
+    const int32_t dmax = out->deg_max;
     // skewed: largest total degree >= 16 x the mean 2m/n
     const bool skewed = (int64_t)dmax * n >= 32 * (int64_t)m;
     if (order == SSSP_ORDER_DEGREE || skewed) {
@@ -636,8 +650,7 @@ static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, 
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
   a.target = target;
-  a.scope_all = g->scope == SSSP_SCOPE_ALL ||
-                (g->scope == SSSP_SCOPE_AUTO && effective_auto_all(g));
+  a.scope_all = a.g.all;
   a.any_lc = a.g.lc;
   if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
   LaunchGeom geo;
@@ -719,8 +732,10 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   a.D = (int32_t *)cost;
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
-  for (int32_t i = 0; i < num_inst; ++i)
+  for (int32_t i = 0; i < num_inst; ++i) {
     if (relax_correcting(&graphs[inst_graph[i]])) a.any_lc = 1;
+    if (scope_all_of(&graphs[inst_graph[i]])) a.scope_all = 1;
+  }
   if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
   GraphDev *dg;
   InstDev *di;
@@ -773,11 +788,20 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
                      hipMemcpyDeviceToHost));
     Ctl c;
     HIPCHK(hipMemcpy(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    // scope ALL: unreachable vertices dropped from the live list in round
+    // r_d are still scanned in every later bound step of their instance
+    // (rounds - 1 of them)
+    std::vector<unsigned long long> dd(2 * (size_t)num_inst, 0ull);
+    if (a.idead)
+      HIPCHK(hipMemcpy(dd.data(), a.idead, sizeof(unsigned long long) * 2 * num_inst,
+                       hipMemcpyDeviceToHost));
     for (int32_t i = 0; i < num_inst; ++i) {
       stats[i].rounds = hr[i];
       stats[i].settled = (int32_t)hst[4 * i + 1];
       stats[i].relaxed_edges = (int64_t)sc[3 * i + 2];
-      stats[i].scanned_in_edges = (int64_t)sc[3 * i];
+      stats[i].scanned_in_edges =
+          (int64_t)(sc[3 * i] + dd[2 * i] * (unsigned long long)(hr[i] > 0 ? hr[i] - 1 : 0) -
+                    dd[2 * i + 1]);
       stats[i].open_visits = (int64_t)sc[3 * i + 1];
     }
     HIPCHK(hipEventRecord(ws.last, stream));

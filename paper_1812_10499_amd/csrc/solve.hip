@@ -205,9 +205,10 @@ __device__ void batch_lds_flush(BatchLds<true> &bl, const RoundArgs &a, int slot
     }
     if (relax) {
       if (bl.scan[i]) atomicAdd(&a.iscanned[3 * i + 2], (unsigned long long)bl.scan[i]);
-    } else if (bl.visit[i]) {
-      atomicAdd(&a.iscanned[3 * i], (unsigned long long)bl.scan[i]);
-      atomicAdd(&a.iscanned[3 * i + 1], (unsigned long long)bl.visit[i]);
+    } else {
+      // the live pass adds scanned counts for instances with no open item here
+      if (bl.scan[i]) atomicAdd(&a.iscanned[3 * i], (unsigned long long)bl.scan[i]);
+      if (bl.visit[i]) atomicAdd(&a.iscanned[3 * i + 1], (unsigned long long)bl.visit[i]);
     }
   }
 }
@@ -769,16 +770,17 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
 // The method's scanned count takes every undiscovered vertex's whole
 // in-degree each round; dropped unreachable ones are settled at the end
 // from dead_deg and dead_deg_r.
-template <class V>
-__device__ void live_pass(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, int r, int NL,
-                          int32_t md, const int32_t *Cold, int32_t *Cnew) {
+template <class V, bool BATCH>
+__device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
+                          const PhaseCtx &pc, int r, int NL, int32_t md, const int32_t *Cold,
+                          int32_t *Cnew) {
   const int tid = threadIdx.x;
-  const int cur = r & 1;
+  const int cur = r & 1, s_now = r % 3;
+  const int I = a.num_inst;
   SmemLive &L = sm.u.l;
   const int32_t *Lv = cur ? a.live_v1 : a.live_v0;
   int32_t *Ln = cur ? a.live_v0 : a.live_v1;
   unsigned long long *lctr = &a.ctl->live_ctr[cur ^ 1];
-  const GraphDev &G = a.g;
   if (tid == 0) L.cnt = 0;
   __syncthreads();
   // tiles of RBS list entries go round-robin to the blocks: the lists keep
@@ -787,27 +789,51 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, i
   for (uint32_t b0 = pc.vbid * RBS; b0 < (uint32_t)NL; b0 += pc.vnb * RBS) {
     const uint32_t i = b0 + (uint32_t)tid;
     bool keep = false;
-    int32_t y = 0;
+    int32_t y = 0;  // state entry
     if (i < (uint32_t)NL) {
       y = (r == 1) ? (int32_t)i : Lv[i];
-      if ((int32_t)(a.D64[y] >> 32) == V::INF) {
+      int32_t sb = 0, gi = 0, ins = 0, mdi = md;
+      if constexpr (BATCH) {
+        // the entry's instance, and that instance's minD this round (INF:
+        // its rounds have ended, so its undiscovered vertices are done)
+        ins = a.inst_of[y];
+        const InstDev id = a.insts[ins];
+        sb = id.sbase;
+        gi = id.graph;
+        mdi = ld_relaxed(&a.imin[s_now * I + ins]);
+      }
+      const GraphDev &G = graph_of<BATCH>(a, gi);
+      if (G.all && mdi != V::INF && (int32_t)(a.D64[y] >> 32) == V::INF) {
         const int32_t c = Cold[y];
-        const int4 rec = G.vrec[2 * y];  // out_off, out_degree, in_off, in_degree
+        const int4 rec = G.vrec[2 * (y - sb)];  // out_off, out_degree, in_off, in_degree
         const int32_t b = rec.z, deg = rec.w;
-        scanned += deg;
+        const int32_t *Cg = Cold + sb;  // the instance's C, by graph-local id
+        if constexpr (BATCH) {
+          if (I > kLdsInst) atomicAdd(&a.iscanned[3 * ins], (unsigned long long)deg);
+          else atomicAdd(&bl.scan[ins], (uint32_t)deg);
+        } else {
+          scanned += deg;
+        }
         if (c == V::INF) {
           Cnew[y] = V::INF;
-          ddeg += deg;
-          ddeg_r += (long long)deg * r;
+          if constexpr (BATCH) {
+            if (deg) {
+              atomicAdd(&a.idead[2 * ins], (unsigned long long)deg);
+              atomicAdd(&a.idead[2 * ins + 1], (unsigned long long)deg * (unsigned long long)r);
+            }
+          } else {
+            ddeg += deg;
+            ddeg_r += (long long)deg * r;
+          }
         } else {
           int32_t m = V::INF;
           int32_t j = 0;
           if (deg > 0) {
             // the lightest in-edge alone first: its tail usually decides m
             const int32_t v0 = G.in_src[b], w0 = G.in_w[b];
-            const int32_t c0 = Cold[v0];
-            if (c0 != V::INF) m = V::add(kmax(c0, md), w0);
-            j = (V::add(md, w0) >= m) ? deg : 1;
+            const int32_t c0 = Cg[v0];
+            if (c0 != V::INF) m = V::add(kmax(c0, mdi), w0);
+            j = (V::add(mdi, w0) >= m) ? deg : 1;
           }
           for (; j < deg; j += 4) {
             int32_t vs[4], ws[4];
@@ -819,18 +845,18 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, i
             }
             int32_t cs[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) cs[q] = (j + q < deg) ? Cold[vs[q]] : V::INF;
+            for (int q = 0; q < 4; ++q) cs[q] = (j + q < deg) ? Cg[vs[q]] : V::INF;
             int32_t wl = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               if (j + q < deg) {
-                if (cs[q] != V::INF) m = kmin(m, V::add(kmax(cs[q], md), ws[q]));
+                if (cs[q] != V::INF) m = kmin(m, V::add(kmax(cs[q], mdi), ws[q]));
                 wl = ws[q];
               }
             }
-            if (V::add(md, wl) >= m) break;
+            if (V::add(mdi, wl) >= m) break;
           }
-          Cnew[y] = kmax(kmax(c, md), m);
+          Cnew[y] = kmax(kmax(c, mdi), m);
           keep = true;
         }
       }
@@ -861,11 +887,13 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc, i
       for (int j = tid; j < cnt; j += RBS) Ln[L.base + j] = L.v[j];
     }
   }
-  const long long s1 = wave_sum64(scanned), s2 = wave_sum64(ddeg), s3 = wave_sum64(ddeg_r);
-  if (lane_id() == 0) {
-    if (s1) atomicAdd(&sm.n_scanned, (unsigned long long)s1);
-    if (s2) atomicAdd(&a.ctl->dead_deg, (unsigned long long)s2);
-    if (s3) atomicAdd(&a.ctl->dead_deg_r, (unsigned long long)s3);
+  if constexpr (!BATCH) {
+    const long long s1 = wave_sum64(scanned), s2 = wave_sum64(ddeg), s3 = wave_sum64(ddeg_r);
+    if (lane_id() == 0) {
+      if (s1) atomicAdd(&sm.n_scanned, (unsigned long long)s1);
+      if (s2) atomicAdd(&a.ctl->dead_deg, (unsigned long long)s2);
+      if (s3) atomicAdd(&a.ctl->dead_deg_r, (unsigned long long)s3);
+    }
   }
   __syncthreads();
 }
@@ -943,7 +971,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           xv[OX_OWM] = G.vrec[2 * yl + 1].x;
           // C of an undiscovered vertex: 0, or under scope ALL what the
           // live pass raised it to
-          xv[OX_C] = a.scope_all ? Cold[gy] : 0;
+          xv[OX_C] = G.all ? Cold[gy] : 0;
         }
         S.base[tid] = xv[OX_BASE];
         S.ideg[tid] = xv[OX_IDEG];
@@ -1144,11 +1172,9 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
   }
   stage_flush(S.fr, front, BATCH);
   stage_flush(S.op, next_open, BATCH);
-  if constexpr (!BATCH) {
-    if (NL > 0) {
-      __syncthreads();  // the live pass reuses the stagers' LDS
-      live_pass<V>(a, sm, pc, r, NL, mind_all, Cold, Cnew);
-    }
+  if (NL > 0) {
+    __syncthreads();  // the live pass reuses the stagers' LDS
+    live_pass<V, BATCH>(a, sm, bl, pc, r, NL, mind_all, Cold, Cnew);
   }
   mark(a, r, 1, 8);
   if constexpr (!BATCH) {
@@ -1274,7 +1300,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
     }
     // scope ALL: the bound step also walks the live list (round 1: all n)
     const int NL = (phase == 1 && a.scope_all)
-                       ? (r == 1 ? a.g.n : uni((int)ld_relaxed64(&ctl->live_ctr[cur])))
+                       ? (r == 1 ? a.total : uni((int)ld_relaxed64(&ctl->live_ctr[cur])))
                        : 0;
     const uint32_t WL = CW_LIVE * (uint32_t)NL;
     const uint32_t WT = E + (phase == 0 ? CW_RELAX : CW_FUSED) * (uint32_t)N + WL;
@@ -1427,6 +1453,15 @@ __global__ void init_fill_kernel(RoundArgs a) {
   for (int32_t i = t0; i < kParts * kMaxBlocks; i += stride) a.part[i] = V::INF;
 }
 
+// Batched solves with a scope-ALL graph: the instance of every state entry
+// (block b fills instance b's range).
+__global__ void inst_of_kernel(RoundArgs a) {
+  for (int i = blockIdx.x; i < a.num_inst; i += gridDim.x) {
+    const InstDev id = a.insts[i];
+    for (int32_t j = threadIdx.x; j < id.n; j += blockDim.x) a.inst_of[id.sbase + j] = i;
+  }
+}
+
 // One block: seeds every instance's source, the first frontier (with its
 // out-degree prefix, read by round 1 at parity 1) and the control block.
 template <class V, bool BATCH>
@@ -1478,6 +1513,10 @@ __global__ void init_seed_kernel(RoundArgs a) {
         a.iscanned[3 * i] = 0ull;
         a.iscanned[3 * i + 1] = 0ull;
         a.iscanned[3 * i + 2] = 0ull;
+        if (a.idead) {
+          a.idead[2 * i] = 0ull;
+          a.idead[2 * i + 1] = 0ull;
+        }
         if (a.istat) {
           a.istat[4 * i + 0] = 0;
           a.istat[4 * i + 1] = 0;
@@ -1527,6 +1566,11 @@ static hipError_t launch_solve_t(const RoundArgs &a, int32_t *pred, const Launch
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((init_seed_kernel<V, BATCH>), dim3(1), dim3(RBS), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (BATCH && a.inst_of) {
+      const int nbk = a.num_inst < 1024 ? a.num_inst : 1024;
+      hipLaunchKernelGGL(inst_of_kernel, dim3(nbk), dim3(256), 0, stream, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   {
     RoundArgs arg = a;

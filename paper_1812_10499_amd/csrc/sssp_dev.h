@@ -56,7 +56,8 @@ struct GraphDev {
   const int32_t *u_out_off, *u_out_dst;
   const int32_t *u_in_off, *u_in_src, *u_in_eid, *u_in_w;
   int32_t n, m;
-  int32_t lc;  // label-correcting relax on this graph
+  int32_t lc;   // label-correcting relax on this graph
+  int32_t all;  // C scope ALL on this graph
 };
 
 // Instance i of a batch: graph index, source vertex (graph-local), base of

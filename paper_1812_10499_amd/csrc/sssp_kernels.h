@@ -120,8 +120,10 @@ struct RoundArgs {
   int32_t target;            // single solve: stop once this vertex (caller's id) is fixed, or -1
   // single solve, C scope ALL: the bound step also raises C of undiscovered
   // vertices; live lists (by round parity) hold those whose C is finite
-  int32_t scope_all;
+  int32_t scope_all;  // some graph of the solve runs C scope ALL
   int32_t *live_v0, *live_v1;
+  int32_t *inst_of;              // batch, scope ALL: the instance of each state entry
+  unsigned long long *idead;     // batch, scope ALL: [I][2] dead_deg, dead_deg_r
   // label-correcting relax: per state entry the D it was last relaxed with
   // (INF before its first relax)
   int32_t *DR;

@@ -83,7 +83,7 @@ class Graph:
 
     @property
     def scope(self) -> str:
-        """C scope of single solves as set: "auto", "open" or "all"."""
+        """C scope of the solves as set: "auto", "open" or "all"."""
         return {v: k for k, v in SCOPES.items()}[self.csr.scope]
 
     @scope.setter
@@ -94,9 +94,11 @@ class Graph:
 
     @property
     def effective_scope(self) -> str:
-        """The scope single solves run: "auto" is "all" in degree order."""
+        """The scope solves run: "auto" is "all" when the largest total
+        degree is at least 3m/n."""
         if self.csr.scope == SSSP_SCOPE_AUTO:
-            return "all" if self.csr.order == SSSP_ORDER_DEGREE else "open"
+            c = self.csr
+            return "all" if c.m > 0 and c.deg_max * c.n >= 3 * c.m else "open"
         return "all" if self.csr.scope == SSSP_SCOPE_ALL else "open"
 
     @property

@@ -34,8 +34,9 @@ def check_batch(sp, graphs, glist, inst_graph, inst_source, label):
     c, p = to_np(cost), to_np(pred).astype(np.int64)
     for i, (gi, s) in enumerate(zip(inst_graph, inst_source)):
         g = glist[gi]
-        # batches run C scope OPEN and each graph's relax step
-        ref = oracle_solution(g.n, g.src, g.dst, g.w, s, "open", graphs[gi].effective_relax)
+        # each instance runs its graph's C scope and relax step
+        ref = oracle_solution(g.n, g.src, g.dst, g.w, s, graphs[gi].effective_scope,
+                              graphs[gi].effective_relax)
         sl = slice(bases[i], bases[i] + g.n)
         assert np.array_equal(c[sl], ref["cost"]), (label, i)
         assert np.array_equal(p[sl], ref["pred"]), (label, i)
@@ -44,15 +45,12 @@ def check_batch(sp, graphs, glist, inst_graph, inst_source, label):
         assert st["settled"] == ref["settles"], (label, i)
         assert st["relaxed_edges"] == ref["relaxed"], (label, i)
         assert st["scanned_in_edges"] == ref["scanned"], (label, i)
-        # identical to the single solve of the same instance (batches run
-        # C scope OPEN)
-        prev = graphs[gi].scope
-        graphs[gi].scope = "open"
+        # identical to the single solve of the same instance
         c1, p1, st1 = sp.solve(graphs[gi], s, with_pred=True, with_stats=True)
         sync()
-        graphs[gi].scope = prev
         assert np.array_equal(to_np(c1), c[sl]) and np.array_equal(to_np(p1), to_np(pred)[sl])
         assert st1["rounds"] == st["rounds"] and st1["open_visits"] == st["open_visits"]
+        assert st1["scanned_in_edges"] == st["scanned_in_edges"]
     return cost, pred
 
 
@@ -84,6 +82,21 @@ def test_batch_label_correcting(sp):
     d, _ = gen.diff_workload(side=48, num_sources=8)
     G = sp.Graph(d.n, d.src, d.dst, d.w, relax="correcting")
     check_batch(sp, [G], [d], [0] * 8, [int(s) for s in d.sources], "grid48x8-lc")
+
+
+@pytest.mark.parametrize("scope", ["open", "all"])
+def test_batch_scopes(sp, scope):
+    # every instance in one C scope, mixed numberings, plus a skewed graph
+    glist = gen.batch_workload(count=5, nmin=1000, nmax=20000)
+    glist.append(gen.rmat_workload(scale=12))
+    graphs = [sp.Graph(g.n, g.src, g.dst, g.w.astype(np.float32) if g.w.dtype != np.float32
+                       else g.w, order=("degree" if k % 2 else "input"), scope=scope)
+              for k, g in enumerate(glist)]
+    glist = [gen.Graph(g.name, g.n, g.src, g.dst,
+                       g.w.astype(np.float32) if g.w.dtype != np.float32 else g.w, g.source)
+             for g in glist]
+    check_batch(sp, graphs, glist, [0, 1, 2, 3, 4, 5, 5, 0],
+                [g.source for g in glist] + [int(glist[5].n // 3), 7], "batch-" + scope)
 
 
 def test_batch_workload_shape(sp):
@@ -131,7 +144,9 @@ def test_batch_more_instances_than_lds_slots(sp):
     for i, (gi, s) in enumerate(zip(inst_graph, inst_source)):
         if (gi, s) not in refs:
             g = glist[gi]
-            refs[(gi, s)] = oracle_solution(g.n, g.src, g.dst, g.w, s)
+            refs[(gi, s)] = oracle_solution(g.n, g.src, g.dst, g.w, s,
+                                            graphs[gi].effective_scope,
+                                            graphs[gi].effective_relax)
         ref = refs[(gi, s)]
         sl = slice(bases[i], bases[i] + glist[gi].n)
         assert np.array_equal(c[sl], ref["cost"]), i
