@@ -772,7 +772,9 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   HIPCHK(hipEventRecord(ws.staged, stream));
   KernelTimer tm;
   const KernelTimer *timer = prof_timer(&tm);
+  if ((s = trace_begin(ws, a, stream))) return s;
   HIPCHK(launch_solve(f32, true, a, pred, geo, istat, max_n, timer, stream));
+  if ((s = trace_end(a, geo.blocks, stream))) return s;
   if (stats) {
     // pinned space after the tables
     char *hb = (char *)hp + ((tab_bytes + 63) & ~(size_t)63);
