@@ -352,7 +352,7 @@ sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
   HIPCHK(hipMemcpy(h.data(), a.trace, h.size() * sizeof(long long), hipMemcpyDeviceToHost));
   FILE *f = fopen(path, "a");
   if (!f) return SSSP_ERR_ARG;
-  fprintf(f, "round,start,arr_relax,end_relax,arr_fused,end_fused,nf,ef,no,eo,mode\n");
+  fprintf(f, "round,start,arr_relax,end_relax,arr_fused,end_fused,nf,ef,no,eo,mode,nl\n");
   for (int r = 0; r < nr; ++r) {
     fprintf(f, "%d", r + 1);
     for (int k = 0; k < kTraceFields; ++k) fprintf(f, ",%lld", h[(size_t)r * kTraceFields + k]);

@@ -1345,6 +1345,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
           } else {
             tr[TR_NO] = N;
             tr[TR_EO] = E;
+            tr[TR_NL] = NL;
           }
           // active blocks of the relax (low half) and bound-and-fix phases
           tr[TR_MODE] |= (long long)act << (16 * phase);

@@ -131,11 +131,12 @@ struct RoundArgs {
 };
 
 // Trace record of one round: wall-clock (100 MHz) at the relax start, block
-// 0's arrival at and release from each of the two barriers, the list sizes,
+// 0's arrival at and release from each of the two barriers, the list sizes
+// (fixed, open, and the live list of undiscovered vertices under scope ALL),
 // and which phases ran on one block (bit 0 relax, bit 1 bound-and-fix).
 enum TraceField {
   TR_START = 0, TR_ARR_RELAX, TR_END_RELAX, TR_ARR_FUSED, TR_END_FUSED,
-  TR_NF, TR_EF, TR_NO, TR_EO, TR_MODE, kTraceFields
+  TR_NF, TR_EF, TR_NO, TR_EO, TR_MODE, TR_NL, kTraceFields
 };
 
 constexpr int kBlkFields = 4;
