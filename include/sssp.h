@@ -297,6 +297,83 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
                           const int32_t *inst_source, int32_t num_inst, const int32_t *pred,
                           const float *grad_cost, float *grad_w, void *stream);
 
+/*
+ * Launch geometry of the persistent round kernel.  Geometry changes only
+ * the speed of a solve: costs, parents and counters are the same under
+ * every setting.  A zero field takes the default.
+ *   blocks:      grid size, 1 .. the co-resident maximum (default: that
+ *                maximum, one 1024-thread block per compute unit);
+ *   solo_edges:  a phase with at most this many edges runs on one block
+ *                with block barriers only (default 8192; negative: never);
+ *   block_units: otherwise the phase runs on about (work units) /
+ *                block_units blocks, a power of two (default 4096).
+ */
+typedef struct {
+  int32_t blocks;
+  int32_t solo_edges;
+  int32_t block_units;
+} sssp_launch;
+
+/*
+ * Default geometry of the calling device's sssp_solve, sssp_solve_target
+ * and sssp_solve_batch calls (null: back to the defaults).  A blocks value
+ * above the co-resident maximum is SSSP_ERR_ARG.
+ */
+sssp_status sssp_set_launch(const sssp_launch *launch);
+
+/*
+ * Replayable solves.  A plan fixes the graphs, instances and output buffers
+ * of a batch (the layout of sssp_solve_batch) and records every kernel of
+ * the solve once into a HIP graph; sssp_plan_run replays it with one
+ * launch.  The round kernel's node is cooperative, as in the direct call.
+ *   kind SSSP_PLAN_BATCH:    one persistent launch for all instances, as
+ *                            sssp_solve_batch;
+ *   kind SSSP_PLAN_SEQUENCE: one single solve (sssp_solve) per instance,
+ *                            back to back, into the same layout.
+ *   cost, pred (device; pred nullable): written by every run; they, the
+ *           graphs' buffers and the graphs' contents must stay valid until
+ *           the plan is destroyed (new weights via sssp_set_weights are
+ *           picked up by the next run: the plan holds pointers, not values).
+ *   with_stats: non-zero to keep the per-instance counters that
+ *           sssp_plan_stats reads (the batch kind counts them in the
+ *           kernel, at some cost; the sequence kind always has them).
+ *   launch (nullable): geometry of the plan's round kernels.
+ * Ownership: the plan allocates its own device state (it shares nothing
+ * with the workspace cache or other plans) when created, on the current
+ * device; run allocates nothing.  Runs of one plan must not overlap (its
+ * state is reused): replay it on one stream, or order the streams.
+ * Creation synchronizes the device; errors as for sssp_solve_batch.
+ */
+typedef enum { SSSP_PLAN_BATCH = 0, SSSP_PLAN_SEQUENCE = 1 } sssp_plan_kind;
+typedef struct sssp_plan_s *sssp_plan;
+
+sssp_status sssp_plan_create(const sssp_csr *graphs, int32_t num_graphs,
+                             const int32_t *inst_graph, const int32_t *inst_source,
+                             int32_t num_inst, sssp_plan_kind kind, void *cost, int32_t *pred,
+                             int32_t with_stats, const sssp_launch *launch, sssp_plan *plan);
+/* Replay on `stream` (asynchronous).  SSSP_ERR_ARG on another device. */
+sssp_status sssp_plan_run(sssp_plan plan, void *stream);
+/* Counters of the last run, num_inst entries (host); synchronizes the
+ * stream.  SSSP_ERR_ARG for a batch plan created without with_stats. */
+sssp_status sssp_plan_stats(sssp_plan plan, sssp_stats *stats, void *stream);
+/* Waits for the device, then frees the plan's graph and state. */
+sssp_status sssp_plan_destroy(sssp_plan plan);
+
+/*
+ * Launch-geometry autotuner: builds a plan for the given solves and times
+ * its replays (HIP events on `stream`, `reps` timed runs after one warm-up,
+ * mean taken) under candidate geometries, one field at a time (blocks:
+ * maximum, 1/2, 1/4; solo_edges: 2048, 8192, 32768; block_units: 2048,
+ * 4096, 8192), keeping a candidate only when it beats the best so far.
+ * *best receives the fastest geometry, *best_ms its mean run time.  Writes
+ * cost and pred like a run; synchronizes.  Arguments as for
+ * sssp_plan_create; reps in [1, 100].
+ */
+sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int32_t *inst_graph,
+                          const int32_t *inst_source, int32_t num_inst, sssp_plan_kind kind,
+                          void *cost, int32_t *pred, int32_t reps, sssp_launch *best,
+                          double *best_ms, void *stream);
+
 /* Free the calling device's workspace cache (synchronizes the device). */
 sssp_status sssp_release_workspace(void);
 

@@ -23,8 +23,12 @@ SSSP_RELAX_AUTO, SSSP_RELAX_SETTING, SSSP_RELAX_CORRECTING = 0, 1, 2
 (SSSP_OK, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_WEIGHT, SSSP_ERR_OVERFLOW, SSSP_ERR_NOMEM,
  SSSP_ERR_HIP, SSSP_ERR_INTERNAL) = range(8)
 
+SSSP_PLAN_BATCH, SSSP_PLAN_SEQUENCE = 0, 1
+
 EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_solve",
-           "sssp_solve_target", "sssp_solve_batch", "sssp_backward", "sssp_release_workspace", "sssp_strerror",
+           "sssp_solve_target", "sssp_solve_batch", "sssp_backward", "sssp_set_launch",
+           "sssp_plan_create", "sssp_plan_run", "sssp_plan_stats", "sssp_plan_destroy",
+           "sssp_autotune", "sssp_release_workspace", "sssp_strerror",
            "sssp_profile_enable", "sssp_profile_read")
 
 
@@ -49,6 +53,15 @@ class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("settled", ctypes.c_int32),
                 ("relaxed_edges", ctypes.c_int64), ("scanned_in_edges", ctypes.c_int64),
                 ("open_visits", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Launch(ctypes.Structure):
+    """Launch geometry of the round kernel (0 in a field: the default)."""
+    _fields_ = [("blocks", ctypes.c_int32), ("solo_edges", ctypes.c_int32),
+                ("block_units", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,6 +102,22 @@ def lib():
         L.sssp_solve_batch.restype = ctypes.c_int
         L.sssp_backward.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, i32, vp, vp, vp, vp]
         L.sssp_backward.restype = ctypes.c_int
+        L.sssp_set_launch.argtypes = [ctypes.POINTER(Launch)]
+        L.sssp_set_launch.restype = ctypes.c_int
+        L.sssp_plan_create.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, i32, ctypes.c_int, vp,
+                                       vp, i32, ctypes.POINTER(Launch),
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.sssp_plan_create.restype = ctypes.c_int
+        L.sssp_plan_run.argtypes = [vp, vp]
+        L.sssp_plan_run.restype = ctypes.c_int
+        L.sssp_plan_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
+        L.sssp_plan_stats.restype = ctypes.c_int
+        L.sssp_plan_destroy.argtypes = [vp]
+        L.sssp_plan_destroy.restype = ctypes.c_int
+        L.sssp_autotune.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, i32, ctypes.c_int, vp, vp,
+                                    i32, ctypes.POINTER(Launch), ctypes.POINTER(ctypes.c_double),
+                                    vp]
+        L.sssp_autotune.restype = ctypes.c_int
         L.sssp_release_workspace.argtypes = []
         L.sssp_release_workspace.restype = ctypes.c_int
         L.sssp_profile_enable.argtypes = [ctypes.c_int]
@@ -175,3 +204,52 @@ def sssp_profile_read():
 
 def sssp_release_workspace():
     _check(lib().sssp_release_workspace(), "sssp_release_workspace")
+
+
+def sssp_set_launch(launch):
+    """launch: a Launch, or None for the defaults."""
+    _check(lib().sssp_set_launch(ctypes.byref(launch) if launch is not None else None),
+           "sssp_set_launch")
+
+
+def _batch_args(graphs, inst_graph, inst_source):
+    ga = (Csr * len(graphs))(*graphs)
+    ig = _arr(ctypes.c_int32, inst_graph)
+    isrc = _arr(ctypes.c_int32, inst_source)
+    return ga, ig, isrc
+
+
+def sssp_plan_create(graphs, inst_graph, inst_source, kind, cost, pred, with_stats, launch):
+    """Returns the plan handle (an int)."""
+    ga, ig, isrc = _batch_args(graphs, inst_graph, inst_source)
+    h = ctypes.c_void_p(0)
+    _check(lib().sssp_plan_create(ga, len(graphs), ctypes.cast(ig, ctypes.c_void_p),
+                                  ctypes.cast(isrc, ctypes.c_void_p), len(ig), kind, cost, pred,
+                                  1 if with_stats else 0,
+                                  ctypes.byref(launch) if launch is not None else None,
+                                  ctypes.byref(h)), "sssp_plan_create")
+    return h.value
+
+
+def sssp_plan_run(plan, stream):
+    _check(lib().sssp_plan_run(plan, stream), "sssp_plan_run")
+
+
+def sssp_plan_stats(plan, stats, stream):
+    _check(lib().sssp_plan_stats(plan, stats, stream), "sssp_plan_stats")
+
+
+def sssp_plan_destroy(plan):
+    _check(lib().sssp_plan_destroy(plan), "sssp_plan_destroy")
+
+
+def sssp_autotune(graphs, inst_graph, inst_source, kind, cost, pred, reps, stream):
+    """Returns (Launch, mean milliseconds per run under it)."""
+    ga, ig, isrc = _batch_args(graphs, inst_graph, inst_source)
+    best = Launch()
+    ms = ctypes.c_double(0.0)
+    _check(lib().sssp_autotune(ga, len(graphs), ctypes.cast(ig, ctypes.c_void_p),
+                               ctypes.cast(isrc, ctypes.c_void_p), len(ig), kind, cost, pred,
+                               int(reps), ctypes.byref(best), ctypes.byref(ms), stream),
+           "sssp_autotune")
+    return best, ms.value

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,7 @@ struct DevWS {
   size_t pinned_cap = 0;
   hipEvent_t last = nullptr;  // completion of the previous call's work
   hipEvent_t staged = nullptr;
+  sssp_launch cfg = {0, 0, 0};  // default geometry of direct solves (sssp_set_launch)
 };
 
 std::mutex g_mu;
@@ -142,6 +144,27 @@ sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
   }
   geo->blocks = w.cus * w.bpc[k];
   geo->cus = w.cus;
+  return SSSP_OK;
+}
+
+// The round kernel's geometry under `L` (null or zero fields: defaults;
+// the environment variables SSSP_SOLO_EDGES and SSSP_BLOCK_UNITS override
+// the defaults for measurement).
+sssp_status resolve_launch(DevWS &w, bool f32, bool batch, const sssp_launch *L,
+                           LaunchGeom *geo, RoundArgs &a) {
+  sssp_status s;
+  if ((s = geometry(w, f32, batch, geo))) return s;
+  if (L && L->blocks) {
+    if (L->blocks < 1 || L->blocks > geo->blocks) return SSSP_ERR_ARG;
+    geo->blocks = L->blocks;
+  }
+  a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
+  if (L && L->solo_edges) a.solo_edges = L->solo_edges < 0 ? 0 : L->solo_edges;
+  a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
+  if (L && L->block_units) {
+    if (L->block_units < 0) return SSSP_ERR_ARG;
+    a.block_units = L->block_units;
+  }
   return SSSP_OK;
 }
 
@@ -625,6 +648,31 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
 
 }  // extern "C"
 
+// Round arguments of one solve from `source` (target >= 0: stop once the
+// target is fixed) into `cost`, with its state buffers.
+static sssp_status single_args(DevWS &ws, const sssp_csr *g, int32_t source, int32_t target,
+                               void *cost, RoundArgs &a) {
+  memset(&a, 0, sizeof(a));
+  a.g = graph_dev(g);
+  a.num_inst = 1;
+  a.source = source;
+  a.total = g->n;
+  a.max_rounds = g->n + 1;
+  a.D = (int32_t *)cost;
+  a.target = target;
+  a.scope_all = a.g.all;
+  a.any_lc = a.g.lc;
+  return state_buffers(ws, g->n, 1, false, a);
+}
+
+static void single_stats(const Ctl *c, sssp_stats *stats) {
+  stats->rounds = c->rounds;
+  stats->settled = (int32_t)c->settled;
+  stats->relaxed_edges = c->relaxed;
+  stats->scanned_in_edges = c->scanned;
+  stats->open_visits = c->open_visits;
+}
+
 // One solve from `source`; with target >= 0 the rounds stop once the target
 // is fixed (no parent pointers then).
 static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, void *cost,
@@ -640,26 +688,16 @@ static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, 
   if ((s = ws_for_current(&wp))) return s;
   DevWS &ws = *wp;
   RoundArgs a;
-  memset(&a, 0, sizeof(a));
-  a.g = graph_dev(g);
-  a.num_inst = 1;
-  a.source = source;
-  a.total = g->n;
-  a.max_rounds = g->n + 1;
-  a.D = (int32_t *)cost;
-  a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
-  a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
-  a.target = target;
-  a.scope_all = a.g.all;
-  a.any_lc = a.g.lc;
-  if ((s = state_buffers(ws, g->n, 1, false, a))) return s;
+  if ((s = single_args(ws, g, source, target, cost, a))) return s;
   LaunchGeom geo;
-  if ((s = geometry(ws, f32, false, &geo))) return s;
+  if ((s = resolve_launch(ws, f32, false, &ws.cfg, &geo, a))) return s;
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
   KernelTimer tm;
   const KernelTimer *timer = prof_timer(&tm);
   if ((s = trace_begin(ws, a, stream))) return s;
-  HIPCHK(launch_solve(f32, false, a, pred, geo, nullptr, g->n, timer, stream));
+  Launcher L;
+  L.stream = stream;
+  HIPCHK(launch_solve(f32, false, a, pred, geo, nullptr, g->n, timer, L));
   if ((s = trace_end(a, geo.blocks, stream))) return s;
   if (stats) {
     void *hp;
@@ -667,11 +705,7 @@ static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, 
     HIPCHK(hipMemcpyAsync(hp, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     const Ctl *c = (const Ctl *)hp;
-    stats->rounds = c->rounds;
-    stats->settled = (int32_t)c->settled;
-    stats->relaxed_edges = c->relaxed;
-    stats->scanned_in_edges = c->scanned;
-    stats->open_visits = c->open_visits;
+    single_stats(c, stats);
     if (c->status) {
       HIPCHK(hipEventRecord(ws.last, stream));
       return SSSP_ERR_INTERNAL;
@@ -679,6 +713,111 @@ static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, 
   }
   HIPCHK(hipEventRecord(ws.last, stream));
   return SSSP_OK;
+}
+
+// Host checks of a batch; *total and *max_n receive the number of state
+// entries and the largest instance.
+static sssp_status check_batch(const sssp_csr *graphs, int32_t num_graphs,
+                               const int32_t *inst_graph, const int32_t *inst_source,
+                               int32_t num_inst, void *cost, int64_t *total, int32_t *max_n) {
+  if (!graphs || num_graphs <= 0 || !inst_graph || !inst_source || num_inst <= 0 || !cost)
+    return SSSP_ERR_ARG;
+  const int32_t dtype = graphs[0].dtype;
+  for (int32_t gi = 0; gi < num_graphs; ++gi) {
+    if (!csr_ok(&graphs[gi]) || graphs[gi].dtype != dtype) return SSSP_ERR_ARG;
+    if (overflow_risk(&graphs[gi])) return SSSP_ERR_OVERFLOW;
+  }
+  *total = 0;
+  *max_n = 0;
+  for (int32_t i = 0; i < num_inst; ++i) {
+    const int32_t gi = inst_graph[i];
+    if (gi < 0 || gi >= num_graphs) return SSSP_ERR_ARG;
+    const int32_t n = graphs[gi].n;
+    if (inst_source[i] < 0 || inst_source[i] >= n) return SSSP_ERR_ARG;
+    *total += n;
+    if (n > *max_n) *max_n = n;
+  }
+  if (*total >= (int64_t)INT_MAX) return SSSP_ERR_ARG;
+  return SSSP_OK;
+}
+
+// The host copies of a batch's graph and instance tables.
+static void fill_tables(const sssp_csr *graphs, int32_t num_graphs, const int32_t *inst_graph,
+                        const int32_t *inst_source, int32_t num_inst, GraphDev *hg,
+                        InstDev *hi) {
+  for (int32_t gi = 0; gi < num_graphs; ++gi) hg[gi] = graph_dev(&graphs[gi]);
+  int32_t base = 0;
+  for (int32_t i = 0; i < num_inst; ++i) {
+    hi[i].graph = inst_graph[i];
+    hi[i].source = inst_source[i];
+    hi[i].sbase = base;
+    hi[i].n = graphs[inst_graph[i]].n;
+    base += hi[i].n;
+  }
+}
+
+// Round arguments and state buffers of a batch (the tables a.graphs and
+// a.insts are allocated, not filled).  stats: count per-instance counters.
+static sssp_status batch_args(DevWS &ws, const sssp_csr *graphs, int32_t num_graphs,
+                              const int32_t *inst_graph, int32_t num_inst, int64_t total,
+                              int32_t max_n, void *cost, int32_t *pred, bool stats,
+                              RoundArgs &a) {
+  memset(&a, 0, sizeof(a));
+  a.num_inst = num_inst;
+  a.total = (int32_t)total;
+  a.max_rounds = max_n + 1;
+  a.target = -1;
+  a.D = (int32_t *)cost;
+  for (int32_t i = 0; i < num_inst; ++i) {
+    if (relax_correcting(&graphs[inst_graph[i]])) a.any_lc = 1;
+    if (scope_all_of(&graphs[inst_graph[i]])) a.scope_all = 1;
+  }
+  sssp_status s;
+  if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
+  GraphDev *dg;
+  InstDev *di;
+  if ((s = ws_arr(ws, S_GTAB, (size_t)num_graphs, &dg))) return s;
+  if ((s = ws_arr(ws, S_ITAB, (size_t)num_inst, &di))) return s;
+  a.graphs = dg;
+  a.insts = di;
+  if (stats) {
+    if ((s = ws_arr(ws, S_ISTAT, 4 * (size_t)num_inst, &a.istat))) return s;
+    if (!pred && (s = ws_arr(ws, S_SPRED, (size_t)a.total, &a.scratch_pred))) return s;
+  }
+  return SSSP_OK;
+}
+
+// Per-instance counters of a finished batch (synchronizes the stream).
+static sssp_status batch_stats(const RoundArgs &a, int32_t num_inst, sssp_stats *stats,
+                               hipStream_t stream) {
+  HIPCHK(hipStreamSynchronize(stream));
+  const size_t I = (size_t)num_inst;
+  std::vector<long long> st(4 * I);
+  std::vector<int32_t> rounds(I);
+  std::vector<unsigned long long> sc(3 * I), dd(2 * I, 0ull);
+  HIPCHK(hipMemcpy(st.data(), a.istat, sizeof(long long) * 4 * I, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(rounds.data(), a.irounds, sizeof(int32_t) * I, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(sc.data(), a.iscanned, sizeof(unsigned long long) * 3 * I,
+                   hipMemcpyDeviceToHost));
+  // scope ALL: unreachable vertices dropped from the live list in round
+  // r_d are still scanned in every later bound step of their instance
+  // (rounds - 1 of them)
+  if (a.idead)
+    HIPCHK(hipMemcpy(dd.data(), a.idead, sizeof(unsigned long long) * 2 * I,
+                     hipMemcpyDeviceToHost));
+  Ctl c;
+  HIPCHK(hipMemcpy(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < I; ++i) {
+    const int32_t r = rounds[i];
+    stats[i].rounds = r;
+    stats[i].settled = (int32_t)st[4 * i + 1];
+    stats[i].relaxed_edges = (int64_t)sc[3 * i + 2];
+    stats[i].scanned_in_edges = (int64_t)(sc[3 * i] +
+                                          dd[2 * i] * (unsigned long long)(r > 0 ? r - 1 : 0) -
+                                          dd[2 * i + 1]);
+    stats[i].open_visits = (int64_t)sc[3 * i + 1];
+  }
+  return c.status ? SSSP_ERR_INTERNAL : SSSP_OK;
 }
 
 extern "C" {
@@ -698,120 +837,347 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
                              const int32_t *inst_graph, const int32_t *inst_source,
                              int32_t num_inst, void *cost, int32_t *pred, sssp_stats *stats,
                              void *stream_) {
-  if (!graphs || num_graphs <= 0 || !inst_graph || !inst_source || num_inst <= 0 || !cost)
-    return SSSP_ERR_ARG;
-  const int32_t dtype = graphs[0].dtype;
-  for (int32_t gi = 0; gi < num_graphs; ++gi) {
-    if (!csr_ok(&graphs[gi]) || graphs[gi].dtype != dtype) return SSSP_ERR_ARG;
-    if (overflow_risk(&graphs[gi])) return SSSP_ERR_OVERFLOW;
-  }
-  int64_t total = 0;
-  int32_t max_n = 0;
-  for (int32_t i = 0; i < num_inst; ++i) {
-    const int32_t gi = inst_graph[i];
-    if (gi < 0 || gi >= num_graphs) return SSSP_ERR_ARG;
-    const int32_t n = graphs[gi].n;
-    if (inst_source[i] < 0 || inst_source[i] >= n) return SSSP_ERR_ARG;
-    total += n;
-    if (n > max_n) max_n = n;
-  }
-  if (total >= (int64_t)INT_MAX) return SSSP_ERR_ARG;
+  int64_t total;
+  int32_t max_n;
+  sssp_status s;
+  if ((s = check_batch(graphs, num_graphs, inst_graph, inst_source, num_inst, cost, &total,
+                       &max_n)))
+    return s;
   hipStream_t stream = (hipStream_t)stream_;
-  const bool f32 = dtype == SSSP_F32;
+  const bool f32 = graphs[0].dtype == SSSP_F32;
   Guard guard;
   DevWS *wp;
-  sssp_status s;
   if ((s = ws_for_current(&wp))) return s;
   DevWS &ws = *wp;
   RoundArgs a;
-  memset(&a, 0, sizeof(a));
-  a.num_inst = num_inst;
-  a.total = (int32_t)total;
-  a.max_rounds = max_n + 1;
-  a.target = -1;
-  a.D = (int32_t *)cost;
-  a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
-  a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
-  for (int32_t i = 0; i < num_inst; ++i) {
-    if (relax_correcting(&graphs[inst_graph[i]])) a.any_lc = 1;
-    if (scope_all_of(&graphs[inst_graph[i]])) a.scope_all = 1;
-  }
-  if ((s = state_buffers(ws, a.total, num_inst, true, a))) return s;
-  GraphDev *dg;
-  InstDev *di;
-  if ((s = ws_arr(ws, S_GTAB, (size_t)num_graphs, &dg))) return s;
-  if ((s = ws_arr(ws, S_ITAB, (size_t)num_inst, &di))) return s;
-  long long *istat = nullptr;
-  if (stats) {
-    if ((s = ws_arr(ws, S_ISTAT, 4 * (size_t)num_inst, &istat))) return s;
-    a.istat = istat;
-    if (!pred && (s = ws_arr(ws, S_SPRED, (size_t)a.total, &a.scratch_pred))) return s;
-  }
+  if ((s = batch_args(ws, graphs, num_graphs, inst_graph, num_inst, total, max_n, cost, pred,
+                      stats != nullptr, a)))
+    return s;
   const size_t tab_bytes = sizeof(GraphDev) * num_graphs + sizeof(InstDev) * num_inst;
-  const size_t stat_bytes = (sizeof(long long) * 4 + sizeof(int32_t) + 8) * (size_t)num_inst;
   void *hp;
-  if ((s = pinned_get(ws, tab_bytes + stat_bytes + 64, &hp))) return s;
+  if ((s = pinned_get(ws, tab_bytes, &hp))) return s;
   GraphDev *hg = (GraphDev *)hp;
   InstDev *hi = (InstDev *)(hg + num_graphs);
-  for (int32_t gi = 0; gi < num_graphs; ++gi) hg[gi] = graph_dev(&graphs[gi]);
-  int32_t base = 0;
-  for (int32_t i = 0; i < num_inst; ++i) {
-    hi[i].graph = inst_graph[i];
-    hi[i].source = inst_source[i];
-    hi[i].sbase = base;
-    hi[i].n = graphs[inst_graph[i]].n;
-    base += hi[i].n;
-  }
-  a.graphs = dg;
-  a.insts = di;
+  fill_tables(graphs, num_graphs, inst_graph, inst_source, num_inst, hg, hi);
   LaunchGeom geo;
-  if ((s = geometry(ws, f32, true, &geo))) return s;
+  if ((s = resolve_launch(ws, f32, true, &ws.cfg, &geo, a))) return s;
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
-  HIPCHK(hipMemcpyAsync(dg, hg, sizeof(GraphDev) * num_graphs, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(di, hi, sizeof(InstDev) * num_inst, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync((void *)a.graphs, hg, sizeof(GraphDev) * num_graphs,
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync((void *)a.insts, hi, sizeof(InstDev) * num_inst, hipMemcpyHostToDevice,
+                        stream));
   HIPCHK(hipEventRecord(ws.staged, stream));
   KernelTimer tm;
   const KernelTimer *timer = prof_timer(&tm);
   if ((s = trace_begin(ws, a, stream))) return s;
-  HIPCHK(launch_solve(f32, true, a, pred, geo, istat, max_n, timer, stream));
+  Launcher L;
+  L.stream = stream;
+  HIPCHK(launch_solve(f32, true, a, pred, geo, a.istat, max_n, timer, L));
   if ((s = trace_end(a, geo.blocks, stream))) return s;
-  if (stats) {
-    // pinned space after the tables
-    char *hb = (char *)hp + ((tab_bytes + 63) & ~(size_t)63);
-    long long *hst = (long long *)hb;
-    int32_t *hr = (int32_t *)(hst + 4 * (size_t)num_inst);
-    HIPCHK(hipMemcpyAsync(hst, istat, sizeof(long long) * 4 * num_inst, hipMemcpyDeviceToHost,
-                          stream));
-    HIPCHK(hipMemcpyAsync(hr, a.irounds, sizeof(int32_t) * num_inst, hipMemcpyDeviceToHost,
-                          stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    std::vector<unsigned long long> sc(3 * (size_t)num_inst);
-    HIPCHK(hipMemcpy(sc.data(), a.iscanned, sizeof(unsigned long long) * 3 * num_inst,
-                     hipMemcpyDeviceToHost));
-    Ctl c;
-    HIPCHK(hipMemcpy(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-    // scope ALL: unreachable vertices dropped from the live list in round
-    // r_d are still scanned in every later bound step of their instance
-    // (rounds - 1 of them)
-    std::vector<unsigned long long> dd(2 * (size_t)num_inst, 0ull);
-    if (a.idead)
-      HIPCHK(hipMemcpy(dd.data(), a.idead, sizeof(unsigned long long) * 2 * num_inst,
-                       hipMemcpyDeviceToHost));
-    for (int32_t i = 0; i < num_inst; ++i) {
-      stats[i].rounds = hr[i];
-      stats[i].settled = (int32_t)hst[4 * i + 1];
-      stats[i].relaxed_edges = (int64_t)sc[3 * i + 2];
-      stats[i].scanned_in_edges =
-          (int64_t)(sc[3 * i] + dd[2 * i] * (unsigned long long)(hr[i] > 0 ? hr[i] - 1 : 0) -
-                    dd[2 * i + 1]);
-      stats[i].open_visits = (int64_t)sc[3 * i + 1];
-    }
-    HIPCHK(hipEventRecord(ws.last, stream));
-    if (c.status) return SSSP_ERR_INTERNAL;
+  if (stats) s = batch_stats(a, num_inst, stats, stream);
+  HIPCHK(hipEventRecord(ws.last, stream));
+  return s;
+}
+
+sssp_status sssp_set_launch(const sssp_launch *launch) {
+  Guard guard;
+  DevWS *wp;
+  sssp_status s;
+  if ((s = ws_for_current(&wp))) return s;
+  if (!launch) {
+    wp->cfg = sssp_launch{0, 0, 0};
     return SSSP_OK;
   }
-  HIPCHK(hipEventRecord(ws.last, stream));
+  // the grid must fit both kernel variants of both dtypes
+  for (int k = 0; k < 4; ++k) {
+    LaunchGeom geo;
+    RoundArgs a;
+    if ((s = resolve_launch(*wp, k & 1, (k & 2) != 0, launch, &geo, a))) return s;
+  }
+  wp->cfg = *launch;
   return SSSP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans
+struct sssp_plan_s {
+  int dev = 0;
+  int32_t kind = SSSP_PLAN_BATCH;
+  int32_t num_inst = 0;
+  bool with_stats = false;
+  bool f32 = false;
+  DevWS ws;  // the plan's own state (never the shared cache)
+  RoundArgs a;                  // batch kind: the solve's arguments
+  int32_t *batch_pred = nullptr;  // batch kind: the parent output (nullable)
+  std::vector<RoundArgs> seq;   // sequence kind: one per instance
+  std::vector<int32_t> seq_n;   // sequence kind: instance sizes
+  std::vector<int32_t *> seq_pred;
+  int32_t max_n = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void ws_free(DevWS &w) {
+  for (int i = 0; i < NSLOTS; ++i) {
+    if (w.buf[i]) (void)hipFree(w.buf[i]);
+    w.buf[i] = nullptr;
+    w.cap[i] = 0;
+  }
+  if (w.pinned) (void)hipHostFree(w.pinned);
+  w.pinned = nullptr;
+  w.pinned_cap = 0;
+}
+
+static void plan_drop_graph(sssp_plan_s *p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+}
+
+// (Re)records the plan's kernels into a new HIP graph under geometry `L`.
+static sssp_status plan_record(sssp_plan_s *p, const sssp_launch *L) {
+  plan_drop_graph(p);
+  LaunchGeom geo;
+  const bool batch = p->kind == SSSP_PLAN_BATCH;
+  sssp_status s;
+  RoundArgs probe;
+  memset(&probe, 0, sizeof(probe));
+  if ((s = resolve_launch(p->ws, p->f32, batch, L, &geo, probe))) return s;
+  HIPCHK(hipGraphCreate(&p->graph, 0));
+  Launcher rec;
+  rec.graph = p->graph;
+  if (batch) {
+    p->a.solo_edges = probe.solo_edges;
+    p->a.block_units = probe.block_units;
+    HIPCHK(launch_solve(p->f32, true, p->a, p->batch_pred, geo, p->a.istat, p->max_n, nullptr,
+                        rec));
+  } else {
+    for (size_t i = 0; i < p->seq.size(); ++i) {
+      p->seq[i].solo_edges = probe.solo_edges;
+      p->seq[i].block_units = probe.block_units;
+      HIPCHK(launch_solve(p->f32, false, p->seq[i], p->seq_pred[i], geo, nullptr, p->seq_n[i],
+                          nullptr, rec));
+    }
+  }
+  HIPCHK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  return SSSP_OK;
+}
+
+static sssp_status plan_build(const sssp_csr *graphs, int32_t num_graphs,
+                              const int32_t *inst_graph, const int32_t *inst_source,
+                              int32_t num_inst, sssp_plan_kind kind, void *cost, int32_t *pred,
+                              int32_t with_stats, const sssp_launch *launch, sssp_plan_s *p) {
+  int64_t total;
+  int32_t max_n;
+  sssp_status s;
+  if (kind != SSSP_PLAN_BATCH && kind != SSSP_PLAN_SEQUENCE) return SSSP_ERR_ARG;
+  if ((s = check_batch(graphs, num_graphs, inst_graph, inst_source, num_inst, cost, &total,
+                       &max_n)))
+    return s;
+  HIPCHK(hipGetDevice(&p->dev));
+  HIPCHK(hipDeviceGetAttribute(&p->ws.cus, hipDeviceAttributeMultiprocessorCount, p->dev));
+  p->ws.init = true;
+  p->kind = kind;
+  p->num_inst = num_inst;
+  p->with_stats = with_stats != 0;
+  p->f32 = graphs[0].dtype == SSSP_F32;
+  p->max_n = max_n;
+  std::vector<GraphDev> hg((size_t)num_graphs);
+  std::vector<InstDev> hi((size_t)num_inst);
+  fill_tables(graphs, num_graphs, inst_graph, inst_source, num_inst, hg.data(), hi.data());
+  if (kind == SSSP_PLAN_BATCH) {
+    if ((s = batch_args(p->ws, graphs, num_graphs, inst_graph, num_inst, total, max_n, cost,
+                        pred, p->with_stats, p->a)))
+      return s;
+    HIPCHK(hipMemcpy((void *)p->a.graphs, hg.data(), sizeof(GraphDev) * num_graphs,
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy((void *)p->a.insts, hi.data(), sizeof(InstDev) * num_inst,
+                     hipMemcpyHostToDevice));
+    p->batch_pred = pred;
+  } else {
+    // one set of state buffers for the largest instance, reused solve
+    // after solve, and one control block per instance for its counters
+    RoundArgs base;
+    memset(&base, 0, sizeof(base));
+    for (int32_t i = 0; i < num_inst; ++i) {
+      if (relax_correcting(&graphs[inst_graph[i]])) base.any_lc = 1;
+      if (scope_all_of(&graphs[inst_graph[i]])) base.scope_all = 1;
+    }
+    if ((s = state_buffers(p->ws, max_n, 1, false, base))) return s;
+    Ctl *ctls;
+    if ((s = ws_arr(p->ws, S_CTL, (size_t)num_inst, &ctls))) return s;
+    for (int32_t i = 0; i < num_inst; ++i) {
+      const sssp_csr *g = &graphs[inst_graph[i]];
+      RoundArgs a = base;
+      a.g = graph_dev(g);
+      a.num_inst = 1;
+      a.source = inst_source[i];
+      a.total = g->n;
+      a.max_rounds = g->n + 1;
+      a.D = (int32_t *)cost + hi[i].sbase;
+      a.target = -1;
+      a.scope_all = a.g.all;
+      a.any_lc = a.g.lc;
+      a.ctl = ctls + i;
+      p->seq.push_back(a);
+      p->seq_n.push_back(g->n);
+      p->seq_pred.push_back(pred ? pred + hi[i].sbase : nullptr);
+    }
+  }
+  return plan_record(p, launch);
+}
+
+// Runs the plan once on `stream` (no synchronization).
+static sssp_status plan_launch(sssp_plan_s *p, hipStream_t stream) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != p->dev) return SSSP_ERR_ARG;
+  HIPCHK(hipGraphLaunch(p->exec, stream));
+  return SSSP_OK;
+}
+
+extern "C" {
+
+sssp_status sssp_plan_create(const sssp_csr *graphs, int32_t num_graphs,
+                             const int32_t *inst_graph, const int32_t *inst_source,
+                             int32_t num_inst, sssp_plan_kind kind, void *cost, int32_t *pred,
+                             int32_t with_stats, const sssp_launch *launch, sssp_plan *plan) {
+  if (!plan) return SSSP_ERR_ARG;
+  *plan = nullptr;
+  if (kind != SSSP_PLAN_BATCH && kind != SSSP_PLAN_SEQUENCE) return SSSP_ERR_ARG;
+  {
+    int64_t total;
+    int32_t max_n;
+    const sssp_status s = check_batch(graphs, num_graphs, inst_graph, inst_source, num_inst,
+                                      cost, &total, &max_n);
+    if (s) return s;
+  }
+  sssp_plan_s *p = new (std::nothrow) sssp_plan_s();
+  if (!p) return SSSP_ERR_NOMEM;
+  sssp_status s = plan_build(graphs, num_graphs, inst_graph, inst_source, num_inst, kind, cost,
+                             pred, with_stats, launch, p);
+  if (s == SSSP_OK && hipDeviceSynchronize() != hipSuccess) s = SSSP_ERR_HIP;
+  if (s != SSSP_OK) {
+    (void)hipDeviceSynchronize();
+    plan_drop_graph(p);
+    ws_free(p->ws);
+    delete p;
+    return s;
+  }
+  *plan = p;
+  return SSSP_OK;
+}
+
+sssp_status sssp_plan_run(sssp_plan plan, void *stream) {
+  if (!plan) return SSSP_ERR_ARG;
+  return plan_launch(plan, (hipStream_t)stream);
+}
+
+sssp_status sssp_plan_stats(sssp_plan plan, sssp_stats *stats, void *stream_) {
+  if (!plan || !stats) return SSSP_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (plan->kind == SSSP_PLAN_BATCH) {
+    if (!plan->with_stats) return SSSP_ERR_ARG;
+    return batch_stats(plan->a, plan->num_inst, stats, stream);
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  std::vector<Ctl> c((size_t)plan->num_inst);
+  HIPCHK(hipMemcpy(c.data(), plan->seq[0].ctl, sizeof(Ctl) * c.size(), hipMemcpyDeviceToHost));
+  sssp_status s = SSSP_OK;
+  for (int32_t i = 0; i < plan->num_inst; ++i) {
+    single_stats(&c[i], &stats[i]);
+    if (c[i].status) s = SSSP_ERR_INTERNAL;
+  }
+  return s;
+}
+
+sssp_status sssp_plan_destroy(sssp_plan plan) {
+  if (!plan) return SSSP_OK;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipSetDevice(plan->dev));
+  const hipError_t e = hipDeviceSynchronize();
+  plan_drop_graph(plan);
+  ws_free(plan->ws);
+  delete plan;
+  HIPCHK(hipSetDevice(dev));
+  HIPCHK(e);
+  return SSSP_OK;
+}
+
+sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int32_t *inst_graph,
+                          const int32_t *inst_source, int32_t num_inst, sssp_plan_kind kind,
+                          void *cost, int32_t *pred, int32_t reps, sssp_launch *best,
+                          double *best_ms, void *stream_) {
+  if (!best || reps < 1 || reps > 100) return SSSP_ERR_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  sssp_plan p = nullptr;
+  sssp_status s = sssp_plan_create(graphs, num_graphs, inst_graph, inst_source, num_inst, kind,
+                                   cost, pred, 0, nullptr, &p);
+  if (s) return s;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  LaunchGeom full;
+  RoundArgs probe;
+  memset(&probe, 0, sizeof(probe));
+  // mean replay time of the plan under geometry L (re-recorded)
+  auto time_of = [&](const sssp_launch &L, double *ms) -> sssp_status {
+    sssp_status st = plan_record(p, &L);
+    if (st) return st;
+    if ((st = plan_launch(p, stream))) return st;  // warm-up (uploads the graph)
+    HIPCHK(hipEventRecord(t0, stream));
+    for (int32_t k = 0; k < reps; ++k)
+      if ((st = plan_launch(p, stream))) return st;
+    HIPCHK(hipEventRecord(t1, stream));
+    HIPCHK(hipEventSynchronize(t1));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, t0, t1));
+    *ms = (double)f / reps;
+    return SSSP_OK;
+  };
+  auto run = [&]() -> sssp_status {
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    sssp_status st;
+    if ((st = resolve_launch(p->ws, p->f32, kind == SSSP_PLAN_BATCH, nullptr, &full, probe)))
+      return st;
+    sssp_launch cur = {full.blocks, probe.solo_edges, probe.block_units};
+    double cur_ms;
+    if ((st = time_of(cur, &cur_ms))) return st;
+    const int32_t blocks[3] = {full.blocks, full.blocks / 2, full.blocks / 4};
+    const int32_t solo[3] = {2048, 8192, 32768};
+    const int32_t units[3] = {2048, 4096, 8192};
+    for (int field = 0; field < 3; ++field) {
+      for (int c = 0; c < 3; ++c) {
+        sssp_launch cand = cur;
+        if (field == 0) cand.blocks = blocks[c];
+        if (field == 1) cand.solo_edges = solo[c];
+        if (field == 2) cand.block_units = units[c];
+        if (cand.blocks < 1 || (cand.blocks == cur.blocks && cand.solo_edges == cur.solo_edges &&
+                                cand.block_units == cur.block_units))
+          continue;
+        double ms;
+        if ((st = time_of(cand, &ms))) return st;
+        if (ms < cur_ms) {
+          cur = cand;
+          cur_ms = ms;
+        }
+      }
+    }
+    // leave cost and pred as a run under the chosen geometry writes them
+    if ((st = plan_record(p, &cur))) return st;
+    if ((st = plan_launch(p, stream))) return st;
+    HIPCHK(hipStreamSynchronize(stream));
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return SSSP_OK;
+  };
+  s = run();
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  const sssp_status s2 = sssp_plan_destroy(p);
+  return s ? s : s2;
 }
 
 sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int32_t *inst_graph,

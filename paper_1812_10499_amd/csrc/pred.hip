@@ -151,29 +151,33 @@ __global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *
 
 template <class V, bool BATCH>
 static hipError_t launch_emit_t(const RoundArgs &a, int32_t *pred, long long *istat,
-                                int32_t max_n, hipStream_t stream) {
+                                int32_t max_n, Launcher &L) {
   hipError_t e;
+  RoundArgs arg = a;
+  int32_t *p = pred, *degen = a.degen, *lvl = a.lvl, *flag = a.flag;
+  long long *st = istat;
   const dim3 grid((max_n + 255) / 256, BATCH ? a.num_inst : 1);
-  hipLaunchKernelGGL((emit_kernel<V, BATCH>), grid, dim3(256), 0, stream, a, pred, a.degen,
-                     a.lvl, istat);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  void *eargs[] = {&arg, &p, &degen, &lvl, &st};
+  if ((e = launch_kernel(L, (const void *)emit_kernel<V, BATCH>, grid, dim3(256), eargs,
+                         false)) != hipSuccess)
+    return e;
   if (pred && V::INF == KeyF32::INF) {
-    hipLaunchKernelGGL((pred_degen_kernel<V, BATCH>), dim3(1), dim3(1024), 0, stream, a, pred,
-                       a.degen, a.lvl, a.flag);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    void *dargs[] = {&arg, &p, &degen, &lvl, &flag};
+    if ((e = launch_kernel(L, (const void *)pred_degen_kernel<V, BATCH>, dim3(1), dim3(1024),
+                           dargs, false)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }
 
 hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
-                       const LaunchGeom &geo, long long *istat, int32_t max_n,
-                       hipStream_t stream) {
+                       const LaunchGeom &geo, long long *istat, int32_t max_n, Launcher &L) {
   (void)geo;
   if (f32)
-    return batch ? launch_emit_t<KeyF32, true>(a, pred, istat, max_n, stream)
-                 : launch_emit_t<KeyF32, false>(a, pred, istat, max_n, stream);
-  return batch ? launch_emit_t<KeyI32, true>(a, pred, istat, max_n, stream)
-               : launch_emit_t<KeyI32, false>(a, pred, istat, max_n, stream);
+    return batch ? launch_emit_t<KeyF32, true>(a, pred, istat, max_n, L)
+                 : launch_emit_t<KeyF32, false>(a, pred, istat, max_n, L);
+  return batch ? launch_emit_t<KeyI32, true>(a, pred, istat, max_n, L)
+               : launch_emit_t<KeyI32, false>(a, pred, istat, max_n, L);
 }
 
 }  // namespace sssp

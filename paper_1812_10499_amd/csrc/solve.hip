@@ -38,6 +38,7 @@
 // phase grows.  A barrier among k blocks costs far less than one across
 // the whole grid, which matters for the long tails of small rounds (grids,
 // the end of every solve).
+#include <cstring>
 #include <type_traits>
 
 #include "sssp_dev.h"
@@ -1553,48 +1554,78 @@ __global__ void init_seed_kernel(RoundArgs a) {
 }
 
 // ------------------------------------------------------- host launchers
+hipError_t launch_kernel(Launcher &L, const void *fn, dim3 grid, dim3 block, void **args,
+                         bool cooperative) {
+  if (!L.graph) {
+    return cooperative ? hipLaunchCooperativeKernel(fn, grid, block, args, 0, L.stream)
+                       : hipLaunchKernel(fn, grid, block, args, 0, L.stream);
+  }
+  hipKernelNodeParams p;
+  memset(&p, 0, sizeof(p));
+  p.func = const_cast<void *>(fn);
+  p.gridDim = grid;
+  p.blockDim = block;
+  p.kernelParams = args;
+  hipGraphNode_t node;
+  hipError_t e = hipGraphAddKernelNode(&node, L.graph, L.last ? &L.last : nullptr,
+                                       L.last ? 1 : 0, &p);
+  if (e != hipSuccess) return e;
+  if (cooperative) {
+    hipKernelNodeAttrValue v;
+    memset(&v, 0, sizeof(v));
+    v.cooperative = 1;
+    if ((e = hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v)) !=
+        hipSuccess)
+      return e;
+  }
+  L.last = node;
+  return hipSuccess;
+}
+
 template <class V, bool BATCH>
 static hipError_t launch_solve_t(const RoundArgs &a, int32_t *pred, const LaunchGeom &geo,
                                  long long *istat, int32_t max_n, const KernelTimer *timer,
-                                 hipStream_t stream) {
+                                 Launcher &L) {
   hipError_t e;
   if (geo.blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+  RoundArgs arg = a;
+  void *params[] = {&arg};
   {
     int blocks = (int)((a.total + 255) / 256);
     if (blocks < (kParts * kMaxBlocks) / 256) blocks = (kParts * kMaxBlocks) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(init_fill_kernel<V>, dim3(blocks), dim3(256), 0, stream, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((init_seed_kernel<V, BATCH>), dim3(1), dim3(RBS), 0, stream, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_kernel(L, (const void *)init_fill_kernel<V>, dim3(blocks), dim3(256), params,
+                           false)) != hipSuccess)
+      return e;
+    if ((e = launch_kernel(L, (const void *)init_seed_kernel<V, BATCH>, dim3(1), dim3(RBS),
+                           params, false)) != hipSuccess)
+      return e;
     if (BATCH && a.inst_of) {
       const int nbk = a.num_inst < 1024 ? a.num_inst : 1024;
-      hipLaunchKernelGGL(inst_of_kernel, dim3(nbk), dim3(256), 0, stream, a);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = launch_kernel(L, (const void *)inst_of_kernel, dim3(nbk), dim3(256), params,
+                             false)) != hipSuccess)
+        return e;
     }
   }
-  {
-    RoundArgs arg = a;
-    void *params[] = {&arg};
-    if (timer && (e = hipEventRecord(timer->start, stream)) != hipSuccess) return e;
-    e = hipLaunchCooperativeKernel((const void *)rounds_kernel<V, BATCH>, dim3(geo.blocks),
-                                   dim3(RBS), params, 0, stream);
-    if (e != hipSuccess) return e;
-    if (timer && (e = hipEventRecord(timer->stop, stream)) != hipSuccess) return e;
-  }
+  if (L.graph) timer = nullptr;
+  if (timer && (e = hipEventRecord(timer->start, L.stream)) != hipSuccess) return e;
+  if ((e = launch_kernel(L, (const void *)rounds_kernel<V, BATCH>, dim3(geo.blocks), dim3(RBS),
+                         params, true)) != hipSuccess)
+    return e;
+  if (timer && (e = hipEventRecord(timer->stop, L.stream)) != hipSuccess) return e;
   // the emit pass writes the costs (and parents) out of the keys
-  return launch_pred(V::INF == KeyF32::INF, BATCH, a, pred, geo, istat, max_n, stream);
+  return launch_pred(V::INF == KeyF32::INF, BATCH, a, pred, geo, istat, max_n, L);
 }
 
 hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                         const LaunchGeom &geo, long long *istat, int32_t max_n,
-                        const KernelTimer *timer, hipStream_t stream) {
+                        const KernelTimer *timer, Launcher &L) {
   if (f32) {
-    return batch ? launch_solve_t<KeyF32, true>(a, pred, geo, istat, max_n, timer, stream)
-                 : launch_solve_t<KeyF32, false>(a, pred, geo, istat, max_n, timer, stream);
+    return batch ? launch_solve_t<KeyF32, true>(a, pred, geo, istat, max_n, timer, L)
+                 : launch_solve_t<KeyF32, false>(a, pred, geo, istat, max_n, timer, L);
   }
-  return batch ? launch_solve_t<KeyI32, true>(a, pred, geo, istat, max_n, timer, stream)
-               : launch_solve_t<KeyI32, false>(a, pred, geo, istat, max_n, timer, stream);
+  return batch ? launch_solve_t<KeyI32, true>(a, pred, geo, istat, max_n, timer, L)
+               : launch_solve_t<KeyI32, false>(a, pred, geo, istat, max_n, timer, L);
 }
 
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu) {

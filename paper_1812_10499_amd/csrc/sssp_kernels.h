@@ -168,12 +168,26 @@ __device__ __forceinline__ const GraphDev &graph_of(const RoundArgs &a, int gi) 
   else return a.g;
 }
 
+// Where a solve's kernels go: onto `stream` at once, or (graph non-null)
+// appended to `graph` as a chain of kernel nodes in launch order, each
+// depending on the one before (`last`).  The persistent kernel's node
+// carries the cooperative attribute, so a replay keeps its blocks
+// co-resident like the direct cooperative launch.
+struct Launcher {
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphNode_t last = nullptr;
+};
+// args: one pointer per kernel parameter (copied when the node is added)
+hipError_t launch_kernel(Launcher &L, const void *fn, dim3 grid, dim3 block, void **args,
+                         bool cooperative);
+
+// timer: eager launches only (a graph records no events)
 hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                         const LaunchGeom &geo, long long *istat, int32_t max_n,
-                        const KernelTimer *timer, hipStream_t stream);
+                        const KernelTimer *timer, Launcher &L);
 hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
-                       const LaunchGeom &geo, long long *istat, int32_t max_n,
-                       hipStream_t stream);
+                       const LaunchGeom &geo, long long *istat, int32_t max_n, Launcher &L);
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
 
 // ------------------------------------------------------------- builder

@@ -204,6 +204,82 @@ def solve_batch(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source:
     return cost, pred, stats
 
 
+PLAN_KINDS = {"batch": _abi.SSSP_PLAN_BATCH, "sequence": _abi.SSSP_PLAN_SEQUENCE}
+
+
+def _launch(launch):
+    if launch is None or isinstance(launch, _abi.Launch):
+        return launch
+    return _abi.Launch(int(launch.get("blocks", 0)), int(launch.get("solo_edges", 0)),
+                       int(launch.get("block_units", 0)))
+
+
+class Plan:
+    """Solves recorded once into a HIP graph and replayed by :meth:`run`.
+
+    kind "batch": one persistent launch for all instances (as
+    :func:`solve_batch`); "sequence": one single solve per instance, back
+    to back.  ``cost`` and ``pred`` (the latter optional) are allocated here
+    in the batch layout and rewritten by every run.  ``launch`` is a dict
+    (blocks, solo_edges, block_units) or None for the defaults.
+    """
+
+    def __init__(self, graphs: Sequence[Graph], inst_graph: Sequence[int],
+                 inst_source: Sequence[int], kind: str = "batch", with_pred: bool = True,
+                 with_stats: bool = False, launch=None):
+        _, total = batch_layout(graphs, inst_graph)
+        dev = graphs[0].device
+        self.graphs = list(graphs)  # keeps the graph buffers alive
+        self.num_inst = len(inst_graph)
+        self.cost = torch.empty(total, dtype=graphs[0].value_dtype, device=dev)
+        self.pred = torch.empty(total, dtype=torch.int32, device=dev) if with_pred else None
+        self.handle = None
+        self.handle = _abi.sssp_plan_create(
+            [g.csr for g in graphs], inst_graph, inst_source, PLAN_KINDS[kind],
+            self.cost.data_ptr(), self.pred.data_ptr() if with_pred else None, with_stats,
+            _launch(launch))
+
+    def run(self):
+        """Replays the recorded solves on the current stream (asynchronous)."""
+        _abi.sssp_plan_run(self.handle, _stream())
+        return self.cost, self.pred
+
+    def stats(self):
+        st = (Stats * self.num_inst)()
+        _abi.sssp_plan_stats(self.handle, st, _stream())
+        return [s.as_dict() for s in st]
+
+    def close(self):
+        if self.handle:
+            _abi.sssp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source: Sequence[int],
+             kind: str = "batch", reps: int = 2):
+    """Times replays under candidate launch geometries; returns (launch dict,
+    mean ms per run).  Pass the dict to :class:`Plan` or :func:`set_launch`."""
+    _, total = batch_layout(graphs, inst_graph)
+    dev = graphs[0].device
+    cost = torch.empty(total, dtype=graphs[0].value_dtype, device=dev)
+    pred = torch.empty(total, dtype=torch.int32, device=dev)
+    best, ms = _abi.sssp_autotune([g.csr for g in graphs], inst_graph, inst_source,
+                                  PLAN_KINDS[kind], cost.data_ptr(), pred.data_ptr(), reps,
+                                  _stream())
+    return best.as_dict(), ms
+
+
+def set_launch(launch=None):
+    """Default launch geometry of this device's direct solves (None: defaults)."""
+    _abi.sssp_set_launch(_launch(launch))
+
+
 def backward(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source: Sequence[int],
              pred: torch.Tensor, grad_cost: torch.Tensor) -> torch.Tensor:
     """dL/dw for L = sum grad_cost * cost over the pred trees; returns

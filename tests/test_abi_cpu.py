@@ -32,7 +32,9 @@ def test_header_declares_the_abi():
     names = declared_functions()
     assert names == sorted(["sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights",
                             "sssp_solve", "sssp_solve_target", "sssp_solve_batch",
-                            "sssp_backward",
+                            "sssp_backward", "sssp_set_launch", "sssp_plan_create",
+                            "sssp_plan_run", "sssp_plan_stats", "sssp_plan_destroy",
+                            "sssp_autotune",
                             "sssp_release_workspace", "sssp_strerror",
                             "sssp_profile_enable", "sssp_profile_read"])
 
@@ -125,6 +127,20 @@ def test_host_argument_errors(sp):
                                                None)) == S
     assert _status(lambda: sp.sssp_backward([c], [0], [10], 0x1000, 0x1000, 0x1000, None)) == S
     assert _status(lambda: sp.sssp_backward([c], [0], [0], None, 0x1000, 0x1000, None)) == S
+    # plans and the autotuner check their batch like sssp_solve_batch
+    B, Q = sp.SSSP_PLAN_BATCH, sp.SSSP_PLAN_SEQUENCE
+    assert _status(lambda: sp.sssp_plan_create([c], [1], [0], B, 0x1000, None, 0, None)) == S
+    assert _status(lambda: sp.sssp_plan_create([c], [0], [10], Q, 0x1000, None, 0, None)) == S
+    assert _status(lambda: sp.sssp_plan_create([c], [0], [0], 2, 0x1000, None, 0, None)) == S
+    assert _status(lambda: sp.sssp_plan_create([c], [0], [0], B, None, None, 0, None)) == S
+    assert _status(lambda: sp.sssp_plan_create([c, f], [0, 1], [0, 0], B, 0x1000, None, 0,
+                                               None)) == S
+    assert _status(lambda: sp.sssp_plan_run(None, None)) == S
+    assert _status(lambda: sp.sssp_plan_stats(None, sp.Stats(), None)) == S
+    assert _status(lambda: sp.sssp_plan_destroy(None)) == 0
+    assert _status(lambda: sp.sssp_autotune([c], [0], [0], B, 0x1000, None, 0, None)) == S
+    assert _status(lambda: sp.sssp_autotune([c], [0], [0], B, 0x1000, None, 101, None)) == S
+    assert _status(lambda: sp.sssp_autotune([c], [0], [11], B, 0x1000, None, 2, None)) == S
     # builder: bad sizes, missing pointers, short buffer
     out = sp.Csr()
     I = sp.SSSP_ORDER_INPUT
