@@ -7,7 +7,8 @@ progress goes to stderr.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22]
 
 Other workloads: grid1024, random4096, rmatNN (single solves, same fields),
-batch256 (256 instances in one launch against 256 single solves),
+batch256 (256 instances in one launch against 256 single solves, as direct calls and
+as autotuned HIP-graph replays),
 diff512 (64-source forward, backward and both against 64 single solves) and
 target22 (single-target early exit to eight targets on the RMAT-22 graph).
 
@@ -148,9 +149,24 @@ def bench_batch(args, sp, torch):
     for _ in range(args.warmup):
         batched()
         singles()
-    t_batch = timed(batched, args.steps, stream)
+    t_direct = timed(batched, args.steps, stream)
     t_single = timed(singles, max(1, args.steps // 4), stream)
-    log("batch %.2f ms, 256 singles %.2f ms" % (t_batch, t_single))
+    log("batch %.2f ms, 256 singles %.2f ms (direct calls)" % (t_direct, t_single))
+    # the autotuned geometry, replayed from HIP graphs: the batch and the
+    # 256 single solves back to back
+    tune_b, _ = sp.autotune(graphs, ig, isrc, kind="batch", reps=2)
+    tune_s, _ = sp.autotune(graphs, ig, isrc, kind="sequence", reps=1)
+    log("autotuned: batch %s, sequence %s" % (tune_b, tune_s))
+    plan_b = sp.Plan(graphs, ig, isrc, kind="batch", launch=tune_b)
+    plan_s = sp.Plan(graphs, ig, isrc, kind="sequence", launch=tune_s)
+    for _ in range(args.warmup):
+        plan_b.run()
+        plan_s.run()
+    t_batch = timed(plan_b.run, args.steps, stream)
+    t_single_plan = timed(plan_s.run, max(1, args.steps // 4), stream)
+    plan_b.close()
+    plan_s.close()
+    log("batch %.2f ms, 256 singles %.2f ms (tuned, graph replay)" % (t_batch, t_single_plan))
     cpu = None
     if not args.no_cpu_baseline:
         e, sec, k = oracle_sample(list(zip(glist, isrc)))
@@ -161,8 +177,13 @@ def bench_batch(args, sp, torch):
         "dtype": "f32",
         "config": {"workload": "batch256_random_deg8_f32", "instances": len(glist),
                    "sum_n": total, "sum_m": sum(g.m for g in glist), "m_reach": m_reach},
+        "timed": "autotuned batch plan (one HIP-graph replay per step)",
+        "batch_direct_ms": round(t_direct, 4),
         "single_solves_ms": round(t_single, 3),
+        "single_solves_plan_ms": round(t_single_plan, 3),
         "batched_vs_single_speedup": round(t_single / t_batch, 3),
+        "batched_vs_single_plan_speedup": round(t_single_plan / t_batch, 3),
+        "launch_batch": tune_b, "launch_sequence": tune_s,
         "rounds_max": max(s["rounds"] for s in stats),
         "rounds_sum": sum(s["rounds"] for s in stats),
         "dijkstra_settles": sum(s["settled"] for s in stats),
@@ -360,6 +381,13 @@ def main():
     sp.sssp_profile_enable(False)
     k_ms = kms / max(launches, 1)
 
+    # the same solve replayed from a HIP graph (no per-call host work)
+    plan = sp.Plan([G], [0], [g.source], kind="sequence")
+    for _ in range(args.warmup):
+        plan.run()
+    ms_plan = timed(plan.run, args.steps, stream)
+    plan.close()
+
     m_reach = stats["relaxed_edges"]
     gteps = m_reach / (ms_step * 1e-3) / 1e9
     alg_bytes = (BYTES_PER_RELAXED_EDGE * stats["relaxed_edges"] +
@@ -394,6 +422,7 @@ def main():
         "config": {"workload": wname, "n": g.n, "m": g.m, "source": g.source,
                    "vertex_order": G.order,
                    "weights": wdesc, "m_reach": m_reach},
+        "plan_ms_per_step": round(ms_plan, 4),
         "solve_gbps_algorithmic": round(solve_bytes / (ms_step * 1e-3) / 1e9, 1),
         "rounds": stats["rounds"],
         "dijkstra_settles": stats["settled"],
