@@ -318,6 +318,46 @@ __device__ void stage_flush(Stager<CAP, NX> &st, const ListRef &l, bool batch) {
   __syncthreads();
 }
 
+// Both stagers of the bound step flushed together: the two reservations are
+// issued from different waves before either is waited for, so their
+// device-atomic latencies overlap.
+template <int CAP, int N1, int N2>
+__device__ void stage_flush2(Stager<CAP, N1> &s1, const ListRef &l1, Stager<CAP, N2> &s2,
+                             const ListRef &l2, bool batch) {
+  const int c1 = s1.cnt, c2 = s2.cnt;
+  if (c1 == 0 && c2 == 0) return;
+  if (threadIdx.x == 0 && c1)
+    s1.base = atomicAdd(l1.ctr, ((unsigned long long)c1 << 32) | (unsigned long long)s1.deg);
+  if (threadIdx.x == SSSP_WAVE && c2)
+    s2.base = atomicAdd(l2.ctr, ((unsigned long long)c2 << 32) | (unsigned long long)s2.deg);
+  __syncthreads();
+  const unsigned long long b1 = s1.base, b2 = s2.base;
+  const int32_t bc1 = (int32_t)(b1 >> 32), bd1 = (int32_t)(uint32_t)(b1 & 0xffffffffull);
+  const int32_t bc2 = (int32_t)(b2 >> 32), bd2 = (int32_t)(uint32_t)(b2 & 0xffffffffull);
+  for (int j = threadIdx.x; j < c1; j += RBS) {
+    l1.v[bc1 + j] = s1.v[j];
+    l1.p[bc1 + j] = bd1 + s1.d[j];
+    if (batch) l1.i[bc1 + j] = s1.inst[j];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) l1.x[k][bc1 + j] = s1.x[k][j];
+  }
+  for (int j = threadIdx.x; j < c2; j += RBS) {
+    l2.v[bc2 + j] = s2.v[j];
+    l2.p[bc2 + j] = bd2 + s2.d[j];
+    if (batch) l2.i[bc2 + j] = s2.inst[j];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) l2.x[k][bc2 + j] = s2.x[k][j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s1.cnt = 0;
+    s1.deg = 0;
+    s2.cnt = 0;
+    s2.deg = 0;
+  }
+  __syncthreads();
+}
+
 // Block-collective push: entry j of the thread's v/d/ins arrays is pushed
 // iff bit j of `mask` is set (arrays are indexed by compile-time j only, so
 // they stay in VGPRs).  Flushes first when the stager would overflow.
@@ -1171,8 +1211,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       ++pw.windows;
     }
   }
-  stage_flush(S.fr, front, BATCH);
-  stage_flush(S.op, next_open, BATCH);
+  stage_flush2(S.fr, front, S.op, next_open, BATCH);
   if (NL > 0) {
     __syncthreads();  // the live pass reuses the stagers' LDS
     live_pass<V, BATCH>(a, sm, bl, pc, r, NL, mind_all, Cold, Cnew);
