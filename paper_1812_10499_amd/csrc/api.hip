@@ -38,7 +38,7 @@ struct DevWS {
   size_t pinned_cap = 0;
   hipEvent_t last = nullptr;  // completion of the previous call's work
   hipEvent_t staged = nullptr;
-  sssp_launch cfg = {0, 0, 0};  // default geometry of direct solves (sssp_set_launch)
+  sssp_launch cfg = {0, 0, 0, 0};  // default geometry of direct solves (sssp_set_launch)
 };
 
 std::mutex g_mu;
@@ -165,6 +165,8 @@ sssp_status resolve_launch(DevWS &w, bool f32, bool batch, const sssp_launch *L,
     if (L->block_units < 0) return SSSP_ERR_ARG;
     a.block_units = L->block_units;
   }
+  geo->small_n = kSmallN;
+  if (L && L->small_n) geo->small_n = L->small_n < 0 ? 0 : (L->small_n < kSmallN ? L->small_n : kSmallN);
   return SSSP_OK;
 }
 
@@ -885,7 +887,7 @@ sssp_status sssp_set_launch(const sssp_launch *launch) {
   sssp_status s;
   if ((s = ws_for_current(&wp))) return s;
   if (!launch) {
-    wp->cfg = sssp_launch{0, 0, 0};
+    wp->cfg = sssp_launch{0, 0, 0, 0};
     return SSSP_OK;
   }
   // the grid must fit both kernel variants of both dtypes
@@ -1142,20 +1144,23 @@ sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int3
     sssp_status st;
     if ((st = resolve_launch(p->ws, p->f32, kind == SSSP_PLAN_BATCH, nullptr, &full, probe)))
       return st;
-    sssp_launch cur = {full.blocks, probe.solo_edges, probe.block_units};
+    sssp_launch cur = {full.blocks, probe.solo_edges, probe.block_units, full.small_n};
     double cur_ms;
     if ((st = time_of(cur, &cur_ms))) return st;
     const int32_t blocks[3] = {full.blocks, full.blocks / 2, full.blocks / 4};
     const int32_t solo[3] = {2048, 8192, 32768};
     const int32_t units[3] = {2048, 4096, 8192};
-    for (int field = 0; field < 3; ++field) {
+    const int32_t small[3] = {full.small_n, -1, full.small_n};
+    for (int field = 0; field < 4; ++field) {
       for (int c = 0; c < 3; ++c) {
         sssp_launch cand = cur;
         if (field == 0) cand.blocks = blocks[c];
         if (field == 1) cand.solo_edges = solo[c];
         if (field == 2) cand.block_units = units[c];
+        if (field == 3) cand.small_n = small[c];
         if (cand.blocks < 1 || (cand.blocks == cur.blocks && cand.solo_edges == cur.solo_edges &&
-                                cand.block_units == cur.block_units))
+                                cand.block_units == cur.block_units &&
+                                cand.small_n == cur.small_n))
           continue;
         double ms;
         if ((st = time_of(cand, &ms))) return st;

@@ -1,0 +1,256 @@
+// The rounds of a single solve on a small graph (n <= kSmallN) in one
+// workgroup, with the whole per-vertex state in LDS: the (D, parent) keys,
+// both C buffers, the relax set, the open lists and the last-relaxed D of
+// label-correcting relax.  Only the graph arrays are read from global memory
+// (through this CU's L2).  The phases are separated by block barriers alone,
+// so a round costs a few microseconds instead of the grid barriers and
+// hand-overs of the persistent kernel; results and counters are the same
+// round for round (Section VI's rounds in the adopted order: relax, minD and
+// the threshold, the lower bounds of Eq. 1, fix).  The keys are written back
+// to global memory at the end for the emit pass.
+#include "sssp_dev.h"
+#include "sssp_kernels.h"
+
+namespace sssp {
+
+constexpr int SBS = 1024;  // threads of the workgroup
+
+struct SmallLds {
+  unsigned long long D[kSmallN];  // (D << 32) | equal-cost flag << 31 | edge id
+  int32_t C[2][kSmallN];          // lower bounds by round parity (INF: fixed)
+  int32_t F[kSmallN];             // relax set: vertex ...
+  int32_t FD[kSmallN];            // ... and the D it is relaxed with
+  int32_t O[2][kSmallN];          // open lists by round parity
+  int32_t DR[kSmallN];            // label-correcting: D of the last relax (INF: never)
+  int32_t pfx[SBS + 1];           // out-degree prefix of a window of relax items
+  int32_t wbase[SBS];             // out-list start of a window item
+  int32_t wdx[SBS];               // its relax D
+  uint64_t scan[SBS / SSSP_WAVE + 1];
+  int32_t red[2 * (SBS / SSSP_WAVE)];
+  int32_t nF, nO, nF2, nO2, target_hit;
+  unsigned long long relaxed, scanned, visits;
+  unsigned long long settled;
+};
+
+template <class V>
+__global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
+  __shared__ SmallLds s;
+  const int tid = threadIdx.x;
+  const GraphDev &G = a.g;
+  const int n = G.n;
+  const bool lc = G.lc != 0, all = a.scope_all != 0;
+  Ctl *ctl = a.ctl;
+  int32_t src = a.source, tgt = a.target;
+  if (G.rank) {
+    src = G.rank[src];
+    if (tgt >= 0) tgt = G.rank[tgt];
+  }
+  for (int y = tid; y < n; y += SBS) {
+    const bool is_s = y == src;
+    s.D[y] = make_key(is_s ? 0 : V::INF, -1, false);
+    s.C[0][y] = s.C[1][y] = is_s ? V::INF : 0;  // the source is fixed from the start
+    s.DR[y] = V::INF;
+  }
+  if (tid == 0) {
+    s.F[0] = src;
+    s.FD[0] = 0;
+    s.nF = 1;
+    s.nO = 0;
+    s.target_hit = (tgt >= 0 && tgt == src) ? 1 : 0;
+    s.relaxed = s.scanned = s.visits = 0ull;
+    s.settled = 1ull;  // the source
+  }
+  __syncthreads();
+  int r = 0, o = 0, status = 0;  // o: the open list being built this round
+  for (;;) {
+    if (tgt >= 0 && s.target_hit) break;  // the frontier that fixed it is not relaxed
+    ++r;
+    if (r > a.max_rounds) {
+      status = 7;
+      break;
+    }
+    const int cur = r & 1;  // the bound step reads C[cur] and writes C[cur ^ 1]
+    // (A) relax the relax set's out-edges, each from its D at the start of
+    // the step; first discoveries join the open list
+    const int nF = s.nF;
+    unsigned long long nrel = 0;
+    for (int i0 = 0; i0 < nF; i0 += SBS) {
+      const int i = i0 + tid;
+      int32_t deg = 0;
+      if (i < nF) {
+        const int32_t x = s.F[i];
+        const int32_t b = G.out_off[x];
+        deg = G.out_off[x + 1] - b;
+        s.wbase[tid] = b;
+        s.wdx[tid] = s.FD[i];
+        if (lc) s.DR[x] = s.FD[i];
+      }
+      uint64_t tot;
+      s.pfx[tid] = (int32_t)block_excl_scan64<SBS>((uint64_t)deg, s.scan, &tot);
+      if (tid == 0) s.pfx[SBS] = (int32_t)tot;
+      __syncthreads();
+      const int ET = (int)tot;
+      nrel += (unsigned long long)ET;
+      for (int e = tid; e < ET; e += SBS) {
+        int lo = 0, len = SBS;  // last window item with pfx <= e
+        while (len > 1) {
+          const int half = len >> 1;
+          if (s.pfx[lo + half] <= e) lo += half;
+          len -= half;
+        }
+        const int32_t pos = s.wbase[lo] + (e - s.pfx[lo]);
+        const int32_t y = G.out_dst[pos];
+        const int32_t w = G.out_w[pos];
+        const int32_t eid = G.out_eid ? G.out_eid[pos] : pos;
+        const int32_t dx = s.wdx[lo];
+        const int32_t cand = V::add(dx, w);
+        const unsigned long long old = atomicMin(&s.D[y], make_key(cand, eid, cand == dx));
+        if ((int32_t)(old >> 32) == V::INF) s.O[o][atomicAdd(&s.nO, 1)] = y;
+      }
+      __syncthreads();
+    }
+    const int nO = s.nO;
+    if (tid == 0) s.relaxed += nrel;
+    if (nO == 0) break;  // (A) left nothing open
+    // (B) minD and the threshold over the open list
+    int32_t md = V::INF, th = V::INF;
+    for (int i = tid; i < nO; i += SBS) {
+      const int32_t y = s.O[o][i];
+      const int32_t dy = (int32_t)(s.D[y] >> 32);
+      md = kmin(md, dy);
+      th = kmin(th, V::add(dy, G.out_wmin[y]));
+    }
+    block_min2<SBS>(md, th, s.red);
+    // (C) lower bounds (Eq. 1), Jacobi: read C[cur], write C[cur ^ 1].
+    // In-lists are ascending by weight and every term max(C[v], minD) + w
+    // is at least minD + w, so the scan of a list stops at the first edge
+    // with minD + w >= min(D[y], m_y); the counters take whole in-degrees.
+    const int32_t *Cold = s.C[cur];
+    int32_t *Cnew = s.C[cur ^ 1];
+    unsigned long long nscan = 0;
+    for (int i = tid; i < nO; i += SBS) {
+      const int32_t y = s.O[o][i];
+      const int32_t dy = (int32_t)(s.D[y] >> 32);
+      const int4 rec = G.vrec[2 * y];  // out_off, out_degree, in_off, in_degree
+      int32_t m = V::INF;
+      for (int32_t j = 0; j < rec.w; ++j) {
+        const int32_t w = G.in_w[rec.z + j];
+        if (V::add(md, w) >= kmin(dy, m)) break;
+        const int32_t cv = Cold[G.in_src[rec.z + j]];
+        if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+      }
+      Cnew[y] = kmax(kmax(Cold[y], md), kmin(dy, m));
+      nscan += (unsigned long long)rec.w;
+    }
+    if (all) {
+      // SP_4's scope: every undiscovered vertex (D = INF) too
+      for (int y = tid; y < n; y += SBS) {
+        if ((int32_t)(s.D[y] >> 32) != V::INF) continue;
+        const int4 rec = G.vrec[2 * y];
+        int32_t m = V::INF;
+        for (int32_t j = 0; j < rec.w; ++j) {
+          const int32_t w = G.in_w[rec.z + j];
+          if (V::add(md, w) >= m) break;
+          const int32_t cv = Cold[G.in_src[rec.z + j]];
+          if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+        }
+        Cnew[y] = kmax(kmax(Cold[y], md), m);
+        nscan += (unsigned long long)rec.w;
+      }
+    }
+    if (tid == 0) {
+      s.nF2 = 0;
+      s.nO2 = 0;
+    }
+    __syncthreads();
+    // (D) fix: C' >= D or D <= thr.  Fixed vertices get C = INF in both
+    // buffers; the next relax set is the newly fixed vertices (label-
+    // correcting: those and the survivors whose D fell since their last
+    // relax, the fixed ones only if it fell)
+    unsigned long long nfix = 0;
+    for (int i = tid; i < nO; i += SBS) {
+      const int32_t y = s.O[o][i];
+      const int32_t dy = (int32_t)(s.D[y] >> 32);
+      const int32_t cn = Cnew[y];
+      const bool relax_again = !lc || dy < s.DR[y];
+      if (cn >= dy || dy <= th) {
+        s.C[0][y] = s.C[1][y] = V::INF;
+        ++nfix;
+        if (y == tgt) s.target_hit = 1;
+        if (relax_again) {
+          const int q = atomicAdd(&s.nF2, 1);
+          s.F[q] = y;
+          s.FD[q] = dy;
+        }
+      } else {
+        s.O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
+        if (lc && relax_again) {
+          const int q = atomicAdd(&s.nF2, 1);
+          s.F[q] = y;
+          s.FD[q] = dy;
+        }
+      }
+    }
+    const long long f = wave_sum64((long long)nfix), sc = wave_sum64((long long)nscan);
+    if (lane_id() == 0) {
+      if (f) atomicAdd(&s.settled, (unsigned long long)f);
+      if (sc) atomicAdd(&s.scanned, (unsigned long long)sc);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s.visits += (unsigned long long)nO;
+      s.nF = s.nF2;
+      s.nO = s.nO2;
+    }
+    o ^= 1;
+    __syncthreads();
+  }
+  __syncthreads();
+  // the keys for the emit pass, and the control block it and the host read
+  for (int y = tid; y < n; y += SBS) a.D64[y] = s.D[y];
+  if (tid == 0) {
+    ctl->front_ctr[0] = ctl->front_ctr[1] = 0ull;
+    ctl->open_ctr[0] = ctl->open_ctr[1] = 0ull;
+    ctl->live_ctr[0] = ctl->live_ctr[1] = 0ull;
+    ctl->go = ctl->go_a = 0u;
+    ctl->deg_count = 0;
+    ctl->heavy_count = 0;
+    ctl->resume_round = ctl->resume_phase = ctl->done = ctl->resume_act = 0;
+    ctl->resume_aep = 0u;
+    ctl->solo_phases = 0;
+    ctl->dead_deg = ctl->dead_deg_r = 0ull;
+    ctl->rounds = r;
+    ctl->status = status;
+    ctl->settled = (long long)s.settled;
+    ctl->relaxed = (long long)s.relaxed;
+    ctl->scanned = (long long)s.scanned;
+    ctl->open_visits = (long long)s.visits;
+    ctl->target_id = tgt;
+    ctl->target_hit = s.target_hit;
+  }
+}
+
+template <class V>
+static hipError_t launch_small_t(const RoundArgs &a, int32_t *pred, const KernelTimer *timer,
+                                 Launcher &L) {
+  hipError_t e;
+  if (a.total > kSmallN || a.num_inst != 1) return hipErrorInvalidValue;
+  RoundArgs arg = a;
+  void *params[] = {&arg};
+  if (L.graph) timer = nullptr;
+  if (timer && (e = hipEventRecord(timer->start, L.stream)) != hipSuccess) return e;
+  if ((e = launch_kernel(L, (const void *)small_rounds_kernel<V>, dim3(1), dim3(SBS), params,
+                         false)) != hipSuccess)
+    return e;
+  if (timer && (e = hipEventRecord(timer->stop, L.stream)) != hipSuccess) return e;
+  LaunchGeom geo = {1, 1};
+  return launch_pred(V::INF == KeyF32::INF, false, a, pred, geo, nullptr, a.total, L);
+}
+
+hipError_t launch_small(bool f32, const RoundArgs &a, int32_t *pred, const KernelTimer *timer,
+                        Launcher &L) {
+  return f32 ? launch_small_t<KeyF32>(a, pred, timer, L)
+             : launch_small_t<KeyI32>(a, pred, timer, L);
+}
+
+}  // namespace sssp

@@ -1627,6 +1627,7 @@ static hipError_t launch_solve_t(const RoundArgs &a, int32_t *pred, const Launch
                                  Launcher &L) {
   hipError_t e;
   if (geo.blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+  if (!BATCH && a.total <= geo.small_n) return launch_small(V::INF == KeyF32::INF, a, pred, timer, L);
   RoundArgs arg = a;
   void *params[] = {&arg};
   {

@@ -145,7 +145,11 @@ constexpr int kMarks = 12;
 struct LaunchGeom {
   int blocks;  // persistent grid size (co-resident)
   int cus;
+  int small_n = 0;  // single solves of at most this many vertices run in one workgroup
 };
+
+// Largest graph the one-workgroup solver holds in LDS.
+constexpr int kSmallN = 4096;
 
 constexpr unsigned long long kKeyEidMask = 0x7fffffffull;
 constexpr unsigned long long kKeyEqualCost = 0x80000000ull;
@@ -189,6 +193,9 @@ hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
 hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                        const LaunchGeom &geo, long long *istat, int32_t max_n, Launcher &L);
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
+// a single solve of a.total <= kSmallN vertices in one workgroup, then the emit pass
+hipError_t launch_small(bool f32, const RoundArgs &a, int32_t *pred, const KernelTimer *timer,
+                        Launcher &L);
 
 // ------------------------------------------------------------- builder
 struct BuildTemps {
