@@ -228,11 +228,20 @@ def bench_diff(args, sp, torch):
     for _ in range(args.warmup):
         both()
         singles()
+    t_fwd_default = timed(fwd, args.steps, stream)
+    t_single = timed(singles, max(1, args.steps // 4), stream)
+    # the autotuned launch geometry of the 64-source forward, made the
+    # default of the direct calls timed below
+    tuned, _ = sp.autotune([G], ig, srcs, kind="batch", reps=2)
+    sp.set_launch(tuned)
+    for _ in range(args.warmup):
+        both()
     t_fwd = timed(fwd, args.steps, stream)
     t_bwd = timed(bwd, args.steps, stream)
     t_both = timed(both, args.steps, stream)
-    t_single = timed(singles, max(1, args.steps // 4), stream)
-    log("fwd %.2f bwd %.2f both %.2f ms; 64 singles %.2f ms" % (t_fwd, t_bwd, t_both, t_single))
+    sp.set_launch(None)
+    log("tuned %s: fwd %.2f (default geometry %.2f) bwd %.2f both %.2f ms; 64 singles %.2f ms"
+        % (tuned, t_fwd, t_fwd_default, t_bwd, t_both, t_single))
     cpu = None
     if not args.no_cpu_baseline:
         e, sec, k = oracle_sample([(d, s) for s in srcs])
@@ -243,6 +252,8 @@ def bench_diff(args, sp, torch):
         "dtype": "f32",
         "config": {"workload": "diff_grid512_f32_x64", "n": d.n, "m": d.m, "sources": S,
                    "m_reach": m_reach},
+        "timed": "direct calls under the autotuned launch geometry",
+        "launch": tuned, "forward_default_geometry_ms": round(t_fwd_default, 3),
         "forward_ms": round(t_fwd, 3), "backward_ms": round(t_bwd, 3),
         "forward_backward_ms": round(t_both, 3), "single_solves_ms": round(t_single, 3),
         "rounds_max": max(s["rounds"] for s in stats),
@@ -381,12 +392,16 @@ def main():
     sp.sssp_profile_enable(False)
     k_ms = kms / max(launches, 1)
 
-    # the same solve replayed from a HIP graph (no per-call host work)
+    # the same solve replayed from a HIP graph (no per-call host work), with
+    # the default and with the autotuned launch geometry
     plan = sp.Plan([G], [0], [g.source], kind="sequence")
     for _ in range(args.warmup):
         plan.run()
     ms_plan = timed(plan.run, args.steps, stream)
     plan.close()
+    tuned, ms_tuned = sp.autotune([G], [0], [g.source], kind="sequence",
+                                  reps=max(1, min(10, int(200.0 / max(ms_plan, 1e-3)))))
+    log("plan %.3f ms, tuned plan %.3f ms %s" % (ms_plan, ms_tuned, tuned))
 
     m_reach = stats["relaxed_edges"]
     gteps = m_reach / (ms_step * 1e-3) / 1e9
@@ -423,6 +438,7 @@ def main():
                    "vertex_order": G.order,
                    "weights": wdesc, "m_reach": m_reach},
         "plan_ms_per_step": round(ms_plan, 4),
+        "tuned_plan_ms_per_step": round(ms_tuned, 4), "launch_tuned": tuned,
         "solve_gbps_algorithmic": round(solve_bytes / (ms_step * 1e-3) / 1e9, 1),
         "rounds": stats["rounds"],
         "dijkstra_settles": stats["settled"],

@@ -13,24 +13,49 @@
 
 namespace sssp {
 
-constexpr int SBS = 1024;  // threads of the workgroup
+constexpr int SBS = 1024;                 // threads of the workgroup
+constexpr int kSlots = kSmallN / SBS;     // vertices per thread: y = tid + k * SBS
+static_assert(kSlots * SBS == kSmallN, "whole slots");
 
+// The open set O is implicit: y is open iff it is discovered (D < INF) and
+// not fixed (C < INF; fixed vertices carry C = INF in both buffers, and a
+// discovered vertex never has C = INF otherwise, as C <= D).
 struct SmallLds {
   unsigned long long D[kSmallN];  // (D << 32) | equal-cost flag << 31 | edge id
   int32_t C[2][kSmallN];          // lower bounds by round parity (INF: fixed)
   int32_t F[kSmallN];             // relax set: vertex ...
   int32_t FD[kSmallN];            // ... and the D it is relaxed with
-  int32_t O[2][kSmallN];          // open lists by round parity
   int32_t DR[kSmallN];            // label-correcting: D of the last relax (INF: never)
   int32_t pfx[SBS + 1];           // out-degree prefix of a window of relax items
   int32_t wbase[SBS];             // out-list start of a window item
   int32_t wdx[SBS];               // its relax D
   uint64_t scan[SBS / SSSP_WAVE + 1];
   int32_t red[2 * (SBS / SSSP_WAVE)];
-  int32_t nF, nO, nF2, nO2, target_hit;
-  unsigned long long relaxed, scanned, visits;
-  unsigned long long settled;
+  int32_t nF, nF2, nO, target_hit;
+  unsigned long long relaxed, scanned, visits, settled;
 };
+
+// m_y of Eq. 1 over y's weight-ordered in-list (first edge from registers):
+// the scan stops at the first edge with minD + w >= lim, as every later term
+// max(C[v], minD) + w is at least minD + w.
+template <class V>
+__device__ __forceinline__ int32_t small_m(const GraphDev &G, const int32_t *Cold, int32_t b,
+                                           int32_t deg, int32_t s0, int32_t w0, int32_t md,
+                                           int32_t lim) {
+  int32_t m = V::INF;
+  if (deg == 0 || V::add(md, w0) >= lim) return m;
+  {
+    const int32_t cv = Cold[s0];
+    if (cv != V::INF) m = V::add(kmax(cv, md), w0);
+  }
+  for (int32_t j = 1; j < deg; ++j) {
+    const int32_t w = G.in_w[b + j];
+    if (V::add(md, w) >= kmin(lim, m)) break;
+    const int32_t cv = Cold[G.in_src[b + j]];
+    if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+  }
+  return m;
+}
 
 template <class V>
 __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
@@ -45,11 +70,27 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
     src = G.rank[src];
     if (tgt >= 0) tgt = G.rank[tgt];
   }
-  for (int y = tid; y < n; y += SBS) {
-    const bool is_s = y == src;
-    s.D[y] = make_key(is_s ? 0 : V::INF, -1, false);
-    s.C[0][y] = s.C[1][y] = is_s ? V::INF : 0;  // the source is fixed from the start
-    s.DR[y] = V::INF;
+  // this thread's vertices: in-list offset and length, lightest in-edge, out_wmin
+  int32_t ib[kSlots], id[kSlots], s0[kSlots], w0[kSlots], owm[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    const int y = tid + k * SBS;
+    ib[k] = id[k] = s0[k] = 0;
+    w0[k] = owm[k] = V::INF;
+    if (y < n) {
+      const int4 rec = G.vrec[2 * y];  // out_off, out_degree, in_off, in_degree
+      ib[k] = rec.z;
+      id[k] = rec.w;
+      owm[k] = G.vrec[2 * y + 1].x;
+      if (rec.w > 0) {
+        s0[k] = G.in_src[rec.z];
+        w0[k] = G.in_w[rec.z];
+      }
+      const bool is_s = y == src;
+      s.D[y] = make_key(is_s ? 0 : V::INF, -1, false);
+      s.C[0][y] = s.C[1][y] = is_s ? V::INF : 0;  // the source is fixed from the start
+      s.DR[y] = V::INF;
+    }
   }
   if (tid == 0) {
     s.F[0] = src;
@@ -61,7 +102,7 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
     s.settled = 1ull;  // the source
   }
   __syncthreads();
-  int r = 0, o = 0, status = 0;  // o: the open list being built this round
+  int r = 0, status = 0;
   for (;;) {
     if (tgt >= 0 && s.target_hit) break;  // the frontier that fixed it is not relaxed
     ++r;
@@ -71,7 +112,7 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
     }
     const int cur = r & 1;  // the bound step reads C[cur] and writes C[cur ^ 1]
     // (A) relax the relax set's out-edges, each from its D at the start of
-    // the step; first discoveries join the open list
+    // the step (first discoveries join O by getting a finite D)
     const int nF = s.nF;
     unsigned long long nrel = 0;
     for (int i0 = 0; i0 < nF; i0 += SBS) {
@@ -87,7 +128,6 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
       }
       uint64_t tot;
       s.pfx[tid] = (int32_t)block_excl_scan64<SBS>((uint64_t)deg, s.scan, &tot);
-      if (tid == 0) s.pfx[SBS] = (int32_t)tot;
       __syncthreads();
       const int ET = (int)tot;
       nrel += (unsigned long long)ET;
@@ -104,90 +144,82 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
         const int32_t eid = G.out_eid ? G.out_eid[pos] : pos;
         const int32_t dx = s.wdx[lo];
         const int32_t cand = V::add(dx, w);
-        const unsigned long long old = atomicMin(&s.D[y], make_key(cand, eid, cand == dx));
-        if ((int32_t)(old >> 32) == V::INF) s.O[o][atomicAdd(&s.nO, 1)] = y;
+        atomicMin(&s.D[y], make_key(cand, eid, cand == dx));
       }
       __syncthreads();
     }
+    const int32_t *Cold = s.C[cur];
+    int32_t *Cnew = s.C[cur ^ 1];
+    // (B) minD and the threshold over O, and |O|
+    int32_t md = V::INF, th = V::INF;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      const int y = tid + k * SBS;
+      if (y < n) {
+        const int32_t dy = (int32_t)(s.D[y] >> 32);
+        if (dy != V::INF && Cold[y] != V::INF) {
+          md = kmin(md, dy);
+          th = kmin(th, V::add(dy, owm[k]));
+          ++cnt;
+        }
+      }
+    }
+    {
+      const long long c = wave_sum64((long long)cnt);
+      if (lane_id() == 0 && c) atomicAdd(&s.nO, (int32_t)c);
+    }
+    block_min2<SBS>(md, th, s.red);  // its barriers also publish nO
     const int nO = s.nO;
     if (tid == 0) s.relaxed += nrel;
     if (nO == 0) break;  // (A) left nothing open
-    // (B) minD and the threshold over the open list
-    int32_t md = V::INF, th = V::INF;
-    for (int i = tid; i < nO; i += SBS) {
-      const int32_t y = s.O[o][i];
-      const int32_t dy = (int32_t)(s.D[y] >> 32);
-      md = kmin(md, dy);
-      th = kmin(th, V::add(dy, G.out_wmin[y]));
-    }
-    block_min2<SBS>(md, th, s.red);
-    // (C) lower bounds (Eq. 1), Jacobi: read C[cur], write C[cur ^ 1].
-    // In-lists are ascending by weight and every term max(C[v], minD) + w
-    // is at least minD + w, so the scan of a list stops at the first edge
-    // with minD + w >= min(D[y], m_y); the counters take whole in-degrees.
-    const int32_t *Cold = s.C[cur];
-    int32_t *Cnew = s.C[cur ^ 1];
+    // (C) lower bounds (Eq. 1), Jacobi over C[cur]; SP_4's scope also
+    // raises C of undiscovered vertices (an unreachable one, C = INF, keeps
+    // it).  The counters take whole in-degrees.
     unsigned long long nscan = 0;
-    for (int i = tid; i < nO; i += SBS) {
-      const int32_t y = s.O[o][i];
-      const int32_t dy = (int32_t)(s.D[y] >> 32);
-      const int4 rec = G.vrec[2 * y];  // out_off, out_degree, in_off, in_degree
-      int32_t m = V::INF;
-      for (int32_t j = 0; j < rec.w; ++j) {
-        const int32_t w = G.in_w[rec.z + j];
-        if (V::add(md, w) >= kmin(dy, m)) break;
-        const int32_t cv = Cold[G.in_src[rec.z + j]];
-        if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
-      }
-      Cnew[y] = kmax(kmax(Cold[y], md), kmin(dy, m));
-      nscan += (unsigned long long)rec.w;
-    }
-    if (all) {
-      // SP_4's scope: every undiscovered vertex (D = INF) too
-      for (int y = tid; y < n; y += SBS) {
-        if ((int32_t)(s.D[y] >> 32) != V::INF) continue;
-        const int4 rec = G.vrec[2 * y];
-        int32_t m = V::INF;
-        for (int32_t j = 0; j < rec.w; ++j) {
-          const int32_t w = G.in_w[rec.z + j];
-          if (V::add(md, w) >= m) break;
-          const int32_t cv = Cold[G.in_src[rec.z + j]];
-          if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      const int y = tid + k * SBS;
+      if (y < n) {
+        const int32_t dy = (int32_t)(s.D[y] >> 32);
+        const int32_t c = Cold[y];
+        const bool open = dy != V::INF && c != V::INF;
+        const bool undiscovered = dy == V::INF && all;
+        if (open || undiscovered) {
+          // m_y matters below min(D[y], m_y); D = INF for undiscovered ones
+          const int32_t m = c == V::INF ? V::INF
+                                        : small_m<V>(G, Cold, ib[k], id[k], s0[k], w0[k], md, dy);
+          Cnew[y] = kmax(kmax(c, md), kmin(dy, m));
+          nscan += (unsigned long long)id[k];
         }
-        Cnew[y] = kmax(kmax(Cold[y], md), m);
-        nscan += (unsigned long long)rec.w;
       }
     }
-    if (tid == 0) {
-      s.nF2 = 0;
-      s.nO2 = 0;
-    }
+    if (tid == 0) s.nF2 = 0;
     __syncthreads();
     // (D) fix: C' >= D or D <= thr.  Fixed vertices get C = INF in both
     // buffers; the next relax set is the newly fixed vertices (label-
     // correcting: those and the survivors whose D fell since their last
     // relax, the fixed ones only if it fell)
     unsigned long long nfix = 0;
-    for (int i = tid; i < nO; i += SBS) {
-      const int32_t y = s.O[o][i];
-      const int32_t dy = (int32_t)(s.D[y] >> 32);
-      const int32_t cn = Cnew[y];
-      const bool relax_again = !lc || dy < s.DR[y];
-      if (cn >= dy || dy <= th) {
-        s.C[0][y] = s.C[1][y] = V::INF;
-        ++nfix;
-        if (y == tgt) s.target_hit = 1;
-        if (relax_again) {
-          const int q = atomicAdd(&s.nF2, 1);
-          s.F[q] = y;
-          s.FD[q] = dy;
-        }
-      } else {
-        s.O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
-        if (lc && relax_again) {
-          const int q = atomicAdd(&s.nF2, 1);
-          s.F[q] = y;
-          s.FD[q] = dy;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      const int y = tid + k * SBS;
+      if (y < n) {
+        const int32_t dy = (int32_t)(s.D[y] >> 32);
+        if (dy != V::INF && Cold[y] != V::INF) {
+          const int32_t cn = Cnew[y];
+          const bool relax_again = !lc || dy < s.DR[y];
+          const bool fix = cn >= dy || dy <= th;
+          if (fix) {
+            s.C[0][y] = s.C[1][y] = V::INF;
+            ++nfix;
+            if (y == tgt) s.target_hit = 1;
+          }
+          if (relax_again && (fix || lc)) {
+            const int q = atomicAdd(&s.nF2, 1);
+            s.F[q] = y;
+            s.FD[q] = dy;
+          }
         }
       }
     }
@@ -200,9 +232,8 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
     if (tid == 0) {
       s.visits += (unsigned long long)nO;
       s.nF = s.nF2;
-      s.nO = s.nO2;
+      s.nO = 0;
     }
-    o ^= 1;
     __syncthreads();
   }
   __syncthreads();
