@@ -334,6 +334,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the plan-replay and autotuner timings of single-solve "
+                         "workloads (profiler runs: only the timed direct solves launch)")
     ap.add_argument("--order", default="auto", choices=["auto", "input", "degree"],
                     help="vertex numbering of the solver's working copy")
     args = ap.parse_args()
@@ -394,14 +397,16 @@ def main():
 
     # the same solve replayed from a HIP graph (no per-call host work), with
     # the default and with the autotuned launch geometry
-    plan = sp.Plan([G], [0], [g.source], kind="sequence")
-    for _ in range(args.warmup):
-        plan.run()
-    ms_plan = timed(plan.run, args.steps, stream)
-    plan.close()
-    tuned, ms_tuned = sp.autotune([G], [0], [g.source], kind="sequence",
-                                  reps=max(1, min(10, int(200.0 / max(ms_plan, 1e-3)))))
-    log("plan %.3f ms, tuned plan %.3f ms %s" % (ms_plan, ms_tuned, tuned))
+    ms_plan = ms_tuned = tuned = None
+    if not args.no_tune:
+        plan = sp.Plan([G], [0], [g.source], kind="sequence")
+        for _ in range(args.warmup):
+            plan.run()
+        ms_plan = timed(plan.run, args.steps, stream)
+        plan.close()
+        tuned, ms_tuned = sp.autotune([G], [0], [g.source], kind="sequence",
+                                      reps=max(1, min(10, int(200.0 / max(ms_plan, 1e-3)))))
+        log("plan %.3f ms, tuned plan %.3f ms %s" % (ms_plan, ms_tuned, tuned))
 
     m_reach = stats["relaxed_edges"]
     gteps = m_reach / (ms_step * 1e-3) / 1e9
@@ -411,7 +416,7 @@ def main():
                  BYTES_PER_OPEN_VISIT * stats["open_visits"])
     solve_bytes = alg_bytes + BYTES_PER_PRED_EDGE * m_reach
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(args.workload) if g.n > 4096 else None
     log("step %.3f ms, round kernel %.3f ms (%d launches), %.2f GTEPS, %.1f GB/s algorithmic"
         % (ms_step, k_ms, launches, gteps, achieved))
 
@@ -437,8 +442,9 @@ def main():
         "config": {"workload": wname, "n": g.n, "m": g.m, "source": g.source,
                    "vertex_order": G.order,
                    "weights": wdesc, "m_reach": m_reach},
-        "plan_ms_per_step": round(ms_plan, 4),
-        "tuned_plan_ms_per_step": round(ms_tuned, 4), "launch_tuned": tuned,
+        "plan_ms_per_step": round(ms_plan, 4) if ms_plan is not None else None,
+        "tuned_plan_ms_per_step": round(ms_tuned, 4) if ms_tuned is not None else None,
+        "launch_tuned": tuned,
         "solve_gbps_algorithmic": round(solve_bytes / (ms_step * 1e-3) / 1e9, 1),
         "rounds": stats["rounds"],
         "dijkstra_settles": stats["settled"],
@@ -446,7 +452,9 @@ def main():
         "scanned_in_edges_per_edge": round(stats["scanned_in_edges"] / max(g.m, 1), 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic, "kernel": "rounds_kernel",
+                     "traffic": traffic,
+                     # graphs of at most 4096 vertices run in the one-workgroup solver
+                     "kernel": "small_rounds_kernel" if g.n <= 4096 else "rounds_kernel",
                      "kernel_ms": round(k_ms, 4), "algorithmic_bytes": alg_bytes,
                      "traffic_gbps": (round(traffic / (k_ms * 1e-3) / 1e9, 1)
                                       if traffic is not None else None)},
