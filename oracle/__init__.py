@@ -208,11 +208,19 @@ MODE_ADOPTED, MODE_SCOPE_ALL, MODE_LITERAL_FIG5 = 0, 1, 2
 MODE_LC = 4  # or-ed with MODE_ADOPTED / MODE_SCOPE_ALL: label-correcting relax
 
 
-def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=None):
+def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=None,
+              delta=None):
     """Run the round simulator.  Returns dict(cost, rounds, fixed_per_round,
     relaxed_edges, scanned_in_edges, settled, violations).  With a target
-    (modes 0 and 1) the rounds stop once the target is fixed."""
+    (modes 0 and 1) the rounds stop once the target is fixed.  delta (with
+    MODE_LC): an open vertex joins the relax set only while D < minD + delta
+    (None: no bound)."""
     k, w = _kind(w)
+    if delta is None:
+        dl = {"i32": ctypes.c_int32(2**31 - 1), "f32": ctypes.c_float(np.inf),
+              "f64": ctypes.c_double(np.inf)}[k]
+    else:
+        dl = {"i32": ctypes.c_int32, "f32": ctypes.c_float, "f64": ctypes.c_double}[k](delta)
     src, dst = _i32(src), _i32(dst)
     cost = np.empty(n, dtype=w.dtype)
     cap = 4 * n + 8
@@ -226,7 +234,7 @@ def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=
         tc = np.ascontiguousarray(true_cost, dtype=w.dtype)
     rc = _call("oracle_round_sim_" + k, ctypes.c_int32(n), ctypes.c_int64(len(src)), _p(src),
                _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int32(t), ctypes.c_int(mode),
-               _p(cost),
+               dl, _p(cost),
                ctypes.byref(rounds), _p(fpr), ctypes.c_int64(cap), _p(stats),
                _p(tc) if tc is not None else None, ctypes.byref(viol))
     if rc != 0:

@@ -21,31 +21,37 @@
 #define SFX i32
 #define INF_V INT32_MAX
 #define ADD(a, w) (((a) == INT32_MAX || (w) == INT32_MAX) ? INT32_MAX : (a) + (w))
+#define ADDSAT(a, w) (((int64_t)(a) + (int64_t)(w) >= INT32_MAX) ? INT32_MAX : (a) + (w))
 #include "oracle_typed.inc"
 #undef T
 #undef SFX
 #undef INF_V
 #undef ADD
+#undef ADDSAT
 
 #define T float
 #define SFX f32
 #define INF_V INFINITY
 #define ADD(a, w) ((float)((float)(a) + (float)(w)))
+#define ADDSAT(a, w) ADD(a, w)
 #include "oracle_typed.inc"
 #undef T
 #undef SFX
 #undef INF_V
 #undef ADD
+#undef ADDSAT
 
 #define T double
 #define SFX f64
 #define INF_V ((double)INFINITY)
 #define ADD(a, w) ((a) + (w))
+#define ADDSAT(a, w) ADD(a, w)
 #include "oracle_typed.inc"
 #undef T
 #undef SFX
 #undef INF_V
 #undef ADD
+#undef ADDSAT
 
 /* ------------------------------------------------------ stable CSR / CSC */
 /*

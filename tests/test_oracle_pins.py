@@ -531,6 +531,57 @@ def test_label_correcting_costs_and_invariants(dtype):
             assert r["relaxed_edges"] >= ls["relaxed_edges"]
 
 
+def test_delta_bucket_closed_forms():
+    """Delta-stepping with the method (Section I): an open vertex joins the
+    relax set only while D < minD + delta.  On the hand-worked graph above,
+    vertex 1 survives round 1 with D = 10 while minD = 1, so it is relaxed
+    early (five relaxed edges) iff 10 < 1 + delta, i.e. delta > 9; costs and
+    rounds do not change."""
+    src = np.array([0, 0, 2, 1], np.int32)
+    dst = np.array([1, 2, 1, 3], np.int32)
+    w = np.array([10, 1, 1, 1], np.int32)
+    for delta, relaxed in ((0, 4), (5, 4), (9, 4), (10, 5), (100, 5), (None, 5),
+                           (2**31 - 2, 5)):
+        r = oracle.round_sim(4, src, dst, w, 0, mode=oracle.MODE_LC, delta=delta)
+        assert r["cost"].tolist() == [0, 2, 1, 3], delta
+        assert r["rounds"] == 4 and r["relaxed_edges"] == relaxed, (delta, r)
+    # float32: the same boundary at delta = 9 (10 < 1 + delta)
+    wf = w.astype(np.float32)
+    for delta, relaxed in ((9.0, 4), (9.5, 5), (float("inf"), 5)):
+        r = oracle.round_sim(4, src, dst, wf, 0, mode=oracle.MODE_LC, delta=delta)
+        assert r["relaxed_edges"] == relaxed, (delta, r)
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_delta_bucket_limits_and_costs(dtype):
+    """delta = 0 is label-setting and an unbounded delta (INF, or an int32
+    delta whose sum with minD saturates) is full label-correcting, counter
+    for counter; every delta reaches Dijkstra's costs with the per-round
+    invariants intact."""
+    rng = np.random.default_rng(19)
+    big = 2**31 - 2 if dtype == np.int32 else np.float32(3e38)
+    for _ in range(200):
+        n, src, dst, w, s = tiny_graph(rng, dtype, n=int(rng.integers(1, 30)))
+        c, settles = oracle.dijkstra(n, src, dst, w, s)
+        for mode in (oracle.MODE_ADOPTED, oracle.MODE_SCOPE_ALL):
+            ls = oracle.round_sim(n, src, dst, w, s, mode=mode)
+            lc = oracle.round_sim(n, src, dst, w, s, mode=mode | oracle.MODE_LC)
+            z = oracle.round_sim(n, src, dst, w, s, mode=mode | oracle.MODE_LC, delta=0)
+            for k in ("rounds", "relaxed_edges", "scanned_in_edges", "settled"):
+                assert z[k] == ls[k], (k, z, ls)
+            if dtype == np.int32:
+                b = oracle.round_sim(n, src, dst, w, s, mode=mode | oracle.MODE_LC, delta=big)
+                for k in ("rounds", "relaxed_edges", "scanned_in_edges", "settled"):
+                    assert b[k] == lc[k], (k, b, lc)
+            for delta in (1, 3, 10) if dtype == np.int32 else (0.05, 0.2, 1.0):
+                r = oracle.round_sim(n, src, dst, w, s, mode=mode | oracle.MODE_LC, delta=delta,
+                                     true_cost=c)
+                assert np.array_equal(r["cost"], c)
+                assert r["violations"] == 0
+                assert 1 <= r["rounds"] <= settles and r["settled"] == settles
+                assert r["relaxed_edges"] >= ls["relaxed_edges"]
+
+
 def _heap_ops(o):
     return o["remove_min"] + o["insert"] + o["adjust"]
 
