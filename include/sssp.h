@@ -103,7 +103,12 @@ typedef enum { SSSP_SCOPE_AUTO = 0, SSSP_SCOPE_OPEN = 1, SSSP_SCOPE_ALL = 2 } ss
  *                          Fig. 6) explores every discovered vertex: also the
  *                          open vertices whose D fell since their last relax,
  *                          each from its D at the start of the step; a fixed
- *                          vertex already relaxed at its final D is skipped
+ *                          vertex already relaxed at its final D is skipped;
+ *                          with a finite `delta` (sssp_csr) an open vertex
+ *                          joins only while D < minD + delta, minD of the
+ *                          round that found it open: the first bucket of
+ *                          Delta-stepping (Section I), so delta = 0 is
+ *                          label-setting
  *   SSSP_RELAX_AUTO        the mode the graph's vertex order suggests (see
  *                          the definition in the library: SETTING for now
  *                          on every graph)
@@ -127,6 +132,10 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  *                 builder sets SSSP_SCOPE_AUTO; the caller may change it)
  *   relax         sssp_relax of the solves on this graph (likewise AUTO)
  *   deg_max       largest out-degree + in-degree (filled by the builder)
+ *   delta         bucket width of label-correcting relax as a key of the
+ *                 graph's dtype (the int32 value, or the float32 bit
+ *                 pattern); INF (0x7fffffff, or +inf's bits), the
+ *                 builder's value, is no bound; must lie in [0, INF]
  * The solver's working copy.  Always: in-lists ordered by weight, so that
  * the in-edges a lower-bound step needs (minD + w < D[y]) form a prefix:
  *   s_in_off[n+1], s_in_src[m] (solver ids), s_in_eid[m], s_in_w[m]
@@ -152,6 +161,7 @@ typedef struct {
   int32_t scope; /* sssp_scope of single solves */
   int32_t relax; /* sssp_relax of every solve on this graph */
   int32_t deg_max; /* largest total degree */
+  int32_t delta;   /* label-correcting bucket width (key); INF: none */
   const int32_t *out_off;
   const int32_t *out_dst;
   const void *out_w;

@@ -36,6 +36,7 @@ class Csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("scope", ctypes.c_int32),
                 ("relax", ctypes.c_int32), ("deg_max", ctypes.c_int32),
+                ("delta", ctypes.c_int32),
                 ("out_off", ctypes.c_void_p), ("out_dst", ctypes.c_void_p),
                 ("out_w", ctypes.c_void_p), ("in_off", ctypes.c_void_p),
                 ("in_src", ctypes.c_void_p), ("in_eid", ctypes.c_void_p),

@@ -173,7 +173,8 @@ sssp_status resolve_launch(DevWS &w, bool f32, bool batch, const sssp_launch *L,
 bool csr_ok(const sssp_csr *g) {
   if (!(g && g->n > 0 && g->m >= 0 && (g->dtype == SSSP_I32 || g->dtype == SSSP_F32) &&
         g->scope >= SSSP_SCOPE_AUTO && g->scope <= SSSP_SCOPE_ALL &&
-        g->relax >= SSSP_RELAX_AUTO && g->relax <= SSSP_RELAX_CORRECTING &&
+        g->relax >= SSSP_RELAX_AUTO && g->relax <= SSSP_RELAX_CORRECTING && g->delta >= 0 &&
+        g->delta <= (g->dtype == SSSP_F32 ? 0x7f800000 : 0x7fffffff) &&
         g->out_off && g->in_off && g->out_wmin && g->s_out_off && g->s_in_off &&
         g->s_out_wmin && g->s_vrec &&
         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
@@ -223,6 +224,7 @@ GraphDev graph_dev(const sssp_csr *g) {
   d.n = g->n;
   d.m = g->m;
   d.lc = relax_correcting(g) ? 1 : 0;
+  d.delta = g->delta;
   d.all = scope_all_of(g) ? 1 : 0;
   return d;
 }
@@ -530,6 +532,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->scope = SSSP_SCOPE_AUTO;
   out->relax = SSSP_RELAX_AUTO;
   out->deg_max = 0;
+  out->delta = dtype == SSSP_F32 ? 0x7f800000 : 0x7fffffff;  // no bucket bound
   out->out_off = out_off;
   out->out_dst = out_dst;
   out->out_w = out_w;

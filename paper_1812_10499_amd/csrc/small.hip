@@ -215,7 +215,8 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
             ++nfix;
             if (y == tgt) s.target_hit = 1;
           }
-          if (relax_again && (fix || lc)) {
+          // an open vertex only while in the first bucket above minD
+          if (relax_again && (fix || (lc && dy < V::add(md, G.delta)))) {
             const int q = atomicAdd(&s.nF2, 1);
             s.F[q] = y;
             s.FD[q] = dy;

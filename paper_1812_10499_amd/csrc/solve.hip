@@ -1181,8 +1181,9 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
               const int32_t tn = V::add(Dy, S.owm[tid]);
               sv = Dy;
               st = tn;
-              if (Dy < dr && G.lc) {
-                // label-correcting: relaxed again from its lower D
+              if (G.lc && Dy < dr && Dy < V::add(md, G.delta)) {
+                // label-correcting: relaxed again from its lower D (while in
+                // the first bucket above minD)
                 hf = true;
                 fd = S.odeg[tid];
                 fx[FX_OOFF] = S.ooff[tid];

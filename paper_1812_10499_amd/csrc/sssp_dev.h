@@ -56,8 +56,9 @@ struct GraphDev {
   const int32_t *u_out_off, *u_out_dst;
   const int32_t *u_in_off, *u_in_src, *u_in_eid, *u_in_w;
   int32_t n, m;
-  int32_t lc;   // label-correcting relax on this graph
-  int32_t all;  // C scope ALL on this graph
+  int32_t lc;     // label-correcting relax on this graph
+  int32_t all;    // C scope ALL on this graph
+  int32_t delta;  // label-correcting: open vertices join the relax set while D < minD + delta
 };
 
 // Instance i of a batch: graph index, source vertex (graph-local), base of

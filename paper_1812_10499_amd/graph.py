@@ -43,12 +43,13 @@ class Graph:
     picks the vertex numbering of the solver's working copy ("auto",
     "input" or "degree"); ``scope`` the C scope of single solves ("auto",
     "open" or "all"; see :attr:`scope`), ``relax`` the relax step ("auto",
-    "setting" or "correcting"; see :attr:`relax`).  Results never depend on
-    any of them.
+    "setting" or "correcting"; see :attr:`relax`), ``delta`` the bucket
+    width of label-correcting relax (see :attr:`delta`).  Results never
+    depend on any of them.
     """
 
     def __init__(self, n: int, src, dst, w, device="cuda", order: str = "auto",
-                 scope: str = "auto", relax: str = "auto"):
+                 scope: str = "auto", relax: str = "auto", delta=None):
         device = torch.device(device)
         if isinstance(w, torch.Tensor):
             wt = w.to(device).contiguous()
@@ -80,6 +81,7 @@ class Graph:
         self.perm = self.perm[:m]
         self.scope = scope
         self.relax = relax
+        self.delta = delta
 
     @property
     def scope(self) -> str:
@@ -116,6 +118,31 @@ class Graph:
     def effective_relax(self) -> str:
         """The relax step solves run: "auto" is "setting"."""
         return "correcting" if self.csr.relax == SSSP_RELAX_CORRECTING else "setting"
+
+    @property
+    def delta(self):
+        """Bucket width of label-correcting relax (an open vertex joins the
+        relax set only while D < minD + delta), or None for no bound."""
+        if self.dtype == SSSP_F32:
+            v = float(np.array([self.csr.delta], np.int32).view(np.float32)[0])
+            return None if v == float("inf") else v
+        return None if self.csr.delta == I32_INF else int(self.csr.delta)
+
+    @delta.setter
+    def delta(self, value):
+        if value is None:
+            self.csr.delta = 0x7f800000 if self.dtype == SSSP_F32 else I32_INF
+            return
+        if self.dtype == SSSP_F32:
+            v = np.float32(value)
+            if not (v >= 0):
+                raise ValueError("delta must be >= 0")
+            self.csr.delta = int(np.array([v], np.float32).view(np.int32)[0])
+        else:
+            v = int(value)
+            if v < 0:
+                raise ValueError("delta must be >= 0")
+            self.csr.delta = min(v, I32_INF)
 
     @property
     def order(self) -> str:

@@ -17,13 +17,14 @@ def oracle_mode(scope, relax="setting"):
     return mode | (oracle.MODE_LC if relax == "correcting" else 0)
 
 
-def oracle_solution(n, src, dst, w, source, scope="open", relax="setting"):
+def oracle_solution(n, src, dst, w, source, scope="open", relax="setting", delta=None):
     """(cost, pred (int64), settles, rounds, fixed_per_round, stats) from the
-    oracle, the round counts under the given C scope and relax step."""
+    oracle, the round counts under the given C scope, relax step and
+    label-correcting bucket width."""
     cost, settles = oracle.dijkstra(n, src, dst, w, source)
     O = oracle.csr(n, src, dst)
     pred, _ = oracle.pred(O, w, source, cost)
-    sim = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(scope, relax))
+    sim = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(scope, relax), delta=delta)
     assert np.array_equal(sim["cost"], cost)
     return dict(cost=cost, pred=pred, settles=settles, rounds=sim["rounds"],
                 relaxed=sim["relaxed_edges"], scanned=sim["scanned_in_edges"], csr=O)

@@ -108,6 +108,13 @@ def test_host_argument_errors(sp):
     bad = _fake_csr(sp)
     bad.scope = 3  # not an sssp_scope
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    # the bucket width is a key in [0, INF]: negative, or a float32 NaN
+    bad = _fake_csr(sp)
+    bad.delta = -1
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    bad = _fake_csr(sp, dtype=1)
+    bad.delta = 0x7fc00000
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
     # single-target solve: the target must be a vertex
     assert _status(lambda: sp.sssp_solve_target(c, 0, -1, 0x1000, None, None)) == S
     assert _status(lambda: sp.sssp_solve_target(c, 0, 10, 0x1000, None, None)) == S
