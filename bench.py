@@ -408,7 +408,11 @@ def main():
                                       reps=max(1, min(10, int(200.0 / max(ms_plan, 1e-3)))))
         log("plan %.3f ms, tuned plan %.3f ms %s" % (ms_plan, ms_tuned, tuned))
 
-    m_reach = stats["relaxed_edges"]
+    # edges whose tail is reachable (label-correcting relax may relax some twice)
+    import numpy as np
+    reach = cost.cpu().numpy() != (np.inf if G.value_dtype == torch.float32 else 2**31 - 1)
+    odeg = np.diff(G.arrays()["out_off"].cpu().numpy())
+    m_reach = int(odeg[reach].sum())
     gteps = m_reach / (ms_step * 1e-3) / 1e9
     alg_bytes = (BYTES_PER_RELAXED_EDGE * stats["relaxed_edges"] +
                  BYTES_PER_SETTLED * stats["settled"] +
@@ -446,6 +450,8 @@ def main():
         "tuned_plan_ms_per_step": round(ms_tuned, 4) if ms_tuned is not None else None,
         "launch_tuned": tuned,
         "solve_gbps_algorithmic": round(solve_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "relax": G.effective_relax, "delta": G.effective_delta,
+        "relaxed_edges": stats["relaxed_edges"],
         "rounds": stats["rounds"],
         "dijkstra_settles": stats["settled"],
         "settles_per_round": round(stats["settled"] / max(stats["rounds"], 1), 1),

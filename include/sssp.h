@@ -109,9 +109,11 @@ typedef enum { SSSP_SCOPE_AUTO = 0, SSSP_SCOPE_OPEN = 1, SSSP_SCOPE_ALL = 2 } ss
  *                          round that found it open: the first bucket of
  *                          Delta-stepping (Section I), so delta = 0 is
  *                          label-setting
- *   SSSP_RELAX_AUTO        the mode the graph's vertex order suggests (see
- *                          the definition in the library: SETTING for now
- *                          on every graph)
+ *   SSSP_RELAX_AUTO        CORRECTING with delta = 0.4 w_max on graphs of
+ *                          low degree spread (deg_max * n < 3m) and wide
+ *                          weight spread (w_max >= 16 w_min), where the
+ *                          threshold rule fixes few vertices per round;
+ *                          SETTING otherwise
  * Honoured per graph by single and batched solves.
  */
 typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTING = 2 } sssp_relax;
@@ -128,6 +130,7 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  *                 outWeight array of SP_3 and SP_4, Figs. 5 and 6)
  *   w_max         largest weight (filled by the builder; used for the
  *                 int32 overflow precondition)
+ *   w_min         smallest weight (filled by the builder; 0 with no edges)
  *   scope         sssp_scope of the single solves on this graph (the
  *                 builder sets SSSP_SCOPE_AUTO; the caller may change it)
  *   relax         sssp_relax of the solves on this graph (likewise AUTO)
@@ -171,6 +174,7 @@ typedef struct {
   const void *in_w;
   const void *out_wmin;
   double w_max;
+  double w_min;
   const int32_t *vid;
   const int32_t *rank;
   const int32_t *s_out_off;

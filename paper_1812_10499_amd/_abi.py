@@ -41,7 +41,7 @@ class Csr(ctypes.Structure):
                 ("out_w", ctypes.c_void_p), ("in_off", ctypes.c_void_p),
                 ("in_src", ctypes.c_void_p), ("in_eid", ctypes.c_void_p),
                 ("in_w", ctypes.c_void_p), ("out_wmin", ctypes.c_void_p),
-                ("w_max", ctypes.c_double),
+                ("w_max", ctypes.c_double), ("w_min", ctypes.c_double),
                 ("vid", ctypes.c_void_p), ("rank", ctypes.c_void_p),
                 ("s_out_off", ctypes.c_void_p), ("s_out_dst", ctypes.c_void_p),
                 ("s_out_w", ctypes.c_void_p), ("s_out_eid", ctypes.c_void_p),

@@ -192,8 +192,43 @@ bool scope_all_of(const sssp_csr *g) {
   return g->scope == SSSP_SCOPE_ALL;
 }
 
-// The relax step a graph's solves use (SSSP_RELAX_AUTO: label-setting).
-bool relax_correcting(const sssp_csr *g) { return g->relax == SSSP_RELAX_CORRECTING; }
+// SSSP_RELAX_AUTO: label-correcting relax in buckets of 0.4 w_max on graphs
+// of low degree spread (largest total degree below 3m/n: the AUTO scope's
+// OPEN case) whose weights spread widely (w_max >= 16 w_min), label-setting
+// otherwise.  Measured on grids: weights in [1, 1000] (the threshold rule
+// fixes few vertices per round there) take 26 % fewer rounds and 21 % less
+// time at 0.1 % more relaxed edges; weights in [0.5, 1.5] gain nothing.
+bool auto_correcting(const sssp_csr *g) {
+  return g->m > 0 && (int64_t)g->deg_max * g->n < 3 * (int64_t)g->m &&
+         g->w_max >= 16.0 * g->w_min;
+}
+
+// The relax step a graph's solves use.
+bool relax_correcting(const sssp_csr *g) {
+  if (g->relax == SSSP_RELAX_AUTO) return auto_correcting(g);
+  return g->relax == SSSP_RELAX_CORRECTING;
+}
+
+// The bucket width (a key) of a graph's label-correcting relax.
+int32_t relax_delta(const sssp_csr *g) {
+  if (g->relax != SSSP_RELAX_AUTO) return g->delta;
+  if (g->dtype == SSSP_F32) {
+    const float d = (float)(0.4 * g->w_max);
+    int32_t k;
+    memcpy(&k, &d, sizeof(k));
+    return k;
+  }
+  const int32_t d = (int32_t)(0.4 * g->w_max);
+  return d > 1 ? d : 1;
+}
+
+// A weight key as the value it encodes.
+double key_value(int32_t key, bool f32) {
+  if (!f32) return (double)key;
+  float f;
+  memcpy(&f, &key, sizeof(f));
+  return (double)f;
+}
 
 bool overflow_risk(const sssp_csr *g) {
   if (g->dtype != SSSP_I32) return false;
@@ -224,7 +259,7 @@ GraphDev graph_dev(const sssp_csr *g) {
   d.n = g->n;
   d.m = g->m;
   d.lc = relax_correcting(g) ? 1 : 0;
-  d.delta = g->delta;
+  d.delta = relax_delta(g);
   d.all = scope_all_of(g) ? 1 : 0;
   return d;
 }
@@ -541,13 +576,8 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->in_eid = in_eid;
   out->in_w = in_w;
   out->out_wmin = out_wmin;
-  if (f32) {
-    float f;
-    memcpy(&f, &wkey_max, sizeof(f));
-    out->w_max = (double)f;
-  } else {
-    out->w_max = (double)wkey_max;
-  }
+  out->w_max = key_value(wkey_max, f32);
+  out->w_min = m > 0 ? key_value(0x7fffffff - hs[3], f32) : 0.0;
   if (overflow_risk(out)) return SSSP_ERR_OVERFLOW;
   HIPCHK(launch_build(n, m, f32, src, dst, (const int32_t *)w, out_off, out_dst, out_w, in_off,
                       in_src, in_eid, in_w, out_wmin, perm, t, stream));
@@ -626,14 +656,8 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
     HIPCHK(hipEventRecord(ws.last, stream));
     return SSSP_ERR_WEIGHT;
   }
-  double w_max;
-  if (f32) {
-    float f;
-    memcpy(&f, &hs[1], sizeof(f));
-    w_max = (double)f;
-  } else {
-    w_max = (double)hs[1];
-  }
+  const double w_max = key_value(hs[1], f32);
+  const double w_min = g->m > 0 ? key_value(0x7fffffff - hs[3], f32) : 0.0;
   if (g->dtype == SSSP_I32 && (double)(g->n - 1) * w_max >= (double)INT_MAX) {
     HIPCHK(hipEventRecord(ws.last, stream));
     return SSSP_ERR_OVERFLOW;
@@ -648,6 +672,7 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));
   g->w_max = w_max;
+  g->w_min = w_min;
   return SSSP_OK;
 }
 

@@ -39,9 +39,11 @@ size_t build_hist_entries(int32_t m) {
 }
 
 // -------------------------------------------------------------- validate
+// status: [0] error flags, [1] largest weight key, [3] INT32_MAX minus the
+// smallest weight key (a maximum, so the zeroed word is its identity)
 __global__ void validate_kernel(int32_t n, int32_t m, int f32, const int32_t *src,
                                 const int32_t *dst, const int32_t *w, int32_t *status) {
-  int32_t bad = 0, wmax = 0;
+  int32_t bad = 0, wmax = 0, wmin_c = 0;
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
     const int32_t k = w[i];
     if (src) {
@@ -50,10 +52,14 @@ __global__ void validate_kernel(int32_t n, int32_t m, int f32, const int32_t *sr
     }
     // int32: w >= 1.  float32 key: w > 0 and finite  <=>  0 < bits < 0x7f800000
     if (f32 ? (k <= 0 || k >= 0x7f800000) : (k < 1)) bad |= BAD_WEIGHT;
-    else wmax = kmax(wmax, k);
+    else {
+      wmax = kmax(wmax, k);
+      wmin_c = kmax(wmin_c, 0x7fffffff - k);
+    }
   }
   if (bad) atomicOr(&status[0], bad);
   if (wmax) atomicMax(&status[1], wmax);
+  if (wmin_c) atomicMax(&status[3], wmin_c);
 }
 
 hipError_t launch_validate(int32_t n, int32_t m, bool f32, const int32_t *src,

@@ -114,10 +114,29 @@ class Graph:
             raise ValueError("relax must be one of %s" % sorted(RELAXES))
         self.csr.relax = RELAXES[value]
 
+    def _auto_correcting(self) -> bool:
+        c = self.csr
+        return c.m > 0 and c.deg_max * c.n < 3 * c.m and c.w_max >= 16.0 * c.w_min
+
     @property
     def effective_relax(self) -> str:
-        """The relax step solves run: "auto" is "setting"."""
+        """The relax step solves run: "auto" is "correcting" on graphs of low
+        degree spread (deg_max * n < 3m) and wide weight spread (w_max >= 16
+        w_min), else "setting"."""
+        if self.csr.relax == SSSP_RELAX_AUTO:
+            return "correcting" if self._auto_correcting() else "setting"
         return "correcting" if self.csr.relax == SSSP_RELAX_CORRECTING else "setting"
+
+    @property
+    def effective_delta(self):
+        """The bucket width label-correcting solves use (None: no bound, or
+        label-setting): under "auto", 0.4 w_max (int32: truncated, at least 1)."""
+        if self.effective_relax != "correcting":
+            return None
+        if self.csr.relax == SSSP_RELAX_AUTO:
+            d = 0.4 * self.csr.w_max
+            return float(np.float32(d)) if self.dtype == SSSP_F32 else max(1, int(d))
+        return self.delta
 
     @property
     def delta(self):

@@ -36,7 +36,7 @@ def check_batch(sp, graphs, glist, inst_graph, inst_source, label):
         g = glist[gi]
         # each instance runs its graph's C scope and relax step
         ref = oracle_solution(g.n, g.src, g.dst, g.w, s, graphs[gi].effective_scope,
-                              graphs[gi].effective_relax)
+                              graphs[gi].effective_relax, graphs[gi].effective_delta)
         sl = slice(bases[i], bases[i] + g.n)
         assert np.array_equal(c[sl], ref["cost"]), (label, i)
         assert np.array_equal(p[sl], ref["pred"]), (label, i)
@@ -146,7 +146,7 @@ def test_batch_more_instances_than_lds_slots(sp):
             g = glist[gi]
             refs[(gi, s)] = oracle_solution(g.n, g.src, g.dst, g.w, s,
                                             graphs[gi].effective_scope,
-                                            graphs[gi].effective_relax)
+                                            graphs[gi].effective_relax, graphs[gi].effective_delta)
         ref = refs[(gi, s)]
         sl = slice(bases[i], bases[i] + glist[gi].n)
         assert np.array_equal(c[sl], ref["cost"]), i

@@ -41,7 +41,7 @@ def case(sp):
             g = glist[gi]
             refs[(gi, s)] = oracle_solution(g.n, g.src, g.dst, g.w, s,
                                             graphs[gi].effective_scope,
-                                            graphs[gi].effective_relax)
+                                            graphs[gi].effective_relax, graphs[gi].effective_delta)
     return dict(glist=glist, graphs=graphs, inst_graph=inst_graph, inst_source=inst_source,
                 refs=refs)
 
@@ -175,7 +175,7 @@ def test_plan_sees_new_weights(sp):
             sync()
             for i, s in enumerate((0, g.n - 1)):
                 ref = oracle_solution(g.n, g.src, g.dst, ww, s, G.effective_scope,
-                                      G.effective_relax)
+                                      G.effective_relax, G.effective_delta)
                 sl = slice(i * g.n, (i + 1) * g.n)
                 assert np.array_equal(to_np(cost)[sl], ref["cost"]), (k, i)
                 assert np.array_equal(to_np(pred)[sl].astype(np.int64), ref["pred"]), (k, i)

@@ -34,7 +34,8 @@ def both_paths(sp, n, src, dst, w, source, label, order="auto", scope="auto", re
     print("case", label, "n=%d m=%d order=%s scope=%s relax=%s target=%s" % (
         n, len(src), order, scope, relax, target), flush=True)
     G = sp.Graph(n, src, dst, w, order=order, scope=scope, relax=relax)
-    ref = oracle_solution(n, src, dst, w, source, G.effective_scope, G.effective_relax)
+    ref = oracle_solution(n, src, dst, w, source, G.effective_scope, G.effective_relax,
+                          G.effective_delta)
     out = {}
     for name, launch in PATHS.items():
         sp.set_launch(launch)
@@ -155,7 +156,7 @@ def test_sequence_plan_of_small_graphs(sp):
             for i, (gi, s) in enumerate(zip(inst_graph, inst_source)):
                 n, src, dst, w = glist[gi]
                 ref = oracle_solution(n, src, dst, w, s, graphs[gi].effective_scope,
-                                      graphs[gi].effective_relax)
+                                      graphs[gi].effective_relax, graphs[gi].effective_delta)
                 sl = slice(bases[i], bases[i] + n)
                 assert_same_solution(cost[sl], pred[sl], stats[i], ref, "plan-%d-%d" % (rep, i))
     finally:

@@ -55,7 +55,8 @@ def run_case(sp, n, src, dst, w, source, label, order="auto", scope="auto", rela
     G = check_build(sp, n, src, dst, w, order, scope, relax)
     cost, pred, st = sp.solve(G, source, with_pred=True, with_stats=True)
     sync()
-    ref = oracle_solution(n, src, dst, w, source, G.effective_scope, G.effective_relax)
+    ref = oracle_solution(n, src, dst, w, source, G.effective_scope, G.effective_relax,
+                          G.effective_delta)
     assert_same_solution(cost, pred, st, ref, label)
     # a second solve on the same graph reuses the workspace
     cost2, pred2, _ = sp.solve(G, source, with_pred=True)
@@ -229,7 +230,7 @@ def test_set_weights_then_solve(sp, order):
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
     ref = oracle_solution(g.n, g.src, g.dst, w2, g.source, G.effective_scope,
-                          G.effective_relax)
+                          G.effective_relax, G.effective_delta)
     assert_same_solution(cost, pred, st, ref, "rmat12-reweighted-" + order)
     # invalid weights are refused before anything is written
     bad = torch.from_numpy(w2[to_np(G.perm)]).cuda()
@@ -275,6 +276,6 @@ def test_workload_rmat22_full(sp):
     cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
     sync()
     ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source, G.effective_scope,
-                          G.effective_relax)
+                          G.effective_relax, G.effective_delta)
     assert_same_solution(cost, pred, st, ref, "rmat22")
     print("rmat22 rounds", st, flush=True)

@@ -30,7 +30,8 @@ def check_target(sp, G, n, src, dst, w, source, target, label):
     cost, st = sp.solve_target(G, source, target, with_stats=True)
     sync()
     mode = oracle_mode(G.effective_scope, G.effective_relax)
-    ref = oracle.round_sim(n, src, dst, w, source, mode=mode, target=target)
+    ref = oracle.round_sim(n, src, dst, w, source, mode=mode, target=target,
+                           delta=G.effective_delta)
     full, _ = oracle.dijkstra(n, src, dst, w, source)
     c = to_np(cost)
     bad = np.nonzero(c != ref["cost"])[0]
