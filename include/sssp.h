@@ -324,13 +324,19 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
  *   small_n:     a single solve (sssp_solve, sssp_solve_target, the
  *                sequence plan) of a graph with at most this many vertices
  *                runs all its rounds in one workgroup with the per-vertex
- *                state in LDS (default and maximum 4096; negative: never).
+ *                state in LDS (default and maximum 4096; negative: never);
+ *   wg:          solves whose graphs all run C scope OPEN run each instance
+ *                in a workgroup of its own, with block barriers only (up to
+ *                `blocks` workgroups at a time): 0 (default) when every
+ *                graph has low degree spread (deg_max * n < 3m: many small
+ *                rounds), 1 always, negative never.
  */
 typedef struct {
   int32_t blocks;
   int32_t solo_edges;
   int32_t block_units;
   int32_t small_n;
+  int32_t wg;
 } sssp_launch;
 
 /*
@@ -383,8 +389,8 @@ sssp_status sssp_plan_destroy(sssp_plan plan);
  * its replays (HIP events on `stream`, `reps` timed runs after one warm-up,
  * mean taken) under candidate geometries, one field at a time (blocks:
  * maximum, 1/2, 1/4; solo_edges: 2048, 8192, 32768; block_units: 2048,
- * 4096, 8192; small_n: the default, never), keeping a candidate only when
- * it beats the best so far.
+ * 4096, 8192; small_n: the default, never; wg: the default, never,
+ * always), keeping a candidate only when it beats the best so far.
  * *best receives the fastest geometry, *best_ms its mean run time.  Writes
  * cost and pred like a run; synchronizes.  Arguments as for
  * sssp_plan_create; reps in [1, 100].

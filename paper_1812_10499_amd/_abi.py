@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
 class Launch(ctypes.Structure):
     """Launch geometry of the round kernel (0 in a field: the default)."""
     _fields_ = [("blocks", ctypes.c_int32), ("solo_edges", ctypes.c_int32),
-                ("block_units", ctypes.c_int32), ("small_n", ctypes.c_int32)]
+                ("block_units", ctypes.c_int32), ("small_n", ctypes.c_int32),
+                ("wg", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

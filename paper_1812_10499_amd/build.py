@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SO = os.path.join(PKG, "libsssp.so")
-SOURCES = ["api.hip", "solve.hip", "small.hip", "pred.hip", "build_csr.hip", "backward.hip"]
+SOURCES = ["api.hip", "solve.hip", "small.hip", "wg.hip", "pred.hip", "build_csr.hip",
+           "backward.hip"]
 HEADERS = ["sssp_dev.h", "sssp_kernels.h"]
 
 HIPCC_FLAGS = [

@@ -38,7 +38,7 @@ struct DevWS {
   size_t pinned_cap = 0;
   hipEvent_t last = nullptr;  // completion of the previous call's work
   hipEvent_t staged = nullptr;
-  sssp_launch cfg = {0, 0, 0, 0};  // default geometry of direct solves (sssp_set_launch)
+  sssp_launch cfg = {0, 0, 0, 0, 0};  // default geometry of direct solves (sssp_set_launch)
 };
 
 std::mutex g_mu;
@@ -150,8 +150,11 @@ sssp_status geometry(DevWS &w, bool f32, bool batch, LaunchGeom *geo) {
 // The round kernel's geometry under `L` (null or zero fields: defaults;
 // the environment variables SSSP_SOLO_EDGES and SSSP_BLOCK_UNITS override
 // the defaults for measurement).
+// low_spread: every graph of the launch has low degree spread (the default
+// condition of the one-workgroup-per-instance path, which also needs C
+// scope OPEN: checked per launch).
 sssp_status resolve_launch(DevWS &w, bool f32, bool batch, const sssp_launch *L,
-                           LaunchGeom *geo, RoundArgs &a) {
+                           LaunchGeom *geo, RoundArgs &a, bool low_spread = false) {
   sssp_status s;
   if ((s = geometry(w, f32, batch, geo))) return s;
   if (L && L->blocks) {
@@ -167,6 +170,8 @@ sssp_status resolve_launch(DevWS &w, bool f32, bool batch, const sssp_launch *L,
   }
   geo->small_n = kSmallN;
   if (L && L->small_n) geo->small_n = L->small_n < 0 ? 0 : (L->small_n < kSmallN ? L->small_n : kSmallN);
+  const int wg = L ? L->wg : 0;
+  geo->wg = wg > 0 || (wg == 0 && low_spread) ? 1 : 0;
   return SSSP_OK;
 }
 
@@ -186,9 +191,14 @@ bool csr_ok(const sssp_csr *g) {
 
 // The C scope a graph's solves use (SSSP_SCOPE_AUTO: ALL when the largest
 // total degree is at least 3m/n).
+// Low degree spread: the largest total degree below 3m/n (meshes, grids:
+// many small rounds).
+bool low_spread(const sssp_csr *g) {
+  return g->m > 0 && (int64_t)g->deg_max * g->n < 3 * (int64_t)g->m;
+}
+
 bool scope_all_of(const sssp_csr *g) {
-  if (g->scope == SSSP_SCOPE_AUTO)
-    return g->m > 0 && (int64_t)g->deg_max * g->n >= 3 * (int64_t)g->m;
+  if (g->scope == SSSP_SCOPE_AUTO) return g->m > 0 && !low_spread(g);
   return g->scope == SSSP_SCOPE_ALL;
 }
 
@@ -198,10 +208,7 @@ bool scope_all_of(const sssp_csr *g) {
 // otherwise.  Measured on grids: weights in [1, 1000] (the threshold rule
 // fixes few vertices per round there) take 26 % fewer rounds and 21 % less
 // time at 0.1 % more relaxed edges; weights in [0.5, 1.5] gain nothing.
-bool auto_correcting(const sssp_csr *g) {
-  return g->m > 0 && (int64_t)g->deg_max * g->n < 3 * (int64_t)g->m &&
-         g->w_max >= 16.0 * g->w_min;
-}
+bool auto_correcting(const sssp_csr *g) { return low_spread(g) && g->w_max >= 16.0 * g->w_min; }
 
 // The relax step a graph's solves use.
 bool relax_correcting(const sssp_csr *g) {
@@ -720,7 +727,7 @@ static sssp_status solve_one(const sssp_csr *g, int32_t source, int32_t target, 
   RoundArgs a;
   if ((s = single_args(ws, g, source, target, cost, a))) return s;
   LaunchGeom geo;
-  if ((s = resolve_launch(ws, f32, false, &ws.cfg, &geo, a))) return s;
+  if ((s = resolve_launch(ws, f32, false, &ws.cfg, &geo, a, low_spread(g)))) return s;
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
   KernelTimer tm;
   const KernelTimer *timer = prof_timer(&tm);
@@ -769,6 +776,13 @@ static sssp_status check_batch(const sssp_csr *graphs, int32_t num_graphs,
   }
   if (*total >= (int64_t)INT_MAX) return SSSP_ERR_ARG;
   return SSSP_OK;
+}
+
+// Whether every graph a batch's instances use has low degree spread.
+static bool all_low_spread(const sssp_csr *graphs, const int32_t *inst_graph, int32_t num_inst) {
+  for (int32_t i = 0; i < num_inst; ++i)
+    if (!low_spread(&graphs[inst_graph[i]])) return false;
+  return true;
 }
 
 // The host copies of a batch's graph and instance tables.
@@ -890,7 +904,9 @@ sssp_status sssp_solve_batch(const sssp_csr *graphs, int32_t num_graphs,
   InstDev *hi = (InstDev *)(hg + num_graphs);
   fill_tables(graphs, num_graphs, inst_graph, inst_source, num_inst, hg, hi);
   LaunchGeom geo;
-  if ((s = resolve_launch(ws, f32, true, &ws.cfg, &geo, a))) return s;
+  if ((s = resolve_launch(ws, f32, true, &ws.cfg, &geo, a,
+                          all_low_spread(graphs, inst_graph, num_inst))))
+    return s;
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
   HIPCHK(hipMemcpyAsync((void *)a.graphs, hg, sizeof(GraphDev) * num_graphs,
                         hipMemcpyHostToDevice, stream));
@@ -915,7 +931,7 @@ sssp_status sssp_set_launch(const sssp_launch *launch) {
   sssp_status s;
   if ((s = ws_for_current(&wp))) return s;
   if (!launch) {
-    wp->cfg = sssp_launch{0, 0, 0, 0};
+    wp->cfg = sssp_launch{0, 0, 0, 0, 0};
     return SSSP_OK;
   }
   // the grid must fit both kernel variants of both dtypes
@@ -943,6 +959,8 @@ struct sssp_plan_s {
   std::vector<RoundArgs> seq;   // sequence kind: one per instance
   std::vector<int32_t> seq_n;   // sequence kind: instance sizes
   std::vector<int32_t *> seq_pred;
+  std::vector<char> seq_low;    // sequence kind: the instance's graph has low degree spread
+  bool low_spread = false;      // batch kind: every graph has
   int32_t max_n = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -974,7 +992,7 @@ static sssp_status plan_record(sssp_plan_s *p, const sssp_launch *L) {
   sssp_status s;
   RoundArgs probe;
   memset(&probe, 0, sizeof(probe));
-  if ((s = resolve_launch(p->ws, p->f32, batch, L, &geo, probe))) return s;
+  if ((s = resolve_launch(p->ws, p->f32, batch, L, &geo, probe, p->low_spread))) return s;
   HIPCHK(hipGraphCreate(&p->graph, 0));
   Launcher rec;
   rec.graph = p->graph;
@@ -984,10 +1002,13 @@ static sssp_status plan_record(sssp_plan_s *p, const sssp_launch *L) {
     HIPCHK(launch_solve(p->f32, true, p->a, p->batch_pred, geo, p->a.istat, p->max_n, nullptr,
                         rec));
   } else {
+    const int wg = L ? L->wg : 0;
     for (size_t i = 0; i < p->seq.size(); ++i) {
       p->seq[i].solo_edges = probe.solo_edges;
       p->seq[i].block_units = probe.block_units;
-      HIPCHK(launch_solve(p->f32, false, p->seq[i], p->seq_pred[i], geo, nullptr, p->seq_n[i],
+      LaunchGeom gi = geo;
+      gi.wg = wg > 0 || (wg == 0 && p->seq_low[i]) ? 1 : 0;
+      HIPCHK(launch_solve(p->f32, false, p->seq[i], p->seq_pred[i], gi, nullptr, p->seq_n[i],
                           nullptr, rec));
     }
   }
@@ -1026,6 +1047,7 @@ static sssp_status plan_build(const sssp_csr *graphs, int32_t num_graphs,
     HIPCHK(hipMemcpy((void *)p->a.insts, hi.data(), sizeof(InstDev) * num_inst,
                      hipMemcpyHostToDevice));
     p->batch_pred = pred;
+    p->low_spread = all_low_spread(graphs, inst_graph, num_inst);
   } else {
     // one set of state buffers for the largest instance, reused solve
     // after solve, and one control block per instance for its counters
@@ -1054,6 +1076,7 @@ static sssp_status plan_build(const sssp_csr *graphs, int32_t num_graphs,
       p->seq.push_back(a);
       p->seq_n.push_back(g->n);
       p->seq_pred.push_back(pred ? pred + hi[i].sbase : nullptr);
+      p->seq_low.push_back(low_spread(g) ? 1 : 0);
     }
   }
   return plan_record(p, launch);
@@ -1172,23 +1195,25 @@ sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int3
     sssp_status st;
     if ((st = resolve_launch(p->ws, p->f32, kind == SSSP_PLAN_BATCH, nullptr, &full, probe)))
       return st;
-    sssp_launch cur = {full.blocks, probe.solo_edges, probe.block_units, full.small_n};
+    sssp_launch cur = {full.blocks, probe.solo_edges, probe.block_units, full.small_n, 0};
     double cur_ms;
     if ((st = time_of(cur, &cur_ms))) return st;
     const int32_t blocks[3] = {full.blocks, full.blocks / 2, full.blocks / 4};
     const int32_t solo[3] = {2048, 8192, 32768};
     const int32_t units[3] = {2048, 4096, 8192};
     const int32_t small[3] = {full.small_n, -1, full.small_n};
-    for (int field = 0; field < 4; ++field) {
+    const int32_t wgs[3] = {0, -1, 1};
+    for (int field = 0; field < 5; ++field) {
       for (int c = 0; c < 3; ++c) {
         sssp_launch cand = cur;
         if (field == 0) cand.blocks = blocks[c];
         if (field == 1) cand.solo_edges = solo[c];
         if (field == 2) cand.block_units = units[c];
         if (field == 3) cand.small_n = small[c];
+        if (field == 4) cand.wg = wgs[c];
         if (cand.blocks < 1 || (cand.blocks == cur.blocks && cand.solo_edges == cur.solo_edges &&
                                 cand.block_units == cur.block_units &&
-                                cand.small_n == cur.small_n))
+                                cand.small_n == cur.small_n && cand.wg == cur.wg))
           continue;
         double ms;
         if ((st = time_of(cand, &ms))) return st;

@@ -1629,6 +1629,8 @@ static hipError_t launch_solve_t(const RoundArgs &a, int32_t *pred, const Launch
   hipError_t e;
   if (geo.blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
   if (!BATCH && a.total <= geo.small_n) return launch_small(V::INF == KeyF32::INF, a, pred, timer, L);
+  if (geo.wg && !a.scope_all)
+    return launch_wg(V::INF == KeyF32::INF, BATCH, a, pred, geo, istat, max_n, timer, L);
   RoundArgs arg = a;
   void *params[] = {&arg};
   {

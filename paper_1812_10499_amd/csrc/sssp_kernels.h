@@ -146,6 +146,7 @@ struct LaunchGeom {
   int blocks;  // persistent grid size (co-resident)
   int cus;
   int small_n = 0;  // single solves of at most this many vertices run in one workgroup
+  int wg = 0;       // every instance in a workgroup of its own (scope OPEN only)
 };
 
 // Largest graph the one-workgroup solver holds in LDS.
@@ -193,6 +194,10 @@ hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
 hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                        const LaunchGeom &geo, long long *istat, int32_t max_n, Launcher &L);
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
+// every instance's rounds in a workgroup of its own (C scope OPEN), then the emit pass
+hipError_t launch_wg(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
+                     const LaunchGeom &geo, long long *istat, int32_t max_n,
+                     const KernelTimer *timer, Launcher &L);
 // a single solve of a.total <= kSmallN vertices in one workgroup, then the emit pass
 hipError_t launch_small(bool f32, const RoundArgs &a, int32_t *pred, const KernelTimer *timer,
                         Launcher &L);

@@ -1,0 +1,271 @@
+// The rounds of each solve in one workgroup: instance i of a launch runs on
+// block i (blocks loop over the instances when there are more), with its
+// state in global memory (the (D, parent) keys, both C buffers, the relax
+// set, the open lists by parity, label-correcting's DR) and block barriers
+// only: no grid barrier, no hand-over, and no instance waits for another.
+// For graphs of low degree spread under C scope OPEN (meshes, grids), whose
+// rounds are many and small; the rounds, counters and keys are those of the
+// persistent kernel (Section VI's rounds in the adopted order: relax, minD
+// and the threshold, the lower bounds of Eq. 1, fix).
+#include "sssp_dev.h"
+#include "sssp_kernels.h"
+
+namespace sssp {
+
+constexpr int WBS = 1024;  // threads of the workgroup
+
+struct WgLds {
+  int32_t pfx[WBS + 1];  // out-degree prefix of a window of relax items
+  int32_t wbase[WBS];    // out-list start of a window item
+  int32_t wdx[WBS];      // its relax D
+  uint64_t scan[WBS / SSSP_WAVE + 1];
+  int32_t red[2 * (WBS / SSSP_WAVE)];
+  int32_t nF, nF2, nO, nO2, target_hit;
+  unsigned long long relaxed, scanned, visits, settled;
+};
+
+template <class V, bool BATCH>
+__global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
+  __shared__ WgLds s;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {
+    // the control block the emit pass and the host read
+    Ctl *c = a.ctl;
+    c->front_ctr[0] = c->front_ctr[1] = 0ull;
+    c->open_ctr[0] = c->open_ctr[1] = 0ull;
+    c->live_ctr[0] = c->live_ctr[1] = 0ull;
+    c->go = c->go_a = 0u;
+    c->deg_count = 0;
+    c->heavy_count = 0;
+    c->resume_round = c->resume_phase = c->done = c->resume_act = 0;
+    c->resume_aep = 0u;
+    c->solo_phases = 0;
+    c->dead_deg = c->dead_deg_r = 0ull;
+    c->status = 0;
+  }
+  for (int inst = blockIdx.x; inst < a.num_inst; inst += gridDim.x) {
+    int32_t sb = 0, gi = 0, src = a.source, n = a.g.n;
+    if constexpr (BATCH) {
+      const InstDev id = a.insts[inst];
+      sb = id.sbase;
+      gi = id.graph;
+      src = id.source;
+      n = id.n;
+    }
+    const GraphDev &G = graph_of<BATCH>(a, gi);
+    const bool lc = G.lc != 0;
+    int32_t tgt = BATCH ? -1 : a.target;
+    if (G.rank) {
+      src = G.rank[src];
+      if (tgt >= 0) tgt = G.rank[tgt];
+    }
+    // D is updated by atomics (performed in L2): its reads after a barrier
+    // bypass the CU's L1 (agent-scope loads); the other arrays are written
+    // and read by plain accesses of this workgroup only
+    unsigned long long *D = a.D64 + sb;
+    int32_t *C[2] = {a.C0 + sb, a.C1 + sb};
+    int32_t *DR = a.DR ? a.DR + sb : nullptr;
+    int32_t *F = a.front_v + sb, *FD = a.front_x[FX_D] + sb;
+    int32_t *O[2] = {a.open_v0 + sb, a.open_v1 + sb};
+    for (int y = tid; y < n; y += WBS) {
+      const bool is_s = y == src;
+      D[y] = make_key(is_s ? 0 : V::INF, -1, false);
+      C[0][y] = C[1][y] = is_s ? V::INF : 0;  // the source is fixed from the start
+      if (lc) DR[y] = V::INF;
+    }
+    if (tid == 0) {
+      F[0] = src;
+      FD[0] = 0;
+      s.nF = 1;
+      s.nO = 0;
+      s.target_hit = (tgt >= 0 && tgt == src) ? 1 : 0;
+      s.relaxed = s.scanned = s.visits = 0ull;
+      s.settled = 1ull;  // the source
+    }
+    __syncthreads();
+    int r = 0, o = 0, status = 0;  // o: the open list being built this round
+    for (;;) {
+      if (tgt >= 0 && s.target_hit) break;  // the frontier that fixed it is not relaxed
+      ++r;
+      if (r > n + 1) {
+        status = 7;
+        break;
+      }
+      const int cur = r & 1;  // the bound step reads C[cur] and writes C[cur ^ 1]
+      // (A) relax the relax set's out-edges, each from its D at the start of
+      // the step; first discoveries join the open list
+      const int nF = s.nF;
+      unsigned long long nrel = 0;
+      for (int i0 = 0; i0 < nF; i0 += WBS) {
+        const int i = i0 + tid;
+        int32_t deg = 0;
+        if (i < nF) {
+          const int32_t x = F[i];
+          const int32_t b = G.out_off[x];
+          deg = G.out_off[x + 1] - b;
+          s.wbase[tid] = b;
+          s.wdx[tid] = FD[i];
+          if (lc) DR[x] = FD[i];
+        }
+        uint64_t tot;
+        s.pfx[tid] = (int32_t)block_excl_scan64<WBS>((uint64_t)deg, s.scan, &tot);
+        __syncthreads();
+        const int ET = (int)tot;
+        nrel += (unsigned long long)ET;
+        for (int e = tid; e < ET; e += WBS) {
+          int lo = 0, len = WBS;  // last window item with pfx <= e
+          while (len > 1) {
+            const int half = len >> 1;
+            if (s.pfx[lo + half] <= e) lo += half;
+            len -= half;
+          }
+          const int32_t pos = s.wbase[lo] + (e - s.pfx[lo]);
+          const int32_t y = G.out_dst[pos];
+          const int32_t w = G.out_w[pos];
+          const int32_t eid = G.out_eid ? G.out_eid[pos] : pos;
+          const int32_t dx = s.wdx[lo];
+          const int32_t cand = V::add(dx, w);
+          const unsigned long long key = make_key(cand, eid, cand == dx);
+          if (key < D[y]) {  // may be stale: only filters the atomic
+            const unsigned long long old = atomicMin(&D[y], key);
+            if ((int32_t)(old >> 32) == V::INF) O[o][atomicAdd(&s.nO, 1)] = y;
+          }
+        }
+        __syncthreads();
+      }
+      const int nO = s.nO;
+      if (tid == 0) s.relaxed += nrel;
+      if (nO == 0) break;  // (A) left nothing open
+      // (B) minD and the threshold over the open list
+      int32_t md = V::INF, th = V::INF;
+      for (int i = tid; i < nO; i += WBS) {
+        const int32_t y = O[o][i];
+        const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
+        md = kmin(md, dy);
+        th = kmin(th, V::add(dy, G.out_wmin[y]));
+      }
+      block_min2<WBS>(md, th, s.red);
+      // (C) lower bounds (Eq. 1), Jacobi: read C[cur], write C[cur ^ 1].
+      // In-lists are ascending by weight and every term max(C[v], minD) + w
+      // is at least minD + w, so a scan stops at the first edge with
+      // minD + w >= min(D[y], m_y); the counters take whole in-degrees.
+      const int32_t *Cold = C[cur];
+      int32_t *Cnew = C[cur ^ 1];
+      unsigned long long nscan = 0;
+      for (int i = tid; i < nO; i += WBS) {
+        const int32_t y = O[o][i];
+        const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
+        const int4 rec = G.vrec[2 * y];  // out_off, out_degree, in_off, in_degree
+        int32_t m = V::INF;
+        for (int32_t j = 0; j < rec.w; ++j) {
+          const int32_t w = G.in_w[rec.z + j];
+          if (V::add(md, w) >= kmin(dy, m)) break;
+          const int32_t cv = Cold[G.in_src[rec.z + j]];
+          if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+        }
+        Cnew[y] = kmax(kmax(Cold[y], md), kmin(dy, m));
+        nscan += (unsigned long long)rec.w;
+      }
+      if (tid == 0) {
+        s.nF2 = 0;
+        s.nO2 = 0;
+      }
+      __syncthreads();
+      // (D) fix: C' >= D or D <= thr.  Fixed vertices get C = INF in both
+      // buffers; the next relax set is the newly fixed vertices (label-
+      // correcting: those and, within the first bucket above minD, the
+      // survivors whose D fell since their last relax; the fixed ones only
+      // if it fell)
+      unsigned long long nfix = 0;
+      for (int i = tid; i < nO; i += WBS) {
+        const int32_t y = O[o][i];
+        const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
+        const int32_t cn = Cnew[y];
+        const bool relax_again = !lc || dy < DR[y];
+        const bool fix = cn >= dy || dy <= th;
+        if (fix) {
+          C[0][y] = C[1][y] = V::INF;
+          ++nfix;
+          if (y == tgt) s.target_hit = 1;
+        } else {
+          O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
+        }
+        if (relax_again && (fix || (lc && dy < V::add(md, G.delta)))) {
+          const int q = atomicAdd(&s.nF2, 1);
+          F[q] = y;
+          FD[q] = dy;
+        }
+      }
+      const long long f = wave_sum64((long long)nfix), sc = wave_sum64((long long)nscan);
+      if (lane_id() == 0) {
+        if (f) atomicAdd(&s.settled, (unsigned long long)f);
+        if (sc) atomicAdd(&s.scanned, (unsigned long long)sc);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        s.visits += (unsigned long long)nO;
+        s.nF = s.nF2;
+        s.nO = s.nO2;
+      }
+      o ^= 1;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      if constexpr (BATCH) {
+        a.irounds[inst] = r;
+        a.iscanned[3 * inst] = s.scanned;
+        a.iscanned[3 * inst + 1] = s.visits;
+        a.iscanned[3 * inst + 2] = s.relaxed;
+        if (a.istat) {  // the emit pass adds the reachable count (= settled)
+          a.istat[4 * inst + 0] = 0;
+          a.istat[4 * inst + 1] = 0;
+          a.istat[4 * inst + 2] = 0;
+          a.istat[4 * inst + 3] = 0;
+        }
+        if (status) atomicMax(&a.ctl->status, status);
+      } else {
+        Ctl *c = a.ctl;
+        c->rounds = r;
+        c->status = status;
+        c->settled = (long long)s.settled;
+        c->relaxed = (long long)s.relaxed;
+        c->scanned = (long long)s.scanned;
+        c->open_visits = (long long)s.visits;
+        c->target_id = tgt;
+        c->target_hit = s.target_hit;
+      }
+    }
+    __syncthreads();  // the next instance reuses the LDS
+  }
+}
+
+template <class V, bool BATCH>
+static hipError_t launch_wg_t(const RoundArgs &a, int32_t *pred, const LaunchGeom &geo,
+                              long long *istat, int32_t max_n, const KernelTimer *timer,
+                              Launcher &L) {
+  hipError_t e;
+  if (a.scope_all) return hipErrorInvalidValue;  // the live pass is not here
+  RoundArgs arg = a;
+  void *params[] = {&arg};
+  int blocks = a.num_inst < geo.blocks ? a.num_inst : geo.blocks;
+  if (blocks < 1) blocks = 1;
+  if (L.graph) timer = nullptr;
+  if (timer && (e = hipEventRecord(timer->start, L.stream)) != hipSuccess) return e;
+  if ((e = launch_kernel(L, (const void *)wg_rounds_kernel<V, BATCH>, dim3(blocks), dim3(WBS),
+                         params, false)) != hipSuccess)
+    return e;
+  if (timer && (e = hipEventRecord(timer->stop, L.stream)) != hipSuccess) return e;
+  return launch_pred(V::INF == KeyF32::INF, BATCH, a, pred, geo, istat, max_n, L);
+}
+
+hipError_t launch_wg(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
+                     const LaunchGeom &geo, long long *istat, int32_t max_n,
+                     const KernelTimer *timer, Launcher &L) {
+  if (f32)
+    return batch ? launch_wg_t<KeyF32, true>(a, pred, geo, istat, max_n, timer, L)
+                 : launch_wg_t<KeyF32, false>(a, pred, geo, istat, max_n, timer, L);
+  return batch ? launch_wg_t<KeyI32, true>(a, pred, geo, istat, max_n, timer, L)
+               : launch_wg_t<KeyI32, false>(a, pred, geo, istat, max_n, timer, L);
+}
+
+}  // namespace sssp

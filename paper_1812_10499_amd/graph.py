@@ -257,7 +257,8 @@ def _launch(launch):
     if launch is None or isinstance(launch, _abi.Launch):
         return launch
     return _abi.Launch(int(launch.get("blocks", 0)), int(launch.get("solo_edges", 0)),
-                       int(launch.get("block_units", 0)), int(launch.get("small_n", 0)))
+                       int(launch.get("block_units", 0)), int(launch.get("small_n", 0)),
+                       int(launch.get("wg", 0)))
 
 
 class Plan:
@@ -267,7 +268,7 @@ class Plan:
     :func:`solve_batch`); "sequence": one single solve per instance, back
     to back.  ``cost`` and ``pred`` (the latter optional) are allocated here
     in the batch layout and rewritten by every run.  ``launch`` is a dict
-    (blocks, solo_edges, block_units, small_n) or None for the defaults.
+    (blocks, solo_edges, block_units, small_n, wg) or None for the defaults.
     """
 
     def __init__(self, graphs: Sequence[Graph], inst_graph: Sequence[int],
