@@ -327,9 +327,10 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
  *                state in LDS (default and maximum 4096; negative: never);
  *   wg:          solves whose graphs all run C scope OPEN run each instance
  *                in a workgroup of its own, with block barriers only (up to
- *                `blocks` workgroups at a time): 0 (default) when every
- *                graph has low degree spread (deg_max * n < 3m: many small
- *                rounds), 1 always, negative never.
+ *                `blocks` workgroups at a time), and so does the tree pass
+ *                of sssp_backward: 0 (default) when every graph has low
+ *                degree spread (deg_max * n < 3m: many small rounds, deep
+ *                trees), 1 always, negative never.
  */
 typedef struct {
   int32_t blocks;

@@ -1321,6 +1321,11 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
   hebase[num_graphs] = eb;
   LaunchGeom geo;
   if ((s = geometry(ws, true, true, &geo))) return s;
+  {
+    // deep trees (graphs of low degree spread): each instance in a workgroup
+    const int wg = ws.cfg.wg;
+    geo.wg = wg > 0 || (wg == 0 && all_low_spread(graphs, inst_graph, num_inst)) ? 1 : 0;
+  }
   HIPCHK(hipStreamWaitEvent(stream, ws.last, 0));
   HIPCHK(hipMemcpyAsync(dg, hg, sizeof(GraphDev) * num_graphs, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(di, hi, sizeof(InstDev) * num_inst, hipMemcpyHostToDevice, stream));

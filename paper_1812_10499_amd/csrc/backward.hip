@@ -8,8 +8,9 @@
 // pred[head(e)] == e, so no child lists are built: a top-down pass records
 // the tree level by level (persistent kernel, one grid barrier per level),
 // and a bottom-up pass computes acc deepest level first, each vertex adding
-// its children in edge-id order.  A final edge-parallel kernel sums the
-// instances of each graph in instance order.  Every sum has a fixed order,
+// its children in edge-id order (or, for deep trees, each instance in a
+// workgroup of its own).  A final edge-parallel kernel sums the instances of
+// each graph in instance order.  Every sum has a fixed order,
 // so the result is deterministic.
 #include "sssp_dev.h"
 #include "sssp_kernels.h"
@@ -107,6 +108,80 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
   if (bid == 0 && tid == 0) *a.nlevels = L;
 }
 
+// The same two passes with each instance's tree in a workgroup of its own
+// (blocks loop over the instances) and block barriers only: for deep trees
+// (grids, meshes), whose levels are many and small.  Instance i's level
+// list occupies lv_v[sbase_i, sbase_i + n_i) and the ends of its levels
+// lv_i[sbase_i + l] (a tree has at most n_i levels).
+__global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
+  __shared__ uint64_t scan[BBS / SSSP_WAVE + 1];
+  __shared__ int32_t cnt;
+  const int tid = threadIdx.x;
+  int lmax = 0;
+  for (int ins = blockIdx.x; ins < a.num_inst; ins += gridDim.x) {
+    const InstDev id = a.insts[ins];
+    const GraphDev &G = a.graphs[id.graph];
+    const int32_t sb = id.sbase;
+    int32_t *V = a.lv_v + sb, *LE = a.lv_i + sb;
+    if (tid == 0) {
+      V[0] = id.source;  // graph-local ids in this path
+      cnt = 1;
+    }
+    __syncthreads();
+    // ---- top-down: level L occupies [s, e) of V
+    int s = 0, e = 1, L = 0;
+    while (s < e) {
+      for (int b0 = s; b0 < e; b0 += BBS) {
+        const int idx = b0 + tid;
+        int32_t k0 = 0, k1 = 0;
+        uint32_t nch = 0;
+        if (idx < e) {
+          const int32_t x = V[idx];
+          k0 = G.u_out_off[x];
+          k1 = G.u_out_off[x + 1];
+          for (int32_t k = k0; k < k1; ++k)
+            if (a.pred[sb + G.u_out_dst[k]] == k) ++nch;
+        }
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan64<BBS>((uint64_t)nch, scan, &tot);
+        if (tot > 0) {
+          uint32_t p = (uint32_t)cnt + (uint32_t)ex;
+          if (idx < e && nch) {
+            for (int32_t k = k0; k < k1; ++k) {
+              const int32_t c = G.u_out_dst[k];
+              if (a.pred[sb + c] == k) V[p++] = c;
+            }
+          }
+          __syncthreads();
+          if (tid == 0) cnt += (int32_t)tot;
+          __syncthreads();
+        }
+      }
+      if (tid == 0) LE[L] = e;
+      ++L;
+      s = e;
+      e = cnt;  // every thread reads it after the barriers above
+      __syncthreads();
+    }
+    lmax = L > lmax ? L : lmax;
+    // ---- bottom-up: deepest level first, children in edge-id order
+    for (int lv = L - 1; lv >= 0; --lv) {
+      const int ls = lv == 0 ? 0 : LE[lv - 1], le = LE[lv];
+      for (int idx = ls + tid; idx < le; idx += BBS) {
+        const int32_t y = V[idx];
+        float acc = a.gcost[sb + y];
+        for (int32_t k = G.u_out_off[y]; k < G.u_out_off[y + 1]; ++k) {
+          const int32_t c = G.u_out_dst[k];
+          if (a.pred[sb + c] == k) acc = __fadd_rn(acc, a.acc[sb + c]);
+        }
+        a.acc[sb + y] = acc;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0 && lmax) atomicMax(a.nlevels, lmax);
+}
+
 // grad_w[ebase[g] + e] = sum over instances i of graph g (instance order) of
 // acc_i[head(e)] if pred_i[head(e)] == e
 __global__ void bw_grad_kernel(BackArgs a, const int32_t *goff, const int32_t *ginst,
@@ -138,18 +213,25 @@ hipError_t launch_backward(const BackArgs &a, const LaunchGeom &geo, const int32
   hipError_t e;
   hipLaunchKernelGGL(bw_init_kernel, dim3(1), dim3(256), 0, stream, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  int occ = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)bw_levels_kernel,
-                                                        BBS, 0)) != hipSuccess)
-    return e;
-  int per_cu = geo.blocks / (geo.cus > 0 ? geo.cus : 1);
-  if (occ < per_cu) per_cu = occ;
-  if (per_cu < 1) return hipErrorLaunchFailure;
-  BackArgs arg = a;
-  void *params[] = {&arg};
-  e = hipLaunchCooperativeKernel((const void *)bw_levels_kernel, dim3(geo.cus * per_cu),
-                                 dim3(BBS), params, 0, stream);
-  if (e != hipSuccess) return e;
+  if (geo.wg) {
+    int nbk = a.num_inst < geo.blocks ? a.num_inst : geo.blocks;
+    if (nbk < 1) nbk = 1;
+    hipLaunchKernelGGL(bw_wg_kernel, dim3(nbk), dim3(BBS), 0, stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    int occ = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)bw_levels_kernel,
+                                                          BBS, 0)) != hipSuccess)
+      return e;
+    int per_cu = geo.blocks / (geo.cus > 0 ? geo.cus : 1);
+    if (occ < per_cu) per_cu = occ;
+    if (per_cu < 1) return hipErrorLaunchFailure;
+    BackArgs arg = a;
+    void *params[] = {&arg};
+    e = hipLaunchCooperativeKernel((const void *)bw_levels_kernel, dim3(geo.cus * per_cu),
+                                   dim3(BBS), params, 0, stream);
+    if (e != hipSuccess) return e;
+  }
   int blocks = (total_m + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   if (blocks < 1) blocks = 1;

@@ -148,3 +148,33 @@ def test_plan_sequence_on_wg(sp):
             assert_same_solution(cost[sl], pred[sl], stats[i], ref, "seq-%d" % i)
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("order", ["auto", "degree"])
+def test_backward_both_paths(sp, order):
+    """The backward pass with each tree in a workgroup of its own: the same
+    bits as the grid-wide level pass (children summed in edge-id order on
+    both), and the oracle's fp64 gradient within 1e-5 (relative norm)."""
+    import oracle
+    d, gco = gen.diff_workload(side=72, num_sources=6)
+    G = sp.Graph(d.n, d.src, d.dst, d.w, order=order)
+    srcs = [int(s) for s in d.sources]
+    ig = [0] * len(srcs)
+    gcost = torch.from_numpy(gco.reshape(-1)).cuda()
+    out = {}
+    for name, launch in PATHS.items():
+        sp.set_launch(launch)
+        try:
+            cost, pred, _ = sp.solve_batch([G], ig, srcs)
+            gw = sp.backward([G], ig, srcs, pred, gcost)
+            sync()
+        finally:
+            sp.set_launch(None)
+        out[name] = (to_np(pred), to_np(gw))
+    assert np.array_equal(out["wg"][0], out["grid"][0])
+    assert np.array_equal(out["wg"][1], out["grid"][1])
+    O = oracle.csr(d.n, d.src, d.dst)
+    ref = oracle.grad(O, srcs, out["wg"][0].astype(np.int64).reshape(len(srcs), d.n),
+                      gco.astype(np.float64))
+    err = np.linalg.norm(out["wg"][1].astype(np.float64) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-5, err
