@@ -24,7 +24,8 @@ from .build import kernel_source_hash
 
 def _short(name: str) -> str:
     name = name.replace(".kd", "")
-    for key in ("small_rounds_kernel", "rounds_kernel", "emit_kernel", "pred_degen_kernel", "init_fill_kernel",
+    for key in ("small_rounds_kernel", "wg_rounds_kernel", "bw_wg_kernel", "rounds_kernel",
+                "emit_kernel", "pred_degen_kernel", "init_fill_kernel",
                 "init_seed_kernel", "bw_levels_kernel", "bw_grad_kernel", "bw_init_kernel",
                 "bitwise_not"):
         if key in name:
