@@ -232,7 +232,9 @@ def bench_diff(args, sp, torch):
     t_single = timed(singles, max(1, args.steps // 4), stream)
     # the autotuned launch geometry of the 64-source forward, made the
     # default of the direct calls timed below
-    tuned, _ = sp.autotune([G], ig, srcs, kind="batch", reps=2)
+    tuned = None
+    if not args.no_tune:
+        tuned, _ = sp.autotune([G], ig, srcs, kind="batch", reps=2)
     sp.set_launch(tuned)
     for _ in range(args.warmup):
         both()
