@@ -254,7 +254,7 @@ def bench_diff(args, sp, torch):
         "dtype": "f32",
         "config": {"workload": "diff_grid512_f32_x64", "n": d.n, "m": d.m, "sources": S,
                    "m_reach": m_reach},
-        "timed": "direct calls under the autotuned launch geometry",
+        "timed": "direct calls under the %s launch geometry" % ("autotuned" if tuned else "default"),
         "launch": tuned, "forward_default_geometry_ms": round(t_fwd_default, 3),
         "forward_ms": round(t_fwd, 3), "backward_ms": round(t_bwd, 3),
         "forward_backward_ms": round(t_both, 3), "single_solves_ms": round(t_single, 3),

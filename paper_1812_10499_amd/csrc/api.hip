@@ -1210,7 +1210,11 @@ sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int3
         if (field == 1) cand.solo_edges = solo[c];
         if (field == 2) cand.block_units = units[c];
         if (field == 3) cand.small_n = small[c];
-        if (field == 4) cand.wg = wgs[c];
+        if (field == 4) {
+          cand.wg = wgs[c];
+          // forcing one workgroup per instance only pays with many instances
+          if (cand.wg > 0 && num_inst < full.cus / 4) continue;
+        }
         if (cand.blocks < 1 || (cand.blocks == cur.blocks && cand.solo_edges == cur.solo_edges &&
                                 cand.block_units == cur.block_units &&
                                 cand.small_n == cur.small_n && cand.wg == cur.wg))

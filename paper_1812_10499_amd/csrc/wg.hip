@@ -83,6 +83,11 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       s.settled = 1ull;  // the source
     }
     __syncthreads();
+    // minD / thr offers of this thread's survivors of the last fix step:
+    // with the relax's successful candidates they cover every open vertex's
+    // current D (a survivor whose D fell offered the lower value as a
+    // candidate), so no pass over the open list is needed for them
+    int32_t smd = V::INF, sth = V::INF;
     int r = 0, o = 0, status = 0;  // o: the open list being built this round
     for (;;) {
       if (tgt >= 0 && s.target_hit) break;  // the frontier that fixed it is not relaxed
@@ -92,20 +97,32 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
         break;
       }
       const int cur = r & 1;  // the bound step reads C[cur] and writes C[cur ^ 1]
+      const int32_t *Cold = C[cur];
+      int32_t *Cnew = C[cur ^ 1];
       // (A) relax the relax set's out-edges, each from its D at the start of
-      // the step; first discoveries join the open list
+      // the step; first discoveries join the open list.  Relax items:
+      // FD = the D to relax from (bit 31 set: an open vertex, label-
+      // correcting), or INF: a vertex fixed at a D it was already relaxed
+      // with (no edges).  A fixed item also marks its C in the buffer this
+      // round writes (the other buffer has it since the fix).
       const int nF = s.nF;
       unsigned long long nrel = 0;
+      int32_t md = smd, th = sth;
       for (int i0 = 0; i0 < nF; i0 += WBS) {
         const int i = i0 + tid;
         int32_t deg = 0;
         if (i < nF) {
           const int32_t x = F[i];
-          const int32_t b = G.out_off[x];
-          deg = G.out_off[x + 1] - b;
-          s.wbase[tid] = b;
-          s.wdx[tid] = FD[i];
-          if (lc) DR[x] = FD[i];
+          const int32_t fd = FD[i];
+          const int32_t dx = fd & 0x7fffffff;
+          if (fd >= 0) Cnew[x] = V::INF;
+          if (dx != V::INF) {
+            const int32_t b = G.out_off[x];
+            deg = G.out_off[x + 1] - b;
+            s.wbase[tid] = b;
+            s.wdx[tid] = dx;
+            if (lc) DR[x] = dx;
+          }
         }
         uint64_t tot;
         s.pfx[tid] = (int32_t)block_excl_scan64<WBS>((uint64_t)deg, s.scan, &tot);
@@ -128,7 +145,12 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           const unsigned long long key = make_key(cand, eid, cand == dx);
           if (key < D[y]) {  // may be stale: only filters the atomic
             const unsigned long long old = atomicMin(&D[y], key);
-            if ((int32_t)(old >> 32) == V::INF) O[o][atomicAdd(&s.nO, 1)] = y;
+            const int32_t od = (int32_t)(old >> 32);
+            if (cand < od) {  // D[y] fell: offer it to minD and thr
+              md = kmin(md, cand);
+              th = kmin(th, V::add(cand, G.out_wmin[y]));
+            }
+            if (od == V::INF) O[o][atomicAdd(&s.nO, 1)] = y;
           }
         }
         __syncthreads();
@@ -137,21 +159,24 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       if (tid == 0) s.relaxed += nrel;
       if (nO == 0) break;  // (A) left nothing open
       // (B) minD and the threshold over the open list
-      int32_t md = V::INF, th = V::INF;
-      for (int i = tid; i < nO; i += WBS) {
-        const int32_t y = O[o][i];
-        const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
-        md = kmin(md, dy);
-        th = kmin(th, V::add(dy, G.out_wmin[y]));
-      }
       block_min2<WBS>(md, th, s.red);
-      // (C) lower bounds (Eq. 1), Jacobi: read C[cur], write C[cur ^ 1].
+      if (tid == 0) {
+        s.nF2 = 0;
+        s.nO2 = 0;
+      }
+      __syncthreads();
+      // (C) lower bounds (Eq. 1), Jacobi: read C[cur], write C[cur ^ 1];
+      // then (D) for the same vertex: it only needs the vertex's own C'.
       // In-lists are ascending by weight and every term max(C[v], minD) + w
       // is at least minD + w, so a scan stops at the first edge with
       // minD + w >= min(D[y], m_y); the counters take whole in-degrees.
-      const int32_t *Cold = C[cur];
-      int32_t *Cnew = C[cur ^ 1];
-      unsigned long long nscan = 0;
+      // Fixed vertices get C = INF (C[cur] at the next relax); the next
+      // relax set is the newly fixed vertices (label-correcting: those and,
+      // within the first bucket above minD, the survivors whose D fell since
+      // their last relax; a fixed one at a D it was relaxed with comes with
+      // no edges, to mark its C)
+      unsigned long long nscan = 0, nfix = 0;
+      smd = sth = V::INF;
       for (int i = tid; i < nO; i += WBS) {
         const int32_t y = O[o][i];
         const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
@@ -163,37 +188,26 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           const int32_t cv = Cold[G.in_src[rec.z + j]];
           if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
         }
-        Cnew[y] = kmax(kmax(Cold[y], md), kmin(dy, m));
+        const int32_t cn = kmax(kmax(Cold[y], md), kmin(dy, m));
         nscan += (unsigned long long)rec.w;
-      }
-      if (tid == 0) {
-        s.nF2 = 0;
-        s.nO2 = 0;
-      }
-      __syncthreads();
-      // (D) fix: C' >= D or D <= thr.  Fixed vertices get C = INF in both
-      // buffers; the next relax set is the newly fixed vertices (label-
-      // correcting: those and, within the first bucket above minD, the
-      // survivors whose D fell since their last relax; the fixed ones only
-      // if it fell)
-      unsigned long long nfix = 0;
-      for (int i = tid; i < nO; i += WBS) {
-        const int32_t y = O[o][i];
-        const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
-        const int32_t cn = Cnew[y];
         const bool relax_again = !lc || dy < DR[y];
-        const bool fix = cn >= dy || dy <= th;
-        if (fix) {
-          C[0][y] = C[1][y] = V::INF;
+        if (cn >= dy || dy <= th) {
+          Cnew[y] = V::INF;
           ++nfix;
           if (y == tgt) s.target_hit = 1;
-        } else {
-          O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
-        }
-        if (relax_again && (fix || (lc && dy < V::add(md, G.delta)))) {
           const int q = atomicAdd(&s.nF2, 1);
           F[q] = y;
-          FD[q] = dy;
+          FD[q] = relax_again ? dy : V::INF;
+        } else {
+          Cnew[y] = cn;
+          O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
+          smd = kmin(smd, dy);
+          sth = kmin(sth, V::add(dy, G.vrec[2 * y + 1].x));
+          if (lc && relax_again && dy < V::add(md, G.delta)) {
+            const int q = atomicAdd(&s.nF2, 1);
+            F[q] = y;
+            FD[q] = dy | kOpenRelax;
+          }
         }
       }
       const long long f = wave_sum64((long long)nfix), sc = wave_sum64((long long)nscan);
