@@ -65,7 +65,9 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
     unsigned long long *D = a.D64 + sb;
     int32_t *C[2] = {a.C0 + sb, a.C1 + sb};
     int32_t *DR = a.DR ? a.DR + sb : nullptr;
+    // relax items: vertex, D to relax from, out-offset, out-degree
     int32_t *F = a.front_v + sb, *FD = a.front_x[FX_D] + sb;
+    int32_t *FO = a.front_x[FX_OOFF] + sb, *FG = a.front_p + sb;
     int32_t *O[2] = {a.open_v0 + sb, a.open_v1 + sb};
     for (int y = tid; y < n; y += WBS) {
       const bool is_s = y == src;
@@ -76,6 +78,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
     if (tid == 0) {
       F[0] = src;
       FD[0] = 0;
+      FO[0] = G.out_off[src];
+      FG[0] = G.out_off[src + 1] - FO[0];
       s.nF = 1;
       s.nO = 0;
       s.target_hit = (tgt >= 0 && tgt == src) ? 1 : 0;
@@ -117,9 +121,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           const int32_t dx = fd & 0x7fffffff;
           if (fd >= 0) Cnew[x] = V::INF;
           if (dx != V::INF) {
-            const int32_t b = G.out_off[x];
-            deg = G.out_off[x + 1] - b;
-            s.wbase[tid] = b;
+            deg = FG[i];
+            s.wbase[tid] = FO[i];
             s.wdx[tid] = dx;
             if (lc) DR[x] = dx;
           }
@@ -142,16 +145,14 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           const int32_t eid = G.out_eid ? G.out_eid[pos] : pos;
           const int32_t dx = s.wdx[lo];
           const int32_t cand = V::add(dx, w);
-          const unsigned long long key = make_key(cand, eid, cand == dx);
-          if (key < D[y]) {  // may be stale: only filters the atomic
-            const unsigned long long old = atomicMin(&D[y], key);
-            const int32_t od = (int32_t)(old >> 32);
-            if (cand < od) {  // D[y] fell: offer it to minD and thr
-              md = kmin(md, cand);
-              th = kmin(th, V::add(cand, G.out_wmin[y]));
-            }
-            if (od == V::INF) O[o][atomicAdd(&s.nO, 1)] = y;
+          // one workgroup: little contention, so straight to the atomic
+          const unsigned long long old = atomicMin(&D[y], make_key(cand, eid, cand == dx));
+          const int32_t od = (int32_t)(old >> 32);
+          if (cand < od) {  // D[y] fell: offer it to minD and thr
+            md = kmin(md, cand);
+            th = kmin(th, V::add(cand, G.out_wmin[y]));
           }
+          if (od == V::INF) O[o][atomicAdd(&s.nO, 1)] = y;
         }
         __syncthreads();
       }
@@ -198,6 +199,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           const int q = atomicAdd(&s.nF2, 1);
           F[q] = y;
           FD[q] = relax_again ? dy : V::INF;
+          FO[q] = rec.x;
+          FG[q] = rec.y;
         } else {
           Cnew[y] = cn;
           O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
@@ -207,6 +210,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             const int q = atomicAdd(&s.nF2, 1);
             F[q] = y;
             FD[q] = dy | kOpenRelax;
+            FO[q] = rec.x;
+            FG[q] = rec.y;
           }
         }
       }
