@@ -390,8 +390,9 @@ sssp_status sssp_plan_destroy(sssp_plan plan);
  * its replays (HIP events on `stream`, `reps` timed runs after one warm-up,
  * mean taken) under candidate geometries, one field at a time (blocks:
  * maximum, 1/2, 1/4; solo_edges: 2048, 8192, 32768; block_units: 2048,
- * 4096, 8192; small_n: the default, never; wg: the default, never,
- * always), keeping a candidate only when it beats the best so far.
+ * 4096, 8192; small_n: the default, never; wg: the default, never, and
+ * always when there are at least a quarter as many instances as compute
+ * units), keeping a candidate only when it beats the best so far.
  * *best receives the fastest geometry, *best_ms its mean run time.  Writes
  * cost and pred like a run; synchronizes.  Arguments as for
  * sssp_plan_create; reps in [1, 100].
