@@ -359,7 +359,9 @@ sssp_status sssp_set_launch(const sssp_launch *launch);
  *   cost, pred (device; pred nullable): written by every run; they, the
  *           graphs' buffers and the graphs' contents must stay valid until
  *           the plan is destroyed (new weights via sssp_set_weights are
- *           picked up by the next run: the plan holds pointers, not values).
+ *           picked up by the next run: the plan holds pointers, not values;
+ *           each graph's C scope, relax step, bucket width and kernel path
+ *           are those it had when the plan was created).
  *   with_stats: non-zero to keep the per-instance counters that
  *           sssp_plan_stats reads (the batch kind counts them in the
  *           kernel, at some cost; the sequence kind always has them).

@@ -178,3 +178,25 @@ def test_backward_both_paths(sp, order):
                       gco.astype(np.float64))
     err = np.linalg.norm(out["wg"][1].astype(np.float64) - ref) / np.linalg.norm(ref)
     assert err <= 1e-5, err
+
+
+def test_batch_plan_on_wg(sp):
+    """A batch plan of grid instances (the one-workgroup-per-instance path)
+    replayed three times, each replay against the oracle."""
+    f = grid_f32(64, 17)
+    G = sp.Graph(f.n, f.src, f.dst, f.w)
+    srcs = [0, f.n // 2 + 5, f.n - 1, 1234]
+    refs = [oracle_solution(f.n, f.src, f.dst, f.w, s, G.effective_scope, G.effective_relax,
+                            G.effective_delta) for s in srcs]
+    plan = sp.Plan([G], [0] * len(srcs), srcs, kind="batch", with_stats=True)
+    try:
+        for rep in range(3):
+            plan.cost.fill_(-1.0)
+            cost, pred = plan.run()
+            sync()
+            stats = plan.stats()
+            for i, ref in enumerate(refs):
+                sl = slice(i * f.n, (i + 1) * f.n)
+                assert_same_solution(cost[sl], pred[sl], stats[i], ref, "plan-%d-%d" % (rep, i))
+    finally:
+        plan.close()
