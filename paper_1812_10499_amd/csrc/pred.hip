@@ -31,17 +31,19 @@ __global__ __launch_bounds__(256) void emit_kernel(RoundArgs a, int32_t *pred, i
     n = id.n;
   }
   const GraphDev &G = graph_of<BATCH>(a, gi);
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;  // solver id
+  // one thread per caller id: the outputs are written in order and a
+  // renumbered graph's keys are gathered through rank
+  const int uy = blockIdx.x * blockDim.x + threadIdx.x;  // the caller's id
   long long c_settled = 0, c_relaxed = 0;
-  if (y < n) {
+  if (uy < n) {
+    const int32_t y = G.rank ? G.rank[uy] : uy;  // solver id
     const unsigned long long k = a.D64[sb + y];
-    const int32_t uy = G.vid ? G.vid[y] : y;  // the caller's id
     const int32_t gy = sb + uy;
     const int32_t d = (int32_t)(k >> 32);
     a.D[gy] = d;
     if (d != V::INF) {
       c_settled = 1;
-      c_relaxed = G.out_off[y + 1] - G.out_off[y];
+      c_relaxed = G.u_out_off[uy + 1] - G.u_out_off[uy];
     }
     if (pred) {
       int32_t p = -1;
