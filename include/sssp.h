@@ -150,8 +150,10 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  *       each out-list ascending by (head solver id, edge id)
  *   s_out_wmin[n]  out_wmin by solver id
  * Always, too: s_vrec[8n], one 32-byte record per solver vertex,
- *   {out_off, out_degree, in_off, in_degree, out_wmin, 0, 0, 0}, so that a
- *   round reads a vertex's offsets and out_wmin from one cache line.
+ *   {out_off, out_degree, in_off, in_degree, out_wmin, s_in_src and s_in_w
+ *   of the first in-list entry (0, 0 with no in-edges), 0}, so that a round
+ *   reads a vertex's offsets, out_wmin and lightest in-edge from one cache
+ *   line.
  * With SSSP_ORDER_INPUT, solver ids are vertex ids: vid, rank and
  * s_out_eid are NULL and s_out_off/dst/w/wmin alias the CSR arrays.
  * These arrays are library-internal; callers only keep them valid.

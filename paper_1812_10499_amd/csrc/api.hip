@@ -675,7 +675,7 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
                             stream));
   HIPCHK(launch_in_lists(g->n, g->m, hs[1], g->out_off, g->out_dst, (const int32_t *)g->out_w,
                          c, t, stream));
-  HIPCHK(launch_vrec(g->n, c, stream));  // out_wmin changed
+  HIPCHK(launch_vrec(g->n, c, stream));  // out_wmin and the in-list heads changed
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));
   g->w_max = w_max;

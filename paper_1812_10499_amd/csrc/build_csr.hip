@@ -468,18 +468,23 @@ hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t
   return hipGetLastError();
 }
 
+// The record also carries the head of the weight-ordered in-list (tail and
+// weight of the lightest in-edge; 0, 0 with no in-edges), so that a pass
+// over many vertices reads its first in-edge from the record's line instead
+// of one line of in_src and one of in_w per vertex.
 __global__ void vrec_kernel(int32_t n, const int32_t *out_off, const int32_t *in_off,
+                            const int32_t *in_src, const int32_t *in_w,
                             const int32_t *out_wmin, int4 *vrec) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t o = out_off[v], i = in_off[v];
-    vrec[2 * v] = make_int4(o, out_off[v + 1] - o, i, in_off[v + 1] - i);
-    vrec[2 * v + 1] = make_int4(out_wmin[v], 0, 0, 0);
+    const int32_t o = out_off[v], i = in_off[v], ideg = in_off[v + 1] - i;
+    vrec[2 * v] = make_int4(o, out_off[v + 1] - o, i, ideg);
+    vrec[2 * v + 1] = make_int4(out_wmin[v], ideg ? in_src[i] : 0, ideg ? in_w[i] : 0, 0);
   }
 }
 
 hipError_t launch_vrec(int32_t n, const SolverCopy &c, hipStream_t stream) {
   hipLaunchKernelGGL(vrec_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, c.out_off,
-                     c.in_off, c.out_wmin, (int4 *)c.vrec);
+                     c.in_off, c.in_src, c.in_w, c.out_wmin, (int4 *)c.vrec);
   return hipGetLastError();
 }
 

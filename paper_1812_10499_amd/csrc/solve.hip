@@ -846,7 +846,9 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
       const GraphDev &G = graph_of<BATCH>(a, gi);
       if (G.all && mdi != V::INF && (int32_t)(a.D64[y] >> 32) == V::INF) {
         const int32_t c = Cold[y];
-        const int4 rec = G.vrec[2 * (y - sb)];  // out_off, out_degree, in_off, in_degree
+        // out_off, out_degree, in_off, in_degree; out_wmin, the lightest
+        // in-edge's tail and weight (the same line)
+        const int4 rec = G.vrec[2 * (y - sb)], rec2 = G.vrec[2 * (y - sb) + 1];
         const int32_t b = rec.z, deg = rec.w;
         const int32_t *Cg = Cold + sb;  // the instance's C, by graph-local id
         if constexpr (BATCH) {
@@ -871,7 +873,7 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
           int32_t j = 0;
           if (deg > 0) {
             // the lightest in-edge alone first: its tail usually decides m
-            const int32_t v0 = G.in_src[b], w0 = G.in_w[b];
+            const int32_t v0 = rec2.y, w0 = rec2.z;
             const int32_t c0 = Cg[v0];
             if (c0 != V::INF) m = V::add(kmax(c0, mdi), w0);
             j = (V::add(mdi, w0) >= m) ? deg : 1;

@@ -46,7 +46,8 @@ __device__ __forceinline__ int32_t kmax(int32_t a, int32_t b) { return a > b ? a
 // the numberings coincide).  The u_ arrays are the caller-numbered CSR/CSC
 // that the parent tie pass and the backward pass walk.
 // vrec: per solver vertex {out_off, out_degree, in_off, in_degree,
-// out_wmin, 0, 0, 0} (one 32-byte record).
+// out_wmin, in_src and in_w of the lightest in-edge (0, 0 if none), 0}
+// (one 32-byte record).
 struct GraphDev {
   const int32_t *out_off, *out_dst, *out_w, *out_eid;
   const int32_t *in_off, *in_src, *in_w;

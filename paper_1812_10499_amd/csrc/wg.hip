@@ -181,13 +181,20 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       for (int i = tid; i < nO; i += WBS) {
         const int32_t y = O[o][i];
         const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
-        const int4 rec = G.vrec[2 * y];  // out_off, out_degree, in_off, in_degree
+        // out_off, out_degree, in_off, in_degree; out_wmin, the lightest
+        // in-edge's tail and weight
+        const int4 rec = G.vrec[2 * y], rec2 = G.vrec[2 * y + 1];
         int32_t m = V::INF;
-        for (int32_t j = 0; j < rec.w; ++j) {
-          const int32_t w = G.in_w[rec.z + j];
-          if (V::add(md, w) >= kmin(dy, m)) break;
-          const int32_t cv = Cold[G.in_src[rec.z + j]];
-          if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+        if (rec.w > 0 && V::add(md, rec2.z) < dy) {
+          // the first edge comes from the record, the rest from the in-list
+          const int32_t c0 = Cold[rec2.y];
+          if (c0 != V::INF) m = V::add(kmax(c0, md), rec2.z);
+          for (int32_t j = 1; j < rec.w; ++j) {
+            const int32_t w = G.in_w[rec.z + j];
+            if (V::add(md, w) >= kmin(dy, m)) break;
+            const int32_t cv = Cold[G.in_src[rec.z + j]];
+            if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+          }
         }
         const int32_t cn = kmax(kmax(Cold[y], md), kmin(dy, m));
         nscan += (unsigned long long)rec.w;
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           Cnew[y] = cn;
           O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
           smd = kmin(smd, dy);
-          sth = kmin(sth, V::add(dy, G.vrec[2 * y + 1].x));
+          sth = kmin(sth, V::add(dy, rec2.x));
           if (lc && relax_again && dy < V::add(md, G.delta)) {
             const int q = atomicAdd(&s.nF2, 1);
             F[q] = y;

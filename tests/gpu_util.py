@@ -96,7 +96,7 @@ def check_solver_copy(G, n, src, dst, w):
     in_off_s = np.concatenate([[0], np.cumsum(np.bincount(rank[head], minlength=n))])
     assert np.array_equal(vr[:, 2], in_off_s[:-1]) and np.array_equal(vr[:, 3], np.diff(in_off_s))
     assert np.array_equal(vr[:, 4], bits(np.ascontiguousarray(wmin_s)))
-    assert not vr[:, 5:].any()
+    assert not vr[:, 7].any()
     for side, order in sides.items():
         key = rank[tail] if side == "out" else rank[head]
         nbr = rank[head] if side == "out" else rank[tail]
@@ -106,3 +106,10 @@ def check_solver_copy(G, n, src, dst, w):
         nb = S["out_dst"] if side == "out" else S["in_src"]
         assert np.array_equal(nb, nbr[order]), side
         assert np.array_equal(bits(S[side + "_w"]), bits(ow[order])), side
+        if side == "in":
+            # the record's copy of each in-list's first (lightest) entry
+            has = np.diff(off) > 0
+            first = off[:-1][has]
+            assert np.array_equal(vr[has, 5], nbr[order][first])
+            assert np.array_equal(vr[has, 6], bits(np.ascontiguousarray(ow[order]))[first])
+            assert not vr[~has, 5:7].any()
