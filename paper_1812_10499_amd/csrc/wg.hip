@@ -13,6 +13,7 @@
 namespace sssp {
 
 constexpr int WBS = 1024;  // threads of the workgroup
+constexpr int kWgItems = 2;  // open-list entries per thread and pass of the bound step
 
 struct WgLds {
   int32_t pfx[WBS + 1];  // out-degree prefix of a window of relax items
@@ -178,47 +179,75 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       // no edges, to mark its C)
       unsigned long long nscan = 0, nfix = 0;
       smd = sth = V::INF;
-      for (int i = tid; i < nO; i += WBS) {
-        const int32_t y = O[o][i];
-        const int32_t dy = (int32_t)(ld_relaxed64(&D[y]) >> 32);
-        // out_off, out_degree, in_off, in_degree; out_wmin, the lightest
-        // in-edge's tail and weight
-        const int4 rec = G.vrec[2 * y], rec2 = G.vrec[2 * y + 1];
-        int32_t m = V::INF;
-        if (rec.w > 0 && V::add(md, rec2.z) < dy) {
-          // the first edge comes from the record, the rest from the in-list
-          const int32_t c0 = Cold[rec2.y];
-          if (c0 != V::INF) m = V::add(kmax(c0, md), rec2.z);
-          for (int32_t j = 1; j < rec.w; ++j) {
-            const int32_t w = G.in_w[rec.z + j];
-            if (V::add(md, w) >= kmin(dy, m)) break;
-            const int32_t cv = Cold[G.in_src[rec.z + j]];
-            if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+      // Each thread takes kWgItems list entries per pass and issues the
+      // loads of all of them before any decision, so that the dependent
+      // chain (entry, then D / record / C, then the lightest tail's C) is
+      // paid once per pass rather than once per entry.
+      for (int i0 = 0; i0 < nO; i0 += kWgItems * WBS) {
+        int32_t y[kWgItems], dy[kWgItems], cy[kWgItems], dr[kWgItems], c0[kWgItems];
+        int4 rec[kWgItems], rec2[kWgItems];
+        bool ok[kWgItems];
+#pragma unroll
+        for (int u = 0; u < kWgItems; ++u) {
+          const int i = i0 + u * WBS + tid;
+          ok[u] = i < nO;
+          y[u] = ok[u] ? O[o][i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kWgItems; ++u) {
+          if (ok[u]) {
+            dy[u] = (int32_t)(ld_relaxed64(&D[y[u]]) >> 32);
+            // out_off, out_degree, in_off, in_degree; out_wmin, the
+            // lightest in-edge's tail and weight
+            rec[u] = G.vrec[2 * y[u]];
+            rec2[u] = G.vrec[2 * y[u] + 1];
+            cy[u] = Cold[y[u]];
+            dr[u] = lc ? DR[y[u]] : 0;
           }
         }
-        const int32_t cn = kmax(kmax(Cold[y], md), kmin(dy, m));
-        nscan += (unsigned long long)rec.w;
-        const bool relax_again = !lc || dy < DR[y];
-        if (cn >= dy || dy <= th) {
-          Cnew[y] = V::INF;
-          ++nfix;
-          if (y == tgt) s.target_hit = 1;
-          const int q = atomicAdd(&s.nF2, 1);
-          F[q] = y;
-          FD[q] = relax_again ? dy : V::INF;
-          FO[q] = rec.x;
-          FG[q] = rec.y;
-        } else {
-          Cnew[y] = cn;
-          O[o ^ 1][atomicAdd(&s.nO2, 1)] = y;
-          smd = kmin(smd, dy);
-          sth = kmin(sth, V::add(dy, rec2.x));
-          if (lc && relax_again && dy < V::add(md, G.delta)) {
+#pragma unroll
+        for (int u = 0; u < kWgItems; ++u) {
+          c0[u] = V::INF;
+          // the first in-edge comes from the record
+          if (ok[u] && rec[u].w > 0 && V::add(md, rec2[u].z) < dy[u]) c0[u] = Cold[rec2[u].y];
+        }
+#pragma unroll
+        for (int u = 0; u < kWgItems; ++u) {
+          if (!ok[u]) continue;
+          int32_t m = V::INF;
+          if (rec[u].w > 0 && V::add(md, rec2[u].z) < dy[u]) {
+            if (c0[u] != V::INF) m = V::add(kmax(c0[u], md), rec2[u].z);
+            for (int32_t j = 1; j < rec[u].w; ++j) {  // the rest from the in-list
+              const int32_t w = G.in_w[rec[u].z + j];
+              if (V::add(md, w) >= kmin(dy[u], m)) break;
+              const int32_t cv = Cold[G.in_src[rec[u].z + j]];
+              if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
+            }
+          }
+          const int32_t cn = kmax(kmax(cy[u], md), kmin(dy[u], m));
+          nscan += (unsigned long long)rec[u].w;
+          const bool relax_again = !lc || dy[u] < dr[u];
+          if (cn >= dy[u] || dy[u] <= th) {
+            Cnew[y[u]] = V::INF;
+            ++nfix;
+            if (y[u] == tgt) s.target_hit = 1;
             const int q = atomicAdd(&s.nF2, 1);
-            F[q] = y;
-            FD[q] = dy | kOpenRelax;
-            FO[q] = rec.x;
-            FG[q] = rec.y;
+            F[q] = y[u];
+            FD[q] = relax_again ? dy[u] : V::INF;
+            FO[q] = rec[u].x;
+            FG[q] = rec[u].y;
+          } else {
+            Cnew[y[u]] = cn;
+            O[o ^ 1][atomicAdd(&s.nO2, 1)] = y[u];
+            smd = kmin(smd, dy[u]);
+            sth = kmin(sth, V::add(dy[u], rec2[u].x));
+            if (lc && relax_again && dy[u] < V::add(md, G.delta)) {
+              const int q = atomicAdd(&s.nF2, 1);
+              F[q] = y[u];
+              FD[q] = dy[u] | kOpenRelax;
+              FO[q] = rec[u].x;
+              FG[q] = rec[u].y;
+            }
           }
         }
       }
