@@ -235,11 +235,18 @@ static hipError_t radix_sort(int32_t *ka, int32_t *va, int32_t *kb, int32_t *vb,
 
 // ---------------------------------------------------------- assembling
 // offsets from sorted keys: off[v] = first position with key >= v
+// off[v] = the number of sorted keys below v (v = 0 .. n): one binary search
+// per vertex, so a long run of vertices with no edges costs no thread more
+// than the others
 __global__ void offsets_kernel(const int32_t *skeys, int32_t m, int32_t n, int32_t *off) {
-  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= m; k += gridDim.x * blockDim.x) {
-    const int32_t prev = (k == 0) ? -1 : skeys[k - 1];
-    const int32_t cur = (k == m) ? n : skeys[k];
-    for (int32_t v = prev + 1; v <= cur; ++v) off[v] = k;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = m;
+    while (lo < hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      if (skeys[mid] < v) lo = mid + 1;
+      else hi = mid;
+    }
+    off[v] = lo;
   }
 }
 
@@ -265,13 +272,58 @@ __global__ void gather_csc_kernel(const int32_t *eid, const int32_t *tail, const
 }
 
 template <bool F32>
-__global__ void wmin_kernel(const int32_t *out_off, const int32_t *out_w, int32_t n,
+__global__ void wmin_fill_kernel(int32_t n, int32_t *out_wmin) {
+  constexpr int32_t INF = F32 ? KeyF32::INF : KeyI32::INF;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    out_wmin[v] = INF;
+}
+
+// the vertex whose out-list holds CSR position k (k < m): the largest v with
+// out_off[v] <= k
+__device__ int32_t owner_of(const int32_t *out_off, int32_t n, int32_t k) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo + 1) >> 1);
+    if (out_off[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Minimum out-weight per vertex over fixed chunks of CSR positions (after
+// wmin_fill_kernel; vertices with no out-edges keep INF).  A list wholly
+// inside one chunk is stored; a list cut by a chunk boundary is combined by
+// atomicMin (weights are positive, so float bits order like int32), so a
+// hub's list costs no thread more than a chunk.
+constexpr int32_t kWminChunk = 256;
+
+template <bool F32>
+__global__ void wmin_kernel(const int32_t *out_off, const int32_t *out_w, int32_t n, int32_t m,
                             int32_t *out_wmin) {
   constexpr int32_t INF = F32 ? KeyF32::INF : KeyI32::INF;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  const int64_t chunks = ((int64_t)m + kWminChunk - 1) / kWminChunk;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < chunks;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k0 = (int32_t)(c * kWminChunk);
+    const int32_t k1 = (int32_t)min((int64_t)m, c * kWminChunk + kWminChunk);
+    int32_t v = owner_of(out_off, n, k0);
+    int32_t vend = out_off[v + 1];
+    bool whole = out_off[v] >= k0;  // v's list starts in this chunk
     int32_t mn = INF;
-    for (int32_t k = out_off[v]; k < out_off[v + 1]; ++k) mn = kmin(mn, out_w[k]);
-    out_wmin[v] = mn;
+    for (int32_t k = k0; k < k1; ++k) {
+      mn = kmin(mn, out_w[k]);
+      if (k + 1 == vend || k + 1 == k1) {
+        if (whole && k + 1 == vend) out_wmin[v] = mn;
+        else atomicMin(&out_wmin[v], mn);
+        if (k + 1 < k1) {
+          // the next non-empty list: usually v + 1's (k + 1 < m, so v + 2 <= n)
+          v = out_off[v + 2] > k + 1 ? v + 1 : owner_of(out_off, n, k + 1);
+          vend = out_off[v + 1];
+          whole = true;
+          mn = INF;
+        }
+      }
+    }
   }
 }
 
@@ -280,6 +332,24 @@ static inline int grid_for(int64_t work) {
   if (b < 1) b = 1;
   if (b > 16384) b = 16384;
   return (int)b;
+}
+
+static void launch_wmin(bool f32, int32_t n, int32_t m, const int32_t *out_off,
+                        const int32_t *out_w, int32_t *out_wmin, hipStream_t stream) {
+  const int gc = grid_for(((int64_t)m + kWminChunk - 1) / kWminChunk);
+  if (f32) {
+    hipLaunchKernelGGL(wmin_fill_kernel<true>, dim3(grid_for(n)), dim3(256), 0, stream, n,
+                       out_wmin);
+    if (m > 0)
+      hipLaunchKernelGGL(wmin_kernel<true>, dim3(gc), dim3(256), 0, stream, out_off, out_w, n,
+                         m, out_wmin);
+  } else {
+    hipLaunchKernelGGL(wmin_fill_kernel<false>, dim3(grid_for(n)), dim3(256), 0, stream, n,
+                       out_wmin);
+    if (m > 0)
+      hipLaunchKernelGGL(wmin_kernel<false>, dim3(gc), dim3(256), 0, stream, out_off, out_w, n,
+                         m, out_wmin);
+  }
 }
 
 hipError_t launch_build(int32_t n, int32_t m, bool f32, const int32_t *src, const int32_t *dst,
@@ -313,12 +383,7 @@ hipError_t launch_build(int32_t n, int32_t m, bool f32, const int32_t *src, cons
                        m, in_src, in_w);
   }
   hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, in_off);
-  if (f32)
-    hipLaunchKernelGGL(wmin_kernel<true>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
-                       out_w, n, out_wmin);
-  else
-    hipLaunchKernelGGL(wmin_kernel<false>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
-                       out_w, n, out_wmin);
+  launch_wmin(f32, n, m, out_off, out_w, out_wmin, stream);
   return hipGetLastError();
 }
 
@@ -505,12 +570,7 @@ hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
                               hipStream_t stream) {
   hipLaunchKernelGGL(set_weights_kernel, dim3(grid_for(m)), dim3(256), 0, stream, w, in_eid, m,
                      out_w, in_w, c.out_eid, c.out_w);
-  if (f32)
-    hipLaunchKernelGGL(wmin_kernel<true>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
-                       out_w, n, out_wmin);
-  else
-    hipLaunchKernelGGL(wmin_kernel<false>, dim3(grid_for(n)), dim3(256), 0, stream, out_off,
-                       out_w, n, out_wmin);
+  launch_wmin(f32, n, m, out_off, out_w, out_wmin, stream);
   if (c.vid)
     hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c.vid,
                        out_wmin, n, c.out_wmin);

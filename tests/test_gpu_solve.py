@@ -104,6 +104,28 @@ def test_edge_cases(sp):
     run_case(sp, fan + 2, src, dst, w, 0, "in-star")
 
 
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_builder_gaps_and_long_lists(sp, dtype):
+    """Offsets and minimum out-weights where long runs of vertices have no
+    edges (before, between and after the used ids) and out-lists cross many
+    fixed-size position chunks of the builder, the lightest edge anywhere in
+    a list."""
+    rng = np.random.default_rng(61)
+    n = 300000
+    used = np.array([5, 6, 150000, 150001, 299990], np.int32)
+    degs = [1000, 3, 700, 1, 257]
+    src = np.concatenate([np.full(d, u, np.int32) for u, d in zip(used, degs)])
+    dst = used[rng.integers(0, len(used), len(src))].astype(np.int32)
+    if dtype == "i32":
+        w = rng.integers(2, 1000, len(src)).astype(np.int32)
+        w[rng.integers(0, len(src), 4)] = 1
+    else:
+        w = (rng.integers(2, 2**24, len(src)) * 2.0 ** -24).astype(np.float32)
+        w[rng.integers(0, len(src), 4)] = 2.0 ** -24
+    for source in (5, 299990):
+        run_case(sp, n, src, dst, w, source, "gaps-%s-%d" % (dtype, source))
+
+
 @pytest.mark.parametrize("order", ["auto", "degree"])
 @pytest.mark.parametrize("dtype", ["i32", "f32"])
 def test_random_small(sp, dtype, order):
