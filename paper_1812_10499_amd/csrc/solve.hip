@@ -872,9 +872,12 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
           int32_t m = V::INF;
           int32_t j = 0;
           if (deg > 0) {
-            // the lightest in-edge alone first: its tail usually decides m
+            // the lightest in-edge alone first: its tail usually decides m.
+            // Round 1 reads the initial C: 0 for every vertex but the
+            // source, and the source is no tail of an undiscovered vertex
+            // (its out-edges were relaxed), so no gather is needed.
             const int32_t v0 = rec2.y, w0 = rec2.z;
-            const int32_t c0 = Cg[v0];
+            const int32_t c0 = (r == 1) ? 0 : Cg[v0];
             if (c0 != V::INF) m = V::add(kmax(c0, mdi), w0);
             j = (V::add(mdi, w0) >= m) ? deg : 1;
           }
