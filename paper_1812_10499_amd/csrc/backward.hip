@@ -120,7 +120,7 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
   int lmax = 0;
   for (int ins = blockIdx.x; ins < a.num_inst; ins += gridDim.x) {
     const InstDev id = a.insts[ins];
-    const GraphDev &G = a.graphs[id.graph];
+    const GraphDev G = a.graphs[id.graph];  // by value: its fields stay in registers
     const int32_t sb = id.sbase;
     int32_t *V = a.lv_v + sb, *LE = a.lv_i + sb;
     if (tid == 0) {

@@ -53,7 +53,9 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       src = id.source;
       n = id.n;
     }
-    const GraphDev &G = graph_of<BATCH>(a, gi);
+    // by value: the fields stay in registers rather than being reloaded
+    // from the graph table after every store
+    const GraphDev G = graph_of<BATCH>(a, gi);
     const bool lc = G.lc != 0;
     int32_t tgt = BATCH ? -1 : a.target;
     if (G.rank) {
