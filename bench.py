@@ -461,26 +461,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic,
-                     "kernel": round_kernel_name(G),
+                     "kernel": G.kernel,
                      "kernel_ms": round(k_ms, 4), "algorithmic_bytes": alg_bytes,
                      "traffic_gbps": (round(traffic / (k_ms * 1e-3) / 1e9, 1)
                                       if traffic is not None else None)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-
-
-def round_kernel_name(G):
-    """The kernel a single solve of G runs under the default launch
-    geometry: at most 4096 vertices, the LDS solver; low degree spread
-    (deg_max * n < 3m) under C scope OPEN, one workgroup per solve; else
-    the persistent grid kernel."""
-    c = G.csr
-    if c.n <= 4096:
-        return "small_rounds_kernel"
-    if c.m > 0 and c.deg_max * c.n < 3 * c.m and G.effective_scope == "open":
-        return "wg_rounds_kernel"
-    return "rounds_kernel"
 
 
 if __name__ == "__main__":

@@ -57,7 +57,7 @@ typedef enum {
   SSSP_ERR_OVERFLOW = 4, /* int32: (n-1) * w_max >= INT32_MAX */
   SSSP_ERR_NOMEM = 5,    /* workspace allocation failed */
   SSSP_ERR_HIP = 6,      /* a HIP runtime call failed */
-  SSSP_ERR_INTERNAL = 7  /* round watchdog tripped (rounds > n + 1) */
+  SSSP_ERR_INTERNAL = 7  /* round watchdog tripped (rounds > n + 1, see sssp_check) */
 } sssp_status;
 
 /*
@@ -191,9 +191,34 @@ typedef struct {
   const int32_t *s_vrec;
 } sssp_csr;
 
+/*
+ * What the AUTO settings of a graph resolve to, for its single solves on the
+ * calling device under that device's default launch geometry
+ * (sssp_set_launch): the C scope (SSSP_SCOPE_OPEN or SSSP_SCOPE_ALL), the
+ * relax step (SSSP_RELAX_SETTING or SSSP_RELAX_CORRECTING), the bucket width
+ * as a key (INF when there is none or the relax is label-setting) and the
+ * round kernel that runs.
+ */
+typedef enum {
+  SSSP_KERNEL_PERSISTENT = 0, /* rounds_kernel: cooperative grid, grid barriers */
+  SSSP_KERNEL_WORKGROUP = 1,  /* wg_rounds_kernel: one workgroup per solve */
+  SSSP_KERNEL_SMALL = 2       /* small_rounds_kernel: one workgroup, state in LDS */
+} sssp_kernel;
+
+typedef struct {
+  int32_t scope;
+  int32_t relax;
+  int32_t delta;
+  int32_t kernel; /* sssp_kernel */
+} sssp_policy;
+
+/* Fills *out for graph g (host pointers); SSSP_ERR_ARG on a malformed graph. */
+sssp_status sssp_policy_of(const sssp_csr *g, sssp_policy *out);
+
 /* Per-solve counters (host struct). */
 typedef struct {
-  int32_t rounds;            /* rounds of the method (non-empty frontiers) */
+  int32_t rounds;            /* rounds of the method: runs of step (A), each
+                                followed by the loop test (see sssp_solve) */
   int32_t settled;           /* reachable vertices (Dijkstra's removeMin count) */
   int64_t relaxed_edges;     /* out-edges of fixed vertices relaxed (once each) */
   int64_t scanned_in_edges;  /* in-edges the lower-bound step covers: the in-degree
@@ -253,8 +278,14 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream);
  *   (C) for y in O: m_y = min over in-edges (v,y,w), v not fixed, of
  *       max(C[v], minD) + w;  C'[y] = max(C[y], minD, min(D[y], m_y))
  *       (all reads of C before any write);
- *   (D) fix y iff C'[y] >= D[y] or D[y] <= thr; stop when (A) leaves O
- *       empty.  rounds <= settled.
+ *   (D) fix y iff C'[y] >= D[y] or D[y] <= thr.
+ * The loop test (is a discovered vertex still not fixed?) follows step (A),
+ * as the test of Fig. 6 follows its relax step: the solve stops when (A)
+ * leaves O empty, and stats->rounds counts the runs of (A).  Under
+ * label-setting relax each run relaxes a non-empty frontier (the last one
+ * the final frontier); under label-correcting relax the last run's relax
+ * set can be empty, when every vertex the previous round fixed was already
+ * relaxed at its final D.  rounds <= settled.
  */
 sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
                        sssp_stats *stats, void *stream);
@@ -405,6 +436,27 @@ sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int3
                           const int32_t *inst_source, int32_t num_inst, sssp_plan_kind kind,
                           void *cost, int32_t *pred, int32_t reps, sssp_launch *best,
                           double *best_ms, void *stream);
+
+/*
+ * Status of the solves queued so far: waits for `stream`, then returns
+ * SSSP_ERR_INTERNAL if any solve on the calling device since the previous
+ * sssp_check (direct calls and plan runs, on any stream) ended with a fault
+ * status -- the round watchdog tripped (rounds beyond n + 1, or beyond the
+ * sssp_set_round_limit limit), or a float32 equal-cost vertex got no parent
+ * -- and clears that condition; SSSP_OK otherwise.  Calls given a stats
+ * pointer report the same condition in their own return value; this call
+ * is how the others (stats == NULL, plan runs) learn of it.
+ */
+sssp_status sssp_check(void *stream);
+
+/*
+ * Diagnostics: caps the round watchdog of every later solve and plan
+ * creation at `limit` rounds (when below the solve's own limit of n + 1);
+ * 0 restores the default.  A solve that reaches the cap stops there with
+ * incomplete results and reports SSSP_ERR_INTERNAL (through stats or
+ * sssp_check).  Process-wide; negative is SSSP_ERR_ARG.
+ */
+sssp_status sssp_set_round_limit(int32_t limit);
 
 /* Free the calling device's workspace cache (synchronizes the device). */
 sssp_status sssp_release_workspace(void);

@@ -104,20 +104,33 @@ def dijkstra(n, src, dst, w, source, target=None):
     return cost, settles.value
 
 
-def sp12(n, src, dst, w, source, variant):
+SP12_HOW = {0: "removeMin", 1: "pred", 2: "inWeight"}
+
+
+def sp12(n, src, dst, w, source, variant, sequence=False):
     """SP_1 (variant 1, Fig. 3) or SP_2 (variant 2, Fig. 4), or Dijkstra in
-    the same framework (variant 0).  Returns (cost, ops) with ops a dict of
-    remove_min, insert, adjust and fixed_by_r counts."""
+    the same framework (variant 0); the outer loop ends once the heap holds
+    no non-fixed vertex (the overloaded H.empty() of Section III).  Returns
+    (cost, ops) with ops a dict of remove_min, insert, adjust and fixed_by_r
+    counts; with sequence=True also the fix sequence as a list of
+    (vertex, how) pairs, how one of SP12_HOW's names."""
     k, w = _kind(w)
     src, dst = _i32(src), _i32(dst)
     cost = np.empty(n, dtype=w.dtype)
     ops = np.zeros(4, dtype=np.int64)
+    seq = np.empty(n, dtype=np.int32)
+    how = np.empty(n, dtype=np.int32)
     rc = _call("oracle_sp12_" + k, ctypes.c_int32(n), ctypes.c_int64(len(src)), _p(src),
-               _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int(variant), _p(cost), _p(ops))
+               _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int(variant), _p(cost), _p(ops),
+               _p(seq), _p(how))
     if rc != 0:
         raise ValueError("oracle_sp12 failed: %d" % rc)
-    return cost, dict(remove_min=int(ops[0]), insert=int(ops[1]), adjust=int(ops[2]),
-                      fixed_by_r=int(ops[3]))
+    o = dict(remove_min=int(ops[0]), insert=int(ops[1]), adjust=int(ops[2]),
+             fixed_by_r=int(ops[3]))
+    if not sequence:
+        return cost, o
+    fixes = [(int(v), SP12_HOW[int(h)]) for v, h in zip(seq, how) if v >= 0]
+    return cost, o, fixes
 
 
 def bellman_ford(n, src, dst, w, source):
@@ -211,7 +224,8 @@ MODE_LC = 4  # or-ed with MODE_ADOPTED / MODE_SCOPE_ALL: label-correcting relax
 def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=None,
               delta=None):
     """Run the round simulator.  Returns dict(cost, rounds, fixed_per_round,
-    relaxed_edges, scanned_in_edges, settled, violations).  With a target
+    scanned_per_round, relaxed_edges, scanned_in_edges, open_visits, settled,
+    violations).  With a target
     (modes 0 and 1) the rounds stop once the target is fixed.  delta (with
     MODE_LC): an open vertex joins the relax set only while D < minD + delta
     (None: no bound)."""
@@ -225,7 +239,8 @@ def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=
     cost = np.empty(n, dtype=w.dtype)
     cap = 4 * n + 8
     fpr = np.zeros(cap, dtype=np.int64)
-    stats = np.zeros(3, dtype=np.int64)
+    spr = np.zeros(cap, dtype=np.int64)
+    stats = np.zeros(4, dtype=np.int64)
     t = -1 if target is None else int(target)
     rounds = ctypes.c_int64(0)
     viol = ctypes.c_int64(0)
@@ -235,14 +250,15 @@ def round_sim(n, src, dst, w, source, mode=MODE_ADOPTED, true_cost=None, target=
     rc = _call("oracle_round_sim_" + k, ctypes.c_int32(n), ctypes.c_int64(len(src)), _p(src),
                _p(dst), _p(w), ctypes.c_int32(source), ctypes.c_int32(t), ctypes.c_int(mode),
                dl, _p(cost),
-               ctypes.byref(rounds), _p(fpr), ctypes.c_int64(cap), _p(stats),
+               ctypes.byref(rounds), _p(fpr), _p(spr), ctypes.c_int64(cap), _p(stats),
                _p(tc) if tc is not None else None, ctypes.byref(viol))
     if rc != 0:
         raise ValueError("oracle_round_sim failed: %d" % rc)
     r = rounds.value
     return dict(cost=cost, rounds=r, fixed_per_round=fpr[:r].copy(),
-                relaxed_edges=int(stats[0]), scanned_in_edges=int(stats[1]),
-                settled=int(stats[2]), violations=viol.value)
+                scanned_per_round=spr[:r].copy(), relaxed_edges=int(stats[0]),
+                scanned_in_edges=int(stats[1]), settled=int(stats[2]),
+                open_visits=int(stats[3]), violations=viol.value)
 
 
 def grad(g: CSR, sources, preds, gcoef):

@@ -12,10 +12,11 @@ from ._abi import (  # noqa: F401
     SSSP_ORDER_AUTO, SSSP_ORDER_DEGREE, SSSP_ORDER_INPUT, SSSP_RELAX_AUTO,
     SSSP_RELAX_CORRECTING, SSSP_RELAX_SETTING, SSSP_SCOPE_ALL, SSSP_SCOPE_AUTO,
     SSSP_SCOPE_OPEN, SSSP_PLAN_BATCH, SSSP_PLAN_SEQUENCE, Csr, Launch,
-    SSSPError, Stats, lib, sssp_backward, sssp_profile_enable, sssp_profile_read,
+    KERNELS, Policy, SSSPError, Stats, lib, sssp_backward, sssp_check, sssp_policy_of,
+    sssp_set_round_limit, sssp_profile_enable, sssp_profile_read,
     sssp_build_csr, sssp_build_csr_bytes, sssp_release_workspace, sssp_set_weights, sssp_solve,
     sssp_solve_batch, sssp_solve_target, sssp_strerror, sssp_set_launch, sssp_plan_create,
     sssp_plan_run, sssp_plan_stats, sssp_plan_destroy, sssp_autotune)
 from .graph import (  # noqa: F401
-    I32_INF, Graph, Plan, SSSPFunction, autotune, backward, batch_layout, set_launch,
-    shortest_paths, solve, solve_batch, solve_target)
+    I32_INF, Graph, Plan, SSSPFunction, autotune, backward, batch_layout, check,
+    set_launch, set_round_limit, shortest_paths, solve, solve_batch, solve_target)

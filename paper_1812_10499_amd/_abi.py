@@ -13,8 +13,7 @@ import os
 import torch  # noqa: F401  (load PyTorch's HIP runtime first: one runtime per process)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SSSP_LIBRARY selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("SSSP_LIBRARY") or os.path.join(_HERE, "libsssp.so")
+LIB_PATH = os.path.join(_HERE, "libsssp.so")
 
 SSSP_I32, SSSP_F32 = 0, 1
 SSSP_ORDER_AUTO, SSSP_ORDER_INPUT, SSSP_ORDER_DEGREE = 0, 1, 2
@@ -29,7 +28,9 @@ EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_s
            "sssp_solve_target", "sssp_solve_batch", "sssp_backward", "sssp_set_launch",
            "sssp_plan_create", "sssp_plan_run", "sssp_plan_stats", "sssp_plan_destroy",
            "sssp_autotune", "sssp_release_workspace", "sssp_strerror",
-           "sssp_profile_enable", "sssp_profile_read")
+           "sssp_profile_enable", "sssp_profile_read", "sssp_check", "sssp_set_round_limit",
+           "sssp_policy_of")
+KERNELS = {0: "rounds_kernel", 1: "wg_rounds_kernel", 2: "small_rounds_kernel"}
 
 
 class Csr(ctypes.Structure):
@@ -48,6 +49,11 @@ class Csr(ctypes.Structure):
                 ("s_in_off", ctypes.c_void_p), ("s_in_src", ctypes.c_void_p),
                 ("s_in_eid", ctypes.c_void_p), ("s_in_w", ctypes.c_void_p),
                 ("s_out_wmin", ctypes.c_void_p), ("s_vrec", ctypes.c_void_p)]
+
+
+class Policy(ctypes.Structure):
+    _fields_ = [("scope", ctypes.c_int32), ("relax", ctypes.c_int32),
+                ("delta", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -127,6 +133,12 @@ def lib():
         L.sssp_profile_read.argtypes = [ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
         L.sssp_profile_read.restype = ctypes.c_int
+        L.sssp_policy_of.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(Policy)]
+        L.sssp_policy_of.restype = ctypes.c_int
+        L.sssp_check.argtypes = [vp]
+        L.sssp_check.restype = ctypes.c_int
+        L.sssp_set_round_limit.argtypes = [i32]
+        L.sssp_set_round_limit.restype = ctypes.c_int
         L.sssp_strerror.argtypes = [ctypes.c_int]
         L.sssp_strerror.restype = ctypes.c_char_p
         del i64p
@@ -202,6 +214,20 @@ def sssp_profile_read():
     ms = ctypes.c_double(0.0)
     _check(lib().sssp_profile_read(ctypes.byref(n), ctypes.byref(ms)), "sssp_profile_read")
     return n.value, ms.value
+
+
+def sssp_policy_of(g: Csr) -> Policy:
+    p = Policy()
+    _check(lib().sssp_policy_of(ctypes.byref(g), ctypes.byref(p)), "sssp_policy_of")
+    return p
+
+
+def sssp_check(stream):
+    _check(lib().sssp_check(stream), "sssp_check")
+
+
+def sssp_set_round_limit(limit: int):
+    _check(lib().sssp_set_round_limit(int(limit)), "sssp_set_round_limit")
 
 
 def sssp_release_workspace():

@@ -43,6 +43,15 @@ struct DevWS {
 
 std::mutex g_mu;
 DevWS g_ws[64];
+int32_t g_round_limit = 0;  // sssp_set_round_limit: 0 is none
+
+// The watchdog's limit for a solve whose largest instance has n vertices:
+// n + 1 (rounds never exceed the reachable count), or a lower limit set for
+// diagnostics.
+int32_t round_limit(int32_t n) {
+  const int32_t lim = n + 1;
+  return (g_round_limit > 0 && g_round_limit < lim) ? g_round_limit : lim;
+}
 
 struct Guard {
   std::lock_guard<std::mutex> lk;
@@ -694,7 +703,7 @@ static sssp_status single_args(DevWS &ws, const sssp_csr *g, int32_t source, int
   a.num_inst = 1;
   a.source = source;
   a.total = g->n;
-  a.max_rounds = g->n + 1;
+  a.max_rounds = round_limit(g->n);
   a.D = (int32_t *)cost;
   a.target = target;
   a.scope_all = a.g.all;
@@ -809,7 +818,7 @@ static sssp_status batch_args(DevWS &ws, const sssp_csr *graphs, int32_t num_gra
   memset(&a, 0, sizeof(a));
   a.num_inst = num_inst;
   a.total = (int32_t)total;
-  a.max_rounds = max_n + 1;
+  a.max_rounds = round_limit(max_n);
   a.target = -1;
   a.D = (int32_t *)cost;
   for (int32_t i = 0; i < num_inst; ++i) {
@@ -1067,7 +1076,7 @@ static sssp_status plan_build(const sssp_csr *graphs, int32_t num_graphs,
       a.num_inst = 1;
       a.source = inst_source[i];
       a.total = g->n;
-      a.max_rounds = g->n + 1;
+      a.max_rounds = round_limit(g->n);
       a.D = (int32_t *)cost + hi[i].sbase;
       a.target = -1;
       a.scope_all = a.g.all;
@@ -1343,6 +1352,43 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
   HIPCHK(launch_backward(b, geo, goff, ginst, ebase, num_graphs, (int32_t)total_m, grad_w,
                          stream));
   HIPCHK(hipEventRecord(ws.last, stream));
+  return SSSP_OK;
+}
+
+sssp_status sssp_policy_of(const sssp_csr *g, sssp_policy *out) {
+  if (!csr_ok(g) || !out) return SSSP_ERR_ARG;
+  const bool f32 = g->dtype == SSSP_F32;
+  const int32_t inf = f32 ? 0x7f800000 : 0x7fffffff;
+  const bool all = scope_all_of(g), lc = relax_correcting(g);
+  out->scope = all ? SSSP_SCOPE_ALL : SSSP_SCOPE_OPEN;
+  out->relax = lc ? SSSP_RELAX_CORRECTING : SSSP_RELAX_SETTING;
+  out->delta = lc ? relax_delta(g) : inf;
+  Guard guard;
+  DevWS *wp;
+  sssp_status s;
+  if ((s = ws_for_current(&wp))) return s;
+  LaunchGeom geo;
+  RoundArgs a;
+  memset(&a, 0, sizeof(a));
+  if ((s = resolve_launch(*wp, f32, false, &wp->cfg, &geo, a, low_spread(g)))) return s;
+  // the choice launch_solve makes for a single solve
+  if (g->n <= geo.small_n) out->kernel = SSSP_KERNEL_SMALL;
+  else if (geo.wg && !all) out->kernel = SSSP_KERNEL_WORKGROUP;
+  else out->kernel = SSSP_KERNEL_PERSISTENT;
+  return SSSP_OK;
+}
+
+sssp_status sssp_check(void *stream) {
+  Guard guard;
+  int32_t f = 0;
+  HIPCHK(fault_flag_take(&f, (hipStream_t)stream));
+  return f ? SSSP_ERR_INTERNAL : SSSP_OK;
+}
+
+sssp_status sssp_set_round_limit(int32_t limit) {
+  if (limit < 0) return SSSP_ERR_ARG;
+  Guard guard;
+  g_round_limit = limit;
   return SSSP_OK;
 }
 

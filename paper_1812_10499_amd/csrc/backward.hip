@@ -1,5 +1,12 @@
 // Backward pass of the shortest-path costs with respect to edge weights.
 //
+// The source of an instance is the root of its tree whatever its pred entry
+// says: it is never taken as a child, and no edge into it gets a gradient.
+// Every other vertex has one parent entry, so a walk down from the root
+// meets each vertex at most once (a vertex on a parent cycle that avoids the
+// root is reachable from no vertex outside that cycle), and the level lists
+// never hold more than the instance's n entries.
+//
 // With cost_i[x] the weight sum along the pred-tree path from instance i's
 // source to x, L = sum_i sum_x g_i[x] * cost_i[x] has
 //   dL/dw[e] = sum_i [e == pred_i[head(e)]] * acc_i[head(e)],
@@ -18,6 +25,14 @@
 namespace sssp {
 
 constexpr int BBS = kBackBlock;
+
+// acc = 0 everywhere, so a vertex whose parent entry names an edge from
+// outside the tree contributes nothing
+__global__ void bw_zero_kernel(BackArgs a) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.total;
+       i += gridDim.x * blockDim.x)
+    a.acc[i] = 0.0f;
+}
 
 __global__ void bw_init_kernel(BackArgs a) {
   for (int i = threadIdx.x; i < a.num_inst; i += blockDim.x) {
@@ -46,7 +61,7 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
   while (s < e) {
     for (int b0 = s + bid * BBS; b0 < e; b0 += nb * BBS) {
       const int idx = b0 + tid;
-      int32_t x = 0, ins = 0, sb = 0, vx = 0, k0 = 0, k1 = 0;
+      int32_t x = 0, ins = 0, sb = 0, vx = 0, k0 = 0, k1 = 0, root = -1;
       const GraphDev *G = nullptr;
       uint32_t nch = 0;
       if (idx < e) {
@@ -54,12 +69,15 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
         ins = a.lv_i[idx];
         const InstDev id = a.insts[ins];
         sb = id.sbase;
+        root = id.source;
         G = &a.graphs[id.graph];
         vx = x - sb;
         k0 = G->u_out_off[vx];
         k1 = G->u_out_off[vx + 1];
-        for (int32_t k = k0; k < k1; ++k)
-          if (a.pred[sb + G->u_out_dst[k]] == k) ++nch;
+        for (int32_t k = k0; k < k1; ++k) {
+          const int32_t c = G->u_out_dst[k];
+          if (c != root && a.pred[sb + c] == k) ++nch;
+        }
       }
       uint64_t tot;
       const uint64_t ex = block_excl_scan64<BBS>((uint64_t)nch, scan, &tot);
@@ -70,7 +88,7 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
         if (idx < e && nch) {
           for (int32_t k = k0; k < k1; ++k) {
             const int32_t c = G->u_out_dst[k];
-            if (a.pred[sb + c] == k) {
+            if (c != root && a.pred[sb + c] == k) {
               a.lv_v[p] = sb + c;
               a.lv_i[p] = ins;
               ++p;
@@ -98,8 +116,8 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
       const int32_t sb = id.sbase, vy = y - sb;
       float acc = a.gcost[y];
       for (int32_t k = G.u_out_off[vy]; k < G.u_out_off[vy + 1]; ++k) {
-        const int32_t c = sb + G.u_out_dst[k];
-        if (a.pred[c] == k) acc = __fadd_rn(acc, a.acc[c]);
+        const int32_t lc = G.u_out_dst[k], c = sb + lc;
+        if (lc != id.source && a.pred[c] == k) acc = __fadd_rn(acc, a.acc[c]);
       }
       a.acc[y] = acc;
     }
@@ -139,8 +157,10 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
           const int32_t x = V[idx];
           k0 = G.u_out_off[x];
           k1 = G.u_out_off[x + 1];
-          for (int32_t k = k0; k < k1; ++k)
-            if (a.pred[sb + G.u_out_dst[k]] == k) ++nch;
+          for (int32_t k = k0; k < k1; ++k) {
+            const int32_t c = G.u_out_dst[k];
+            if (c != id.source && a.pred[sb + c] == k) ++nch;
+          }
         }
         uint64_t tot;
         const uint64_t ex = block_excl_scan64<BBS>((uint64_t)nch, scan, &tot);
@@ -149,7 +169,7 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
           if (idx < e && nch) {
             for (int32_t k = k0; k < k1; ++k) {
               const int32_t c = G.u_out_dst[k];
-              if (a.pred[sb + c] == k) V[p++] = c;
+              if (c != id.source && a.pred[sb + c] == k) V[p++] = c;
             }
           }
           __syncthreads();
@@ -172,7 +192,7 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
         float acc = a.gcost[sb + y];
         for (int32_t k = G.u_out_off[y]; k < G.u_out_off[y + 1]; ++k) {
           const int32_t c = G.u_out_dst[k];
-          if (a.pred[sb + c] == k) acc = __fadd_rn(acc, a.acc[sb + c]);
+          if (c != id.source && a.pred[sb + c] == k) acc = __fadd_rn(acc, a.acc[sb + c]);
         }
         a.acc[sb + y] = acc;
       }
@@ -200,8 +220,8 @@ __global__ void bw_grad_kernel(BackArgs a, const int32_t *goff, const int32_t *g
     const int32_t y = G.u_out_dst[e];
     float sum = 0.0f;
     for (int32_t j = goff[lo]; j < goff[lo + 1]; ++j) {
-      const int32_t sb = a.insts[ginst[j]].sbase;
-      if (a.pred[sb + y] == e) sum = __fadd_rn(sum, a.acc[sb + y]);
+      const InstDev id = a.insts[ginst[j]];
+      if (y != id.source && a.pred[id.sbase + y] == e) sum = __fadd_rn(sum, a.acc[id.sbase + y]);
     }
     grad_w[q] = sum;
   }
@@ -211,6 +231,11 @@ hipError_t launch_backward(const BackArgs &a, const LaunchGeom &geo, const int32
                            const int32_t *ginst, const int32_t *ebase, int32_t num_graphs,
                            int32_t total_m, float *grad_w, hipStream_t stream) {
   hipError_t e;
+  {
+    int zb = (a.total + 255) / 256;
+    if (zb > 4096) zb = 4096;
+    hipLaunchKernelGGL(bw_zero_kernel, dim3(zb < 1 ? 1 : zb), dim3(256), 0, stream, a);
+  }
   hipLaunchKernelGGL(bw_init_kernel, dim3(1), dim3(256), 0, stream, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (geo.wg) {

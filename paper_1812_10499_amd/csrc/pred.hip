@@ -18,6 +18,12 @@
 
 namespace sssp {
 
+// Fault flag of this device: the emit pass of any solve whose rounds tripped
+// the watchdog (or whose level rule left a vertex without a parent) sets it;
+// fault_flag_take reads and clears it.  One word per device, in the code
+// object's own memory, so plan replays set it too.
+__device__ int32_t g_fault_flag;
+
 template <class V, bool BATCH>
 __global__ __launch_bounds__(256) void emit_kernel(RoundArgs a, int32_t *pred, int32_t *degen,
                                                    int32_t *lvl, long long *istat) {
@@ -35,6 +41,7 @@ __global__ __launch_bounds__(256) void emit_kernel(RoundArgs a, int32_t *pred, i
   // renumbered graph's keys are gathered through rank
   const int uy = blockIdx.x * blockDim.x + threadIdx.x;  // the caller's id
   long long c_settled = 0, c_relaxed = 0;
+  if (uy == 0 && inst == 0 && ld_relaxed(&a.ctl->status) != 0) atomicOr(&g_fault_flag, 1);
   if (uy < n) {
     const int32_t y = G.rank ? G.rank[uy] : uy;  // solver id
     const unsigned long long k = a.D64[sb + y];
@@ -76,12 +83,12 @@ template <class V, bool BATCH>
 __global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *pred,
                                                           const int32_t *degen, int32_t *lvl,
                                                           int32_t *flag) {
-  __shared__ int changed;
   const int nd = ld_relaxed(&a.ctl->deg_count);
   if (nd == 0) return;
+  // every level adds at least one vertex or ends the loop, so it runs at
+  // most nd + 1 times; the loop test is a block-wide vote, taken by every
+  // thread at the same barrier
   for (int lv = 0;; ++lv) {
-    if (threadIdx.x == 0) changed = 0;
-    __syncthreads();
     for (int q = threadIdx.x; q < nd; q += blockDim.x) {
       flag[q] = 0;
       const int32_t gy = degen[q];
@@ -108,14 +115,14 @@ __global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *
       }
     }
     __syncthreads();
+    int changed = 0;
     for (int q = threadIdx.x; q < nd; q += blockDim.x) {
       if (flag[q]) {
         lvl[degen[q]] = lv + 1;
         changed = 1;
       }
     }
-    __syncthreads();
-    if (!changed) break;
+    if (!__syncthreads_or(changed)) break;
   }
   for (int q = threadIdx.x; q < nd; q += blockDim.x) {
     const int32_t gy = degen[q];
@@ -147,7 +154,10 @@ __global__ __launch_bounds__(1024) void pred_degen_kernel(RoundArgs a, int32_t *
   __syncthreads();
   for (int q = threadIdx.x; q < nd; q += blockDim.x) {
     pred[degen[q]] = flag[q];
-    if (flag[q] < 0) a.ctl->status = 7;
+    if (flag[q] < 0) {
+      a.ctl->status = 7;
+      atomicOr(&g_fault_flag, 1);
+    }
   }
 }
 
@@ -167,6 +177,20 @@ static hipError_t launch_emit_t(const RoundArgs &a, int32_t *pred, long long *is
     void *dargs[] = {&arg, &p, &degen, &lvl, &flag};
     if ((e = launch_kernel(L, (const void *)pred_degen_kernel<V, BATCH>, dim3(1), dim3(1024),
                            dargs, false)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t fault_flag_take(int32_t *out, hipStream_t stream) {
+  int32_t v = 0;
+  hipError_t e;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+  if ((e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_fault_flag), sizeof(v))) != hipSuccess) return e;
+  *out = v;
+  if (v) {
+    const int32_t zero = 0;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_fault_flag), &zero, sizeof(zero))) != hipSuccess)
       return e;
   }
   return hipSuccess;

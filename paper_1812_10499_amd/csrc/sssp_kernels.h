@@ -193,6 +193,9 @@ hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                         const KernelTimer *timer, Launcher &L);
 hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                        const LaunchGeom &geo, long long *istat, int32_t max_n, Launcher &L);
+// waits for `stream`, then reads (*out: 0 or 1) and clears the device's
+// fault flag, which the emit pass sets for a solve whose status is non-zero
+hipError_t fault_flag_take(int32_t *out, hipStream_t stream);
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
 // every instance's rounds in a workgroup of its own (C scope OPEN), then the emit pass
 hipError_t launch_wg(bool f32, bool batch, const RoundArgs &a, int32_t *pred,

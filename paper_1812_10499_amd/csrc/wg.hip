@@ -99,7 +99,7 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
     for (;;) {
       if (tgt >= 0 && s.target_hit) break;  // the frontier that fixed it is not relaxed
       ++r;
-      if (r > n + 1) {
+      if (r > n + 1 || r > a.max_rounds) {
         status = 7;
         break;
       }

@@ -94,14 +94,27 @@ class Graph:
             raise ValueError("scope must be one of %s" % sorted(SCOPES))
         self.csr.scope = SCOPES[value]
 
+    def policy(self) -> dict:
+        """What the library resolves this graph's AUTO settings to (asked of
+        the library: sssp_policy_of): scope, relax, delta (None: no bound,
+        or label-setting) and the round kernel of a single solve under the
+        device's current default launch geometry."""
+        p = _abi.sssp_policy_of(self.csr)
+        if p.relax != SSSP_RELAX_CORRECTING or p.delta == (
+                0x7f800000 if self.dtype == SSSP_F32 else I32_INF):
+            delta = None
+        elif self.dtype == SSSP_F32:
+            delta = float(np.array([p.delta], np.int32).view(np.float32)[0])
+        else:
+            delta = int(p.delta)
+        return dict(scope="all" if p.scope == SSSP_SCOPE_ALL else "open",
+                    relax="correcting" if p.relax == SSSP_RELAX_CORRECTING else "setting",
+                    delta=delta, kernel=_abi.KERNELS[p.kernel])
+
     @property
     def effective_scope(self) -> str:
-        """The scope solves run: "auto" is "all" when the largest total
-        degree is at least 3m/n."""
-        if self.csr.scope == SSSP_SCOPE_AUTO:
-            c = self.csr
-            return "all" if c.m > 0 and c.deg_max * c.n >= 3 * c.m else "open"
-        return "all" if self.csr.scope == SSSP_SCOPE_ALL else "open"
+        """The scope solves run ("auto" resolved by the library)."""
+        return self.policy()["scope"]
 
     @property
     def relax(self) -> str:
@@ -114,29 +127,21 @@ class Graph:
             raise ValueError("relax must be one of %s" % sorted(RELAXES))
         self.csr.relax = RELAXES[value]
 
-    def _auto_correcting(self) -> bool:
-        c = self.csr
-        return c.m > 0 and c.deg_max * c.n < 3 * c.m and c.w_max >= 16.0 * c.w_min
-
     @property
     def effective_relax(self) -> str:
-        """The relax step solves run: "auto" is "correcting" on graphs of low
-        degree spread (deg_max * n < 3m) and wide weight spread (w_max >= 16
-        w_min), else "setting"."""
-        if self.csr.relax == SSSP_RELAX_AUTO:
-            return "correcting" if self._auto_correcting() else "setting"
-        return "correcting" if self.csr.relax == SSSP_RELAX_CORRECTING else "setting"
+        """The relax step solves run ("auto" resolved by the library)."""
+        return self.policy()["relax"]
 
     @property
     def effective_delta(self):
         """The bucket width label-correcting solves use (None: no bound, or
-        label-setting): under "auto", 0.4 w_max (int32: truncated, at least 1)."""
-        if self.effective_relax != "correcting":
-            return None
-        if self.csr.relax == SSSP_RELAX_AUTO:
-            d = 0.4 * self.csr.w_max
-            return float(np.float32(d)) if self.dtype == SSSP_F32 else max(1, int(d))
-        return self.delta
+        label-setting), as the library resolves it."""
+        return self.policy()["delta"]
+
+    @property
+    def kernel(self) -> str:
+        """The round kernel a single solve of this graph runs now."""
+        return self.policy()["kernel"]
 
     @property
     def delta(self):
@@ -320,6 +325,17 @@ def autotune(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source: Se
                                   PLAN_KINDS[kind], cost.data_ptr(), pred.data_ptr(), reps,
                                   _stream())
     return best.as_dict(), ms
+
+
+def check():
+    """Waits for the current stream; raises SSSPError (SSSP_ERR_INTERNAL) if
+    a solve since the last check on this device hit the round watchdog."""
+    _abi.sssp_check(_stream())
+
+
+def set_round_limit(limit: int = 0):
+    """Diagnostics: cap the round watchdog of later solves (0: the default)."""
+    _abi.sssp_set_round_limit(limit)
 
 
 def set_launch(launch=None):

@@ -27,7 +27,8 @@ def oracle_solution(n, src, dst, w, source, scope="open", relax="setting", delta
     sim = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(scope, relax), delta=delta)
     assert np.array_equal(sim["cost"], cost)
     return dict(cost=cost, pred=pred, settles=settles, rounds=sim["rounds"],
-                relaxed=sim["relaxed_edges"], scanned=sim["scanned_in_edges"], csr=O)
+                relaxed=sim["relaxed_edges"], scanned=sim["scanned_in_edges"],
+                open_visits=sim["open_visits"], csr=O)
 
 
 def assert_same_solution(cost, pred, stats, ref, label=""):
@@ -46,6 +47,7 @@ def assert_same_solution(cost, pred, stats, ref, label=""):
         assert stats["settled"] == ref["settles"], (label, stats, ref["settles"])
         assert stats["relaxed_edges"] == ref["relaxed"], (label, stats, ref["relaxed"])
         assert stats["scanned_in_edges"] == ref["scanned"], (label, stats, ref["scanned"])
+        assert stats["open_visits"] == ref["open_visits"], (label, stats, ref["open_visits"])
 
 
 def sync():

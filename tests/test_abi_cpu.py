@@ -36,7 +36,8 @@ def test_header_declares_the_abi():
                             "sssp_plan_run", "sssp_plan_stats", "sssp_plan_destroy",
                             "sssp_autotune",
                             "sssp_release_workspace", "sssp_strerror",
-                            "sssp_profile_enable", "sssp_profile_read"])
+                            "sssp_profile_enable", "sssp_profile_read", "sssp_check",
+                            "sssp_set_round_limit", "sssp_policy_of"])
 
 
 def test_library_exports_every_declared_symbol(sp):
@@ -81,6 +82,13 @@ def _status(fn):
     except Exception as e:  # SSSPError
         return e.status
     return 0
+
+
+def test_round_limit_argument(sp):
+    with pytest.raises(sp.SSSPError) as e:
+        sp.sssp_set_round_limit(-1)
+    assert e.value.status == sp.SSSP_ERR_ARG
+    sp.sssp_set_round_limit(0)
 
 
 def test_host_argument_errors(sp):

@@ -45,6 +45,7 @@ def check_batch(sp, graphs, glist, inst_graph, inst_source, label):
         assert st["settled"] == ref["settles"], (label, i)
         assert st["relaxed_edges"] == ref["relaxed"], (label, i)
         assert st["scanned_in_edges"] == ref["scanned"], (label, i)
+        assert st["open_visits"] == ref["open_visits"], (label, i)
         # identical to the single solve of the same instance
         c1, p1, st1 = sp.solve(graphs[gi], s, with_pred=True, with_stats=True)
         sync()
@@ -153,6 +154,7 @@ def test_batch_more_instances_than_lds_slots(sp):
         assert np.array_equal(p[sl], ref["pred"]), i
         assert stats[i]["rounds"] == ref["rounds"], i
         assert stats[i]["scanned_in_edges"] == ref["scanned"], i
+        assert stats[i]["open_visits"] == ref["open_visits"], i
 
 
 def grad_reference(glist, graphs_np_csr, inst_graph, inst_source, preds, gco, bases):

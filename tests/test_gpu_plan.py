@@ -64,6 +64,7 @@ def check_against_oracle(sp, case, cost, pred, stats, label):
             assert st["settled"] == ref["settles"], (label, i)
             assert st["relaxed_edges"] == ref["relaxed"], (label, i)
             assert st["scanned_in_edges"] == ref["scanned"], (label, i)
+            assert st["open_visits"] == ref["open_visits"], (label, i)
 
 
 @pytest.mark.parametrize("kind", ["batch", "sequence"])

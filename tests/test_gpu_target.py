@@ -42,6 +42,7 @@ def check_target(sp, G, n, src, dst, w, source, target, label):
     assert st["settled"] == ref["settled"], (label, st, ref["settled"])
     assert st["relaxed_edges"] == ref["relaxed_edges"], (label, st, ref["relaxed_edges"])
     assert st["scanned_in_edges"] == ref["scanned_in_edges"], (label, st, ref["scanned_in_edges"])
+    assert st["open_visits"] == ref["open_visits"], (label, st, ref["open_visits"])
     return st
 
 

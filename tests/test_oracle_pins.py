@@ -152,6 +152,152 @@ def test_worked_example_costs_pred_rounds():
         assert r["cost"].tolist() == ex["cost"]
         assert r["rounds"] == 3 and r["fixed_per_round"].tolist() == [2, 2, 0]
         assert r["violations"] == 0
+        # The step-(C) work, counted as every in-edge of every vertex the step
+        # covers (in-degrees: v1 1, v2 2, v3 3, v4 2).  Scope OPEN covers
+        # O = {v1, v2} in round 1 and O = {v3, v4} in round 2: [3, 5, 0], and
+        # 4 open visits.  Scope ALL also covers the undiscovered non-fixed
+        # vertices, v3 and v4 in round 1 (their C rises to 5 and 4, which
+        # changes no fix here): [8, 5, 0].
+        assert r["scanned_per_round"].tolist() == [3, 5, 0]
+        assert r["scanned_in_edges"] == 8 and r["open_visits"] == 4
+        a = oracle.round_sim(n, src, dst, w, s, mode=oracle.MODE_SCOPE_ALL, true_cost=c)
+        assert a["rounds"] == 3 and a["fixed_per_round"].tolist() == [2, 2, 0]
+        assert a["scanned_per_round"].tolist() == [8, 5, 0]
+        assert a["scanned_in_edges"] == 13 and a["open_visits"] == 4
+        assert a["relaxed_edges"] == r["relaxed_edges"] == 8
+
+
+def test_worked_example_sp12_narratives():
+    """The narratives of Sections III and IV run SP_1 and SP_2 on the worked
+    example.  SP_1: v0 is removed; v1 is fixed when pred[1] reaches 0; v2 is
+    removed next; exploring it fixes v4 (pred 0), and exploring v4 fixes v3
+    (pred 0).  SP_2: the same start, but exploring v2 fixes v3 by Lemma
+    inWeight (8 <= d + inWeight[3] = 2 + 6) before v4 (pred 0).  Both stop
+    with every vertex fixed: two removeMin calls (v0, v2), the stale heap
+    entries of v3 and v4 never removed (the overloaded H.empty()), four
+    insertions (v0, then v2, v3, v4 from Q), no adjustment."""
+    for ex, src, dst, w in _worked_graphs():
+        n, s = ex["n"], ex["source"]
+        c1, o1, f1 = oracle.sp12(n, src, dst, w, s, 1, sequence=True)
+        c2, o2, f2 = oracle.sp12(n, src, dst, w, s, 2, sequence=True)
+        assert c1.tolist() == c2.tolist() == ex["cost"]
+        assert f1 == [(0, "removeMin"), (1, "pred"), (2, "removeMin"), (4, "pred"), (3, "pred")]
+        assert f2 == [(0, "removeMin"), (1, "pred"), (2, "removeMin"), (3, "inWeight"),
+                      (4, "pred")]
+        for o in (o1, o2):
+            assert o == dict(remove_min=2, insert=4, adjust=0, fixed_by_r=3)
+        # Dijkstra in the same framework removes all five vertices
+        c0, o0 = oracle.sp12(n, src, dst, w, s, 0)
+        assert c0.tolist() == ex["cost"] and o0["remove_min"] == 5
+
+
+def _scope_all_graph():
+    """Vertices 0 (source), u = 1, y = 2, a = 3, b = 4, c = 5, z = 6; edges
+    0->y (10), u->y (1), 0->a (1), a->b (1), b->c (1), y->z (1).  u has no
+    in-edge, so it is never discovered."""
+    src = np.array([0, 1, 0, 3, 4, 2], np.int32)
+    dst = np.array([2, 2, 3, 4, 5, 6], np.int32)
+    w = np.array([10, 1, 1, 1, 1, 1], np.int32)
+    return 7, src, dst, w
+
+
+def test_scope_all_round_semantics():
+    """Step 4 of SP_4 raises C of every non-fixed vertex (Section VI); the
+    adopted round's scope OPEN raises it for the discovered ones only.
+    Worked by hand on _scope_all_graph (D: y 10, a 1, b 2, c 3, z 11):
+    OPEN: round 1 fixes a (minD 1; y's in-edge from the undiscovered u holds
+      m_y = max(C[u] = 0, minD) + 1 = 2 < 10); round 2 fixes b (C[y] = 3);
+      round 3 fixes c and, since c has no out-edge, thr = min(10 + 1, 3 +
+      inf) = 11 >= D[y], also y; round 4 fixes z; round 5 relaxes z and finds
+      nothing open.  5 rounds, fixed [1, 1, 2, 1, 0].
+    ALL: round 1 is the same for O = {y, a}, and the undiscovered vertices
+      get C' = max(C, minD, m): u has no in-edge, so C[u] = inf; b, c, z get
+      2.  Round 2 reads C[u] = inf, so m_y = inf and C'[y] = D[y] = 10: y is
+      fixed with b.  Round 3 relaxes y and b (z: D 11, c: D 3) and fixes both
+      (z's only in-edge has a fixed tail; c is the argmin).  Round 4 finds
+      nothing open.  4 rounds, fixed [1, 2, 2, 0].
+    Scanned in-edges (every in-edge of every covered vertex; in-degrees
+    u 0, y 2, a 1, b 1, c 1, z 1): OPEN 3 + 3 + 3 + 1 = 10, one per round
+    [3, 3, 3, 1, 0]; ALL (O, then the undiscovered vertices): round 1
+    3 + 3, round 2 3 + 2, round 3 2 + 0: [6, 5, 2, 0] = 13.  Open visits:
+    OPEN 2 + 2 + 2 + 1 = 7, ALL 2 + 2 + 2 = 6."""
+    n, src, dst, w = _scope_all_graph()
+    c, settles = oracle.dijkstra(n, src, dst, w, 0)
+    assert c.tolist() == [0, I32_INF, 10, 1, 2, 3, 11] and settles == 6
+    op = oracle.round_sim(n, src, dst, w, 0, mode=oracle.MODE_ADOPTED, true_cost=c)
+    al = oracle.round_sim(n, src, dst, w, 0, mode=oracle.MODE_SCOPE_ALL, true_cost=c)
+    for r in (op, al):
+        assert np.array_equal(r["cost"], c) and r["violations"] == 0
+        assert r["relaxed_edges"] == 5 and r["settled"] == 6
+    assert op["rounds"] == 5 and op["fixed_per_round"].tolist() == [1, 1, 2, 1, 0]
+    assert al["rounds"] == 4 and al["fixed_per_round"].tolist() == [1, 2, 2, 0]
+    assert op["scanned_per_round"].tolist() == [3, 3, 3, 1, 0]
+    assert al["scanned_per_round"].tolist() == [6, 5, 2, 0]
+    assert op["scanned_in_edges"] == 10 and al["scanned_in_edges"] == 13
+    assert op["open_visits"] == 7 and al["open_visits"] == 6
+
+
+def test_scanned_and_open_visits_closed_forms():
+    """Step (C)'s work on shapes where it has a closed form.
+    A path 0 -> 1 -> ... -> k: round j (1..k) has O = {j} with in-degree 1,
+    so OPEN scans k in-edges with k open visits; ALL also covers the
+    undiscovered j+1..k in round j, k - j + 1 vertices of in-degree 1 each,
+    so it scans k + (k-1) + ... + 1 = k(k+1)/2.
+    A star with L leaves: round 1 has O = all leaves (in-degree 1 each), so
+    L scanned and L visits in both scopes (nothing is undiscovered).
+    A complete bipartite layer: the source feeds p middle vertices, each
+    feeding all q sinks; in round 2 the q sinks have in-degree p each, and a
+    sink with a parallel edge counts it twice."""
+    for k in (1, 2, 7, 30):
+        src = np.arange(k, dtype=np.int32)
+        dst = src + 1
+        w = np.full(k, 3, np.int32)
+        op = oracle.round_sim(k + 1, src, dst, w, 0)
+        al = oracle.round_sim(k + 1, src, dst, w, 0, mode=oracle.MODE_SCOPE_ALL)
+        assert op["scanned_in_edges"] == k and op["open_visits"] == k
+        assert op["scanned_per_round"].tolist() == [1] * k + [0]
+        assert al["scanned_in_edges"] == k * (k + 1) // 2 and al["open_visits"] == k
+        assert al["scanned_per_round"].tolist() == list(range(k, 0, -1)) + [0]
+    for leaves in (1, 5, 100):
+        src = np.zeros(leaves, np.int32)
+        dst = np.arange(1, leaves + 1, dtype=np.int32)
+        w = np.arange(1, leaves + 1, dtype=np.int32)[::-1].copy()
+        for mode in (oracle.MODE_ADOPTED, oracle.MODE_SCOPE_ALL):
+            r = oracle.round_sim(leaves + 1, src, dst, w, 0, mode=mode)
+            assert r["scanned_in_edges"] == leaves and r["open_visits"] == leaves
+    p, q = 3, 4
+    src = [0] * p + [1 + i for i in range(p) for _ in range(q)] + [1]
+    dst = [1 + i for i in range(p)] + [1 + p + j for _ in range(p) for j in range(q)] + [1 + p]
+    src, dst = np.array(src, np.int32), np.array(dst, np.int32)
+    w = np.full(len(src), 2, np.int32)
+    r = oracle.round_sim(1 + p + q, src, dst, w, 0)
+    # round 1: the p middles (in-degree 1); round 2: the q sinks (p each, one
+    # with an extra parallel edge)
+    assert r["scanned_per_round"].tolist() == [p, p * q + 1, 0]
+    assert r["open_visits"] == p + q
+
+
+def test_label_correcting_ending():
+    """The loop test follows each run of step (A), as Fig. 6's test follows
+    its relax step, and rounds counts the runs of (A).  Worked by hand on
+    0->a (1), 0->y (3), u->y (1), a->0 (1) (vertices 0, a = 1, y = 2, u = 3;
+    u is never discovered): round 1 relaxes 0 (D[a] = 1, D[y] = 3), minD 1,
+    thr = min(1 + 1, 3 + inf) = 2; a is fixed, y survives (m_y = max(C[u],
+    1) + 1 = 2 < 3).  Label-correcting: y joins the relax set (D = 3 <
+    minD + delta), so round 2 relaxes a (its edge to the fixed 0 changes
+    nothing) and y (no out-edge) at D = 3; y is then fixed (minD 3).  Round
+    3's relax set is empty (y was relaxed at its final D) and O is empty:
+    that run of (A) is the loop test's, and counts.  Label-setting: round 3
+    relaxes y.  Both: 3 rounds, fixed [1, 1, 0], relaxed edges 3."""
+    src = np.array([0, 0, 3, 1], np.int32)
+    dst = np.array([1, 2, 2, 0], np.int32)
+    w = np.array([1, 3, 1, 1], np.int32)
+    for scope in (oracle.MODE_ADOPTED, oracle.MODE_SCOPE_ALL):
+        for lc in (0, oracle.MODE_LC):
+            r = oracle.round_sim(4, src, dst, w, 0, mode=scope | lc)
+            assert r["cost"].tolist() == [0, 1, 3, I32_INF]
+            assert r["rounds"] == 3 and r["fixed_per_round"].tolist() == [1, 1, 0], (scope, lc)
+            assert r["relaxed_edges"] == 3
 
 
 def test_fig5_literal_order_counterexample():
