@@ -444,8 +444,9 @@ sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int3
  * status -- the round watchdog tripped (rounds beyond n + 1, or beyond the
  * sssp_set_round_limit limit), or a float32 equal-cost vertex got no parent
  * -- and clears that condition; SSSP_OK otherwise.  Calls given a stats
- * pointer report the same condition in their own return value; this call
- * is how the others (stats == NULL, plan runs) learn of it.
+ * pointer also report the condition in their own return value (and still
+ * count for the next sssp_check); this call is how the others (stats ==
+ * NULL, plan runs) learn of it.
  */
 sssp_status sssp_check(void *stream);
 
@@ -458,7 +459,8 @@ sssp_status sssp_check(void *stream);
  */
 sssp_status sssp_set_round_limit(int32_t limit);
 
-/* Free the calling device's workspace cache (synchronizes the device). */
+/* Free the calling device's workspace cache and events, and the profiler's
+ * events (synchronizes the device).  Later calls set the device up again. */
 sssp_status sssp_release_workspace(void);
 
 /*

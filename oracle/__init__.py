@@ -107,6 +107,36 @@ def dijkstra(n, src, dst, w, source, target=None):
 SP12_HOW = {0: "removeMin", 1: "pred", 2: "inWeight"}
 
 
+class Adjacency:
+    """A graph's out-adjacency built once (the COO indices of each tail's
+    edges), so that :meth:`dijkstra` times the search alone."""
+
+    def __init__(self, n, src, dst, w):
+        k, self.w = _kind(w)
+        self.kind = k
+        self.n = int(n)
+        src = _i32(src)
+        self.dst = _i32(dst)
+        self.off = np.empty(self.n + 1, dtype=np.int64)
+        self.adj = np.empty(max(len(src), 1), dtype=np.int32)
+        rc = _call("oracle_out_adjacency", ctypes.c_int32(self.n), ctypes.c_int64(len(src)),
+                   _p(src), _p(self.off), _p(self.adj))
+        if rc != 0:
+            raise ValueError("oracle_out_adjacency failed: %d" % rc)
+
+    def dijkstra(self, source, target=None):
+        """(cost, settles) of Fig. 1's algorithm from `source`, as :func:`dijkstra`."""
+        cost = np.empty(self.n, dtype=self.w.dtype)
+        settles = ctypes.c_int64(0)
+        t = -1 if target is None else int(target)
+        rc = _call("oracle_dijkstra_adj_" + self.kind, ctypes.c_int32(self.n), _p(self.off),
+                   _p(self.adj), _p(self.dst), _p(self.w), ctypes.c_int32(source),
+                   ctypes.c_int32(t), _p(cost), ctypes.byref(settles))
+        if rc != 0:
+            raise ValueError("oracle_dijkstra_adj failed: %d" % rc)
+        return cost, settles.value
+
+
 def sp12(n, src, dst, w, source, variant, sequence=False):
     """SP_1 (variant 1, Fig. 3) or SP_2 (variant 2, Fig. 4), or Dijkstra in
     the same framework (variant 0); the outer loop ends once the heap holds

@@ -16,6 +16,24 @@
 #include <string.h>
 #include <math.h>
 
+/* Out-adjacency of a COO edge list: off[n+1] and adj[m], the COO indices of
+ * each tail's edges in input order (a stable counting sort by tail). */
+int oracle_out_adjacency(int32_t n, int64_t m, const int32_t *src, int64_t *off, int32_t *adj) {
+  if (n <= 0 || m < 0) return -1;
+  for (int32_t v = 0; v <= n; ++v) off[v] = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    if (src[i] < 0 || src[i] >= n) return -2;
+    off[src[i] + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!fill) return -2;
+  for (int32_t v = 0; v < n; ++v) fill[v] = off[v];
+  for (int64_t i = 0; i < m; ++i) adj[fill[src[i]]++] = (int32_t)i;
+  free(fill);
+  return 0;
+}
+
 /* --------------------------------------------------------- typed parts */
 #define T int32_t
 #define SFX i32

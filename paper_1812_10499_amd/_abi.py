@@ -7,6 +7,7 @@ status.  Pointers are passed as Python ints (device addresses, e.g.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -144,6 +145,22 @@ def lib():
         del i64p
         _lib = L
     return _lib
+
+
+def _release_at_exit():
+    """Frees the library's device resources before the process ends, while
+    the HIP runtime is still up: live plans, then the workspace and events."""
+    if _lib is None:
+        return
+    try:
+        from . import graph
+        graph.close_plans()
+        _lib.sssp_release_workspace()
+    except Exception:
+        pass
+
+
+atexit.register(_release_at_exit)
 
 
 def _check(status: int, where: str):

@@ -1408,6 +1408,18 @@ sssp_status sssp_release_workspace(void) {
   if (w.pinned) HIPCHK(hipHostFree(w.pinned));
   w.pinned = nullptr;
   w.pinned_cap = 0;
+  if (w.last) HIPCHK(hipEventDestroy(w.last));
+  if (w.staged) HIPCHK(hipEventDestroy(w.staged));
+  w.last = w.staged = nullptr;
+  w.bpc[0] = w.bpc[1] = w.bpc[2] = w.bpc[3] = 0;
+  w.init = false;  // the next call sets the device up again (its launch defaults stay)
+  // the profiler's event pairs (created on whichever device was current)
+  for (KernelTimer &t : g_prof.pool) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  g_prof.pool.clear();
+  g_prof.used = 0;
   return SSSP_OK;
 }
 

@@ -7,6 +7,7 @@ path.
 from __future__ import annotations
 
 import ctypes
+import weakref
 from typing import Sequence
 
 import numpy as np
@@ -256,6 +257,13 @@ def solve_batch(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source:
 
 
 PLAN_KINDS = {"batch": _abi.SSSP_PLAN_BATCH, "sequence": _abi.SSSP_PLAN_SEQUENCE}
+_live_plans = weakref.WeakSet()
+
+
+def close_plans():
+    """Destroys every plan still open (called at process exit)."""
+    for p in list(_live_plans):
+        p.close()
 
 
 def _launch(launch):
@@ -290,6 +298,7 @@ class Plan:
             [g.csr for g in graphs], inst_graph, inst_source, PLAN_KINDS[kind],
             self.cost.data_ptr(), self.pred.data_ptr() if with_pred else None, with_stats,
             _launch(launch))
+        _live_plans.add(self)
 
     def run(self):
         """Replays the recorded solves on the current stream (asynchronous)."""

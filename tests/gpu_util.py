@@ -18,15 +18,15 @@ def oracle_mode(scope, relax="setting"):
 
 
 def oracle_solution(n, src, dst, w, source, scope="open", relax="setting", delta=None):
-    """(cost, pred (int64), settles, rounds, fixed_per_round, stats) from the
-    oracle, the round counts under the given C scope, relax step and
-    label-correcting bucket width."""
+    """cost, pred (int64), ties (vertices that took the equal-cost level
+    rule), settles, and the round counters under the given C scope, relax
+    step and label-correcting bucket width, from the oracle."""
     cost, settles = oracle.dijkstra(n, src, dst, w, source)
     O = oracle.csr(n, src, dst)
-    pred, _ = oracle.pred(O, w, source, cost)
+    pred, ties = oracle.pred(O, w, source, cost)
     sim = oracle.round_sim(n, src, dst, w, source, mode=oracle_mode(scope, relax), delta=delta)
     assert np.array_equal(sim["cost"], cost)
-    return dict(cost=cost, pred=pred, settles=settles, rounds=sim["rounds"],
+    return dict(cost=cost, pred=pred, ties=ties, settles=settles, rounds=sim["rounds"],
                 relaxed=sim["relaxed_edges"], scanned=sim["scanned_in_edges"],
                 open_visits=sim["open_visits"], csr=O)
 
@@ -115,3 +115,13 @@ def check_solver_copy(G, n, src, dst, w):
             assert np.array_equal(vr[has, 5], nbr[order][first])
             assert np.array_equal(vr[has, 6], bits(np.ascontiguousarray(ow[order]))[first])
             assert not vr[~has, 5:7].any()
+
+
+def pool_map(fn, items):
+    """fn over items on a thread pool of up to 16 host threads (the oracle's
+    C calls release the GIL), results in order."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1, len(items)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))

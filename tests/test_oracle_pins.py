@@ -75,6 +75,8 @@ def test_dijkstra_matches_path_enumeration(dtype):
         bf = brute_force_paths(n, src, dst, w, s)
         assert np.array_equal(c, bf), (n, src, dst, w, s, c, bf)
         assert settles == int(np.sum(c != _inf(dtype)))
+        ca, sa = oracle.Adjacency(n, src, dst, w).dijkstra(s)
+        assert np.array_equal(ca, bf) and sa == settles
 
 
 @pytest.mark.parametrize("dtype", [np.int32, np.float32, np.float64])
