@@ -95,25 +95,30 @@ def test_watchdog_in_plans_and_batches(sp):
 
 
 @pytest.mark.parametrize("wg", [1, -1])
-def test_backward_ignores_a_parent_of_the_source(sp, wg):
+@pytest.mark.parametrize("num_sources", [1, 3])
+def test_backward_ignores_a_parent_of_the_source(sp, wg, num_sources):
     """pred[source] set to an in-edge of the source whose tail is in the
-    source's own tree: the source stays the root, that edge gets gradient 0,
-    and every other gradient is the one of the well-formed pred array."""
+    source's own tree: the source stays the root and the gradients are those
+    of the well-formed pred array, bit for bit.  With one source that edge
+    (its head is the source) gets gradient 0; with several it may still be a
+    tree edge of another source's tree."""
     d, gco = gen.diff_workload(side=32, num_sources=3)
     G = sp.Graph(d.n, d.src, d.dst, d.w)
-    srcs = [int(s) for s in d.sources]
+    srcs = [int(s) for s in d.sources][:num_sources]
     S = len(srcs)
+    gco = gco[:S]
     _, pred, _ = sp.solve_batch([G], [0] * S, srcs)
     sync()
-    gcost = torch.from_numpy(gco.reshape(-1)).cuda()
+    gcost = torch.from_numpy(np.ascontiguousarray(gco).reshape(-1)).cuda()
     O = oracle.csr(d.n, d.src, d.dst)
     bad = pred.clone()
     into = []
     for i, s in enumerate(srcs):
-        # in-edges of the source (edge ids are CSR positions; O.in_eid lists them by head)
+        # an in-edge of the source (O.in_eid lists edge ids by head)
         e = int(O.in_eid[O.in_off[s]])
         into.append(e)
         bad[i * d.n + s] = e
+    print("backward root test: wg", wg, "sources", S, flush=True)
     try:
         sp.set_launch({"wg": wg})
         ref = to_np(sp.backward([G], [0] * S, srcs, pred, gcost))
@@ -124,6 +129,6 @@ def test_backward_ignores_a_parent_of_the_source(sp, wg):
     p = to_np(pred).astype(np.int64).reshape(S, d.n)
     want = oracle.grad(O, srcs, p, gco.astype(np.float64))
     assert np.linalg.norm(ref - want) / np.linalg.norm(want) <= 1e-5
-    for e in into:
-        assert got[e] == 0.0 and ref[e] == 0.0
     assert np.array_equal(got, ref)
+    if S == 1:
+        assert got[into[0]] == 0.0
