@@ -57,7 +57,8 @@ typedef enum {
   SSSP_ERR_OVERFLOW = 4, /* int32: (n-1) * w_max >= INT32_MAX */
   SSSP_ERR_NOMEM = 5,    /* workspace allocation failed */
   SSSP_ERR_HIP = 6,      /* a HIP runtime call failed */
-  SSSP_ERR_INTERNAL = 7  /* round watchdog tripped (rounds > n + 1, see sssp_check) */
+  SSSP_ERR_INTERNAL = 7, /* round watchdog tripped (rounds > n + 1, see sssp_check) */
+  SSSP_ERR_CAPACITY = 8  /* sssp_solve_noalloc: the solve's state exceeds its static scratch */
 } sssp_status;
 
 /*
@@ -289,6 +290,27 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream);
  */
 sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
                        sssp_stats *stats, void *stream);
+
+/*
+ * sssp_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, same results and counters, with all of its state in one
+ * static region of 64 MiB per device that the library's code object holds
+ * from load to process end, instead of the workspace cache.  The call makes
+ * no hipMalloc, hipFree, event creation or other allocating runtime call
+ * (its first call on a device only looks the region's address up).
+ *   Arguments, semantics and errors as for sssp_solve, plus
+ *   SSSP_ERR_CAPACITY (nothing queued) when the solve's state does not fit
+ *   the region: it needs about 140 bytes per vertex plus 0.4 MB, so every
+ *   graph with n <= 450,000 fits, whatever its scope and relax step.
+ * Every call on one device shares that device's region and leaves its
+ * contents behind (each solve initializes what it reads first): calls that
+ * overlap on one device race, so order them (one stream, or events).  Calls
+ * are not ordered against sssp_solve's workspace use either; neither shares
+ * memory with the other.  The round trace and the profiler do not apply.
+ */
+sssp_status sssp_solve_noalloc(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
+                               sssp_stats *stats, void *stream);
 
 /*
  * Single-target early exit (Section I: a shortest path to one destination

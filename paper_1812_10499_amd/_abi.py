@@ -21,7 +21,7 @@ SSSP_ORDER_AUTO, SSSP_ORDER_INPUT, SSSP_ORDER_DEGREE = 0, 1, 2
 SSSP_SCOPE_AUTO, SSSP_SCOPE_OPEN, SSSP_SCOPE_ALL = 0, 1, 2
 SSSP_RELAX_AUTO, SSSP_RELAX_SETTING, SSSP_RELAX_CORRECTING = 0, 1, 2
 (SSSP_OK, SSSP_ERR_ARG, SSSP_ERR_GRAPH, SSSP_ERR_WEIGHT, SSSP_ERR_OVERFLOW, SSSP_ERR_NOMEM,
- SSSP_ERR_HIP, SSSP_ERR_INTERNAL) = range(8)
+ SSSP_ERR_HIP, SSSP_ERR_INTERNAL, SSSP_ERR_CAPACITY) = range(9)
 
 SSSP_PLAN_BATCH, SSSP_PLAN_SEQUENCE = 0, 1
 
@@ -30,7 +30,7 @@ EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_s
            "sssp_plan_create", "sssp_plan_run", "sssp_plan_stats", "sssp_plan_destroy",
            "sssp_autotune", "sssp_release_workspace", "sssp_strerror",
            "sssp_profile_enable", "sssp_profile_read", "sssp_check", "sssp_set_round_limit",
-           "sssp_policy_of")
+           "sssp_policy_of", "sssp_solve_noalloc")
 KERNELS = {0: "rounds_kernel", 1: "wg_rounds_kernel", 2: "small_rounds_kernel"}
 
 
@@ -103,6 +103,9 @@ def lib():
         L.sssp_set_weights.restype = ctypes.c_int
         L.sssp_solve.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, ctypes.POINTER(Stats), vp]
         L.sssp_solve.restype = ctypes.c_int
+        L.sssp_solve_noalloc.argtypes = [ctypes.POINTER(Csr), i32, vp, vp,
+                                         ctypes.POINTER(Stats), vp]
+        L.sssp_solve_noalloc.restype = ctypes.c_int
         L.sssp_solve_target.argtypes = [ctypes.POINTER(Csr), i32, i32, vp,
                                         ctypes.POINTER(Stats), vp]
         L.sssp_solve_target.restype = ctypes.c_int
@@ -195,6 +198,12 @@ def sssp_solve(g: Csr, source, cost, pred, stats, stream):
     _check(lib().sssp_solve(ctypes.byref(g), source, cost, pred,
                             ctypes.byref(stats) if stats is not None else None, stream),
            "sssp_solve")
+
+
+def sssp_solve_noalloc(g: Csr, source, cost, pred, stats, stream):
+    _check(lib().sssp_solve_noalloc(ctypes.byref(g), source, cost, pred,
+                                    ctypes.byref(stats) if stats is not None else None, stream),
+           "sssp_solve_noalloc")
 
 
 def sssp_solve_target(g: Csr, source, target, cost, stats, stream):

@@ -340,60 +340,96 @@ sssp_status build_temps(DevWS &ws, int32_t n, int32_t m, BuildTemps *t) {
   return SSSP_OK;
 }
 
-// Round-state buffers for `total` state entries.
-sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
-                          RoundArgs &a) {
+// Where a solve's state arrays come from: the per-device workspace cache
+// (slots grown on demand) ...
+struct WsAlloc {
+  DevWS &w;
+  template <class T>
+  sssp_status operator()(int slot, size_t count, T **out) {
+    return ws_arr(w, slot, count, out);
+  }
+};
+
+// ... or consecutive 256-byte-aligned pieces of one fixed region (the
+// static scratch of sssp_solve_noalloc); a region too small is
+// SSSP_ERR_CAPACITY.  With base == nullptr it only measures.
+struct CarveAlloc {
+  char *base;
+  size_t cap;
+  size_t used = 0;
+  template <class T>
+  sssp_status operator()(int, size_t count, T **out) {
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 256;
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (off > cap || bytes > cap - off) return SSSP_ERR_CAPACITY;
+    *out = base ? (T *)(base + off) : nullptr;
+    used = off + bytes;
+    return SSSP_OK;
+  }
+};
+
+// Round-state arrays for `total` state entries.
+template <class Alloc>
+sssp_status state_arrays(Alloc &al, int32_t total, int32_t num_inst, bool batch,
+                         RoundArgs &a) {
   const size_t T = (size_t)total;
   sssp_status s;
-  if ((s = ws_arr(w, S_D64, T, &a.D64))) return s;
-  if ((s = ws_arr(w, S_C, T, &a.C0))) return s;
-  if ((s = ws_arr(w, S_C1, T, &a.C1))) return s;
-  if ((s = ws_arr(w, S_ARRIVE, T, &a.arrive))) return s;
-  if ((s = ws_arr(w, S_MTMP, T, &a.mtmp))) return s;
-  if ((s = ws_arr(w, S_OV0, T, &a.open_v0))) return s;
-  if ((s = ws_arr(w, S_OP0, T, &a.open_p0))) return s;
-  if ((s = ws_arr(w, S_OV1, T, &a.open_v1))) return s;
-  if ((s = ws_arr(w, S_OP1, T, &a.open_p1))) return s;
-  if ((s = ws_arr(w, S_FV, T, &a.front_v))) return s;
-  if ((s = ws_arr(w, S_FP, T, &a.front_p))) return s;
+  if ((s = al(S_D64, T, &a.D64))) return s;
+  if ((s = al(S_C, T, &a.C0))) return s;
+  if ((s = al(S_C1, T, &a.C1))) return s;
+  if ((s = al(S_ARRIVE, T, &a.arrive))) return s;
+  if ((s = al(S_MTMP, T, &a.mtmp))) return s;
+  if ((s = al(S_OV0, T, &a.open_v0))) return s;
+  if ((s = al(S_OP0, T, &a.open_p0))) return s;
+  if ((s = al(S_OV1, T, &a.open_v1))) return s;
+  if ((s = al(S_OP1, T, &a.open_p1))) return s;
+  if ((s = al(S_FV, T, &a.front_v))) return s;
+  if ((s = al(S_FP, T, &a.front_p))) return s;
   {
     // list payload words: kFX per frontier entry, kOX per open entry and parity
     int32_t *fx, *ox0, *ox1;
-    if ((s = ws_arr(w, S_FX, kFX * T, &fx))) return s;
-    if ((s = ws_arr(w, S_OX0, kOX * T, &ox0))) return s;
-    if ((s = ws_arr(w, S_OX1, kOX * T, &ox1))) return s;
+    if ((s = al(S_FX, kFX * T, &fx))) return s;
+    if ((s = al(S_OX0, kOX * T, &ox0))) return s;
+    if ((s = al(S_OX1, kOX * T, &ox1))) return s;
     for (int k = 0; k < kFX; ++k) a.front_x[k] = fx + (size_t)k * T;
     for (int k = 0; k < kOX; ++k) {
       a.open_x0[k] = ox0 + (size_t)k * T;
       a.open_x1[k] = ox1 + (size_t)k * T;
     }
   }
-  if ((s = ws_arr(w, S_CTL, 1, &a.ctl))) return s;
-  if ((s = ws_arr(w, S_FLAGS, (size_t)kMaxBlocks * kFlagStride, &a.flags))) return s;
-  if ((s = ws_arr(w, S_PART, (size_t)kParts * kMaxBlocks, &a.part))) return s;
-  if ((s = ws_arr(w, S_HEAVY, 2 * T, &a.heavy))) return s;
-  if ((s = ws_arr(w, S_DEGEN, 2 * T, &a.degen))) return s;
-  if ((s = ws_arr(w, S_LVL, T, &a.lvl))) return s;
-  if ((s = ws_arr(w, S_FLAG, T, &a.flag))) return s;
+  if ((s = al(S_CTL, 1, &a.ctl))) return s;
+  if ((s = al(S_FLAGS, (size_t)kMaxBlocks * kFlagStride, &a.flags))) return s;
+  if ((s = al(S_PART, (size_t)kParts * kMaxBlocks, &a.part))) return s;
+  if ((s = al(S_HEAVY, 2 * T, &a.heavy))) return s;
+  if ((s = al(S_DEGEN, 2 * T, &a.degen))) return s;
+  if ((s = al(S_LVL, T, &a.lvl))) return s;
+  if ((s = al(S_FLAG, T, &a.flag))) return s;
   if (a.scope_all) {
-    if ((s = ws_arr(w, S_LV0, T, &a.live_v0))) return s;
-    if ((s = ws_arr(w, S_LV1, T, &a.live_v1))) return s;
+    if ((s = al(S_LV0, T, &a.live_v0))) return s;
+    if ((s = al(S_LV1, T, &a.live_v1))) return s;
     if (batch) {
-      if ((s = ws_arr(w, S_INSTOF, T, &a.inst_of))) return s;
-      if ((s = ws_arr(w, S_IDEAD, 2 * (size_t)num_inst, &a.idead))) return s;
+      if ((s = al(S_INSTOF, T, &a.inst_of))) return s;
+      if ((s = al(S_IDEAD, 2 * (size_t)num_inst, &a.idead))) return s;
     }
   }
-  if (a.any_lc && (s = ws_arr(w, S_DR, T, &a.DR))) return s;
+  if (a.any_lc && (s = al(S_DR, T, &a.DR))) return s;
   if (batch) {
-    if ((s = ws_arr(w, S_OI0, T, &a.open_i0))) return s;
-    if ((s = ws_arr(w, S_OI1, T, &a.open_i1))) return s;
-    if ((s = ws_arr(w, S_FI, T, &a.front_i))) return s;
-    if ((s = ws_arr(w, S_IMIN, 3 * (size_t)num_inst, &a.imin))) return s;
-    if ((s = ws_arr(w, S_ITHR, 3 * (size_t)num_inst, &a.ithr))) return s;
-    if ((s = ws_arr(w, S_IROUNDS, (size_t)num_inst, &a.irounds))) return s;
-    if ((s = ws_arr(w, S_ISCAN, 3 * (size_t)num_inst, &a.iscanned))) return s;
+    if ((s = al(S_OI0, T, &a.open_i0))) return s;
+    if ((s = al(S_OI1, T, &a.open_i1))) return s;
+    if ((s = al(S_FI, T, &a.front_i))) return s;
+    if ((s = al(S_IMIN, 3 * (size_t)num_inst, &a.imin))) return s;
+    if ((s = al(S_ITHR, 3 * (size_t)num_inst, &a.ithr))) return s;
+    if ((s = al(S_IROUNDS, (size_t)num_inst, &a.irounds))) return s;
+    if ((s = al(S_ISCAN, 3 * (size_t)num_inst, &a.iscanned))) return s;
   }
   return SSSP_OK;
+}
+
+sssp_status state_buffers(DevWS &w, int32_t total, int32_t num_inst, bool batch,
+                          RoundArgs &a) {
+  WsAlloc al{w};
+  return state_arrays(al, total, num_inst, batch, a);
 }
 
 // Round trace: with SSSP_TRACE=<path> in the environment, a solve records
@@ -531,6 +567,7 @@ const char *sssp_strerror(sssp_status st) {
     case SSSP_ERR_NOMEM: return "device workspace allocation failed";
     case SSSP_ERR_HIP: return "HIP runtime error";
     case SSSP_ERR_INTERNAL: return "internal error (round watchdog)";
+    case SSSP_ERR_CAPACITY: return "graph too large for the static scratch of sssp_solve_noalloc";
   }
   return "unknown status";
 }
@@ -696,8 +733,8 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
 
 // Round arguments of one solve from `source` (target >= 0: stop once the
 // target is fixed) into `cost`, with its state buffers.
-static sssp_status single_args(DevWS &ws, const sssp_csr *g, int32_t source, int32_t target,
-                               void *cost, RoundArgs &a) {
+static void single_fill(const sssp_csr *g, int32_t source, int32_t target, void *cost,
+                        RoundArgs &a) {
   memset(&a, 0, sizeof(a));
   a.g = graph_dev(g);
   a.num_inst = 1;
@@ -708,6 +745,11 @@ static sssp_status single_args(DevWS &ws, const sssp_csr *g, int32_t source, int
   a.target = target;
   a.scope_all = a.g.all;
   a.any_lc = a.g.lc;
+}
+
+static sssp_status single_args(DevWS &ws, const sssp_csr *g, int32_t source, int32_t target,
+                               void *cost, RoundArgs &a) {
+  single_fill(g, source, target, cost, a);
   return state_buffers(ws, g->n, 1, false, a);
 }
 
@@ -878,6 +920,63 @@ extern "C" {
 sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
                        sssp_stats *stats, void *stream) {
   return solve_one(g, source, -1, cost, pred, stats, stream);
+}
+
+// Per-device set-up of sssp_solve_noalloc, done on its first call on a
+// device: the static scratch region's address, the CU count and (cached on
+// first use) the round kernel's co-residency, so that later calls make no
+// allocating runtime call.
+struct NoAllocDev {
+  bool init = false;
+  char *scratch = nullptr;
+  int cus = 0;
+  int bpc[4] = {0, 0, 0, 0};
+};
+static NoAllocDev g_na[64];
+
+sssp_status sssp_solve_noalloc(const sssp_csr *g, int32_t source, void *cost, int32_t *pred,
+                               sssp_stats *stats, void *stream_) {
+  if (!csr_ok(g) || !cost || source < 0 || source >= g->n) return SSSP_ERR_ARG;
+  if (overflow_risk(g)) return SSSP_ERR_OVERFLOW;
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool f32 = g->dtype == SSSP_F32;
+  Guard guard;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SSSP_ERR_ARG;
+  NoAllocDev &nd = g_na[dev];
+  if (!nd.init) {
+    void *p = nullptr;
+    HIPCHK(scratch_address(&p));
+    HIPCHK(hipDeviceGetAttribute(&nd.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    nd.scratch = (char *)p;
+    nd.init = true;
+  }
+  RoundArgs a;
+  single_fill(g, source, -1, cost, a);
+  CarveAlloc al{nd.scratch, kScratchBytes};
+  sssp_status s;
+  if ((s = state_arrays(al, g->n, 1, false, a))) return s;
+  // the device's default geometry (sssp_set_launch), resolved on a stack
+  // copy of the set-up values
+  DevWS tmp;
+  tmp.cus = nd.cus;
+  memcpy(tmp.bpc, nd.bpc, sizeof(nd.bpc));
+  tmp.cfg = g_ws[dev].cfg;
+  LaunchGeom geo;
+  if ((s = resolve_launch(tmp, f32, false, &tmp.cfg, &geo, a, low_spread(g)))) return s;
+  memcpy(nd.bpc, tmp.bpc, sizeof(nd.bpc));
+  Launcher L;
+  L.stream = stream;
+  HIPCHK(launch_solve(f32, false, a, pred, geo, nullptr, g->n, nullptr, L));
+  if (stats) {
+    Ctl c;
+    HIPCHK(hipMemcpyAsync(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    single_stats(&c, stats);
+    if (c.status) return SSSP_ERR_INTERNAL;
+  }
+  return SSSP_OK;
 }
 
 sssp_status sssp_solve_target(const sssp_csr *g, int32_t source, int32_t target, void *cost,

@@ -1676,6 +1676,17 @@ hipError_t launch_solve(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                : launch_solve_t<KeyI32, false>(a, pred, geo, istat, max_n, timer, L);
 }
 
+// ------------------------------------------------ static scratch region
+// The state of an allocation-free solve (sssp_solve_noalloc) lives here:
+// one region per device, part of this code object, held until the process
+// ends.  In host code the array's name stands for no device address; the
+// address comes from hipGetSymbolAddress, taken once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void **ptr) {
+  return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu) {
   const void *k = f32 ? (batch ? (const void *)rounds_kernel<KeyF32, true>
                                : (const void *)rounds_kernel<KeyF32, false>)

@@ -197,6 +197,12 @@ hipError_t launch_pred(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
 // fault flag, which the emit pass sets for a solve whose status is non-zero
 hipError_t fault_flag_take(int32_t *out, hipStream_t stream);
 hipError_t round_kernel_occupancy(bool f32, bool batch, int *blocks_per_cu);
+
+// Bytes of the static scratch region of allocation-free solves, and its
+// device address on the current device (call once per device, with that
+// device current).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+hipError_t scratch_address(void **ptr);
 // every instance's rounds in a workgroup of its own (C scope OPEN), then the emit pass
 hipError_t launch_wg(bool f32, bool batch, const RoundArgs &a, int32_t *pred,
                      const LaunchGeom &geo, long long *istat, int32_t max_n,

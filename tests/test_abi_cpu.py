@@ -37,7 +37,8 @@ def test_header_declares_the_abi():
                             "sssp_autotune",
                             "sssp_release_workspace", "sssp_strerror",
                             "sssp_profile_enable", "sssp_profile_read", "sssp_check",
-                            "sssp_set_round_limit", "sssp_policy_of"])
+                            "sssp_set_round_limit", "sssp_policy_of",
+                            "sssp_solve_noalloc"])
 
 
 def test_library_exports_every_declared_symbol(sp):
@@ -49,7 +50,7 @@ def test_library_exports_every_declared_symbol(sp):
 
 def test_strerror_and_sizes(sp):
     assert sp.sssp_strerror(0) == "ok"
-    for s in range(1, 8):
+    for s in range(1, 9):
         assert sp.sssp_strerror(s) and sp.sssp_strerror(s) != "unknown status"
     I, A, D = sp.SSSP_ORDER_INPUT, sp.SSSP_ORDER_AUTO, sp.SSSP_ORDER_DEGREE
     assert sp.sssp_build_csr_bytes(0, 10, sp.SSSP_I32, I) == 0
