@@ -49,7 +49,7 @@ namespace sssp {
 constexpr int RBS = kRoundBlock;  // threads per block of the round kernel
 constexpr int EPT = 4;            // edges per thread per sub-chunk
 constexpr int WIN = RBS;          // list items per window
-constexpr int CAP_R = RBS * EPT;  // relax staging capacity (>= one sub-chunk)
+constexpr int CAP_R = RBS * EPT;  // relax: block staging capacity of first discoveries
 constexpr int CAP_F = RBS;        // bound-and-fix staging capacity per list (>= one window)
 constexpr uint32_t CW_RELAX = 4;  // work units per frontier item (its loads and list entry)
 constexpr uint32_t CW_FUSED = 16; // work units per open item (loads, decision, list entry)
@@ -72,6 +72,19 @@ struct Stager {
 
 
 
+// LDS staging of the first discoveries of a relax phase.  A wave reserves
+// places with one LDS atomic (no block barrier per batch of edges); places
+// beyond the capacity go straight to the global list.  d holds the
+// discovering candidate, an upper bound of the vertex's D this round; the
+// block flush turns it into the entry's work count.
+struct RelaxStage {
+  int32_t v[CAP_R];
+  int32_t d[CAP_R];
+  int32_t inst[CAP_R];
+  int32_t cnt;  // places reserved (may exceed CAP_R: the rest went global)
+  unsigned long long base;
+};
+
 struct SmemRelax {
   int32_t pfx[WIN + 1];
   int32_t epfx[WIN];  // edge prefix of the window's edge sub-ranges
@@ -81,7 +94,7 @@ struct SmemRelax {
   int32_t sb[WIN];
   int32_t gi[WIN];
   int32_t inst[WIN];
-  Stager<CAP_R, 0> st;
+  RelaxStage st;
 };
 
 struct SmemFused {
@@ -94,6 +107,11 @@ struct SmemFused {
   int32_t odeg[WIN];
   int32_t owm[WIN];
   int32_t acc[WIN];
+  // 1 + the largest list position among the item's edges that pass this
+  // round's weight test (they form a prefix: its length, the item's work
+  // next round), or kNoCount when the scan may have stopped short of that
+  // prefix (a first discovery cut by the probe)
+  int32_t cnt[WIN];
   int32_t dy[WIN];
   int32_t cy[WIN];
   int32_t mind[WIN];
@@ -358,46 +376,6 @@ __device__ void stage_flush2(Stager<CAP, N1> &s1, const ListRef &l1, Stager<CAP,
   __syncthreads();
 }
 
-// Block-collective push: entry j of the thread's v/d/ins arrays is pushed
-// iff bit j of `mask` is set (arrays are indexed by compile-time j only, so
-// they stay in VGPRs).  Flushes first when the stager would overflow.
-template <int CAP, int K>
-__device__ void stage_push(Stager<CAP, 0> &st, uint32_t mask, const int32_t (&v)[K],
-                           const int32_t (&d)[K], const int32_t (&ins)[K], const ListRef &l,
-                           bool batch, SmemAll &sm) {
-  uint32_t dsum = 0;
-  int n_local = 0;
-#pragma unroll
-  for (int j = 0; j < K; ++j)
-    if ((mask >> j) & 1u) {
-      dsum += (uint32_t)d[j];
-      ++n_local;
-    }
-  uint64_t tot;
-  const uint64_t ex = block_excl_scan64<RBS>(((uint64_t)n_local << 32) | dsum, sm.scan, &tot);
-  const int tcnt = (int)(tot >> 32);
-  if (tcnt == 0) return;  // uniform
-  if (st.cnt + tcnt > CAP) stage_flush(st, l, batch);
-  int pos = st.cnt + (int)(ex >> 32);
-  uint32_t dpos = st.deg + (uint32_t)(ex & 0xffffffffull);
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    if ((mask >> j) & 1u) {
-      st.v[pos] = v[j];
-      st.d[pos] = (int32_t)dpos;
-      st.inst[pos] = ins[j];
-      dpos += (uint32_t)d[j];
-      ++pos;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    st.cnt += tcnt;
-    st.deg += (uint32_t)(tot & 0xffffffffull);
-  }
-  __syncthreads();
-}
-
 // One item per thread into each of two payload stagers, with a single scan.
 template <int N1, int N2>
 __device__ void stage_push2(Stager<CAP_F, N1> &s1, bool h1, int32_t v1, int32_t d1, int32_t i1,
@@ -513,65 +491,225 @@ __device__ __forceinline__ int32_t useful_in_edges_at(const GraphDev &G, int32_t
 // (no search).  Cold must be stable for the whole relax step (the bound step
 // writes the other C buffer).
 constexpr int kProbe = 2;
+constexpr int32_t kNoCount = 0x40000000;  // above any list position
 
-template <class V>
-__device__ __forceinline__ int32_t discovery_in_edges(const GraphDev &G, const int32_t *Cold,
-                                                      int32_t y, int32_t md, int32_t dy) {
-  const int32_t b = G.in_off[y];
-  const int32_t deg = G.in_off[y + 1] - b;
-  if (deg <= 16) return deg;
-  int32_t c[kProbe], wv[kProbe];
+// The work of K first discoveries (bit k of `valid`: entry k is one), the
+// rule above taken one step at a time for all K entries, so that their
+// dependent loads overlap: the vertex record (in-offset, in-degree and the
+// lightest in-edge), the second lightest in-edge and both tails' lower
+// bounds, then the weight searches in lockstep.  gy is a state index, dy
+// the discovering candidate; md is the minD of an earlier round (md_prev, or
+// per instance in a batch).
+template <class V, bool BATCH, int K>
+__device__ void discovery_work_x(const RoundArgs &a, const int32_t *Cold, uint32_t valid,
+                                 const int32_t (&gy)[K], const int32_t (&dy)[K],
+                                 const int32_t (&ins)[K], int32_t md_prev, int r,
+                                 int32_t (&out)[K]) {
+  int32_t sb[K], gi[K], md[K], b[K], deg[K], v0[K], w0[K];
 #pragma unroll
-  for (int l = 0; l < kProbe; ++l) {
-    c[l] = G.in_src[b + l];
-    wv[l] = G.in_w[b + l];
-  }
-#pragma unroll
-  for (int l = 0; l < kProbe; ++l) c[l] = Cold[c[l]];
-  int hit = kProbe;
-#pragma unroll
-  for (int l = kProbe - 1; l >= 0; --l)
-    if (c[l] <= md) hit = l;
-  if (hit < kProbe) {
-    // the edges that pass the weight test form a prefix of the list
-    int32_t p = 0;
-#pragma unroll
-    for (int l = 0; l < kProbe; ++l) p += (l <= hit && V::add(md, wv[l]) < dy) ? 1 : 0;
-    return p;
-  }
-  if constexpr (std::is_same<V, KeyI32>::value) {
-    // Integer weights: a probed tail j with C[j] > md still bounds the scan.
-    // For every minD >= md its term max(C[j], minD) + w_j is at most
-    // minD + w_j + (C[j] - md), so each edge k with w_k >= W* =
-    // min_j (w_j + C[j] - md) has minD + w_k >= that term: only the edges
-    // lighter than W*, and the probe edge j* that attains it, can set m_y.
-    long long ws = (long long)V::INF + V::INF;
-    int js = -1;
-#pragma unroll
-    for (int l = 0; l < kProbe; ++l) {
-      if (c[l] != V::INF) {
-        const long long t = (long long)wv[l] + (c[l] - md);
-        if (t < ws) {
-          ws = t;
-          js = l;
+  for (int k = 0; k < K; ++k) {
+    out[k] = 0;
+    sb[k] = gi[k] = 0;
+    md[k] = md_prev;
+    b[k] = deg[k] = v0[k] = w0[k] = 0;
+    if ((valid >> k) & 1u) {
+      if constexpr (BATCH) {
+        const InstDev id = a.insts[ins[k]];
+        sb[k] = id.sbase;
+        gi[k] = id.graph;
+        md[k] = 0;
+        if (r > 1) {
+          md[k] = ld_relaxed(&a.imin[((r + 2) % 3) * a.num_inst + ins[k]]);
+          if (md[k] == V::INF) md[k] = 0;
         }
       }
-    }
-    if (js >= 0) {
-      // One search for the weight bound min(dy - md, W*): md + w < dy is
-      // w < dy - md (dy <= INF, so the saturating add hides nothing), and
-      // j* itself lies below W* (C[j*] > md here), so the count keeps it.
-      const long long lim = ws < (long long)dy - md ? ws : (long long)dy - md;
-      int32_t lo = 0, hi = deg;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if ((long long)G.in_w[b + mid] < lim) lo = mid + 1;
-        else hi = mid;
-      }
-      return lo;
+      const GraphDev &G = graph_of<BATCH>(a, gi[k]);
+      const int32_t y = gy[k] - sb[k];
+      const int4 rec = G.vrec[2 * y], rec2 = G.vrec[2 * y + 1];
+      b[k] = rec.z;
+      deg[k] = rec.w;
+      v0[k] = rec2.y;  // the lightest in-edge's tail and weight
+      w0[k] = rec2.z;
     }
   }
-  return useful_in_edges_at<V>(G, b, deg, md, dy);
+  // short lists are taken whole; longer ones probe their two lightest edges
+  uint32_t probe = 0;
+  int32_t v1[K], w1[K], c0[K], c1[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    v1[k] = w1[k] = 0;
+    if ((valid >> k) & 1u) {
+      if (deg[k] > 16) {
+        const GraphDev &G = graph_of<BATCH>(a, gi[k]);
+        probe |= 1u << k;
+        v1[k] = G.in_src[b[k] + 1];
+        w1[k] = G.in_w[b[k] + 1];
+      } else {
+        out[k] = deg[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    c0[k] = c1[k] = V::INF;
+    if ((probe >> k) & 1u) {
+      c0[k] = Cold[sb[k] + v0[k]];
+      c1[k] = Cold[sb[k] + v1[k]];
+    }
+  }
+  uint32_t search = 0, bylim = 0;
+  int32_t lo[K], hi[K], lim[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    lo[k] = hi[k] = lim[k] = 0;
+    if (!((probe >> k) & 1u)) continue;
+    const int hit = c0[k] <= md[k] ? 0 : (c1[k] <= md[k] ? 1 : kProbe);
+    if (hit < kProbe) {
+      // the edges that pass the weight test form a prefix of the list
+      int32_t p = V::add(md[k], w0[k]) < dy[k] ? 1 : 0;
+      if (hit == 1 && V::add(md[k], w1[k]) < dy[k]) ++p;
+      out[k] = p;
+      continue;
+    }
+    lo[k] = 0;
+    hi[k] = deg[k];
+    search |= 1u << k;
+    if constexpr (std::is_same<V, KeyI32>::value) {
+      // Integer weights: a probed tail j with C[j] > md still bounds the
+      // scan.  For every minD >= md its term max(C[j], minD) + w_j is at
+      // most minD + w_j + (C[j] - md), so each edge with weight at least
+      // W* = min_j (w_j + C[j] - md) has minD + w >= that term: only the
+      // edges lighter than W*, and the probe edge j* that attains it, can
+      // set m_y.  One search then finds the weight bound min(dy - md, W*):
+      // md + w < dy is w < dy - md (dy <= INF, so the saturating add hides
+      // nothing), and j* itself lies below W* (C[j*] > md here).  The bound
+      // is at most dy - md, so it fits an int32.
+      long long ws = (long long)V::INF + V::INF;
+      if (c0[k] != V::INF) ws = (long long)w0[k] + (c0[k] - md[k]);
+      if (c1[k] != V::INF) {
+        const long long t = (long long)w1[k] + (c1[k] - md[k]);
+        if (t < ws) ws = t;
+      }
+      if (c0[k] != V::INF || c1[k] != V::INF) {
+        bylim |= 1u << k;
+        const long long dm = (long long)dy[k] - md[k];
+        lim[k] = (int32_t)(ws < dm ? ws : dm);
+      }
+    }
+  }
+  // the weight searches, one step for every searching entry per pass
+  while (search) {
+    int32_t x[K], mid[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      mid[k] = (lo[k] + hi[k]) >> 1;
+      x[k] = ((search >> k) & 1u) ? graph_of<BATCH>(a, gi[k]).in_w[b[k] + mid[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!((search >> k) & 1u)) continue;
+      const bool pass = ((bylim >> k) & 1u) ? x[k] < lim[k] : V::add(md[k], x[k]) < dy[k];
+      if (pass) lo[k] = mid[k] + 1;
+      else hi[k] = mid[k];
+      if (lo[k] >= hi[k]) {
+        search &= ~(1u << k);
+        out[k] = lo[k];
+      }
+    }
+  }
+}
+
+// Block-collective flush of the relax stager (all threads, after a barrier
+// that made its contents current).  Thread t takes the entries 4t .. 4t+3
+// and counts their useful in-edges, so the searches of a flush run side by
+// side; one block scan and one atomicAdd reserve the list slots and the
+// work range.  Entries carry the "no payload" mark: the bound step reads the
+// vertex record.
+template <class V, bool BATCH>
+__device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l,
+                            const int32_t *Cold, int32_t md_prev, int r, SmemAll &sm) {
+  const int cnt = st.cnt < CAP_R ? st.cnt : CAP_R;
+  if (cnt == 0) return;  // uniform
+  constexpr int PER = CAP_R / RBS;
+  const int j0 = threadIdx.x * PER;
+  int32_t work[PER], gy[PER], dy[PER], ins[PER];
+  uint32_t valid = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    gy[k] = dy[k] = ins[k] = 0;
+    if (j0 + k < cnt) {
+      valid |= 1u << k;
+      gy[k] = st.v[j0 + k];
+      dy[k] = st.d[j0 + k];
+      ins[k] = st.inst[j0 + k];
+    }
+  }
+  discovery_work_x<V, BATCH, PER>(a, Cold, valid, gy, dy, ins, md_prev, r, work);
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) sum += (uint32_t)work[k];
+  uint64_t tot;
+  const uint64_t ex = block_excl_scan64<RBS>((uint64_t)sum, sm.scan, &tot);
+  if (threadIdx.x == 0)
+    st.base = atomicAdd(l.ctr, ((unsigned long long)cnt << 32) | (tot & 0xffffffffull));
+  __syncthreads();
+  const unsigned long long b = st.base;
+  const int32_t bc = (int32_t)(b >> 32);
+  uint32_t p = (uint32_t)(b & 0xffffffffull) + (uint32_t)ex;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int j = j0 + k;
+    if (j < cnt) {
+      l.v[bc + j] = st.v[j];
+      l.p[bc + j] = (int32_t)p;
+      if (BATCH) l.i[bc + j] = st.inst[j];
+      if (l.x[0]) l.x[0][bc + j] = -1;
+      p += (uint32_t)work[k];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) st.cnt = 0;
+  __syncthreads();
+}
+
+// Discoveries a wave could not place in the stager (it was full): straight
+// to the global list, one atomicAdd for the wave.  All lanes of the wave
+// call it; mask selects the lane's entries among its EPT candidates.
+template <class V, bool BATCH>
+__device__ void relax_push_global(const RoundArgs &a, const ListRef &l, const int32_t *Cold,
+                                  int32_t md_prev, int r, uint32_t mask,
+                                  const int32_t (&gy)[EPT], const int32_t (&dy)[EPT],
+                                  const int32_t (&ins)[EPT]) {
+  int32_t work[EPT];
+  discovery_work_x<V, BATCH, EPT>(a, Cold, mask, gy, dy, ins, md_prev, r, work);
+  uint32_t n = 0, wsum = 0;
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    if ((mask >> j) & 1u) {
+      ++n;
+      wsum += (uint32_t)work[j];
+    }
+  }
+  const uint64_t mine = ((uint64_t)n << 32) | wsum;
+  const uint64_t inc = wave_incl_scan64(mine);
+  const uint64_t tot = __shfl(inc, SSSP_WAVE - 1, SSSP_WAVE);
+  unsigned long long base = 0;
+  if (lane_id() == 0 && tot) base = atomicAdd(l.ctr, (unsigned long long)tot);
+  base = __shfl(base, 0, SSSP_WAVE);
+  const uint64_t ex = inc - mine;
+  int32_t pos = (int32_t)(base >> 32) + (int32_t)(ex >> 32);
+  uint32_t p = (uint32_t)(base & 0xffffffffull) + (uint32_t)(ex & 0xffffffffull);
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    if ((mask >> j) & 1u) {
+      l.v[pos] = gy[j];
+      l.p[pos] = (int32_t)p;
+      if (BATCH) l.i[pos] = ins[j];
+      if (l.x[0]) l.x[0][pos] = -1;
+      ++pos;
+      p += (uint32_t)work[j];
+    }
+  }
 }
 
 // ================================================================== relax
@@ -598,10 +736,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
   }
   int32_t lmin = V::INF, ltmin = V::INF;
   SmemRelax &S = sm.u.r;
-  if (tid == 0) {
-    S.st.cnt = 0;
-    S.st.deg = 0;
-  }
+  if (tid == 0) S.st.cnt = 0;
   if constexpr (BATCH) batch_lds_reset<V>(bl, I);
   __syncthreads();
   mark(a, r, 0, 2);
@@ -720,7 +855,6 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
           val[j] = val[j] && cand[j] <= (int32_t)(dk[j] >> 32);
           if (val[j]) key[j] = make_key(cand[j], eid[j], cand[j] == S.dx[it[j]]);
         }
-        int32_t nv[EPT], nd[EPT], ni[EPT];
         uint32_t nmask = 0, smask = 0;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -735,7 +869,6 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          nv[j] = nd[j] = ni[j] = 0;
           const bool sj = (smask >> j) & 1u;
           int32_t th = V::INF;
           if (sj) {
@@ -750,26 +883,39 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
           if constexpr (BATCH)
             batch_offer<V>(bl, a, s_now, sj, sj ? S.inst[it[j]] : 0, sj ? cand[j] : V::INF,
                            th);
-          if (sj) {
-            const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-            if ((nmask >> j) & 1u) {
-              // queued for this round's bound step; D[y] can only drop
-              // below cand before it runs
-              int32_t md = md_prev;
-              if constexpr (BATCH) {
-                md = 0;
-                if (r > 1) {
-                  md = ld_relaxed(&a.imin[((r + 2) % 3) * I + S.inst[it[j]]]);
-                  if (md == V::INF) md = 0;
-                }
-              }
-              nv[j] = gy[j];
-              nd[j] = discovery_in_edges<V>(G, Cold + S.sb[it[j]], y[j], md, cand[j]);
+        }
+        // first discoveries (queued for this round's bound step; D[y] can
+        // only drop below cand before it runs): places in the stager by one
+        // LDS atomic per wave; what does not fit goes to the global list
+        {
+          const int nl = __popc(nmask);
+          const uint32_t incl = wave_incl_scan32((uint32_t)nl);
+          const int tot = __shfl((int)incl, SSSP_WAVE - 1, SSSP_WAVE);
+          if (tot) {
+            int old = 0;
+            if (lane_id() == 0) old = atomicAdd(&S.st.cnt, tot);
+            old = __shfl(old, 0, SSSP_WAVE);
+            int pos = old + (int)incl - nl;
+            int32_t ni[EPT];
+            uint32_t over = 0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
               ni[j] = S.inst[it[j]];
+              if ((nmask >> j) & 1u) {
+                if (pos < CAP_R) {
+                  S.st.v[pos] = gy[j];
+                  S.st.d[pos] = cand[j];
+                  S.st.inst[pos] = ni[j];
+                } else {
+                  over |= 1u << j;
+                }
+                ++pos;
+              }
             }
+            if (old + tot > CAP_R)  // wave-uniform
+              relax_push_global<V, BATCH>(a, olist, Cold, md_prev, r, over, gy, cand, ni);
           }
         }
-        stage_push<CAP_R, EPT>(S.st, nmask, nv, nd, ni, olist, BATCH, sm);
       }
       __syncthreads();
       if (pw.windows == 0) mark(a, r, 0, 5);
@@ -779,7 +925,9 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
     }
   }
   __syncthreads();
-  stage_flush(S.st, olist, BATCH);
+  // the phase's discoveries to the open list (S.st.cnt is current); what
+  // did not fit went to the list during the phase
+  relax_flush<V, BATCH>(a, S.st, olist, Cold, md_prev, r, sm);
   mark(a, r, 0, 6);
   if constexpr (!BATCH) {
     block_min2<RBS>(lmin, ltmin, sm.red);
@@ -989,6 +1137,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
     while (k < e1) {
       const int idx = i + tid;
       S.acc[tid] = V::INF;
+      S.cnt[tid] = 0;
       if (idx < NO) {
         const int32_t gy = Ov[idx];
         S.pfx[tid] = Op[idx] + (int32_t)(CW_FUSED * (uint32_t)idx);
@@ -1018,6 +1167,8 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           // C of an undiscovered vertex: 0, or under scope ALL what the
           // live pass raised it to
           xv[OX_C] = G.all ? Cold[gy] : 0;
+          // the probe may have cut its scan short of the weight prefix
+          if (xv[OX_IDEG] > 16) S.cnt[tid] = kNoCount;
         }
         S.base[tid] = xv[OX_BASE];
         S.ideg[tid] = xv[OX_IDEG];
@@ -1089,8 +1240,10 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           const int32_t md = BATCH ? (val[j] ? S.mind[it[j]] : 0) : mind_all;
           const int32_t t = val[j] ? V::add(kmax(cv[j], md), wt[j]) : V::INF;
           const int myit = val[j] ? it[j] : -1;
-          // segmented min into LDS; one LDS atomic per wave when the whole
-          // wave works on one item (hub vertices)
+          // 1 + the edge's position in the item's list
+          const int32_t c1 = val[j] ? pos[j] - S.base[it[j]] + 1 : 0;
+          // segmented min (and position max) into LDS; one LDS atomic per
+          // wave when the whole wave works on one item (hub vertices)
           const uint64_t act = __ballot(val[j]);
           if (act) {
             const int lead = __ffsll((unsigned long long)act) - 1;
@@ -1098,9 +1251,14 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
             const uint64_t same = __ballot(val[j] && myit == it0);
             if (same == act) {
               const int32_t wm = wave_min(t);
-              if (lane_id() == lead && wm < V::INF) atomicMin(&S.acc[it0], wm);
-            } else if (val[j] && t < V::INF) {
-              atomicMin(&S.acc[myit], t);
+              const int32_t wc = wave_max(c1);
+              if (lane_id() == lead) {
+                if (wm < V::INF) atomicMin(&S.acc[it0], wm);
+                atomicMax(&S.cnt[it0], wc);
+              }
+            } else if (val[j]) {
+              if (t < V::INF) atomicMin(&S.acc[myit], t);
+              atomicMax(&S.cnt[myit], c1);
             }
           }
         }
@@ -1174,8 +1332,14 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
               fx[FX_D] = Dy;
             } else {
               Cnew[gy] = Cn;
-              // next round: minD >= md and D[y] <= Dy
-              od = useful_in_edges_at<V>(G, S.base[tid], S.ideg[tid], md, Dy);
+              // Next round (minD >= md, D[y] <= Dy) needs at most the
+              // edges that passed this round's weight test, a prefix of the
+              // list; the scan counted it, unless the item was split over
+              // blocks or its scan may have stopped short (then a search)
+              const int32_t sc = S.cnt[tid];
+              od = (fb == lb && sc < kNoCount)
+                       ? sc
+                       : useful_in_edges_at<V>(G, S.base[tid], S.ideg[tid], md, Dy);
               ho = true;
               ox[OX_BASE] = S.base[tid];
               ox[OX_IDEG] = S.ideg[tid];

@@ -77,6 +77,12 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
   return v;
 }
 
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = kmax(v, __shfl_xor(v, o, SSSP_WAVE));
+  return v;
+}
+
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, SSSP_WAVE);
