@@ -87,7 +87,7 @@ def host_info():
 
 
 # threads of the CPU baseline's pool for independent solves: the host's
-# cores, at most 16 (the share of a one-GPU machine)
+# cores, at most 16 (a host's share per GPU on an eight-GPU node)
 CPU_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
@@ -109,9 +109,38 @@ def cpu_baseline(g, m_reach, budget_s=12.0):
     per = el / runs
     out = {"value": m_reach / per / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
            "sample": "%d full solve(s) of the same graph and source, adjacency built "
-                     "beforehand; %.2f s per solve" % (runs, per)}
+                     "beforehand; %.4g s per solve" % (runs, per)}
     out.update(host_info())
     return out
+
+
+# Block barriers per round on the critical path of the one-workgroup round
+# kernels (small_rounds_kernel, wg_rounds_kernel) in their common case (at
+# most 1024 relax items): the relax window's scan (3) and its two barriers,
+# the minD / thr reduction (2), and three around the bound step.
+BLOCK_BARRIERS_PER_ROUND = 10
+# Dependent global-memory steps per round on that path: relax (list entry,
+# out-edges, atomicMin, out_wmin of a lowered head) and bound (list entry,
+# D / vertex record / C, the lightest tail's C, the next in-edges).
+DEPENDENT_STEPS_PER_ROUND = 8
+
+
+def latency_bound(rounds: int, kernel_ms: float):
+    """Round-latency bound of a one-workgroup solve, t >= rounds x barriers
+    per round x t_barrier, with t_barrier measured now on this GPU; and a
+    tighter chain estimate that adds DEPENDENT_STEPS_PER_ROUND L2-resident
+    dependent loads per round (measured too)."""
+    from paper_1812_10499_amd import probe
+    tb = probe.block_barrier_us()
+    tl = probe.dependent_load_ns(2 << 20) / 1e3
+    b_ms = rounds * BLOCK_BARRIERS_PER_ROUND * tb / 1e3
+    c_ms = rounds * (BLOCK_BARRIERS_PER_ROUND * tb + DEPENDENT_STEPS_PER_ROUND * tl) / 1e3
+    return {"model": "rounds x barriers per round x t_barrier", "rounds": rounds,
+            "barriers_per_round": BLOCK_BARRIERS_PER_ROUND, "t_barrier_us": round(tb, 4),
+            "bound_ms": round(b_ms, 3), "frac": round(b_ms / kernel_ms, 4),
+            "chain_steps_per_round": DEPENDENT_STEPS_PER_ROUND,
+            "t_dependent_load_us": round(tl, 4), "chain_bound_ms": round(c_ms, 3),
+            "chain_frac": round(c_ms / kernel_ms, 4), "kernel_ms": round(kernel_ms, 4)}
 
 
 def timed(fn, steps, stream):
@@ -285,6 +314,9 @@ def bench_diff(args, sp, torch):
     sp.set_launch(None)
     log("tuned %s: fwd %.2f (default geometry %.2f) bwd %.2f both %.2f ms; 64 singles %.2f ms"
         % (tuned, t_fwd, t_fwd_default, t_bwd, t_both, t_single))
+    # the forward runs each source in a workgroup of its own: its rounds are
+    # bound by the deepest source's round latency
+    lat = latency_bound(max(s["rounds"] for s in stats), t_fwd)
     cpu = None
     if not args.no_cpu_baseline:
         e, sec, k = oracle_sample([(d, s) for s in srcs] * 4, budget_s=8.0)
@@ -304,6 +336,7 @@ def bench_diff(args, sp, torch):
         "forward_backward_ms": round(t_both, 3), "single_solves_ms": round(t_single, 3),
         "rounds_max": max(s["rounds"] for s in stats),
         "dijkstra_settles": sum(s["settled"] for s in stats),
+        "latency": lat,
         "cpu_baseline": cpu,
     }
 
@@ -514,6 +547,9 @@ def main():
                                       if traffic is not None else None)},
         "cpu_baseline": cpu,
     }
+    if G.kernel in ("small_rounds_kernel", "wg_rounds_kernel"):
+        # one workgroup runs the solve: bound by round latency
+        out["latency"] = latency_bound(stats["rounds"], k_ms)
     print(json.dumps(out), flush=True)
 
 

@@ -39,16 +39,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles (the caller asked for a build)."""
+PROBE_SO = os.path.join(PKG, "libsssp_probe.so")
+
+
+def _hipcc(out: str, srcs, verbose: bool):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = SO + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] \
-        + sources()
+        + list(srcs)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, SO)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Always recompiles (the caller asked for a build): the library and the
+    measurement probes (libsssp_probe.so, csrc/probe.hip)."""
+    _hipcc(SO, sources(), verbose)
+    _hipcc(PROBE_SO, [os.path.join(CSRC, "probe.hip")], verbose)
     return SO
 
 

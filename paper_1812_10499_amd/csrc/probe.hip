@@ -1,0 +1,146 @@
+// Measurement probes for MI355X (gfx950): the access rates and latencies
+// that bound the round kernels.  Not part of a solve; built into its own
+// library (libsssp_probe.so) and driven by paper_1812_10499_amd.probe.
+//
+//  - random gathers of 8- or 4-byte values at indices read from a stream
+//    (U independent gathers in flight per thread), as the relax and bound
+//    steps gather D and C;
+//  - gather then 64-bit atomicMin where the key is smaller (the relax
+//    step's pre-filtered update);
+//  - a dependent-load chain (one lane follows next[] pointers), the latency
+//    of one step of a round's critical path at a given working-set size;
+//  - block barriers (__syncthreads) in one 1024-thread workgroup, and the
+//    round kernel's grid barrier over a cooperative grid.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sssp_dev.h"
+
+namespace {
+
+constexpr int U = 8;
+
+template <class T>
+__global__ __launch_bounds__(256) void gather_k(const T *__restrict__ arr,
+                                                const uint32_t *__restrict__ idx, int64_t n,
+                                                T *out) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  T acc = (T)-1;
+  for (int64_t b = tid; b < n; b += stride * U) {
+    uint32_t ix[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = b + (int64_t)u * stride;
+      ix[u] = i < n ? idx[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = arr[ix[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = v[u] < acc ? v[u] : acc;
+  }
+  out[tid] = acc;
+}
+
+__global__ __launch_bounds__(256) void gather_atomic_k(unsigned long long *arr,
+                                                       const uint32_t *__restrict__ idx,
+                                                       int64_t n, unsigned long long *out) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long acc = 0;
+  for (int64_t b = tid; b < n; b += stride * U) {
+    uint32_t ix[U];
+    unsigned long long k[U], d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = b + (int64_t)u * stride;
+      ix[u] = i < n ? idx[i] : 0u;
+      k[u] = ((unsigned long long)(uint32_t)(i * 2654435761u) << 20) | (uint64_t)(i & 0xfffff);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) d[u] = arr[ix[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = b + (int64_t)u * stride;
+      if (i < n && k[u] < d[u]) acc += atomicMin(&arr[ix[u]], k[u]);
+    }
+  }
+  out[tid] = acc;
+}
+
+// Each of the 64 lanes of one wave follows next[] for `steps` dependent
+// loads from its own start (a per-lane address keeps them vector loads);
+// the wave waits for its slowest lane at every step.
+__global__ __launch_bounds__(64) void chase_k(const uint32_t *next, const uint32_t *start,
+                                              int64_t steps, uint32_t *out) {
+  uint32_t p = start[threadIdx.x];
+  for (int64_t s = 0; s < steps; ++s) p = next[p];
+  out[threadIdx.x] = p;
+}
+
+// `iters` block barriers, with an LDS store and load between them so that
+// none can be dropped.
+__global__ __launch_bounds__(1024) void sync_k(int iters, int *out) {
+  __shared__ int slot[1024];
+  int v = threadIdx.x;
+  for (int i = 0; i < iters; ++i) {
+    slot[threadIdx.x] = v;
+    __syncthreads();
+    v += slot[(threadIdx.x + 1) & 1023];
+    __syncthreads();
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = v;
+}
+
+// `iters` grid barriers of the round kernel (sssp::grid_barrier) over the
+// whole cooperative grid.  flags (kMaxBlocks * kFlagStride) and go must be
+// zero at launch.
+__global__ __launch_bounds__(1024) void grid_sync_k(unsigned int *flags, unsigned int *go,
+                                                    int iters) {
+  unsigned int epoch = 0;
+  for (int i = 0; i < iters; ++i) sssp::grid_barrier(flags, go, epoch);
+}
+
+}  // namespace
+
+extern "C" {
+
+int probe_gather(int width, const void *arr, const uint32_t *idx, int64_t n, void *out,
+                 int blocks, void *stream) {
+  if (width == 8)
+    hipLaunchKernelGGL(gather_k<unsigned long long>, dim3(blocks), dim3(256), 0,
+                       (hipStream_t)stream, (const unsigned long long *)arr, idx, n,
+                       (unsigned long long *)out);
+  else
+    hipLaunchKernelGGL(gather_k<uint32_t>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const uint32_t *)arr, idx, n, (uint32_t *)out);
+  return (int)hipGetLastError();
+}
+
+int probe_gather_atomic(void *arr, const uint32_t *idx, int64_t n, void *out, int blocks,
+                        void *stream) {
+  hipLaunchKernelGGL(gather_atomic_k, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                     (unsigned long long *)arr, idx, n, (unsigned long long *)out);
+  return (int)hipGetLastError();
+}
+
+int probe_chase(const uint32_t *next, const uint32_t *start, int64_t steps, uint32_t *out,
+                void *stream) {
+  hipLaunchKernelGGL(chase_k, dim3(1), dim3(64), 0, (hipStream_t)stream, next, start, steps,
+                     out);
+  return (int)hipGetLastError();
+}
+
+int probe_sync(int iters, int *out, void *stream) {
+  hipLaunchKernelGGL(sync_k, dim3(1), dim3(1024), 0, (hipStream_t)stream, iters, out);
+  return (int)hipGetLastError();
+}
+
+int probe_grid_sync(unsigned int *flags, unsigned int *go, int iters, int blocks,
+                    void *stream) {
+  void *args[] = {&flags, &go, &iters};
+  return (int)hipLaunchCooperativeKernel((const void *)grid_sync_k, dim3(blocks), dim3(1024),
+                                         args, 0, (hipStream_t)stream);
+}
+}

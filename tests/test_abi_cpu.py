@@ -172,3 +172,16 @@ def test_host_argument_errors(sp):
     small = sp.sssp_build_csr_bytes(5, 5, 0, I)
     assert _status(lambda: sp.sssp_build_csr(5, 5, 0, sp.SSSP_ORDER_DEGREE, 0x1000, 0x1000,
                                              0x1000, 0x1000, small, out, None, None)) == S
+
+
+def test_probe_library_exports(sp):
+    """The measurement library (access rates and barrier costs the bench's
+    latency bound uses) loads and exports its entry points."""
+    from paper_1812_10499_amd.build import PROBE_SO
+    if not os.path.exists(PROBE_SO):
+        from paper_1812_10499_amd import build
+        build.build()
+    L = ctypes.CDLL(PROBE_SO)
+    for name in ("probe_gather", "probe_gather_atomic", "probe_chase", "probe_sync",
+                 "probe_grid_sync"):
+        assert hasattr(L, name), name
