@@ -491,7 +491,7 @@ sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
     fclose(fm);
   }
   // per-block records: <path>.blk, one line per (round, phase, block):
-  // round,phase,block,end,windows,first_item,units
+  // round,phase,block,end,windows,first_item,units,mid
   const int nbr = nr < kTraceBlkRounds ? nr : kTraceBlkRounds;
   std::vector<long long> hb((size_t)nbr * 2 * kMaxBlocks * kBlkFields);
   HIPCHK(hipMemcpy(hb.data(), a.trace_blk, hb.size() * sizeof(long long),
@@ -503,7 +503,8 @@ sssp_status trace_end(const RoundArgs &a, int nblocks, hipStream_t stream) {
     for (int ph = 0; ph < 2; ++ph)
       for (int b = 0; b < nblocks; ++b) {
         const long long *e = &hb[(((size_t)r * 2 + ph) * kMaxBlocks + b) * kBlkFields];
-        fprintf(f, "%d,%d,%d,%lld,%lld,%lld,%lld\n", r + 1, ph, b, e[0], e[1], e[2], e[3]);
+        fprintf(f, "%d,%d,%d,%lld,%lld,%lld,%lld,%lld\n", r + 1, ph, b, e[0], e[1], e[2], e[3],
+                e[4]);
       }
   fclose(f);
   return SSSP_OK;

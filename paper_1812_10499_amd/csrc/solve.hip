@@ -257,6 +257,7 @@ struct PhaseWork {
   int windows = 0;
   int first_item = -1;
   uint32_t units = 0;
+  long long t_mid = 0;  // wall-clock after the list windows (before the flush or live pass)
   int32_t bmin = 0, bthr = 0;  // single solve: the block's minD / thr offers
 };
 
@@ -447,15 +448,19 @@ __device__ int find_start_item(const int32_t *lp, int N, uint32_t c, uint32_t e0
   return lo;
 }
 
-// last window position p in [0, WIN) with pfx[p] <= e
+// last window position p in [0, WIN) with pfx[p] <= e (pfx ascending, with
+// pfx[0] <= e): an 8-ary search, four dependent LDS steps instead of ten
+static_assert(WIN == 1024, "window_item splits 1024 = 8 * 8 * 8 * 2");
 __device__ __forceinline__ int window_item(const int32_t *pfx, uint32_t e) {
-  int lo = 0, len = WIN;
-  while (len > 1) {
-    const int half = len >> 1;
-    if ((uint32_t)pfx[lo + half] <= e) lo += half;
-    len -= half;
+  int lo = 0;
+#pragma unroll
+  for (int s = WIN / 8; s >= 2; s /= 8) {  // spans 128, 16, 2
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) c += (uint32_t)pfx[lo + k * s] <= e ? 1 : 0;
+    lo += c * s;
   }
-  return lo;
+  return (uint32_t)pfx[lo + 1] <= e ? lo + 1 : lo;
 }
 
 __device__ __forceinline__ uint32_t chunk_of(uint32_t E, uint32_t vnb) {
@@ -815,104 +820,127 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
       }
       const uint32_t ET = uni((uint32_t)etot);
       for (uint32_t cb = 0; cb < ET; cb += RBS * EPT) {
-        // gathers for all EPT edges are issued before any result is used
+        // Each step below issues the loads (or atomics) of all EPT edges
+        // before any result is read, so the EPT accesses of a lane overlap.
+        // Lanes past the window's last edge repeat it (a valid position)
+        // rather than branch around the loads: a conditional load whose
+        // result is merged back makes the compiler wait for it at once.
         int it[EPT];
-        int32_t pos[EPT], y[EPT], wt[EPT], cand[EPT], gy[EPT], eid[EPT];
-        unsigned long long key[EPT], dk[EPT];
-        bool val[EPT];
+        int32_t pos[EPT], y[EPT], wt[EPT], cand[EPT], gy[EPT], eid[EPT], wm[EPT];
+        unsigned long long key[EPT], dk[EPT], old[EPT];
+        bool val[EPT], doa[EPT], off[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           const uint32_t q = cb + (uint32_t)(j * RBS + tid);
           val[j] = q < ET;
-          it[j] = val[j] ? window_item(S.epfx, q) : 0;
-          pos[j] = S.epos[it[j]] + (int32_t)(q - (uint32_t)S.epfx[it[j]]);
+          const uint32_t qc = val[j] ? q : ET - 1u;
+          it[j] = window_item(S.epfx, qc);
+          pos[j] = S.epos[it[j]] + (int32_t)(qc - (uint32_t)S.epfx[it[j]]);
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          if (val[j]) {
-            // the edge id is the caller's CSR position (out_eid under a renumbering)
-            const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-            y[j] = G.out_dst[pos[j]];
-            wt[j] = G.out_w[pos[j]];
-            eid[j] = G.out_eid ? G.out_eid[pos[j]] : pos[j];
-          }
+          // the edge id is the caller's CSR position (out_eid under a
+          // renumbering; without one the load reads out_dst again)
+          const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
+          const int32_t *E = G.out_eid ? G.out_eid : G.out_dst;
+          y[j] = G.out_dst[pos[j]];
+          wt[j] = G.out_w[pos[j]];
+          eid[j] = E[pos[j]];
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          if (val[j]) {
-            cand[j] = V::add(S.dx[it[j]], wt[j]);
-            gy[j] = S.sb[it[j]] + y[j];
-            // may be stale: only filters the atomic, against contention on
-            // hot heads in the big rounds; a one-block phase goes straight
-            // to the atomic and saves the dependent load
-            dk[j] = pc.solo ? 0x7fffffffffffffffull : a.D64[gy[j]];
-          }
+          if (!graph_of<BATCH>(a, S.gi[it[j]]).out_eid) eid[j] = pos[j];
+          cand[j] = V::add(S.dx[it[j]], wt[j]);
+          gy[j] = S.sb[it[j]] + y[j];
         }
+        // The key read may be stale: it only filters the atomic, against
+        // contention on hot heads in the big rounds; a one-block phase goes
+        // straight to the atomic and saves the dependent load.
+        if (pc.solo) {
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) dk[j] = 0x7fffffffffffffffull;
+        } else {
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) dk[j] = a.D64[gy[j]];
+        }
+        wait_vector_memory();  // then the EPT atomics issue back to back
         // A float edge that leaves the cost unchanged (w below half an ulp)
-        // is an equal-cost parent.
+        // is an equal-cost parent.  Every in-edge of a reachable vertex is
+        // offered once, from a tail with its final cost, so the key ends at
+        // (cost, best parent).
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          val[j] = val[j] && cand[j] <= (int32_t)(dk[j] >> 32);
-          if (val[j]) key[j] = make_key(cand[j], eid[j], cand[j] == S.dx[it[j]]);
-        }
-        uint32_t nmask = 0, smask = 0;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-          // Every in-edge of a reachable vertex is offered once, from a tail
-          // with its final cost, so the key ends at (cost, best parent).
-          if (val[j] && key[j] < dk[j]) {
-            const unsigned long long old = atomicMin(&a.D64[gy[j]], key[j]);
-            const int32_t od = (int32_t)(old >> 32);
-            if (cand[j] < od) smask |= 1u << j;  // D itself decreased
-            if (od == V::INF) nmask |= 1u << j;  // first discovery
-          }
+          key[j] = make_key(cand[j], eid[j], cand[j] == S.dx[it[j]]);
+          doa[j] = val[j] && cand[j] <= (int32_t)(dk[j] >> 32) && key[j] < dk[j];
         }
 #pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (doa[j]) old[j] = atomicMin(&a.D64[gy[j]], key[j]);
+        // Offers to minD and thr.  With the key read first, every candidate
+        // below the D it read is offered, with its head's out_wmin, while
+        // the atomics are in flight.  That covers every value D[y] takes in
+        // the phase (the candidate that first brings D[y] to a value read a
+        // larger D), and a candidate that lost a race to a smaller one is
+        // at least y's final D, itself offered: both minima are exact.
+        // Without the key read, the atomic's old value decides.
+        if (!pc.solo) {
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) off[j] = val[j] && cand[j] < (int32_t)(dk[j] >> 32);
+        } else {
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) off[j] = doa[j] && cand[j] < (int32_t)(old[j] >> 32);
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (off[j]) wm[j] = graph_of<BATCH>(a, S.gi[it[j]]).out_wmin[y[j]];
+        uint32_t nmask = 0;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          if (doa[j] && (int32_t)(old[j] >> 32) == V::INF) nmask |= 1u << j;  // first discovery
+#pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          const bool sj = (smask >> j) & 1u;
           int32_t th = V::INF;
-          if (sj) {
-            // this candidate lowered D[y]: offer it to minD and thr
-            const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-            th = V::add(cand[j], G.out_wmin[y[j]]);
+          if (off[j]) {
+            th = V::add(cand[j], wm[j]);
             if constexpr (!BATCH) {
               lmin = kmin(lmin, cand[j]);
               ltmin = kmin(ltmin, th);
             }
           }
           if constexpr (BATCH)
-            batch_offer<V>(bl, a, s_now, sj, sj ? S.inst[it[j]] : 0, sj ? cand[j] : V::INF,
-                           th);
+            batch_offer<V>(bl, a, s_now, off[j], off[j] ? S.inst[it[j]] : 0,
+                           off[j] ? cand[j] : V::INF, th);
         }
         // first discoveries (queued for this round's bound step; D[y] can
         // only drop below cand before it runs): places in the stager by one
         // LDS atomic per wave; what does not fit goes to the global list
         {
-          const int nl = __popc(nmask);
-          const uint32_t incl = wave_incl_scan32((uint32_t)nl);
-          const int tot = __shfl((int)incl, SSSP_WAVE - 1, SSSP_WAVE);
+          static_assert(EPT < 8, "a lane's discoveries fit three bits");
+          uint32_t utot;
+          const uint32_t ex = wave_excl_small<3>((uint32_t)__popc(nmask), &utot);
+          const int tot = (int)utot;
           if (tot) {
-            int old = 0;
-            if (lane_id() == 0) old = atomicAdd(&S.st.cnt, tot);
-            old = __shfl(old, 0, SSSP_WAVE);
-            int pos = old + (int)incl - nl;
+            int wbase = 0;
+            if (lane_id() == 0) wbase = atomicAdd(&S.st.cnt, tot);
+            wbase = __shfl(wbase, 0, SSSP_WAVE);
+            int sp = wbase + (int)ex;
             int32_t ni[EPT];
             uint32_t over = 0;
 #pragma unroll
             for (int j = 0; j < EPT; ++j) {
               ni[j] = S.inst[it[j]];
               if ((nmask >> j) & 1u) {
-                if (pos < CAP_R) {
-                  S.st.v[pos] = gy[j];
-                  S.st.d[pos] = cand[j];
-                  S.st.inst[pos] = ni[j];
+                if (sp < CAP_R) {
+                  S.st.v[sp] = gy[j];
+                  S.st.d[sp] = cand[j];
+                  S.st.inst[sp] = ni[j];
                 } else {
                   over |= 1u << j;
                 }
-                ++pos;
+                ++sp;
               }
             }
-            if (old + tot > CAP_R)  // wave-uniform
+            if (wbase + tot > CAP_R)  // wave-uniform
               relax_push_global<V, BATCH>(a, olist, Cold, md_prev, r, over, gy, cand, ni);
           }
         }
@@ -925,6 +953,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
     }
   }
   __syncthreads();
+  if (a.trace_blk) pw.t_mid = (long long)wall_clock64();
   // the phase's discoveries to the open list (S.st.cnt is current); what
   // did not fit went to the list during the phase
   relax_flush<V, BATCH>(a, S.st, olist, Cold, md_prev, r, sm);
@@ -1207,33 +1236,42 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
       }
       const uint32_t ET = uni((uint32_t)etot);
       for (uint32_t cb = 0; cb < ET; cb += RBS * EPT) {
+        // As in the relax step: lanes past the window's last edge repeat it,
+        // so that the EPT loads of a step issue together, unconditionally.
         int it[EPT];
-        int32_t pos[EPT], v[EPT], wt[EPT], cv[EPT];
+        int32_t pos[EPT], v[EPT], wt[EPT], cv[EPT], sbv[EPT], dyv[EPT];
         bool val[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
           const uint32_t q = cb + (uint32_t)(j * RBS + tid);
           val[j] = q < ET;
-          it[j] = val[j] ? window_item(S.epfx, q) : 0;
-          pos[j] = S.base[it[j]] + S.eoff[it[j]] + (int32_t)(q - (uint32_t)S.epfx[it[j]]);
+          const uint32_t qc = val[j] ? q : ET - 1u;
+          it[j] = window_item(S.epfx, qc);
+          pos[j] = S.base[it[j]] + S.eoff[it[j]] + (int32_t)(qc - (uint32_t)S.epfx[it[j]]);
+          sbv[j] = S.sb[it[j]];
+          dyv[j] = S.dy[it[j]];
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          if (val[j]) {
-            const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-            v[j] = G.in_src[pos[j]];
-            wt[j] = G.in_w[pos[j]];
-          }
+          const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
+          v[j] = G.in_src[pos[j]];
+          wt[j] = G.in_w[pos[j]];
         }
+        // the loaded values count as used here: no load moves into the
+        // gather's condition below
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) asm volatile("" : "+v"(v[j]), "+v"(wt[j]));
         // An in-edge can only lower min(D[y], m_y) below D[y] if
         // minD + w < D[y]: its term max(C[v], minD) + w is at least
         // minD + w (rounding is monotone).  Every other edge leaves C'[y]
         // exactly as it is, so its tail's lower bound is not gathered.
+        // Every lane gathers (a filtered one reads entry 0: one line for all
+        // of them), so that no load sits in a branch.
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          const int32_t md = BATCH ? (val[j] ? S.mind[it[j]] : 0) : mind_all;
-          val[j] = val[j] && V::add(md, wt[j]) < S.dy[it[j]];
-          if (val[j]) cv[j] = Cold[S.sb[it[j]] + v[j]];
+          const int32_t md = BATCH ? S.mind[it[j]] : mind_all;
+          val[j] = val[j] & (V::add(md, wt[j]) < dyv[j]);
+          cv[j] = Cold[val[j] ? sbv[j] + v[j] : 0];
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -1382,6 +1420,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
     }
   }
   stage_flush2(S.fr, front, S.op, next_open, BATCH);
+  if (a.trace_blk) pw.t_mid = (long long)wall_clock64();
   if (NL > 0) {
     __syncthreads();  // the live pass reuses the stagers' LDS
     live_pass<V, BATCH>(a, sm, bl, pc, r, NL, mind_all, Cold, Cnew);
@@ -1607,6 +1646,7 @@ __global__ __launch_bounds__(RBS) void rounds_kernel(RoundArgs a) {
       tb[1] = pw.windows;
       tb[2] = pw.first_item;
       tb[3] = pw.units;
+      tb[4] = pw.t_mid;
     }
     if (tr && bid == 0 && tid == 0) tr[phase == 0 ? TR_ARR_RELAX : TR_ARR_FUSED] = (long long)wall_clock64();
     if (solo) {

@@ -110,6 +110,23 @@ __device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v) {
   return v;
 }
 
+// Exclusive prefix over the wave of a per-lane count below 2^B, and the
+// wave's total: one ballot and one lane-mask count per bit, no LDS.
+template <int B>
+__device__ __forceinline__ uint32_t wave_excl_small(uint32_t v, uint32_t *total) {
+  uint32_t ex = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    const unsigned long long m = __ballot((v >> k) & 1u);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    ex += below << k;
+    tot += (uint32_t)__popcll(m) << k;
+  }
+  *total = tot;
+  return ex;
+}
+
 // Block-wide exclusive scan of a uint64 per thread.  `scratch` must hold
 // BS/64 + 1 entries of LDS.  Returns the exclusive prefix; *total gets the
 // block sum.  Contains __syncthreads(); call from all threads.
@@ -228,6 +245,12 @@ __device__ __forceinline__ void wait_own_stores() {
   // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15): only vector memory counts
   __builtin_amdgcn_s_waitcnt(0x0F70);
 }
+
+// Waits for every vector memory access this wave has in flight.  Placed
+// after a group of independent loads, it lets the accesses that depend on
+// them issue back to back: the counter is in order, so a value needed
+// between two of them would otherwise make the later wait for the earlier.
+__device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __device__ __forceinline__ unsigned int ld_flag(const unsigned int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

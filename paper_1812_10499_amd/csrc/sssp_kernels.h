@@ -105,8 +105,8 @@ struct RoundArgs {
   int32_t trace_rounds;
   int32_t trace_blk_rounds;  // rounds with per-block records
   // [round][2 phases][kMaxBlocks][kBlkFields]: per block, the wall-clock at
-  // its phase end, the list windows it walked, its first list item and the
-  // work units of its chunk
+  // its phase end, the list windows it walked, its first list item, the
+  // work units of its chunk and the wall-clock after its list windows
   long long *trace_blk;
   // optional checkpoints: one block's wall-clock at fixed points inside each
   // phase, [round][2 phases][kMarks]
@@ -139,7 +139,7 @@ enum TraceField {
   TR_NF, TR_EF, TR_NO, TR_EO, TR_MODE, TR_NL, kTraceFields
 };
 
-constexpr int kBlkFields = 4;
+constexpr int kBlkFields = 5;
 constexpr int kMarks = 12;
 
 struct LaunchGeom {

@@ -30,10 +30,23 @@ def _read_trace(path):
     if os.path.exists(path + ".blk"):
         with open(path + ".blk") as fh:
             for line in fh:
-                r, ph, b, end, win, first, units = (int(x) for x in line.split(","))
+                r, ph, b, end, win, first, units, mid = (int(x) for x in line.split(","))
                 if end:
-                    blk.setdefault((r, ph), []).append(end)
+                    blk.setdefault((r, ph), []).append((end, mid))
     return rows, blk
+
+
+def _blocks(recs, start):
+    """Mean over the blocks that ran a phase of the time to the end of their
+    list windows and from there to their phase end, and max minus mean of
+    the phase ends: what a perfect balance of the phase would save."""
+    if not recs:
+        return "-"
+    ends = [(e - start) * TICK_US for e, _ in recs]
+    mids = [(m - start) * TICK_US for _, m in recs]
+    mean_end = sum(ends) / len(ends)
+    mean_mid = sum(mids) / len(mids)
+    return "%.1f / %.1f / %.1f" % (mean_mid, mean_end - mean_mid, max(ends) - mean_end)
 
 
 def summarize(rows, blk, kernel_ms, title, cmd):
@@ -43,10 +56,14 @@ def summarize(rows, blk, kernel_ms, title, cmd):
            "their useful in-edges (weight prefix); L = live undiscovered vertices (scope ALL); "
            "act = active blocks (relax/bound); work = block 0 from phase start to barrier "
            "arrival; wait = block 0 at the barrier; spread = last minus first block's phase "
-           "end (blocks that ran the phase). Times in microseconds.", "",
+           "end (blocks that ran the phase). The blocks columns are means over the blocks that "
+           "ran the phase: time in list windows / time after them (relax: the flush of first "
+           "discoveries with their in-edge counts; bound: the list flushes and the live pass) / "
+           "the last block's phase end minus the mean (what perfect balance would save). Times "
+           "in microseconds.", "",
            "| round | F | EF | O | EO | L | act | relax work | relax wait | relax spread | "
-           "bound work | bound wait | bound spread |",
-           "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+           "relax blocks | bound work | bound wait | bound spread | bound blocks |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
     tot = dict(rw=0.0, rwa=0.0, bw=0.0, bwa=0.0)
     t_first = t_last = None
     for r in rows:
@@ -61,18 +78,21 @@ def summarize(rows, blk, kernel_ms, title, cmd):
         bwa = (ef - af) * TICK_US if af else 0.0
         t_first = st if t_first is None else t_first
         t_last = max(ef, er)
-        sp = []
+        sp, bk = [], []
         for ph in (0, 1):
-            ends = blk.get((rd, ph))
+            recs = blk.get((rd, ph))
+            ends = [e for e, _ in recs] if recs else None
             sp.append("%.1f" % ((max(ends) - min(ends)) * TICK_US) if ends and len(ends) > 1
                       else "-")
+            bk.append(_blocks(recs, st if ph == 0 else er))
         tot["rw"] += rw
         tot["rwa"] += rwa
         tot["bw"] += bw
         tot["bwa"] += bwa
-        out.append("| %d | %s | %s | %s | %s | %s | %d/%d | %.1f | %.1f | %s | %.1f | %.1f | %s |"
+        out.append("| %d | %s | %s | %s | %s | %s | %d/%d | %.1f | %.1f | %s | %s | %.1f | %.1f | "
+                   "%s | %s |"
                    % (rd, r["nf"], r["ef"], r["no"], r["eo"], r["nl"], act_r, act_b, rw, rwa,
-                      sp[0], bw, bwa, sp[1]))
+                      sp[0], bk[0], bw, bwa, sp[1], bk[1]))
     span = (t_last - t_first) * TICK_US if t_first is not None else 0.0
     out += ["", "Totals over %d rounds (block 0): relax work %.1f us, relax barrier wait %.1f us,"
             " bound work %.1f us, bound barrier wait %.1f us; first phase start to last "
