@@ -504,12 +504,16 @@ constexpr int32_t kNoCount = 0x40000000;  // above any list position
 // lightest in-edge), the second lightest in-edge and both tails' lower
 // bounds, then the weight searches in lockstep.  gy is a state index, dy
 // the discovering candidate; md is the minD of an earlier round (md_prev, or
-// per instance in a batch).
+// per instance in a batch).  With a payload array, entry k's open-list
+// payload is returned too (read with the vertex record): in-offset,
+// in-degree as -1 - in-degree (the mark of a first discovery), out-offset,
+// out-degree, out_wmin and C (0, or under scope ALL what the live pass
+// raised it to).
 template <class V, bool BATCH, int K>
 __device__ void discovery_work_x(const RoundArgs &a, const int32_t *Cold, uint32_t valid,
                                  const int32_t (&gy)[K], const int32_t (&dy)[K],
                                  const int32_t (&ins)[K], int32_t md_prev, int r,
-                                 int32_t (&out)[K]) {
+                                 int32_t (&out)[K], int32_t (*pay)[K] = nullptr) {
   int32_t sb[K], gi[K], md[K], b[K], deg[K], v0[K], w0[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -535,6 +539,14 @@ __device__ void discovery_work_x(const RoundArgs &a, const int32_t *Cold, uint32
       deg[k] = rec.w;
       v0[k] = rec2.y;  // the lightest in-edge's tail and weight
       w0[k] = rec2.z;
+      if (pay) {
+        pay[OX_BASE][k] = rec.z;
+        pay[OX_IDEG][k] = -1 - rec.w;
+        pay[OX_OOFF][k] = rec.x;
+        pay[OX_ODEG][k] = rec.y;
+        pay[OX_OWM][k] = rec2.x;
+        pay[OX_C][k] = G.all ? Cold[gy[k]] : 0;
+      }
     }
   }
   // short lists are taken whole; longer ones probe their two lightest edges
@@ -628,8 +640,8 @@ __device__ void discovery_work_x(const RoundArgs &a, const int32_t *Cold, uint32
 // that made its contents current).  Thread t takes the entries 4t .. 4t+3
 // and counts their useful in-edges, so the searches of a flush run side by
 // side; one block scan and one atomicAdd reserve the list slots and the
-// work range.  Entries carry the "no payload" mark: the bound step reads the
-// vertex record.
+// work range.  Entries carry their payload, read with the count, so the
+// bound step need not read the vertex record.
 template <class V, bool BATCH>
 __device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l,
                             const int32_t *Cold, int32_t md_prev, int r, SmemAll &sm) {
@@ -637,7 +649,7 @@ __device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l
   if (cnt == 0) return;  // uniform
   constexpr int PER = CAP_R / RBS;
   const int j0 = threadIdx.x * PER;
-  int32_t work[PER], gy[PER], dy[PER], ins[PER];
+  int32_t work[PER], gy[PER], dy[PER], ins[PER], pay[kOX][PER];
   uint32_t valid = 0;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
@@ -649,7 +661,7 @@ __device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l
       ins[k] = st.inst[j0 + k];
     }
   }
-  discovery_work_x<V, BATCH, PER>(a, Cold, valid, gy, dy, ins, md_prev, r, work);
+  discovery_work_x<V, BATCH, PER>(a, Cold, valid, gy, dy, ins, md_prev, r, work, pay);
   uint32_t sum = 0;
 #pragma unroll
   for (int k = 0; k < PER; ++k) sum += (uint32_t)work[k];
@@ -668,7 +680,8 @@ __device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l
       l.v[bc + j] = st.v[j];
       l.p[bc + j] = (int32_t)p;
       if (BATCH) l.i[bc + j] = st.inst[j];
-      if (l.x[0]) l.x[0][bc + j] = -1;
+#pragma unroll
+      for (int q = 0; q < kOX; ++q) l.x[q][bc + j] = pay[q][k];
       p += (uint32_t)work[k];
     }
   }
@@ -678,7 +691,8 @@ __device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l
 }
 
 // Discoveries a wave could not place in the stager (it was full): straight
-// to the global list, one atomicAdd for the wave.  All lanes of the wave
+// to the global list, one atomicAdd for the wave, with the "no payload"
+// mark (the bound step reads their vertex records).  All lanes of the wave
 // call it; mask selects the lane's entries among its EPT candidates.
 template <class V, bool BATCH>
 __device__ void relax_push_global(const RoundArgs &a, const ListRef &l, const int32_t *Cold,
@@ -729,9 +743,10 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
   const int I = a.num_inst;
   Ctl *ctl = a.ctl;
   // first discoveries go to this round's open list, marked "no payload"
+  int32_t *const *Oxw = cur ? a.open_x1 : a.open_x0;
   const ListRef olist = {&ctl->open_ctr[cur], cur ? a.open_v1 : a.open_v0,
                          cur ? a.open_p1 : a.open_p0, cur ? a.open_i1 : a.open_i0,
-                         {cur ? a.open_x1[OX_BASE] : a.open_x0[OX_BASE]}};
+                         {Oxw[0], Oxw[1], Oxw[2], Oxw[3], Oxw[4], Oxw[5]}};
   int32_t *Cnew = cur ? a.C0 : a.C1;
   const int32_t *Cold = cur ? a.C1 : a.C0;  // what this round's bound step reads
   if constexpr (BATCH) {
@@ -1180,12 +1195,20 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           S.thr[tid] = ld_relaxed(&a.ithr[s_now * I + ins]);
         }
         const GraphDev &G = graph_of<BATCH>(a, gi);
-        // everything the item's finish needs: carried by a survivor's entry,
-        // or (first discovery, no payload) one vertex record with C = 0
+        S.dy[tid] = ld_relaxed(key_d(&a.D64[gy]));
+        // everything the item's finish needs, carried by its entry (a first
+        // discovery's in-degree as -1 - in-degree), or (first discovery, no
+        // payload) one vertex record with C = 0
         int32_t xv[kOX];
 #pragma unroll
         for (int k = 0; k < kOX; ++k) xv[k] = Ox[k][idx];
-        if (xv[OX_BASE] < 0) {
+        // (the no-payload mark first: the other words of such an entry are
+        // left over from an earlier list)
+        if (xv[OX_BASE] >= 0 && xv[OX_IDEG] < 0) {
+          xv[OX_IDEG] = -1 - xv[OX_IDEG];
+          // the probe may have cut its scan short of the weight prefix
+          if (xv[OX_IDEG] > 16) S.cnt[tid] = kNoCount;
+        } else if (xv[OX_BASE] < 0) {
           const int32_t yl = gy - sb;
           const int4 rec = G.vrec[2 * yl];  // out_off, out_degree, in_off, in_degree
           xv[OX_BASE] = rec.z;
@@ -1205,7 +1228,6 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
         S.odeg[tid] = xv[OX_ODEG];
         S.owm[tid] = xv[OX_OWM];
         S.cy[tid] = xv[OX_C];
-        S.dy[tid] = ld_relaxed(key_d(&a.D64[gy]));
         S.sb[tid] = sb;
         S.gi[tid] = gi;
         S.inst[tid] = ins;

@@ -35,9 +35,12 @@ enum PartSlot {
 // an open one (label-correcting relax) its D with bit 31 set (D keys are
 // non-negative, so the bit is free).  An open item pushed as a survivor
 // carries what its next bound step needs, so neither phase gathers them.
-// An open item pushed by relax (a first discovery) carries OX_BASE = -1:
-// the bound step then reads the vertex record, and C (0, or under scope
-// ALL what the live pass raised it to).
+// An open item pushed by relax (a first discovery) carries the same words,
+// read from its vertex record when the relax step counts its work, with
+// OX_IDEG = -1 - in-degree (the mark of a first discovery); one pushed when
+// the relax stager was full carries OX_BASE = -1 instead: the bound step
+// then reads the vertex record, and C (0, or under scope ALL what the live
+// pass raised it to).
 constexpr int32_t kOpenRelax = (int32_t)0x80000000;
 enum { FX_OOFF = 0, FX_D, kFX };
 enum { OX_BASE = 0, OX_IDEG, OX_OOFF, OX_ODEG, OX_OWM, OX_C, kOX };
