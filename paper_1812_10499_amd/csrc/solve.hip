@@ -49,7 +49,9 @@ namespace sssp {
 constexpr int RBS = kRoundBlock;  // threads per block of the round kernel
 constexpr int EPT = 4;            // edges per thread per sub-chunk
 constexpr int WIN = RBS;          // list items per window
-constexpr int CAP_R = RBS * EPT;  // relax: block staging capacity of first discoveries
+// relax: block staging capacity of first discoveries (what does not fit
+// goes to the open list without a payload, its work counted inline)
+constexpr int CAP_R = RBS * 7;
 constexpr int CAP_F = RBS;        // bound-and-fix staging capacity per list (>= one window)
 constexpr uint32_t CW_RELAX = 4;  // work units per frontier item (its loads and list entry)
 constexpr uint32_t CW_FUSED = 16; // work units per open item (loads, decision, list entry)
@@ -636,18 +638,13 @@ __device__ void discovery_work_x(const RoundArgs &a, const int32_t *Cold, uint32
   }
 }
 
-// Block-collective flush of the relax stager (all threads, after a barrier
-// that made its contents current).  Thread t takes the entries 4t .. 4t+3
-// and counts their useful in-edges, so the searches of a flush run side by
-// side; one block scan and one atomicAdd reserve the list slots and the
-// work range.  Entries carry their payload, read with the count, so the
-// bound step need not read the vertex record.
+// One pass of the flush below: the stager's entries [off, off + cnt),
+// thread t taking off + 4t .. off + 4t + 3.
 template <class V, bool BATCH>
-__device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l,
-                            const int32_t *Cold, int32_t md_prev, int r, SmemAll &sm) {
-  const int cnt = st.cnt < CAP_R ? st.cnt : CAP_R;
-  if (cnt == 0) return;  // uniform
-  constexpr int PER = CAP_R / RBS;
+__device__ void relax_flush_pass(const RoundArgs &a, RelaxStage &st, const ListRef &l,
+                                 const int32_t *Cold, int32_t md_prev, int r, SmemAll &sm,
+                                 int off, int cnt) {
+  constexpr int PER = 4;
   const int j0 = threadIdx.x * PER;
   int32_t work[PER], gy[PER], dy[PER], ins[PER], pay[kOX][PER];
   uint32_t valid = 0;
@@ -656,9 +653,9 @@ __device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l
     gy[k] = dy[k] = ins[k] = 0;
     if (j0 + k < cnt) {
       valid |= 1u << k;
-      gy[k] = st.v[j0 + k];
-      dy[k] = st.d[j0 + k];
-      ins[k] = st.inst[j0 + k];
+      gy[k] = st.v[off + j0 + k];
+      dy[k] = st.d[off + j0 + k];
+      ins[k] = st.inst[off + j0 + k];
     }
   }
   discovery_work_x<V, BATCH, PER>(a, Cold, valid, gy, dy, ins, md_prev, r, work, pay);
@@ -677,15 +674,29 @@ __device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l
   for (int k = 0; k < PER; ++k) {
     const int j = j0 + k;
     if (j < cnt) {
-      l.v[bc + j] = st.v[j];
+      l.v[bc + j] = gy[k];
       l.p[bc + j] = (int32_t)p;
-      if (BATCH) l.i[bc + j] = st.inst[j];
+      if (BATCH) l.i[bc + j] = ins[k];
 #pragma unroll
       for (int q = 0; q < kOX; ++q) l.x[q][bc + j] = pay[q][k];
       p += (uint32_t)work[k];
     }
   }
-  __syncthreads();
+  __syncthreads();  // st.base is read before the next pass writes it
+}
+
+// Block-collective flush of the relax stager (all threads, after a barrier
+// that made its contents current), in passes of four entries per thread:
+// a thread counts the useful in-edges of its four side by side; one block
+// scan and one atomicAdd per pass reserve the list slots and the work
+// range.  Entries carry their payload, read with the count, so the bound
+// step need not read the vertex record.
+template <class V, bool BATCH>
+__device__ void relax_flush(const RoundArgs &a, RelaxStage &st, const ListRef &l,
+                            const int32_t *Cold, int32_t md_prev, int r, SmemAll &sm) {
+  const int all = st.cnt < CAP_R ? st.cnt : CAP_R;
+  for (int off = 0; off < all; off += 4 * RBS)
+    relax_flush_pass<V, BATCH>(a, st, l, Cold, md_prev, r, sm, off, min(all - off, 4 * RBS));
   if (threadIdx.x == 0) st.cnt = 0;
   __syncthreads();
 }
