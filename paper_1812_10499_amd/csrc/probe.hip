@@ -6,7 +6,8 @@
 //    (U independent gathers in flight per thread), as the relax and bound
 //    steps gather D and C;
 //  - gather then 64-bit atomicMin where the key is smaller (the relax
-//    step's pre-filtered update);
+//    step's pre-filtered update), also with a set share of atomics;
+//  - gathers folded into per-XCD ranges of the array (L2 locality);
 //  - a dependent-load chain (one lane follows next[] pointers), the latency
 //    of one step of a round's critical path at a given working-set size;
 //  - block barriers (__syncthreads) in one 1024-thread workgroup, and the
@@ -69,6 +70,67 @@ __global__ __launch_bounds__(256) void gather_atomic_k(unsigned long long *arr,
   out[tid] = acc;
 }
 
+// Gathers whose indices are folded into one of `parts` equal ranges of the
+// array, the range chosen by the block: part (block / div) % parts.  With
+// div = 1 the blocks of one XCD (workgroups go to the XCDs round-robin)
+// share one range; with div = parts, every range is read from every XCD.
+template <class T>
+__global__ __launch_bounds__(256) void gather_part_k(const T *__restrict__ arr,
+                                                     const uint32_t *__restrict__ idx, int64_t n,
+                                                     T *out, uint32_t span, int parts, int div) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint32_t lo = ((blockIdx.x / div) % parts) * span;
+  T acc = (T)-1;
+  for (int64_t b = tid; b < n; b += stride * U) {
+    uint32_t ix[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = b + (int64_t)u * stride;
+      ix[u] = i < n ? lo + idx[i] % span : lo;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = arr[ix[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = v[u] < acc ? v[u] : acc;
+  }
+  out[tid] = acc;
+}
+
+// The relax step's update with a given share of atomics: every edge's key
+// is gathered, and one edge in `every` whose index is at least `cut`
+// carries the key 0, at most every stored one, so it issues a 64-bit
+// atomicMin (the others carry the largest key and are filtered out).  With
+// the cut above the hubs, a vertex takes few atomics, as in the relax step
+// (its pre-filter keeps nearly all atomics off the hubs).
+__global__ __launch_bounds__(256) void gather_atomic_every_k(unsigned long long *arr,
+                                                             const uint32_t *__restrict__ idx,
+                                                             int64_t n, unsigned long long *out,
+                                                             int every, uint32_t cut) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long acc = 0;
+  for (int64_t b = tid; b < n; b += stride * U) {
+    uint32_t ix[U];
+    unsigned long long k[U], d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = b + (int64_t)u * stride;
+      ix[u] = i < n ? idx[i] : 0u;
+      k[u] = (i % every == 0 && ix[u] >= cut) ? 0ull : ~0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) d[u] = arr[ix[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = b + (int64_t)u * stride;
+      if (i < n && k[u] <= d[u]) acc += atomicMin(&arr[ix[u]], k[u]);
+    }
+  }
+  out[tid] = acc;
+}
+
 // Each of the 64 lanes of one wave follows next[] for `steps` dependent
 // loads from its own start (a per-lane address keeps them vector loads);
 // the wave waits for its slowest lane at every step.
@@ -122,6 +184,25 @@ int probe_gather_atomic(void *arr, const uint32_t *idx, int64_t n, void *out, in
                         void *stream) {
   hipLaunchKernelGGL(gather_atomic_k, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                      (unsigned long long *)arr, idx, n, (unsigned long long *)out);
+  return (int)hipGetLastError();
+}
+
+int probe_gather_part(int width, const void *arr, const uint32_t *idx, int64_t n, void *out,
+                      int blocks, uint32_t span, int parts, int div, void *stream) {
+  if (width == 8)
+    hipLaunchKernelGGL(gather_part_k<unsigned long long>, dim3(blocks), dim3(256), 0,
+                       (hipStream_t)stream, (const unsigned long long *)arr, idx, n,
+                       (unsigned long long *)out, span, parts, div);
+  else
+    hipLaunchKernelGGL(gather_part_k<uint32_t>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const uint32_t *)arr, idx, n, (uint32_t *)out, span, parts, div);
+  return (int)hipGetLastError();
+}
+
+int probe_gather_atomic_every(void *arr, const uint32_t *idx, int64_t n, void *out, int blocks,
+                              int every, uint32_t cut, void *stream) {
+  hipLaunchKernelGGL(gather_atomic_every_k, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                     (unsigned long long *)arr, idx, n, (unsigned long long *)out, every, cut);
   return (int)hipGetLastError();
 }
 

@@ -9,7 +9,11 @@ Measures, on device 0:
     out-edge heads in CSR order (the relax step's pattern), and 4-byte
     values along its in-edge tails (the bound step's pattern), with 8
     independent gathers in flight per thread;
-  * the relax step's update: gather, then 64-bit atomicMin where smaller;
+  * the relax step's update: gather, then 64-bit atomicMin where smaller,
+    and with a set share of the edges issuing the atomic (1 in 1, 4, 16,
+    64);
+  * gathers folded into eighths of the array, one eighth per XCD or every
+    eighth from every XCD (what L2 locality per XCD would buy);
   * dependent-load latency: the 64 lanes of one wave each following a
     random cycle through arrays of 2 MB (fits a 4 MB L2), 64 MB (fits the
     256 MB Infinity Cache, not an L2) and 1 GB (HBM);
@@ -35,6 +39,10 @@ def _lib():
     vp, i64 = ctypes.c_void_p, ctypes.c_int64
     L.probe_gather.argtypes = [ctypes.c_int, vp, vp, i64, vp, ctypes.c_int, vp]
     L.probe_gather_atomic.argtypes = [vp, vp, i64, vp, ctypes.c_int, vp]
+    L.probe_gather_part.argtypes = [ctypes.c_int, vp, vp, i64, vp, ctypes.c_int, ctypes.c_uint32,
+                                    ctypes.c_int, ctypes.c_int, vp]
+    L.probe_gather_atomic_every.argtypes = [vp, vp, i64, vp, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_uint32, vp]
     L.probe_chase.argtypes = [vp, vp, i64, vp, vp]
     L.probe_sync.argtypes = [ctypes.c_int, vp, vp]
     L.probe_grid_sync.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp]
@@ -163,6 +171,33 @@ def main():
                                                 out.data_ptr(), blocks, st)), pre=fill)
     rows.append(("gather + 64-bit atomicMin where smaller, RMAT-22 heads",
                  "%.1f G edges/s" % (M / ms / 1e6), "%.3f ms for 2^26" % ms))
+    # the same with a set share of atomics, kept off the hubs (the relax
+    # step issues one for about 7 % of its edges, nearly none into the 4096
+    # heaviest vertices); the atomics' share is counted on the host
+    fill_lo = lambda: a64.fill_(1 << 40)
+    h = heads.cpu().numpy()
+    pos = np.arange(M)
+    for every, cut in ((64, 65536), (16, 65536), (8, 65536), (4, 65536), (1, 65536),
+                       (16, 0)):
+        share = float(((pos % every == 0) & (h >= cut)).mean())
+        ms = timed(lambda: ok(L.probe_gather_atomic_every(a64.data_ptr(), heads.data_ptr(), M,
+                                                          out.data_ptr(), blocks, every, cut,
+                                                          st)),
+                   pre=fill_lo)
+        rows.append(("gather + 64-bit atomicMin on %.1f %% of the edges (1 in %d, heads >= %d)"
+                     ", RMAT-22 heads" % (100 * share, every, cut),
+                     "%.1f G edges/s, %.2f G atomics/s" % (M / ms / 1e6, share * M / ms / 1e6),
+                     "%.3f ms for 2^26" % ms))
+    del h, pos
+    # L2 locality: gathers folded into eighths of the array, one eighth per
+    # XCD (blocks round-robin over the XCDs) or every eighth from every XCD
+    span = N // 8
+    for label, div in (("one eighth per XCD", 1), ("each eighth from all XCDs", 8)):
+        for name, idx in (("uniform indices", uni), ("RMAT-22 heads", heads)):
+            ms = timed(lambda: ok(L.probe_gather_part(8, a64.data_ptr(), idx.data_ptr(), M,
+                                                      out.data_ptr(), blocks, span, 8, div, st)))
+            rows.append(("8-byte gather folded into eighths, %s, %s" % (label, name),
+                         "%.1f G gathers/s" % (M / ms / 1e6), "%.3f ms for 2^26" % ms))
     del uni
     for label, nbytes in (("2 MB (L2)", 2 << 20), ("64 MB (Infinity Cache)", 64 << 20),
                           ("1 GB (HBM)", 1 << 30)):

@@ -182,6 +182,6 @@ def test_probe_library_exports(sp):
         from paper_1812_10499_amd import build
         build.build()
     L = ctypes.CDLL(PROBE_SO)
-    for name in ("probe_gather", "probe_gather_atomic", "probe_chase", "probe_sync",
-                 "probe_grid_sync"):
+    for name in ("probe_gather", "probe_gather_atomic", "probe_gather_atomic_every",
+                 "probe_gather_part", "probe_chase", "probe_sync", "probe_grid_sync"):
         assert hasattr(L, name), name
