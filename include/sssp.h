@@ -261,6 +261,23 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
 sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream);
 
 /*
+ * Per-edge values between the caller's COO order and edge-id order, for
+ * the weights w(e) of the problem statement (Section I) and gradients with
+ * respect to them: the edge ids are CSR positions, and perm (device, m
+ * entries, as sssp_build_csr writes it) holds perm[k] = COO index of edge
+ * id k, a permutation of 0 .. m-1.
+ *   to_coo = 0: out[k] = in[perm[k]]   (COO order -> edge-id order);
+ *   to_coo = 1: out[perm[k]] = in[k]   (edge-id order -> COO order).
+ * in, out: device arrays of m 4-byte values (float32 or int32), caller
+ * owned; they must not overlap.  SSSP_ERR_ARG for m < 0, or a null pointer
+ * or in == out with m > 0.  A perm that is not a permutation of 0 .. m-1
+ * is not checked (out-of-range entries read or write out of bounds).
+ * Asynchronous on `stream`.
+ */
+sssp_status sssp_permute_edges(const int32_t *perm, int64_t m, const void *in, void *out,
+                               int32_t to_coo, void *stream);
+
+/*
  * Single-source shortest paths by rounds of the lower/upper-bound method.
  *   cost[n] (device, dtype of g): cost[x] = minimum path cost (Section I),
  *           INF if x is unreachable.

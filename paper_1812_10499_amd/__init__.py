@@ -16,7 +16,8 @@ from ._abi import (  # noqa: F401
     KERNELS, Policy, SSSPError, Stats, lib, sssp_backward, sssp_check, sssp_policy_of,
     sssp_set_round_limit, sssp_profile_enable, sssp_profile_read,
     sssp_build_csr, sssp_build_csr_bytes, sssp_release_workspace, sssp_set_weights, sssp_solve,
-    sssp_solve_batch, sssp_solve_noalloc, sssp_solve_target, sssp_strerror, sssp_set_launch, sssp_plan_create,
+    sssp_solve_batch, sssp_solve_noalloc, sssp_solve_target, sssp_strerror, sssp_set_launch,
+    sssp_permute_edges, sssp_plan_create,
     sssp_plan_run, sssp_plan_stats, sssp_plan_destroy, sssp_autotune)
 from .graph import (  # noqa: F401
     I32_INF, Graph, Plan, SSSPFunction, autotune, backward, batch_layout, check,

@@ -30,7 +30,7 @@ EXPORTS = ("sssp_build_csr_bytes", "sssp_build_csr", "sssp_set_weights", "sssp_s
            "sssp_plan_create", "sssp_plan_run", "sssp_plan_stats", "sssp_plan_destroy",
            "sssp_autotune", "sssp_release_workspace", "sssp_strerror",
            "sssp_profile_enable", "sssp_profile_read", "sssp_check", "sssp_set_round_limit",
-           "sssp_policy_of", "sssp_solve_noalloc")
+           "sssp_policy_of", "sssp_solve_noalloc", "sssp_permute_edges")
 KERNELS = {0: "rounds_kernel", 1: "wg_rounds_kernel", 2: "small_rounds_kernel"}
 
 
@@ -101,6 +101,8 @@ def lib():
         L.sssp_build_csr.restype = ctypes.c_int
         L.sssp_set_weights.argtypes = [ctypes.POINTER(Csr), vp, vp]
         L.sssp_set_weights.restype = ctypes.c_int
+        L.sssp_permute_edges.argtypes = [vp, ctypes.c_int64, vp, vp, i32, vp]
+        L.sssp_permute_edges.restype = ctypes.c_int
         L.sssp_solve.argtypes = [ctypes.POINTER(Csr), i32, vp, vp, ctypes.POINTER(Stats), vp]
         L.sssp_solve.restype = ctypes.c_int
         L.sssp_solve_noalloc.argtypes = [ctypes.POINTER(Csr), i32, vp, vp,
@@ -192,6 +194,11 @@ def sssp_build_csr(n, m, dtype, order, src, dst, w, buffer, buffer_bytes, out: C
 
 def sssp_set_weights(g: Csr, w, stream):
     _check(lib().sssp_set_weights(ctypes.byref(g), w, stream), "sssp_set_weights")
+
+
+def sssp_permute_edges(perm, m, src, dst, to_coo, stream):
+    _check(lib().sssp_permute_edges(perm, m, src, dst, 1 if to_coo else 0, stream),
+           "sssp_permute_edges")
 
 
 def sssp_solve(g: Csr, source, cost, pred, stats, stream):

@@ -687,6 +687,17 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   return SSSP_OK;
 }
 
+sssp_status sssp_permute_edges(const int32_t *perm, int64_t m, const void *in, void *out,
+                               int32_t to_coo, void *stream_) {
+  if (m < 0) return SSSP_ERR_ARG;
+  if (m == 0) return SSSP_OK;
+  if (!perm || !in || !out || in == out) return SSSP_ERR_ARG;
+  Guard guard;
+  HIPCHK(launch_permute_edges(perm, m, (const int32_t *)in, (int32_t *)out, to_coo != 0,
+                              (hipStream_t)stream_));
+  return SSSP_OK;
+}
+
 sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
   if (!csr_ok(g) || (g->m > 0 && !w)) return SSSP_ERR_ARG;
   hipStream_t stream = (hipStream_t)stream_;

@@ -577,4 +577,25 @@ hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
   return hipGetLastError();
 }
 
+// ------------------------------------------------- COO <-> edge-id order
+// out[k] = in[perm[k]] (gather into edge-id order) or out[perm[k]] = in[k]
+// (scatter into COO order): consecutive k read perm and one side
+// coalesced; the other side follows the permutation.
+__global__ void permute_edges_kernel(const int32_t *perm, int64_t m, const int32_t *in,
+                                     int32_t *out, bool to_coo) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += stride) {
+    const int32_t p = perm[k];
+    if (to_coo) out[p] = in[k];
+    else out[k] = in[p];
+  }
+}
+
+hipError_t launch_permute_edges(const int32_t *perm, int64_t m, const int32_t *in, int32_t *out,
+                                bool to_coo, hipStream_t stream) {
+  hipLaunchKernelGGL(permute_edges_kernel, dim3(grid_for(m)), dim3(256), 0, stream, perm, m, in,
+                     out, to_coo);
+  return hipGetLastError();
+}
+
 }  // namespace sssp

@@ -261,6 +261,10 @@ hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
                               const int32_t *out_off, const int32_t *in_eid, int32_t *out_w,
                               int32_t *in_w, int32_t *out_wmin, const SolverCopy &c,
                               hipStream_t stream);
+// per-edge 4-byte values through the builder's permutation (perm[k] = COO
+// index of edge id k): out[k] = in[perm[k]], or out[perm[k]] = in[k]
+hipError_t launch_permute_edges(const int32_t *perm, int64_t m, const int32_t *in, int32_t *out,
+                                bool to_coo, hipStream_t stream);
 
 // ------------------------------------------------------------ backward
 struct BackArgs {

@@ -206,6 +206,26 @@ class Graph:
                        out_wmin=self._view(c.s_out_wmin, n, vt))
         return out
 
+    def to_edge_order(self, values_coo: torch.Tensor) -> torch.Tensor:
+        """Per-edge values given in the input (COO) order, in edge-id order
+        (sssp_permute_edges through the builder's permutation)."""
+        return self._permute(values_coo, to_coo=False)
+
+    def to_coo_order(self, values_eid: torch.Tensor) -> torch.Tensor:
+        """Per-edge values given in edge-id order, in the input (COO) order."""
+        return self._permute(values_eid, to_coo=True)
+
+    def _permute(self, v: torch.Tensor, to_coo: bool) -> torch.Tensor:
+        if v.numel() != self.m:
+            raise ValueError("expected %d per-edge values" % self.m)
+        if v.element_size() != 4:
+            raise ValueError("per-edge values must be 4-byte (float32 or int32)")
+        v = v.to(self.device).contiguous()
+        out = torch.empty_like(v)
+        _abi.sssp_permute_edges(self.perm.data_ptr(), self.m, v.data_ptr(), out.data_ptr(),
+                                to_coo, _stream())
+        return out
+
     def set_weights(self, w_eid: torch.Tensor):
         """Replace the weights; w_eid is given in edge-id order."""
         w_eid = w_eid.to(device=self.device, dtype=self.value_dtype).contiguous()
@@ -368,14 +388,19 @@ def backward(graphs: Sequence[Graph], inst_graph: Sequence[int], inst_source: Se
 
 class SSSPFunction(torch.autograd.Function):
     """cost[S, n] = shortest-path costs from S sources on one float32 graph,
-    differentiable in the edge weights (given in edge-id order)."""
+    differentiable in the edge weights.  order "eid": the weights (and their
+    gradient) are in edge-id order; "coo": in the order of the edges the
+    graph was built from (the library permutes them both ways)."""
 
     @staticmethod
-    def forward(ctx, w_eid: torch.Tensor, graph: Graph, sources: Sequence[int]):
-        graph.set_weights(w_eid.detach())
+    def forward(ctx, w: torch.Tensor, graph: Graph, sources: Sequence[int], order: str = "eid"):
+        if order not in ("eid", "coo"):
+            raise ValueError("order must be 'eid' or 'coo'")
+        w = w.detach()
+        graph.set_weights(graph.to_edge_order(w) if order == "coo" else w)
         S = len(sources)
         cost, pred, _ = solve_batch([graph], [0] * S, list(sources), with_pred=True)
-        ctx.graph, ctx.sources = graph, list(sources)
+        ctx.graph, ctx.sources, ctx.order = graph, list(sources), order
         ctx.save_for_backward(pred)
         return cost.view(S, graph.n)
 
@@ -385,8 +410,13 @@ class SSSPFunction(torch.autograd.Function):
         g = ctx.graph
         gw = backward([g], [0] * len(ctx.sources), ctx.sources, pred,
                       grad_cost.reshape(-1))
-        return gw, None, None
+        if ctx.order == "coo":
+            gw = g.to_coo_order(gw)
+        return gw, None, None, None
 
 
-def shortest_paths(w_eid: torch.Tensor, graph: Graph, sources: Sequence[int]) -> torch.Tensor:
-    return SSSPFunction.apply(w_eid, graph, sources)
+def shortest_paths(w: torch.Tensor, graph: Graph, sources: Sequence[int],
+                   order: str = "eid") -> torch.Tensor:
+    """Differentiable costs from `sources`; `w` in edge-id ("eid") or input
+    ("coo") order (see SSSPFunction)."""
+    return SSSPFunction.apply(w, graph, sources, order)

@@ -38,7 +38,7 @@ def test_header_declares_the_abi():
                             "sssp_release_workspace", "sssp_strerror",
                             "sssp_profile_enable", "sssp_profile_read", "sssp_check",
                             "sssp_set_round_limit", "sssp_policy_of",
-                            "sssp_solve_noalloc"])
+                            "sssp_solve_noalloc", "sssp_permute_edges"])
 
 
 def test_library_exports_every_declared_symbol(sp):
@@ -90,6 +90,18 @@ def test_round_limit_argument(sp):
         sp.sssp_set_round_limit(-1)
     assert e.value.status == sp.SSSP_ERR_ARG
     sp.sssp_set_round_limit(0)
+
+
+def test_permute_argument_errors(sp):
+    """Argument errors of sssp_permute_edges, returned before any GPU work;
+    an empty permutation is a no-op."""
+    S = sp.SSSP_ERR_ARG
+    assert _status(lambda: sp.sssp_permute_edges(0x1000, -1, 0x2000, 0x3000, 0, None)) == S
+    assert _status(lambda: sp.sssp_permute_edges(None, 4, 0x2000, 0x3000, 0, None)) == S
+    assert _status(lambda: sp.sssp_permute_edges(0x1000, 4, None, 0x3000, 1, None)) == S
+    assert _status(lambda: sp.sssp_permute_edges(0x1000, 4, 0x2000, None, 1, None)) == S
+    assert _status(lambda: sp.sssp_permute_edges(0x1000, 4, 0x2000, 0x2000, 0, None)) == S
+    sp.sssp_permute_edges(None, 0, None, None, 0, None)
 
 
 def test_host_argument_errors(sp):

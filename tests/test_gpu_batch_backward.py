@@ -279,3 +279,56 @@ def test_autograd_function(sp, order):
                       gco.astype(np.float64))
     got = to_np(w_eid.grad).astype(np.float64)
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("order", ["input", "degree"])
+def test_autograd_coo_order(sp, order):
+    """Weights and gradient in the input (COO) order: the library permutes
+    them through the builder's perm both ways.  Costs equal the edge-id
+    order's bit for bit, the gradient is the edge-id gradient scattered to
+    COO positions (bit for bit), and it matches the CPU gradient."""
+    d, gco = gen.diff_workload(side=20, num_sources=4)
+    G = sp.Graph(d.n, d.src, d.dst, d.w, order=order)
+    perm = to_np(G.perm).astype(np.int64)
+    assert sorted(perm.tolist()) == list(range(d.m))
+    srcs = [int(s) for s in d.sources]
+    g = torch.from_numpy(gco).cuda()
+
+    def run(w, o):
+        w = w.clone().requires_grad_(True)
+        cost = sp.shortest_paths(w, G, srcs, order=o)
+        reach = torch.isfinite(cost)
+        (torch.where(reach, cost, torch.zeros_like(cost)) * g).sum().backward()
+        sync()
+        return cost.detach(), w.grad
+
+    w_coo = torch.from_numpy(d.w).cuda()
+    c_coo, g_coo = run(w_coo, "coo")
+    c_eid, g_eid = run(torch.from_numpy(d.w[perm]).cuda(), "eid")
+    assert torch.equal(c_coo, c_eid)
+    gc, ge = to_np(g_coo), to_np(g_eid)
+    assert np.array_equal(gc[perm], ge)
+    O = oracle.csr(d.n, d.src, d.dst)
+    _, pred, _ = sp.solve_batch([G], [0] * 4, srcs)
+    ref = oracle.grad(O, srcs, to_np(pred).astype(np.int64).reshape(4, d.n),
+                      gco.astype(np.float64))
+    got = ge.astype(np.float64)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_permute_edges_both_ways(sp):
+    """sssp_permute_edges against indexing by perm, on int32 and float32
+    values of an RMAT graph in degree order (a non-trivial permutation)."""
+    g = gen.rmat_workload(scale=12)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, order="degree")
+    perm = G.perm.long()
+    vi = torch.arange(g.m, dtype=torch.int32, device="cuda") * 7 + 3
+    vf = torch.rand(g.m, dtype=torch.float32, device="cuda")
+    for v in (vi, vf):
+        e = G.to_edge_order(v)
+        assert torch.equal(e, v[perm])
+        back = G.to_coo_order(e)
+        assert torch.equal(back, v)
+    sync()
