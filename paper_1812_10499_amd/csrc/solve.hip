@@ -451,18 +451,10 @@ __device__ int find_start_item(const int32_t *lp, int N, uint32_t c, uint32_t e0
 }
 
 // last window position p in [0, WIN) with pfx[p] <= e (pfx ascending, with
-// pfx[0] <= e): an 8-ary search, four dependent LDS steps instead of ten
-static_assert(WIN == 1024, "window_item splits 1024 = 8 * 8 * 8 * 2");
+// pfx[0] <= e)
+static_assert(WIN == 1024, "the window search covers 1024 positions");
 __device__ __forceinline__ int window_item(const int32_t *pfx, uint32_t e) {
-  int lo = 0;
-#pragma unroll
-  for (int s = WIN / 8; s >= 2; s /= 8) {  // spans 128, 16, 2
-    int c = 0;
-#pragma unroll
-    for (int k = 1; k < 8; ++k) c += (uint32_t)pfx[lo + k * s] <= e ? 1 : 0;
-    lo += c * s;
-  }
-  return (uint32_t)pfx[lo + 1] <= e ? lo + 1 : lo;
+  return search1024(pfx, e);
 }
 
 __device__ __forceinline__ uint32_t chunk_of(uint32_t E, uint32_t vnb) {

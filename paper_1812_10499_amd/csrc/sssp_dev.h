@@ -110,6 +110,21 @@ __device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v) {
   return v;
 }
 
+// Last position p in [0, 1024) with pfx[p] <= e, for pfx ascending with
+// pfx[0] <= e (an LDS window's exclusive prefix): an 8-ary search, four
+// dependent LDS steps instead of a binary search's ten.
+__device__ __forceinline__ int search1024(const int32_t *pfx, uint32_t e) {
+  int lo = 0;
+#pragma unroll
+  for (int s = 128; s >= 2; s /= 8) {  // spans 128, 16, 2
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) c += (uint32_t)pfx[lo + k * s] <= e ? 1 : 0;
+    lo += c * s;
+  }
+  return (uint32_t)pfx[lo + 1] <= e ? lo + 1 : lo;
+}
+
 // Exclusive prefix over the wave of a per-lane count below 2^B, and the
 // wave's total: one ballot and one lane-mask count per bit, no LDS.
 template <int B>
