@@ -318,7 +318,7 @@ sssp_status sssp_solve(const sssp_csr *g, int32_t source, void *cost, int32_t *p
  * (its first call on a device only looks the region's address up).
  *   Arguments, semantics and errors as for sssp_solve, plus
  *   SSSP_ERR_CAPACITY (nothing queued) when the solve's state does not fit
- *   the region: it needs about 140 bytes per vertex plus 0.4 MB, so every
+ *   the region: it needs about 148 bytes per vertex plus 0.4 MB, so every
  *   graph with n <= 450,000 fits, whatever its scope and relax step.
  * Every call on one device shares that device's region and leaves its
  * contents behind (each solve initializes what it reads first): calls that

@@ -20,7 +20,7 @@ namespace {
 
 enum Slot {
   S_C, S_C1, S_ARRIVE, S_MTMP, S_OV0, S_OP0, S_OI0, S_OV1, S_OP1, S_OI1, S_FV, S_FP, S_FI, S_CTL,
-  S_IMIN, S_ITHR, S_IROUNDS, S_ISCAN, S_HEAVY, S_DEGEN, S_LVL, S_FLAG, S_SPRED, S_ISTAT,
+  S_IMIN, S_ITHR, S_IROUNDS, S_ISCAN, S_DEGEN, S_LVL, S_FLAG, S_SPRED, S_ISTAT,
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
@@ -387,11 +387,11 @@ sssp_status state_arrays(Alloc &al, int32_t total, int32_t num_inst, bool batch,
   if ((s = al(S_FV, T, &a.front_v))) return s;
   if ((s = al(S_FP, T, &a.front_p))) return s;
   {
-    // list payload words: kFX per frontier entry, kOX per open entry and parity
+    // list payload words: kFX per frontier entry, kOXMem per open entry and parity
     int32_t *fx, *ox0, *ox1;
     if ((s = al(S_FX, kFX * T, &fx))) return s;
-    if ((s = al(S_OX0, kOX * T, &ox0))) return s;
-    if ((s = al(S_OX1, kOX * T, &ox1))) return s;
+    if ((s = al(S_OX0, kOXMem * T, &ox0))) return s;
+    if ((s = al(S_OX1, kOXMem * T, &ox1))) return s;
     for (int k = 0; k < kFX; ++k) a.front_x[k] = fx + (size_t)k * T;
     for (int k = 0; k < kOX; ++k) {
       a.open_x0[k] = ox0 + (size_t)k * T;
@@ -401,7 +401,6 @@ sssp_status state_arrays(Alloc &al, int32_t total, int32_t num_inst, bool batch,
   if ((s = al(S_CTL, 1, &a.ctl))) return s;
   if ((s = al(S_FLAGS, (size_t)kMaxBlocks * kFlagStride, &a.flags))) return s;
   if ((s = al(S_PART, (size_t)kParts * kMaxBlocks, &a.part))) return s;
-  if ((s = al(S_HEAVY, 2 * T, &a.heavy))) return s;
   if ((s = al(S_DEGEN, 2 * T, &a.degen))) return s;
   if ((s = al(S_LVL, T, &a.lvl))) return s;
   if ((s = al(S_FLAG, T, &a.flag))) return s;

@@ -11,7 +11,10 @@
 //  - a dependent-load chain (one lane follows next[] pointers), the latency
 //    of one step of a round's critical path at a given working-set size;
 //  - block barriers (__syncthreads) in one 1024-thread workgroup, and the
-//    round kernel's grid barrier over a cooperative grid.
+//    round kernel's grid barrier over a cooperative grid;
+//  - what one CU's memory pipeline pays per wave instruction (one
+//    1024-thread workgroup): random 4-byte gathers, coalesced 4- and
+//    16-byte loads and stores (the one-workgroup kernel's trade).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -164,9 +167,60 @@ __global__ __launch_bounds__(1024) void grid_sync_k(unsigned int *flags, unsigne
   for (int i = 0; i < iters; ++i) sssp::grid_barrier(flags, go, epoch);
 }
 
+// One workgroup, 8 accesses per thread and iteration, all issued before
+// any is used.  Mode 0: random 4-byte gathers (indices from a per-lane LCG,
+// masked to the array); 1: coalesced 4-byte loads; 2: coalesced 16-byte
+// loads; 3: coalesced 4-byte stores; 4: coalesced 16-byte stores.  The
+// array holds mask + 1 ints (a power of two, at least 4 * 8 * 1024).
+template <int MODE>
+__global__ __launch_bounds__(1024) void cu_access_k(int *__restrict__ a, uint32_t mask, int iters,
+                                                    int *out) {
+  int acc = 0;
+  uint32_t x = threadIdx.x * 2654435761u + 12345u;
+  for (int it = 0; it < iters; ++it) {
+    int v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t lin = ((uint32_t)it * 8u + j) * 1024u + threadIdx.x;
+      if (MODE == 0) {
+        x = x * 1664525u + 1013904223u;
+        v[j] = a[(x >> 4) & mask];
+      } else if (MODE == 1) {
+        v[j] = a[lin & mask];
+      } else if (MODE == 2) {
+        const int4 q = *(const int4 *)(a + ((lin * 4u) & mask));
+        v[j] = q.x ^ q.y ^ q.z ^ q.w;
+      } else if (MODE == 3) {
+        a[lin & mask] = it + j;
+      } else {
+        *(int4 *)(a + ((lin * 4u) & mask)) = make_int4(it, j, 0, 0);
+      }
+    }
+    if (MODE <= 2) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += v[j];
+    }
+  }
+  out[threadIdx.x] = acc;
+}
+
 }  // namespace
 
 extern "C" {
+
+int probe_cu_access(int mode, int *a, uint32_t mask, int iters, int *out, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(cu_access_k<0>, dim3(1), dim3(1024), 0, s, a, mask, iters, out); break;
+    case 1: hipLaunchKernelGGL(cu_access_k<1>, dim3(1), dim3(1024), 0, s, a, mask, iters, out); break;
+    case 2: hipLaunchKernelGGL(cu_access_k<2>, dim3(1), dim3(1024), 0, s, a, mask, iters, out); break;
+    case 3: hipLaunchKernelGGL(cu_access_k<3>, dim3(1), dim3(1024), 0, s, a, mask, iters, out); break;
+    case 4: hipLaunchKernelGGL(cu_access_k<4>, dim3(1), dim3(1024), 0, s, a, mask, iters, out); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
 
 int probe_gather(int width, const void *arr, const uint32_t *idx, int64_t n, void *out,
                  int blocks, void *stream) {

@@ -1816,7 +1816,6 @@ __global__ void init_seed_kernel(RoundArgs a) {
     c->status = 0;
     c->rounds = 0;
     c->deg_count = 0;
-    c->heavy_count = 0;
     c->resume_round = 0;
     c->resume_phase = 0;
     c->done = 0;

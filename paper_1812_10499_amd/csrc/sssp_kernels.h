@@ -40,10 +40,13 @@ enum PartSlot {
 // OX_IDEG = -1 - in-degree (the mark of a first discovery); one pushed when
 // the relax stager was full carries OX_BASE = -1 instead: the bound step
 // then reads the vertex record, and C (0, or under scope ALL what the live
-// pass raised it to).
+// pass raised it to).  The one-workgroup kernel lays the same memory out
+// as two int4 arrays (the vertex record's halves, with C in its last word),
+// so kOXMem words are allocated per open entry.
 constexpr int32_t kOpenRelax = (int32_t)0x80000000;
 enum { FX_OOFF = 0, FX_D, kFX };
 enum { OX_BASE = 0, OX_IDEG, OX_OOFF, OX_ODEG, OX_OWM, OX_C, kOX };
+constexpr int kOXMem = 8;
 
 // Control block of one persistent solve, in device memory.
 struct Ctl {
@@ -54,7 +57,6 @@ struct Ctl {
   int32_t status;                   // 0, or an sssp_status code set on the device
   int32_t rounds;
   int32_t deg_count;    // pred: vertices queued for the equal-cost pass
-  int32_t heavy_count;  // pred: vertices queued for the wave-per-vertex pass
   // hand-over to parked blocks: where to resume, how many blocks are active
   // from there, and the active barrier's epoch
   int32_t resume_round, resume_phase, done, resume_act;
@@ -101,7 +103,7 @@ struct RoundArgs {
   Ctl *ctl;
   int32_t *imin, *ithr, *irounds;  // batch: [3][I], [3][I], [I]
   unsigned long long *iscanned;    // batch: [I][3] scanned in-edges, open visits, relaxed edges
-  int32_t *heavy, *degen, *lvl, *flag, *scratch_pred;
+  int32_t *degen, *lvl, *flag, *scratch_pred;
   long long *istat;                // batch stats [4][I], zeroed by the seed kernel
   // optional round trace (SSSP_TRACE): per round kTraceFields entries
   long long *trace;

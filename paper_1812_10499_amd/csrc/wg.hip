@@ -1,7 +1,7 @@
 // The rounds of each solve in one workgroup: instance i of a launch runs on
 // block i (blocks loop over the instances when there are more), with its
 // state in global memory (the (D, parent) keys, both C buffers, the relax
-// set, the open lists by parity, label-correcting's DR) and block barriers
+// set, the open lists by parity with their payload) and block barriers
 // only: no grid barrier, no hand-over, and no instance waits for another.
 // For graphs of low degree spread under C scope OPEN (meshes, grids), whose
 // rounds are many and small; the rounds, counters and keys are those of the
@@ -25,6 +25,14 @@ struct WgLds {
   unsigned long long relaxed, scanned, visits, settled;
 };
 
+// The open entries' payload by list parity, as two int4 arrays of
+// a.total entries each (in the open-list payload words, kOXMem per entry):
+// the vertex record's two halves, with C in the last word (where the
+// record holds 0).
+__device__ __forceinline__ int4 *wg_payload(const RoundArgs &a, int parity, int32_t sb) {
+  return (int4 *)(parity ? a.open_x1[0] : a.open_x0[0]) + sb;
+}
+
 template <class V, bool BATCH>
 __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
   __shared__ WgLds s;
@@ -37,7 +45,6 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
     c->live_ctr[0] = c->live_ctr[1] = 0ull;
     c->go = c->go_a = 0u;
     c->deg_count = 0;
-    c->heavy_count = 0;
     c->resume_round = c->resume_phase = c->done = c->resume_act = 0;
     c->resume_aep = 0u;
     c->solo_phases = 0;
@@ -67,16 +74,19 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
     // and read by plain accesses of this workgroup only
     unsigned long long *D = a.D64 + sb;
     int32_t *C[2] = {a.C0 + sb, a.C1 + sb};
-    int32_t *DR = a.DR ? a.DR + sb : nullptr;
     // relax items: vertex, D to relax from, out-offset, out-degree
     int32_t *F = a.front_v + sb, *FD = a.front_x[FX_D] + sb;
     int32_t *FO = a.front_x[FX_OOFF] + sb, *FG = a.front_p + sb;
+    // open entries by parity: the vertex, its payload (wg_payload) and the
+    // D it was last relaxed with (INF before its first relax): everything
+    // its bound step reads but D and the tails' C, loaded coalesced rather
+    // than gathered
     int32_t *O[2] = {a.open_v0 + sb, a.open_v1 + sb};
+    int32_t *OR[2] = {a.open_p0 + sb, a.open_p1 + sb};
     for (int y = tid; y < n; y += WBS) {
       const bool is_s = y == src;
       D[y] = make_key(is_s ? 0 : V::INF, -1, false);
       C[0][y] = C[1][y] = is_s ? V::INF : 0;  // the source is fixed from the start
-      if (lc) DR[y] = V::INF;
     }
     if (tid == 0) {
       F[0] = src;
@@ -113,6 +123,7 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       // with (no edges).  A fixed item also marks its C in the buffer this
       // round writes (the other buffer has it since the fix).
       const int nF = s.nF;
+      const int nS = s.nO;  // the open entries with a payload: last round's survivors
       unsigned long long nrel = 0;
       int32_t md = smd, th = sth;
       for (int i0 = 0; i0 < nF; i0 += WBS) {
@@ -127,7 +138,6 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             deg = FG[i];
             s.wbase[tid] = FO[i];
             s.wdx[tid] = dx;
-            if (lc) DR[x] = dx;
           }
         }
         uint64_t tot;
@@ -155,6 +165,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             md = kmin(md, cand);
             th = kmin(th, V::add(cand, G.out_wmin[y]));
           }
+          // a first discovery joins the open list after the survivors, with
+          // no payload: its bound step reads the vertex record
           if (od == V::INF) O[o][atomicAdd(&s.nO, 1)] = y;
         }
         __syncthreads();
@@ -182,52 +194,103 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       unsigned long long nscan = 0, nfix = 0;
       smd = sth = V::INF;
       // Each thread takes kWgItems list entries per pass and issues the
-      // loads of all of them before any decision, so that the dependent
-      // chain (entry, then D / record / C, then the lightest tail's C) is
-      // paid once per pass rather than once per entry.
+      // loads of all of them before any decision: the entries with their
+      // payload (coalesced), then D and the lightest tail's C together
+      // (lanes past the list read entry 0), then the rest of the in-list.
+      // First discoveries (the list's tail, from nS on) have no payload yet:
+      // a wave that holds one reads their vertex records beside D (the
+      // record's last word is 0, the C of an undiscovered vertex; never
+      // relaxed), and the tails' C after.
+      const int4 *Pc = wg_payload(a, o, sb), *Qc = Pc + a.total;
+      int4 *Pn = wg_payload(a, o ^ 1, sb), *Qn = Pn + a.total;
+      static_assert(kWgItems == 2, "slot 1 of a pass is the optional one");
       for (int i0 = 0; i0 < nO; i0 += kWgItems * WBS) {
-        int32_t y[kWgItems], dy[kWgItems], cy[kWgItems], dr[kWgItems], c0[kWgItems];
-        int4 rec[kWgItems], rec2[kWgItems];
+        // (wave-uniform) a wave past the list's end sits the pass out, and
+        // one whose second slot is past it issues no loads for that slot
+        const int wb = i0 + (tid & ~(SSSP_WAVE - 1));
+        if (wb >= nO) continue;
+        const bool two = wb + WBS < nO;
+        int32_t y[kWgItems] = {0, 0}, dy[kWgItems], dr[kWgItems] = {0, 0}, c0[kWgItems] = {0, 0};
+        int4 ra[kWgItems] = {}, rb[kWgItems] = {};  // out_off, out_deg, in_off, in_deg; out_wmin, tail0, w0, C
+        unsigned long long dk[kWgItems] = {0, 0};
         bool ok[kWgItems];
 #pragma unroll
-        for (int u = 0; u < kWgItems; ++u) {
-          const int i = i0 + u * WBS + tid;
-          ok[u] = i < nO;
-          y[u] = ok[u] ? O[o][i] : 0;
-        }
+        for (int u = 0; u < kWgItems; ++u) ok[u] = i0 + u * WBS + tid < nO;
 #pragma unroll
         for (int u = 0; u < kWgItems; ++u) {
-          if (ok[u]) {
-            dy[u] = (int32_t)(ld_relaxed64(&D[y[u]]) >> 32);
-            // out_off, out_degree, in_off, in_degree; out_wmin, the
-            // lightest in-edge's tail and weight
-            rec[u] = G.vrec[2 * y[u]];
-            rec2[u] = G.vrec[2 * y[u] + 1];
-            cy[u] = Cold[y[u]];
-            dr[u] = lc ? DR[y[u]] : 0;
+          if (u == 0 || two) {
+            const int i = i0 + u * WBS + tid;
+            const int ic = ok[u] ? i : 0;
+            const int ip = i < nS ? i : 0;  // (first discoveries: one line for all)
+            y[u] = O[o][ic];
+            ra[u] = Pc[ip];
+            rb[u] = Qc[ip];
+            dr[u] = OR[o][ip];
           }
         }
+        bool fdw = false;
 #pragma unroll
-        for (int u = 0; u < kWgItems; ++u) {
-          c0[u] = V::INF;
-          // the first in-edge comes from the record
-          if (ok[u] && rec[u].w > 0 && V::add(md, rec2[u].z) < dy[u]) c0[u] = Cold[rec2[u].y];
+        for (int u = 0; u < kWgItems; ++u) fdw |= ok[u] && i0 + u * WBS + tid >= nS;
+        // (the empty asm statements mark the loaded values as used there:
+        // every load of a step issues before the wave waits for any)
+        if (__ballot(fdw) == 0ull) {
+#pragma unroll
+          for (int u = 0; u < kWgItems; ++u) {
+            if (u == 0 || two) {
+              dk[u] = ld_relaxed64(&D[y[u]]);
+              // (0 for a vertex with no in-edge; lanes past the list read
+              // entry 0, whose payload is unset when it is a first discovery)
+              c0[u] = Cold[ok[u] ? rb[u].y : 0];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kWgItems; ++u) asm volatile("" : "+v"(dk[u]), "+v"(c0[u]));
+        } else {
+          int4 va[kWgItems] = {}, vb[kWgItems] = {};
+#pragma unroll
+          for (int u = 0; u < kWgItems; ++u) {
+            if (u == 0 || two) {
+              dk[u] = ld_relaxed64(&D[y[u]]);
+              va[u] = G.vrec[2 * y[u]];
+              vb[u] = G.vrec[2 * y[u] + 1];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kWgItems; ++u)
+            asm volatile("" : "+v"(dk[u]), "+v"(va[u].x), "+v"(va[u].y), "+v"(va[u].z),
+                         "+v"(va[u].w), "+v"(vb[u].x), "+v"(vb[u].y), "+v"(vb[u].z));
+#pragma unroll
+          for (int u = 0; u < kWgItems; ++u) {
+            if (i0 + u * WBS + tid >= nS) {
+              ra[u] = va[u];
+              rb[u] = vb[u];
+              dr[u] = V::INF;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kWgItems; ++u)
+            if (u == 0 || two) c0[u] = Cold[rb[u].y];
+#pragma unroll
+          for (int u = 0; u < kWgItems; ++u) asm volatile("" : "+v"(c0[u]));
         }
+#pragma unroll
+        for (int u = 0; u < kWgItems; ++u) dy[u] = (int32_t)(dk[u] >> 32);
 #pragma unroll
         for (int u = 0; u < kWgItems; ++u) {
           if (!ok[u]) continue;
+          const int32_t ioff = ra[u].z, ideg = ra[u].w, w0 = rb[u].z;
           int32_t m = V::INF;
-          if (rec[u].w > 0 && V::add(md, rec2[u].z) < dy[u]) {
-            if (c0[u] != V::INF) m = V::add(kmax(c0[u], md), rec2[u].z);
-            for (int32_t j = 1; j < rec[u].w; ++j) {  // the rest from the in-list
-              const int32_t w = G.in_w[rec[u].z + j];
+          if (ideg > 0 && V::add(md, w0) < dy[u]) {
+            if (c0[u] != V::INF) m = V::add(kmax(c0[u], md), w0);
+            for (int32_t j = 1; j < ideg; ++j) {  // the rest from the in-list
+              const int32_t w = G.in_w[ioff + j];
               if (V::add(md, w) >= kmin(dy[u], m)) break;
-              const int32_t cv = Cold[G.in_src[rec[u].z + j]];
+              const int32_t cv = Cold[G.in_src[ioff + j]];
               if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
             }
           }
-          const int32_t cn = kmax(kmax(cy[u], md), kmin(dy[u], m));
-          nscan += (unsigned long long)rec[u].w;
+          const int32_t cn = kmax(kmax(rb[u].w, md), kmin(dy[u], m));
+          nscan += (unsigned long long)ideg;
           const bool relax_again = !lc || dy[u] < dr[u];
           if (cn >= dy[u] || dy[u] <= th) {
             Cnew[y[u]] = V::INF;
@@ -236,19 +299,27 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             const int q = atomicAdd(&s.nF2, 1);
             F[q] = y[u];
             FD[q] = relax_again ? dy[u] : V::INF;
-            FO[q] = rec[u].x;
-            FG[q] = rec[u].y;
+            FO[q] = ra[u].x;
+            FG[q] = ra[u].y;
           } else {
             Cnew[y[u]] = cn;
-            O[o ^ 1][atomicAdd(&s.nO2, 1)] = y[u];
+            // label-correcting: relaxed again from its lower D (while in the
+            // first bucket above minD)
+            const bool again = lc && relax_again && dy[u] < V::add(md, G.delta);
+            const int q = atomicAdd(&s.nO2, 1);
+            O[o ^ 1][q] = y[u];
+            rb[u].w = cn;
+            Pn[q] = ra[u];
+            Qn[q] = rb[u];
+            OR[o ^ 1][q] = again ? dy[u] : dr[u];
             smd = kmin(smd, dy[u]);
-            sth = kmin(sth, V::add(dy[u], rec2[u].x));
-            if (lc && relax_again && dy[u] < V::add(md, G.delta)) {
-              const int q = atomicAdd(&s.nF2, 1);
-              F[q] = y[u];
-              FD[q] = dy[u] | kOpenRelax;
-              FO[q] = rec[u].x;
-              FG[q] = rec[u].y;
+            sth = kmin(sth, V::add(dy[u], rb[u].x));
+            if (again) {
+              const int p = atomicAdd(&s.nF2, 1);
+              F[p] = y[u];
+              FD[p] = dy[u] | kOpenRelax;
+              FO[p] = ra[u].x;
+              FG[p] = ra[u].y;
             }
           }
         }

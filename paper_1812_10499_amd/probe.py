@@ -19,6 +19,9 @@ Measures, on device 0:
     256 MB Infinity Cache, not an L2) and 1 GB (HBM);
   * a block barrier pair in one 1024-thread workgroup, and the round
     kernel's grid barrier over 8, 64 and 256 cooperative blocks;
+  * one CU (one 1024-thread workgroup): the cost per wave instruction of
+    random 4-byte gathers over 2 MB and 64 MB, and of coalesced 4- and
+    16-byte loads and stores;
   * a 1 GiB device copy for reference.
 """
 from __future__ import annotations
@@ -46,6 +49,7 @@ def _lib():
     L.probe_chase.argtypes = [vp, vp, i64, vp, vp]
     L.probe_sync.argtypes = [ctypes.c_int, vp, vp]
     L.probe_grid_sync.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    L.probe_cu_access.argtypes = [ctypes.c_int, vp, ctypes.c_uint32, ctypes.c_int, vp, vp]
     return L
 
 
@@ -208,6 +212,21 @@ def main():
     for nb in (8, 64, 256):
         rows.append(("grid barrier of the round kernel over %d blocks" % nb,
                      "%.2f us per barrier" % grid_barrier_us(nb), "2000 barriers"))
+    # one CU: 64 iterations x 8 accesses x 16 waves
+    cu_out = torch.empty(1024, dtype=torch.int32, device=dev)
+    for mode, label, nbytes in ((0, "random 4-byte gather over 2 MB", 2 << 20),
+                                (0, "random 4-byte gather over 64 MB", 64 << 20),
+                                (1, "coalesced 4-byte load", 2 << 20),
+                                (2, "coalesced 16-byte load", 2 << 20),
+                                (3, "coalesced 4-byte store", 2 << 20),
+                                (4, "coalesced 16-byte store", 2 << 20)):
+        arr = torch.zeros(nbytes // 4, dtype=torch.int32, device=dev)
+        ms = timed(lambda: ok(L.probe_cu_access(mode, arr.data_ptr(), nbytes // 4 - 1, 64,
+                                                cu_out.data_ptr(), st)))
+        rows.append(("one CU (1024 threads): %s" % label,
+                     "%.1f ns per wave instruction" % (ms * 1e6 / (64 * 8 * 16)),
+                     "8192 instructions"))
+        del arr
     x = torch.empty(1 << 28, dtype=torch.int32, device=dev)
     y = torch.empty_like(x)
     ms = timed(lambda: y.copy_(x))

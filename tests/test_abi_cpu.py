@@ -195,5 +195,6 @@ def test_probe_library_exports(sp):
         build.build()
     L = ctypes.CDLL(PROBE_SO)
     for name in ("probe_gather", "probe_gather_atomic", "probe_gather_atomic_every",
-                 "probe_gather_part", "probe_chase", "probe_sync", "probe_grid_sync"):
+                 "probe_gather_part", "probe_chase", "probe_sync", "probe_grid_sync",
+                 "probe_cu_access"):
         assert hasattr(L, name), name

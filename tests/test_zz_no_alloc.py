@@ -66,6 +66,15 @@ def test_noalloc_matches_solve_on_shrinking_graphs(sp):
     _both(sp, G, g.source, "random3000")
 
 
+def test_noalloc_holds_its_stated_capacity(sp):
+    # the header's promise: every graph with n <= 450,000 fits, whatever its
+    # scope and relax step (scope ALL and label-correcting relax need the
+    # most state)
+    g = gen.random_workload(n=450000, m=1800000)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, scope="all", relax="correcting")
+    _both(sp, G, g.source, "random450000 all correcting")
+
+
 def test_noalloc_refuses_a_graph_beyond_its_region(sp):
     n = 600000
     src = np.arange(n - 1, dtype=np.int32)
