@@ -71,22 +71,61 @@ struct InstDev {
 // ------------------------------------------------------------ wave ops
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Wave-wide reductions (every lane of the wave active; the result is
+// wave-uniform): DPP lane moves combine within each row of 16 lanes (the
+// quad swaps 1 and 2, then the half-row and row mirrors), then one lane of
+// each of the four rows is read into scalar registers.  No LDS traffic and
+// no waits on it, unlike a shuffle ladder.
+enum : int {
+  kDppQuadSwap1 = 0xB1,    // quad_perm [1,0,3,2]
+  kDppQuadSwap2 = 0x4E,    // quad_perm [2,3,0,1]
+  kDppRowMirror = 0x140,   // lane i of a row reads lane 15 - i
+  kDppHalfMirror = 0x141,  // lane i of a half-row reads lane 7 - i
+};
+
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_mov(int32_t v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+template <class Op>
+__device__ __forceinline__ int32_t wave_reduce32(int32_t v, Op op) {
+  v = op(v, dpp_mov<kDppQuadSwap1>(v));
+  v = op(v, dpp_mov<kDppQuadSwap2>(v));
+  v = op(v, dpp_mov<kDppHalfMirror>(v));
+  v = op(v, dpp_mov<kDppRowMirror>(v));
+  const int32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const int32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return op(op(r0, r1), op(r2, r3));
+}
+
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = kmin(v, __shfl_xor(v, o, SSSP_WAVE));
-  return v;
+  return wave_reduce32(v, [](int32_t x, int32_t y) { return kmin(x, y); });
 }
 
 __device__ __forceinline__ int32_t wave_max(int32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = kmax(v, __shfl_xor(v, o, SSSP_WAVE));
-  return v;
+  return wave_reduce32(v, [](int32_t x, int32_t y) { return kmax(x, y); });
+}
+
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_mov64(int64_t v) {
+  const int32_t lo = dpp_mov<CTRL>((int32_t)(uint32_t)v);
+  const int32_t hi = dpp_mov<CTRL>((int32_t)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)((uint64_t)v >> 32), lane);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, SSSP_WAVE);
-  return v;
+  v += dpp_mov64<kDppQuadSwap1>(v);
+  v += dpp_mov64<kDppQuadSwap2>(v);
+  v += dpp_mov64<kDppHalfMirror>(v);
+  v += dpp_mov64<kDppRowMirror>(v);
+  return (readlane64(v, 0) + readlane64(v, 16)) + (readlane64(v, 32) + readlane64(v, 48));
 }
 
 // inclusive prefix sum across the wave
