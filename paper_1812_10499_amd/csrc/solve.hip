@@ -57,6 +57,9 @@ constexpr uint32_t CW_RELAX = 4;  // work units per frontier item (its loads and
 constexpr uint32_t CW_FUSED = 16; // work units per open item (loads, decision, list entry)
 constexpr uint32_t CW_LIVE = 8;   // work units per live undiscovered vertex (scope ALL)
 constexpr int CAP_L = 8 * RBS;    // live-list staging capacity
+constexpr int kLivePT = 4;        // live-list entries per thread and tile
+static_assert(kLivePT * RBS <= CAP_L && RBS < 65536 && kLivePT <= 4,
+              "a tile fits the stager; per-slot counts fit 16-bit fields of one 64-bit scan");
 
 // ----------------------------------------------------------- LDS layouts
 // LDS staging of list appends: vertex, local exclusive work prefix,
@@ -1019,93 +1022,141 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
   unsigned long long *lctr = &a.ctl->live_ctr[cur ^ 1];
   if (tid == 0) L.cnt = 0;
   __syncthreads();
-  // tiles of RBS list entries go round-robin to the blocks: the lists keep
-  // solver order, and under degree order the costly vertices come first
+  // Tiles of LPT * RBS list entries go round-robin to the blocks (the lists
+  // keep solver order, and under degree order the costly vertices come
+  // first); thread tid takes entries tid, tid + RBS, ... of a tile and
+  // issues the loads of all of them before any test (an entry leaves the
+  // list only at the compaction after its discovery, so its own words are
+  // read unconditionally).  A batch takes kLivePT entries per thread: its
+  // long lists of low-degree vertices pay the tile's scan and barriers once
+  // for all of them.  A single solve takes one: a thread's in-edge loops run
+  // one after another, and a degree-ordered list starts with the hubs.
   long long scanned = 0, ddeg = 0, ddeg_r = 0;
-  for (uint32_t b0 = pc.vbid * RBS; b0 < (uint32_t)NL; b0 += pc.vnb * RBS) {
-    const uint32_t i = b0 + (uint32_t)tid;
-    bool keep = false;
-    int32_t y = 0;  // state entry
-    if (i < (uint32_t)NL) {
-      y = (r == 1) ? (int32_t)i : Lv[i];
-      int32_t sb = 0, gi = 0, ins = 0, mdi = md;
-      if constexpr (BATCH) {
-        // the entry's instance, and that instance's minD this round (INF:
-        // its rounds have ended, so its undiscovered vertices are done)
-        ins = a.inst_of[y];
-        const InstDev id = a.insts[ins];
-        sb = id.sbase;
-        gi = id.graph;
-        mdi = ld_relaxed(&a.imin[s_now * I + ins]);
-      }
-      const GraphDev &G = graph_of<BATCH>(a, gi);
-      if (G.all && mdi != V::INF && (int32_t)(a.D64[y] >> 32) == V::INF) {
-        const int32_t c = Cold[y];
-        // out_off, out_degree, in_off, in_degree; out_wmin, the lightest
-        // in-edge's tail and weight (the same line)
-        const int4 rec = G.vrec[2 * (y - sb)], rec2 = G.vrec[2 * (y - sb) + 1];
-        const int32_t b = rec.z, deg = rec.w;
-        const int32_t *Cg = Cold + sb;  // the instance's C, by graph-local id
-        if constexpr (BATCH) {
-          if (I > kLdsInst) atomicAdd(&a.iscanned[3 * ins], (unsigned long long)deg);
-          else atomicAdd(&bl.scan[ins], (uint32_t)deg);
-        } else {
-          scanned += deg;
-        }
-        if (c == V::INF) {
-          Cnew[y] = V::INF;
-          if constexpr (BATCH) {
-            if (deg) {
-              atomicAdd(&a.idead[2 * ins], (unsigned long long)deg);
-              atomicAdd(&a.idead[2 * ins + 1], (unsigned long long)deg * (unsigned long long)r);
-            }
-          } else {
-            ddeg += deg;
-            ddeg_r += (long long)deg * r;
-          }
-        } else {
-          int32_t m = V::INF;
-          int32_t j = 0;
-          if (deg > 0) {
-            // the lightest in-edge alone first: its tail usually decides m.
-            // Round 1 reads the initial C: 0 for every vertex but the
-            // source, and the source is no tail of an undiscovered vertex
-            // (its out-edges were relaxed), so no gather is needed.
-            const int32_t v0 = rec2.y, w0 = rec2.z;
-            const int32_t c0 = (r == 1) ? 0 : Cg[v0];
-            if (c0 != V::INF) m = V::add(kmax(c0, mdi), w0);
-            j = (V::add(mdi, w0) >= m) ? deg : 1;
-          }
-          for (; j < deg; j += 4) {
-            int32_t vs[4], ws[4];
+  constexpr int LPT = BATCH ? kLivePT : 1;
+  constexpr uint32_t TILE = LPT * RBS;
+  for (uint32_t b0 = pc.vbid * TILE; b0 < (uint32_t)NL; b0 += pc.vnb * TILE) {
+    int32_t y[LPT], ins[LPT], sb[LPT], gi[LPT], mdi[LPT], c[LPT];
+    int32_t c0[LPT];
+    unsigned long long dk[LPT];
+    int4 rec[LPT], rec2[LPT];
+    bool val[LPT], keep[LPT];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const bool ok = j + q < deg;
-              vs[q] = ok ? G.in_src[b + j + q] : 0;
-              ws[q] = ok ? G.in_w[b + j + q] : 0;
-            }
-            int32_t cs[4];
+    for (int k = 0; k < LPT; ++k) {
+      const uint32_t i = b0 + (uint32_t)(k * RBS + tid);
+      val[k] = i < (uint32_t)NL;
+      keep[k] = false;
+      y[k] = (r == 1) ? (int32_t)(val[k] ? i : 0u) : Lv[val[k] ? i : 0u];
+    }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) cs[q] = (j + q < deg) ? Cg[vs[q]] : V::INF;
-            int32_t wl = 0;
+    for (int k = 0; k < LPT; ++k) {
+      sb[k] = 0;
+      gi[k] = 0;
+      ins[k] = 0;
+      mdi[k] = md;
+      if constexpr (BATCH) ins[k] = a.inst_of[y[k]];
+      dk[k] = a.D64[y[k]];
+      c[k] = Cold[y[k]];
+    }
+    if constexpr (BATCH) {
+      // the entry's instance, and that instance's minD this round (INF:
+      // its rounds have ended, so its undiscovered vertices are done)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              if (j + q < deg) {
-                if (cs[q] != V::INF) m = kmin(m, V::add(kmax(cs[q], mdi), ws[q]));
-                wl = ws[q];
-              }
-            }
-            if (V::add(mdi, wl) >= m) break;
-          }
-          Cnew[y] = kmax(kmax(c, mdi), m);
-          keep = true;
-        }
+      for (int k = 0; k < LPT; ++k) {
+        const InstDev id = a.insts[ins[k]];
+        sb[k] = id.sbase;
+        gi[k] = id.graph;
+        mdi[k] = ld_relaxed(&a.imin[s_now * I + ins[k]]);
       }
     }
-    // stage the kept vertices; flush to the next live list when full
+    // out_off, out_degree, in_off, in_degree; out_wmin, the lightest
+    // in-edge's tail and weight (the same line)
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const GraphDev &G = graph_of<BATCH>(a, gi[k]);
+      rec[k] = G.vrec[2 * (y[k] - sb[k])];
+      rec2[k] = G.vrec[2 * (y[k] - sb[k]) + 1];
+    }
+    // A batch also gathers the lightest in-edge's tail C here; a single
+    // solve only where the tests below pass (measured faster there).  Round
+    // 1 reads the initial C: 0 for every vertex but the source, and the
+    // source is no tail of an undiscovered vertex, its out-edges having been
+    // relaxed.
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) c0[k] = (r == 1 || !BATCH) ? 0 : Cold[sb[k] + rec2[k].y];
+#pragma unroll
+    for (int k = 0; k < LPT; ++k)
+      asm volatile("" : "+v"(dk[k]), "+v"(c[k]), "+v"(c0[k]), "+v"(rec[k].z), "+v"(rec[k].w),
+                   "+v"(rec2[k].z));
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const GraphDev &G = graph_of<BATCH>(a, gi[k]);
+      if (!(val[k] && G.all && mdi[k] != V::INF && (int32_t)(dk[k] >> 32) == V::INF)) continue;
+      const int32_t b = rec[k].z, deg = rec[k].w;
+      const int32_t *Cg = Cold + sb[k];  // the instance's C, by graph-local id
+      if constexpr (BATCH) {
+        if (I > kLdsInst) atomicAdd(&a.iscanned[3 * ins[k]], (unsigned long long)deg);
+        else atomicAdd(&bl.scan[ins[k]], (uint32_t)deg);
+      } else {
+        scanned += deg;
+      }
+      if (c[k] == V::INF) {
+        Cnew[y[k]] = V::INF;
+        if constexpr (BATCH) {
+          if (deg) {
+            atomicAdd(&a.idead[2 * ins[k]], (unsigned long long)deg);
+            atomicAdd(&a.idead[2 * ins[k] + 1], (unsigned long long)deg * (unsigned long long)r);
+          }
+        } else {
+          ddeg += deg;
+          ddeg_r += (long long)deg * r;
+        }
+        continue;
+      }
+      int32_t m = V::INF;
+      int32_t j = 0;
+      const int32_t mk = mdi[k];
+      if (deg > 0) {
+        // the lightest in-edge alone first: its tail usually decides m
+        const int32_t w0 = rec2[k].z;
+        const int32_t cz = (BATCH || r == 1) ? c0[k] : Cg[rec2[k].y];
+        if (cz != V::INF) m = V::add(kmax(cz, mk), w0);
+        j = (V::add(mk, w0) >= m) ? deg : 1;
+      }
+      for (; j < deg; j += 4) {
+        int32_t vs[4], ws[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = j + q < deg;
+          vs[q] = ok ? G.in_src[b + j + q] : 0;
+          ws[q] = ok ? G.in_w[b + j + q] : 0;
+        }
+        int32_t cs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cs[q] = (j + q < deg) ? Cg[vs[q]] : V::INF;
+        int32_t wl = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (j + q < deg) {
+            if (cs[q] != V::INF) m = kmin(m, V::add(kmax(cs[q], mk), ws[q]));
+            wl = ws[q];
+          }
+        }
+        if (V::add(mk, wl) >= m) break;
+      }
+      Cnew[y[k]] = kmax(kmax(c[k], mk), m);
+      keep[k] = true;
+    }
+    // stage the kept vertices in list order (entry k * RBS + tid of the
+    // tile): one scan of the per-slot keep flags packed in 16-bit fields;
+    // flush to the next live list when full
+    uint64_t packed = 0;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) packed |= (uint64_t)(keep[k] ? 1u : 0u) << (16 * k);
     uint64_t tot;
-    const uint64_t ex = block_excl_scan64<RBS>(keep ? 1ull : 0ull, sm.scan, &tot);
-    const int tcnt = (int)tot;
+    const uint64_t ex = block_excl_scan64<RBS>(packed, sm.scan, &tot);
+    int tcnt = 0;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) tcnt += (int)((tot >> (16 * k)) & 0xffffu);
     if (L.cnt + tcnt > CAP_L) {
       const int cnt = L.cnt;
       if (tid == 0) L.base = (int32_t)atomicAdd(lctr, (unsigned long long)cnt);
@@ -1115,7 +1166,12 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
       if (tid == 0) L.cnt = 0;
       __syncthreads();
     }
-    if (keep) L.v[L.cnt + (int)ex] = y;
+    int before = L.cnt;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      if (keep[k]) L.v[before + (int)((ex >> (16 * k)) & 0xffffu)] = y[k];
+      before += (int)((tot >> (16 * k)) & 0xffffu);
+    }
     __syncthreads();
     if (tid == 0) L.cnt += tcnt;
     __syncthreads();
