@@ -153,13 +153,32 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
         const int idx = b0 + tid;
         int32_t k0 = 0, k1 = 0;
         uint32_t nch = 0;
+        // the children among the first four out-edges (bit q: edge k0 + q)
+        uint32_t cm = 0;
+        int32_t cc[4] = {0, 0, 0, 0};
         if (idx < e) {
           const int32_t x = V[idx];
           k0 = G.u_out_off[x];
           k1 = G.u_out_off[x + 1];
-          for (int32_t k = k0; k < k1; ++k) {
-            const int32_t c = G.u_out_dst[k];
-            if (c != id.source && a.pred[sb + c] == k) ++nch;
+          // four out-edges at a time: their heads, then the heads' parent
+          // entries, each step's loads issued together (past the list's
+          // end a lane reads edge kb again and its test fails)
+          for (int32_t kb = k0; kb < k1; kb += 4) {
+            int32_t c[4], pr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = G.u_out_dst[kb + q < k1 ? kb + q : kb];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pr[q] = a.pred[sb + c[q]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (kb + q < k1 && c[q] != id.source && pr[q] == kb + q) {
+                ++nch;
+                if (kb == k0) {
+                  cm |= 1u << q;
+                  cc[q] = c[q];
+                }
+              }
+            }
           }
         }
         uint64_t tot;
@@ -167,9 +186,15 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
         if (tot > 0) {
           uint32_t p = (uint32_t)cnt + (uint32_t)ex;
           if (idx < e && nch) {
-            for (int32_t k = k0; k < k1; ++k) {
-              const int32_t c = G.u_out_dst[k];
-              if (c != id.source && a.pred[sb + c] == k) V[p++] = c;
+            if (k1 - k0 <= 4) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                if ((cm >> q) & 1u) V[p++] = cc[q];
+            } else {
+              for (int32_t k = k0; k < k1; ++k) {
+                const int32_t c = G.u_out_dst[k];
+                if (c != id.source && a.pred[sb + c] == k) V[p++] = c;
+              }
             }
           }
           __syncthreads();
@@ -190,9 +215,22 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
       for (int idx = ls + tid; idx < le; idx += BBS) {
         const int32_t y = V[idx];
         float acc = a.gcost[sb + y];
-        for (int32_t k = G.u_out_off[y]; k < G.u_out_off[y + 1]; ++k) {
-          const int32_t c = G.u_out_dst[k];
-          if (c != id.source && a.pred[sb + c] == k) acc = __fadd_rn(acc, a.acc[sb + c]);
+        const int32_t k0 = G.u_out_off[y], k1 = G.u_out_off[y + 1];
+        // as above, four out-edges at a time; a head's subtree sum loads
+        // with its parent entry and counts only for a child (in edge order)
+        for (int32_t kb = k0; kb < k1; kb += 4) {
+          int32_t c[4], pr[4];
+          float av[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) c[q] = G.u_out_dst[kb + q < k1 ? kb + q : kb];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            pr[q] = a.pred[sb + c[q]];
+            av[q] = a.acc[sb + c[q]];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (kb + q < k1 && c[q] != id.source && pr[q] == kb + q) acc = __fadd_rn(acc, av[q]);
         }
         a.acc[sb + y] = acc;
       }
