@@ -64,6 +64,9 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
       int32_t x = 0, ins = 0, sb = 0, vx = 0, k0 = 0, k1 = 0, root = -1;
       const GraphDev *G = nullptr;
       uint32_t nch = 0;
+      // the children among the first four out-edges (bit q: edge k0 + q)
+      uint32_t cm = 0;
+      int32_t cc[4] = {0, 0, 0, 0};
       if (idx < e) {
         x = a.lv_v[idx];
         ins = a.lv_i[idx];
@@ -74,9 +77,25 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
         vx = x - sb;
         k0 = G->u_out_off[vx];
         k1 = G->u_out_off[vx + 1];
-        for (int32_t k = k0; k < k1; ++k) {
-          const int32_t c = G->u_out_dst[k];
-          if (c != root && a.pred[sb + c] == k) ++nch;
+        // four out-edges at a time: their heads, then the heads' parent
+        // entries, each step's loads issued together (past the list's end a
+        // lane reads edge kb again and its test fails)
+        for (int32_t kb = k0; kb < k1; kb += 4) {
+          int32_t c[4], pr[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) c[q] = G->u_out_dst[kb + q < k1 ? kb + q : kb];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) pr[q] = a.pred[sb + c[q]];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (kb + q < k1 && c[q] != root && pr[q] == kb + q) {
+              ++nch;
+              if (kb == k0) {
+                cm |= 1u << q;
+                cc[q] = c[q];
+              }
+            }
+          }
         }
       }
       uint64_t tot;
@@ -86,12 +105,23 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
         __syncthreads();
         uint32_t p = sbase + (uint32_t)ex;
         if (idx < e && nch) {
-          for (int32_t k = k0; k < k1; ++k) {
-            const int32_t c = G->u_out_dst[k];
-            if (c != root && a.pred[sb + c] == k) {
-              a.lv_v[p] = sb + c;
-              a.lv_i[p] = ins;
-              ++p;
+          if (k1 - k0 <= 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if ((cm >> q) & 1u) {
+                a.lv_v[p] = sb + cc[q];
+                a.lv_i[p] = ins;
+                ++p;
+              }
+            }
+          } else {
+            for (int32_t k = k0; k < k1; ++k) {
+              const int32_t c = G->u_out_dst[k];
+              if (c != root && a.pred[sb + c] == k) {
+                a.lv_v[p] = sb + c;
+                a.lv_i[p] = ins;
+                ++p;
+              }
             }
           }
         }
@@ -115,9 +145,23 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
       const GraphDev &G = a.graphs[id.graph];
       const int32_t sb = id.sbase, vy = y - sb;
       float acc = a.gcost[y];
-      for (int32_t k = G.u_out_off[vy]; k < G.u_out_off[vy + 1]; ++k) {
-        const int32_t lc = G.u_out_dst[k], c = sb + lc;
-        if (lc != id.source && a.pred[c] == k) acc = __fadd_rn(acc, a.acc[c]);
+      const int32_t k0 = G.u_out_off[vy], k1 = G.u_out_off[vy + 1];
+      // as in the top-down pass, four out-edges at a time; a head's subtree
+      // sum loads with its parent entry and counts only for a child (in
+      // edge order)
+      for (int32_t kb = k0; kb < k1; kb += 4) {
+        int32_t lc[4], pr[4];
+        float av[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lc[q] = G.u_out_dst[kb + q < k1 ? kb + q : kb];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          pr[q] = a.pred[sb + lc[q]];
+          av[q] = a.acc[sb + lc[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (kb + q < k1 && lc[q] != id.source && pr[q] == kb + q) acc = __fadd_rn(acc, av[q]);
       }
       a.acc[y] = acc;
     }
