@@ -13,6 +13,7 @@
 namespace sssp {
 
 constexpr int WBS = 1024;  // threads of the workgroup
+static_assert(WBS == 1024, "the relax window search covers 1024 items");
 constexpr int kWgItems = 2;  // open-list entries per thread and pass of the bound step
 
 struct WgLds {
@@ -146,12 +147,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
         const int ET = (int)tot;
         nrel += (unsigned long long)ET;
         for (int e = tid; e < ET; e += WBS) {
-          int lo = 0, len = WBS;  // last window item with pfx <= e
-          while (len > 1) {
-            const int half = len >> 1;
-            if (s.pfx[lo + half] <= e) lo += half;
-            len -= half;
-          }
+          // the last window item with pfx <= e (an 8-ary search: four LDS steps)
+          const int lo = search1024(s.pfx, (uint32_t)e);
           const int32_t pos = s.wbase[lo] + (e - s.pfx[lo]);
           const int32_t y = G.out_dst[pos];
           const int32_t w = G.out_w[pos];
