@@ -243,8 +243,6 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
     ctl->live_ctr[0] = ctl->live_ctr[1] = 0ull;
     ctl->go = ctl->go_a = 0u;
     ctl->deg_count = 0;
-    ctl->resume_round = ctl->resume_phase = ctl->done = ctl->resume_act = 0;
-    ctl->resume_aep = 0u;
     ctl->solo_phases = 0;
     ctl->dead_deg = ctl->dead_deg_r = 0ull;
     ctl->rounds = r;

@@ -1537,17 +1537,19 @@ __device__ __forceinline__ uint32_t active_for(const RoundArgs &a, uint32_t E, u
   return k < nb ? k : nb;
 }
 
-// Block 0 publishes the resume point and moves `go` one epoch on.
+// Block 0 publishes the resume point in the next hand-over's slot and moves
+// `go` one epoch on.
 __device__ void wake_parked(Ctl *ctl, unsigned int &epoch, int r, int phase, int done,
                             uint32_t act, unsigned int aep) {
   wait_own_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    ctl->resume_round = r;
-    ctl->resume_phase = phase;
-    ctl->done = done;
-    ctl->resume_act = (int32_t)act;
-    ctl->resume_aep = aep;
+    ResumeSlot &s = ctl->resume[(epoch + 1u) % kResumeSlots];
+    s.round = r;
+    s.phase = phase;
+    s.done = done;
+    s.act = (int32_t)act;
+    s.aep = aep;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&ctl->go, epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -1557,19 +1559,32 @@ __device__ void wake_parked(Ctl *ctl, unsigned int &epoch, int r, int phase, int
 
 // A parked block sleeps until a hand-over names it active (or the solve
 // ends) and adopts the resume point.  Returns true when the solve is done.
+// It reads the slot of the hand-over it saw and keeps it only if no more
+// than kResumeSlots - 2 hand-overs followed meanwhile (block 0 writes the
+// slot of hand-over e + 1 before announcing it, so slot g is intact while
+// go < g + kResumeSlots - 1).  Hand-overs can follow only while this block
+// is not among their active blocks (block 0 waits for every active block
+// at the phase's end), so the slot it keeps names it active only if it is
+// the latest; otherwise it waits for the next one.
 __device__ bool park(Ctl *ctl, unsigned int &epoch, unsigned int &aep, int &r, int &phase,
                      uint32_t &act, SmemAll &sm) {
   for (;;) {
     if (threadIdx.x == 0) {
-      unsigned int g;
-      while ((int)((g = ld_flag(&ctl->go)) - epoch) <= 0) __builtin_amdgcn_s_sleep(2);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      unsigned int g, g2;
+      for (;;) {
+        while ((int)((g = ld_flag(&ctl->go)) - epoch) <= 0) __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const ResumeSlot *s = &ctl->resume[g % kResumeSlots];
+        sm.res_round = ld_relaxed(&s->round);
+        sm.res_phase = ld_relaxed(&s->phase);
+        sm.res_done = ld_relaxed(&s->done);
+        sm.res_act = ld_relaxed(&s->act);
+        sm.res_aep = (unsigned int)ld_relaxed((const int32_t *)&s->aep);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        g2 = ld_flag(&ctl->go);
+        if ((int)(g2 - g) <= kResumeSlots - 2) break;
+      }
       sm.res_go = g;
-      sm.res_round = ld_relaxed(&ctl->resume_round);
-      sm.res_phase = ld_relaxed(&ctl->resume_phase);
-      sm.res_done = ld_relaxed(&ctl->done);
-      sm.res_act = ld_relaxed(&ctl->resume_act);
-      sm.res_aep = (unsigned int)ld_relaxed((const int32_t *)&ctl->resume_aep);
     }
     __syncthreads();
     epoch = sm.res_go;
@@ -1867,14 +1882,9 @@ __global__ void init_seed_kernel(RoundArgs a) {
     c->open_ctr[1] = 0ull;
     c->go = 0u;
     c->go_a = 0u;
-    c->resume_act = 0;
-    c->resume_aep = 0u;
     c->status = 0;
     c->rounds = 0;
     c->deg_count = 0;
-    c->resume_round = 0;
-    c->resume_phase = 0;
-    c->done = 0;
     c->settled = c->relaxed = c->scanned = c->open_visits = 0;
     c->solo_phases = 0;
     c->live_ctr[0] = c->live_ctr[1] = 0ull;

@@ -48,6 +48,18 @@ enum { FX_OOFF = 0, FX_D, kFX };
 enum { OX_BASE = 0, OX_IDEG, OX_OOFF, OX_ODEG, OX_OWM, OX_C, kOX };
 constexpr int kOXMem = 8;
 
+// One hand-over to parked blocks: where to resume, whether the solve is
+// done, how many blocks are active from there, and the active barrier's
+// epoch.  Hand-over e (the e-th bump of Ctl::go) lives in slot
+// e % kResumeSlots, so a reader holding e reads a slot that no later
+// hand-over rewrites until e + kResumeSlots.
+constexpr int kResumeSlots = 8;
+struct ResumeSlot {
+  int32_t round, phase, done, act;
+  unsigned int aep;
+  int32_t pad[3];
+};
+
 // Control block of one persistent solve, in device memory.
 struct Ctl {
   unsigned long long front_ctr[2];  // by round parity: (items << 32) | out-degree sum
@@ -57,10 +69,7 @@ struct Ctl {
   int32_t status;                   // 0, or an sssp_status code set on the device
   int32_t rounds;
   int32_t deg_count;    // pred: vertices queued for the equal-cost pass
-  // hand-over to parked blocks: where to resume, how many blocks are active
-  // from there, and the active barrier's epoch
-  int32_t resume_round, resume_phase, done, resume_act;
-  unsigned int resume_aep;
+  ResumeSlot resume[kResumeSlots];  // hand-overs to parked blocks, by go % kResumeSlots
   long long settled, relaxed, scanned, open_visits;
   long long solo_phases;  // phases run by block 0 alone
   // single-target solve: the target's solver id (-1: none) and whether a

@@ -46,8 +46,6 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
     c->live_ctr[0] = c->live_ctr[1] = 0ull;
     c->go = c->go_a = 0u;
     c->deg_count = 0;
-    c->resume_round = c->resume_phase = c->done = c->resume_act = 0;
-    c->resume_aep = 0u;
     c->solo_phases = 0;
     c->dead_deg = c->dead_deg_r = 0ull;
     c->status = 0;
