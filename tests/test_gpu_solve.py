@@ -301,3 +301,25 @@ def test_workload_rmat22_full(sp):
                           G.effective_relax, G.effective_delta)
     assert_same_solution(cost, pred, st, ref, "rmat22")
     print("rmat22 rounds", st, flush=True)
+
+
+@pytest.mark.parametrize("relax", ["setting", "correcting"])
+def test_active_set_handovers(sp, relax):
+    """Many hand-overs between the active block sets of the round kernel:
+    small one-block thresholds and work units make the active set grow and
+    shrink phase after phase, so parked blocks adopt resume points often (a
+    block that took one hand-over's number with the next one's fields once
+    ran a phase twice).  Repeated solves must all equal the oracle's."""
+    g = gen.rmat_workload(scale=14)
+    G = sp.Graph(g.n, g.src, g.dst, g.w, relax=relax, scope="open")
+    ref = oracle_solution(g.n, g.src, g.dst, g.w, g.source, G.effective_scope,
+                          G.effective_relax, G.effective_delta)
+    sp.set_launch(dict(small_n=-1, wg=-1, solo_edges=256, block_units=256))
+    try:
+        for rep in range(6):
+            print("handovers", relax, "solve", rep, flush=True)
+            cost, pred, st = sp.solve(G, g.source, with_pred=True, with_stats=True)
+            sync()
+            assert_same_solution(cost, pred, st, ref, "handovers-%s-%d" % (relax, rep))
+    finally:
+        sp.set_launch(None)
