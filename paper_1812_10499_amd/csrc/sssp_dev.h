@@ -128,24 +128,42 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
   return (readlane64(v, 0) + readlane64(v, 16)) + (readlane64(v, 32) + readlane64(v, 48));
 }
 
-// inclusive prefix sum across the wave
+// Inclusive prefix sums across the wave (every lane active), by DPP:
+// Hillis-Steele steps within each row of 16 lanes (shifts right by 1, 2, 4,
+// 8; lanes without a source add 0), then row 0's total into row 1 and row
+// 2's into row 3 (broadcast of lane 15 of each row), then lane 31's total
+// into rows 2 and 3.
+enum : int { kDppRowShr = 0x110, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143 };
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, CTRL, ROWS, 0xF, true);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_or_zero64(uint64_t v) {
+  const uint32_t lo = dpp_or_zero<CTRL, ROWS>((uint32_t)v);
+  const uint32_t hi = dpp_or_zero<CTRL, ROWS>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < SSSP_WAVE; o <<= 1) {
-    uint64_t t = __shfl_up(v, o, SSSP_WAVE);
-    if (l >= o) v += t;
-  }
+  v += dpp_or_zero64<kDppRowShr + 1, 0xF>(v);
+  v += dpp_or_zero64<kDppRowShr + 2, 0xF>(v);
+  v += dpp_or_zero64<kDppRowShr + 4, 0xF>(v);
+  v += dpp_or_zero64<kDppRowShr + 8, 0xF>(v);
+  v += dpp_or_zero64<kDppRowBcast15, 0xA>(v);
+  v += dpp_or_zero64<kDppRowBcast31, 0xC>(v);
   return v;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < SSSP_WAVE; o <<= 1) {
-    uint32_t t = __shfl_up(v, o, SSSP_WAVE);
-    if (l >= o) v += t;
-  }
+  v += dpp_or_zero<kDppRowShr + 1, 0xF>(v);
+  v += dpp_or_zero<kDppRowShr + 2, 0xF>(v);
+  v += dpp_or_zero<kDppRowShr + 4, 0xF>(v);
+  v += dpp_or_zero<kDppRowShr + 8, 0xF>(v);
+  v += dpp_or_zero<kDppRowBcast15, 0xA>(v);
+  v += dpp_or_zero<kDppRowBcast31, 0xC>(v);
   return v;
 }
 
