@@ -201,7 +201,7 @@ __device__ __forceinline__ void batch_offer(BatchLds<true> &bl, const RoundArgs 
   const uint64_t act = __ballot(on);
   if (!act) return;
   const int lead = __ffsll((unsigned long long)act) - 1;
-  const int i0 = __shfl(ins, lead, SSSP_WAVE);
+  const int i0 = __builtin_amdgcn_readlane(ins, lead);
   if (__ballot(on && ins == i0) == act) {
     const int32_t wv = wave_min(on ? v : V::INF);
     const int32_t wt = wave_min(on ? t : V::INF);
@@ -717,10 +717,10 @@ __device__ void relax_push_global(const RoundArgs &a, const ListRef &l, const in
   }
   const uint64_t mine = ((uint64_t)n << 32) | wsum;
   const uint64_t inc = wave_incl_scan64(mine);
-  const uint64_t tot = __shfl(inc, SSSP_WAVE - 1, SSSP_WAVE);
+  const uint64_t tot = (uint64_t)readlane64((int64_t)inc, SSSP_WAVE - 1);
   unsigned long long base = 0;
   if (lane_id() == 0 && tot) base = atomicAdd(l.ctr, (unsigned long long)tot);
-  base = __shfl(base, 0, SSSP_WAVE);
+  base = (unsigned long long)readlane64((int64_t)base, 0);
   const uint64_t ex = inc - mine;
   int32_t pos = (int32_t)(base >> 32) + (int32_t)(ex >> 32);
   uint32_t p = (uint32_t)(base & 0xffffffffull) + (uint32_t)(ex & 0xffffffffull);
@@ -943,7 +943,7 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
           if (tot) {
             int wbase = 0;
             if (lane_id() == 0) wbase = atomicAdd(&S.st.cnt, tot);
-            wbase = __shfl(wbase, 0, SSSP_WAVE);
+            wbase = __builtin_amdgcn_readlane(wbase, 0);
             int sp = wbase + (int)ex;
             int32_t ni[EPT];
             uint32_t over = 0;
@@ -1366,7 +1366,7 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
           const uint64_t act = __ballot(val[j]);
           if (act) {
             const int lead = __ffsll((unsigned long long)act) - 1;
-            const int it0 = __shfl(myit, lead, SSSP_WAVE);
+            const int it0 = __builtin_amdgcn_readlane(myit, lead);
             const uint64_t same = __ballot(val[j] && myit == it0);
             if (same == act) {
               const int32_t wm = wave_min(t);

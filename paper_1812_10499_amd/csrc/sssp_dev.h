@@ -114,6 +114,7 @@ __device__ __forceinline__ int64_t dpp_mov64(int64_t v) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// Lane `lane` (wave-uniform) of v, in scalar registers.
 __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)v, lane);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)((uint64_t)v >> 32), lane);
