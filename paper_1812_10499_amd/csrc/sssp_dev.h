@@ -200,25 +200,23 @@ __device__ __forceinline__ uint32_t wave_excl_small(uint32_t v, uint32_t *total)
   return ex;
 }
 
-// Block-wide exclusive scan of a uint64 per thread.  `scratch` must hold
-// BS/64 + 1 entries of LDS.  Returns the exclusive prefix; *total gets the
+// Block-wide exclusive scan of a uint64 per thread (BS a multiple of 64, at
+// most 64 waves).  `scratch` must hold BS/64 + 1 entries of LDS.  Returns the exclusive prefix; *total gets the
 // block sum.  Contains __syncthreads(); call from all threads.
 template <int BS>
 __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t *scratch,
                                                      uint64_t *total) {
   constexpr int NW = BS / SSSP_WAVE;
+  static_assert(NW * SSSP_WAVE == BS && NW <= SSSP_WAVE, "whole waves, one wave of totals");
   const int w = threadIdx.x / SSSP_WAVE, l = lane_id();
   uint64_t inc = wave_incl_scan64(v);
   if (l == SSSP_WAVE - 1) scratch[w] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t run = 0;
-    for (int i = 0; i < NW; ++i) {
-      uint64_t t = scratch[i];
-      scratch[i] = run;
-      run += t;
-    }
-    scratch[NW] = run;
+  if (w == 0) {  // the waves' totals, prefixed by wave 0 in one wave scan
+    const uint64_t t = l < NW ? scratch[l] : 0ull;
+    const uint64_t it = wave_incl_scan64(t);
+    if (l < NW) scratch[l] = it - t;
+    if (l == NW - 1) scratch[NW] = it;
   }
   __syncthreads();
   uint64_t res = scratch[w] + inc - v;
@@ -234,6 +232,7 @@ __device__ __forceinline__ void block_excl_scan64x2(uint64_t v1, uint64_t v2, ui
                                                     uint64_t *ex1, uint64_t *ex2,
                                                     uint64_t *tot1, uint64_t *tot2) {
   constexpr int NW = BS / SSSP_WAVE;
+  static_assert(NW * SSSP_WAVE == BS && NW <= SSSP_WAVE, "whole waves, one wave of totals");
   const int w = threadIdx.x / SSSP_WAVE, l = lane_id();
   const uint64_t i1 = wave_incl_scan64(v1), i2 = wave_incl_scan64(v2);
   if (l == SSSP_WAVE - 1) {
@@ -241,15 +240,17 @@ __device__ __forceinline__ void block_excl_scan64x2(uint64_t v1, uint64_t v2, ui
     scratch[NW + 1 + w] = i2;
   }
   __syncthreads();
-  if (threadIdx.x < 2) {
-    uint64_t *s = scratch + threadIdx.x * (NW + 1);
-    uint64_t run = 0;
-    for (int i = 0; i < NW; ++i) {
-      const uint64_t t = s[i];
-      s[i] = run;
-      run += t;
+  if (w == 0) {  // both sets of wave totals, prefixed by wave 0
+    const uint64_t t1 = l < NW ? scratch[l] : 0ull, t2 = l < NW ? scratch[NW + 1 + l] : 0ull;
+    const uint64_t s1 = wave_incl_scan64(t1), s2 = wave_incl_scan64(t2);
+    if (l < NW) {
+      scratch[l] = s1 - t1;
+      scratch[NW + 1 + l] = s2 - t2;
     }
-    s[NW] = run;
+    if (l == NW - 1) {
+      scratch[NW] = s1;
+      scratch[2 * NW + 1] = s2;
+    }
   }
   __syncthreads();
   *ex1 = scratch[w] + i1 - v1;
