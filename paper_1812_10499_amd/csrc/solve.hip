@@ -441,7 +441,10 @@ __device__ int find_start_item(const int32_t *lp, int N, uint32_t c, uint32_t e0
     const bool le = (uint32_t)lp[pos] + c * (uint32_t)pos <= e0;
     if (threadIdx.x == 0) sm.tmax = 0;
     __syncthreads();
-    if (le) atomicMax(&sm.tmax, (int)threadIdx.x);
+    // the last thread with le (they form a prefix): one LDS atomic per wave
+    const uint64_t bl = __ballot(le);
+    if (lane_id() == 0 && bl)
+      atomicMax(&sm.tmax, (int)(threadIdx.x + 63u - (uint32_t)__clzll((long long)bl)));
     __syncthreads();
     const int t = sm.tmax;
     const int nlo = lo + (int)(((int64_t)span * t) / RBS);
