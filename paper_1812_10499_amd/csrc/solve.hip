@@ -467,23 +467,34 @@ __device__ __forceinline__ uint32_t chunk_of(uint32_t E, uint32_t vnb) {
   return (E + vnb - 1) / vnb;
 }
 
+// A prefix search below stops once its interval [lo, hi) holds at most
+// kSearchSlack edges and takes hi: the count then covers the prefix and at
+// most kSearchSlack edges that fail the weight test.  The bound step reads
+// an item's in-edges contiguously and gathers C only for edges that pass,
+// so each extra edge costs a share of a coalesced read, where every search
+// step saved is a dependent random read (a CU issues about one random
+// line per clock, and these searches run in the lists' flushes and
+// finishes).
+constexpr int32_t kSearchSlack = 32;
+
 // Work of an open vertex y in the bound step: its in-edges (v, y, w) with
 // md + w < dy.  The working copy's in-lists are ascending by weight and the
-// rounded add is monotone, so they are a prefix of y's list; its length is
-// found by binary search (short lists are taken whole).  With md at most
-// the minD of the round that scans y and dy at least that round's D[y],
-// the prefix covers every edge the bound step needs.
+// rounded add is monotone, so they are a prefix of y's list; a binary
+// search bounds its length from above, to within kSearchSlack (short lists
+// are taken whole).  With md at most the minD of the round that scans y and
+// dy at least that round's D[y], the prefix covers every edge the bound
+// step needs.
 template <class V>
 __device__ __forceinline__ int32_t useful_in_edges_at(const GraphDev &G, int32_t b, int32_t deg,
                                                       int32_t md, int32_t dy) {
   int32_t lo = 0, hi = deg;
   if (hi <= 16) return hi;
-  while (lo < hi) {
+  while (hi - lo > kSearchSlack) {
     const int32_t mid = (lo + hi) >> 1;
     if (V::add(md, G.in_w[b + mid]) < dy) lo = mid + 1;
     else hi = mid;
   }
-  return lo;
+  return hi;
 }
 
 // Work of a vertex y first discovered in this round's relax step: the
@@ -628,9 +639,9 @@ __device__ void discovery_work_x(const RoundArgs &a, const int32_t *Cold, uint32
       const bool pass = ((bylim >> k) & 1u) ? x[k] < lim[k] : V::add(md[k], x[k]) < dy[k];
       if (pass) lo[k] = mid[k] + 1;
       else hi[k] = mid[k];
-      if (lo[k] >= hi[k]) {
+      if (hi[k] - lo[k] <= kSearchSlack) {
         search &= ~(1u << k);
-        out[k] = lo[k];
+        out[k] = hi[k];
       }
     }
   }
