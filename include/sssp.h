@@ -392,7 +392,7 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
  *   solo_edges:  a phase with at most this many edges runs on one block
  *                with block barriers only (default 8192; negative: never);
  *   block_units: otherwise the phase runs on about (work units) /
- *                block_units blocks, a power of two (default 4096);
+ *                block_units blocks, a power of two (default 2048);
  *   small_n:     a single solve (sssp_solve, sssp_solve_target, the
  *                sequence plan) of a graph with at most this many vertices
  *                runs all its rounds in one workgroup with the per-vertex
@@ -463,8 +463,8 @@ sssp_status sssp_plan_destroy(sssp_plan plan);
  * Launch-geometry autotuner: builds a plan for the given solves and times
  * its replays (HIP events on `stream`, `reps` timed runs after one warm-up,
  * mean taken) under candidate geometries, one field at a time (blocks:
- * maximum, 1/2, 1/4; solo_edges: 2048, 8192, 32768; block_units: 2048,
- * 4096, 8192; small_n: the default, never; wg: the default, never, and
+ * maximum, 1/2, 1/4; solo_edges: 2048, 8192, 32768; block_units: 1024,
+ * 2048, 4096; small_n: the default, never; wg: the default, never, and
  * always when there are at least a quarter as many instances as compute
  * units), keeping a candidate only when it beats the best so far.
  * *best receives the fastest geometry, *best_ms its mean run time.  Writes

@@ -172,7 +172,7 @@ sssp_status resolve_launch(DevWS &w, bool f32, bool batch, const sssp_launch *L,
   }
   a.solo_edges = env_flag("SSSP_SOLO_EDGES", 8192);
   if (L && L->solo_edges) a.solo_edges = L->solo_edges < 0 ? 0 : L->solo_edges;
-  a.block_units = env_flag("SSSP_BLOCK_UNITS", 4096);
+  a.block_units = env_flag("SSSP_BLOCK_UNITS", 2048);
   if (L && L->block_units) {
     if (L->block_units < 0) return SSSP_ERR_ARG;
     a.block_units = L->block_units;
@@ -1319,7 +1319,7 @@ sssp_status sssp_autotune(const sssp_csr *graphs, int32_t num_graphs, const int3
     if ((st = time_of(cur, &cur_ms))) return st;
     const int32_t blocks[3] = {full.blocks, full.blocks / 2, full.blocks / 4};
     const int32_t solo[3] = {2048, 8192, 32768};
-    const int32_t units[3] = {2048, 4096, 8192};
+    const int32_t units[3] = {1024, 2048, 4096};
     const int32_t small[3] = {full.small_n, -1, full.small_n};
     const int32_t wgs[3] = {0, -1, 1};
     for (int field = 0; field < 5; ++field) {
