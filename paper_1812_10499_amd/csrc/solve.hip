@@ -1069,7 +1069,9 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
       mdi[k] = md;
       if constexpr (BATCH) ins[k] = a.inst_of[y[k]];
       dk[k] = a.D64[y[k]];
-      c[k] = Cold[y[k]];
+      // round 1: every C is still 0 but the sources', and they are
+      // discovered (their entries drop at the test below)
+      c[k] = (r == 1) ? 0 : Cold[y[k]];
     }
     if constexpr (BATCH) {
       // the entry's instance, and that instance's minD this round (INF:
