@@ -150,6 +150,9 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  *   s_out_off[n+1], s_out_dst[m] (solver ids), s_out_w[m], s_out_eid[m]
  *       each out-list ascending by (head solver id, edge id)
  *   s_out_wmin[n]  out_wmin by solver id
+ * and s_in_sw[2m]: s_in_src and s_in_w of each in-list entry side by side
+ *   (entry j at 2j, 2j + 1), so that a scan reads an in-edge's tail and
+ *   weight from one place.
  * Always, too: s_vrec[8n], one 32-byte record per solver vertex,
  *   {out_off, out_degree, in_off, in_degree, out_wmin, s_in_src and s_in_w
  *   of the first in-list entry (0, 0 with no in-edges), 0}, so that a round
@@ -190,6 +193,7 @@ typedef struct {
   const void *s_in_w;
   const void *s_out_wmin;
   const int32_t *s_vrec;
+  const int32_t *s_in_sw;
 } sssp_csr;
 
 /*

@@ -49,7 +49,8 @@ class Csr(ctypes.Structure):
                 ("s_out_w", ctypes.c_void_p), ("s_out_eid", ctypes.c_void_p),
                 ("s_in_off", ctypes.c_void_p), ("s_in_src", ctypes.c_void_p),
                 ("s_in_eid", ctypes.c_void_p), ("s_in_w", ctypes.c_void_p),
-                ("s_out_wmin", ctypes.c_void_p), ("s_vrec", ctypes.c_void_p)]
+                ("s_out_wmin", ctypes.c_void_p), ("s_vrec", ctypes.c_void_p),
+                ("s_in_sw", ctypes.c_void_p)]
 
 
 class Policy(ctypes.Structure):

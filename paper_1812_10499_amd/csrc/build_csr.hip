@@ -449,15 +449,18 @@ __global__ void weight_key_kernel(const int32_t *w, int32_t m, int32_t *key,
 }
 
 // entry p of a solver-numbered list: edge id eid[p]; the neighbour's solver
-// id and the weight come from the caller-numbered arrays
+// id and the weight come from the caller-numbered arrays (s_pair, when
+// given, receives both side by side)
 __global__ void copy_gather_kernel(const int32_t *eid, const int32_t *ends, const int32_t *rank,
                                    const int32_t *out_w, int32_t m, int32_t *s_nbr,
-                                   int32_t *s_w) {
+                                   int32_t *s_w, int2 *s_pair) {
   for (int32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
     const int32_t e = eid[p];
     const int32_t v = ends[e];
-    if (s_nbr) s_nbr[p] = rank ? rank[v] : v;
-    s_w[p] = out_w[e];
+    const int32_t nb = rank ? rank[v] : v, w = out_w[e];
+    if (s_nbr) s_nbr[p] = nb;
+    s_w[p] = w;
+    if (s_pair) s_pair[p] = make_int2(nb, w);
   }
 }
 
@@ -498,7 +501,7 @@ hipError_t launch_renumber(int32_t n, int32_t m, int32_t dmax, const int32_t *ou
                        stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(copy_gather_kernel, dim3(gm), dim3(256), 0, stream, c.out_eid, out_dst,
-                       c.rank, out_w, m, c.out_dst, c.out_w);
+                       c.rank, out_w, m, c.out_dst, c.out_w, (int2 *)nullptr);
   }
   hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, c.out_off);
   hipLaunchKernelGGL(copy_wmin_kernel, dim3(grid_for(n)), dim3(256), 0, stream, c.vid, out_wmin,
@@ -527,7 +530,7 @@ hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t
                        stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(copy_gather_kernel, dim3(gm), dim3(256), 0, stream, c.in_eid, t.tail,
-                       c.rank, out_w, m, c.in_src, c.in_w);
+                       c.rank, out_w, m, c.in_src, c.in_w, (int2 *)c.in_sw);
   }
   hipLaunchKernelGGL(offsets_kernel, dim3(gn), dim3(256), 0, stream, t.ka, m, n, c.in_off);
   return hipGetLastError();

@@ -50,9 +50,10 @@ __device__ __forceinline__ int32_t small_m(const GraphDev &G, const int32_t *Col
     if (cv != V::INF) m = V::add(kmax(cv, md), w0);
   }
   for (int32_t j = 1; j < deg; ++j) {
-    const int32_t w = G.in_w[b + j];
+    const int2 e = G.in_sw[b + j];  // tail, weight
+    const int32_t w = e.y;
     if (V::add(md, w) >= kmin(lim, m)) break;
-    const int32_t cv = Cold[G.in_src[b + j]];
+    const int32_t cv = Cold[e.x];
     if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
   }
   return m;

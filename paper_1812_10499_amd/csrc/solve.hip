@@ -570,8 +570,9 @@ __device__ void discovery_work_x(const RoundArgs &a, const int32_t *Cold, uint32
       if (deg[k] > 16) {
         const GraphDev &G = graph_of<BATCH>(a, gi[k]);
         probe |= 1u << k;
-        v1[k] = G.in_src[b[k] + 1];
-        w1[k] = G.in_w[b[k] + 1];
+        const int2 e1 = G.in_sw[b[k] + 1];
+        v1[k] = e1.x;
+        w1[k] = e1.y;
       } else {
         out[k] = deg[k];
       }
@@ -1142,9 +1143,9 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
         int32_t vs[4], ws[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const bool ok = j + q < deg;
-          vs[q] = ok ? G.in_src[b + j + q] : 0;
-          ws[q] = ok ? G.in_w[b + j + q] : 0;
+          const int2 e = (j + q < deg) ? G.in_sw[b + j + q] : make_int2(0, 0);
+          vs[q] = e.x;
+          ws[q] = e.y;
         }
         int32_t cs[4];
 #pragma unroll
@@ -1350,9 +1351,9 @@ __device__ void fused_phase(const RoundArgs &a, SmemAll &sm, const PhaseCtx &pc,
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-          v[j] = G.in_src[pos[j]];
-          wt[j] = G.in_w[pos[j]];
+          const int2 e = graph_of<BATCH>(a, S.gi[it[j]]).in_sw[pos[j]];
+          v[j] = e.x;
+          wt[j] = e.y;
         }
         // the loaded values count as used here: no load moves into the
         // gather's condition below

@@ -239,6 +239,7 @@ struct SolverCopy {
   int32_t *vid, *rank;
   int32_t *out_off, *out_dst, *out_w, *out_eid;
   int32_t *in_off, *in_src, *in_eid, *in_w;
+  int32_t *in_sw;  // (in_src, in_w) pairs
   int32_t *out_wmin;
   int32_t *vrec;  // 8 ints per vertex
 };

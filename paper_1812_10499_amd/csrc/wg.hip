@@ -278,9 +278,10 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           if (ideg > 0 && V::add(md, w0) < dy[u]) {
             if (c0[u] != V::INF) m = V::add(kmax(c0[u], md), w0);
             for (int32_t j = 1; j < ideg; ++j) {  // the rest from the in-list
-              const int32_t w = G.in_w[ioff + j];
+              const int2 e = G.in_sw[ioff + j];  // tail, weight
+              const int32_t w = e.y;
               if (V::add(md, w) >= kmin(dy[u], m)) break;
-              const int32_t cv = Cold[G.in_src[ioff + j]];
+              const int32_t cv = Cold[e.x];
               if (cv != V::INF) m = kmin(m, V::add(kmax(cv, md), w));
             }
           }
