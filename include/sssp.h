@@ -153,6 +153,9 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  * and s_in_sw[2m]: s_in_src and s_in_w of each in-list entry side by side
  *   (entry j at 2j, 2j + 1), so that a scan reads an in-edge's tail and
  *   weight from one place.
+ * and s_out_rec[4m]: per entry of the working copy's out-lists (s_out_*),
+ *   {head solver id, weight, edge id, out_wmin of the head}, so that a
+ *   relax reads an out-edge and its head's out_wmin from one place.
  * Always, too: s_vrec[8n], one 32-byte record per solver vertex,
  *   {out_off, out_degree, in_off, in_degree, out_wmin, s_in_src and s_in_w
  *   of the first in-list entry (0, 0 with no in-edges), 0}, so that a round
@@ -194,6 +197,7 @@ typedef struct {
   const void *s_out_wmin;
   const int32_t *s_vrec;
   const int32_t *s_in_sw;
+  const int32_t *s_out_rec;
 } sssp_csr;
 
 /*

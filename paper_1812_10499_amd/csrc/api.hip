@@ -192,7 +192,8 @@ bool csr_ok(const sssp_csr *g) {
         g->out_off && g->in_off && g->out_wmin && g->s_out_off && g->s_in_off &&
         g->s_out_wmin && g->s_vrec &&
         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
-                       g->s_out_dst && g->s_out_w && g->s_in_src && g->s_in_eid && g->s_in_w && g->s_in_sw))))
+                       g->s_out_dst && g->s_out_w && g->s_in_src && g->s_in_eid && g->s_in_w && g->s_in_sw &&
+                       g->s_out_rec))))
     return false;
   if (g->order == SSSP_ORDER_INPUT) return true;
   return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && (g->m == 0 || g->s_out_eid);
@@ -263,6 +264,7 @@ GraphDev graph_dev(const sssp_csr *g) {
   d.in_src = g->s_in_src;
   d.in_w = (const int32_t *)g->s_in_w;
   d.in_sw = (const int2 *)g->s_in_sw;
+  d.out_rec = (const int4 *)g->s_out_rec;
   d.out_wmin = (const int32_t *)g->s_out_wmin;
   d.vrec = (const int4 *)g->s_vrec;
   d.vid = g->vid;
@@ -285,7 +287,7 @@ GraphDev graph_dev(const sssp_csr *g) {
 // weight-ordered in-lists, then (degree order) the renumbered CSR.
 enum BufArr {
   B_OUT_OFF, B_OUT_DST, B_OUT_W, B_IN_OFF, B_IN_SRC, B_IN_EID, B_IN_W, B_OUT_WMIN,
-  B_S_IN_OFF, B_S_IN_SRC, B_S_IN_EID, B_S_IN_W, B_S_VREC, B_S_IN_SW,
+  B_S_IN_OFF, B_S_IN_SRC, B_S_IN_EID, B_S_IN_W, B_S_VREC, B_S_IN_SW, B_S_OUT_REC,
   B_VID, B_RANK, B_S_OUT_OFF, B_S_OUT_DST, B_S_OUT_W, B_S_OUT_EID, B_S_OUT_WMIN, B_COUNT
 };
 
@@ -299,7 +301,7 @@ Layout build_layout(int32_t n, int32_t m, bool renumber) {
   size_t o = 0;
   const size_t N = (size_t)n, M = (size_t)m;
   const size_t count[B_COUNT] = {N + 1, M, M, N + 1, M, M, M, N, N + 1, M, M, M, 8 * N, 2 * M,
-                                 N,     N, N + 1, M, M, M, N};
+                                 4 * M, N, N, N + 1, M, M, M, N};
   const int narr = renumber ? B_COUNT : B_VID;
   for (int i = 0; i < B_COUNT; ++i) {
     L.off[i] = o;
@@ -323,6 +325,7 @@ SolverCopy solver_copy(const sssp_csr *g) {
   c.in_eid = (int32_t *)g->s_in_eid;
   c.in_w = (int32_t *)g->s_in_w;
   c.in_sw = (int32_t *)g->s_in_sw;
+  c.out_rec = (int32_t *)g->s_out_rec;
   c.out_wmin = (int32_t *)g->s_out_wmin;
   c.vrec = (int32_t *)g->s_vrec;
   return c;
@@ -647,6 +650,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   c.in_eid = arr(B_S_IN_EID);
   c.in_w = arr(B_S_IN_W);
   c.in_sw = arr(B_S_IN_SW);
+  c.out_rec = arr(B_S_OUT_REC);
   c.vrec = arr(B_S_VREC);
   if (m > 0) {
     HIPCHK(launch_degree(n, out_off, in_off, t, stream));
@@ -672,6 +676,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   }
   HIPCHK(launch_in_lists(n, m, wkey_max, out_off, out_dst, out_w, c, t, stream));
   HIPCHK(launch_vrec(n, c, stream));
+  HIPCHK(launch_out_rec(m, c, stream));
   out->s_vrec = c.vrec;
   out->vid = c.vid;
   out->rank = c.rank;
@@ -684,6 +689,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->s_in_eid = c.in_eid;
   out->s_in_w = c.in_w;
   out->s_in_sw = c.in_sw;
+  out->s_out_rec = c.out_rec;
   out->s_out_wmin = c.out_wmin;
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));
@@ -737,6 +743,7 @@ sssp_status sssp_set_weights(sssp_csr *g, const void *w, void *stream_) {
   HIPCHK(launch_in_lists(g->n, g->m, hs[1], g->out_off, g->out_dst, (const int32_t *)g->out_w,
                          c, t, stream));
   HIPCHK(launch_vrec(g->n, c, stream));  // out_wmin and the in-list heads changed
+  HIPCHK(launch_out_rec(g->m, c, stream));  // the weights and the heads' out_wmin
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));
   g->w_max = w_max;

@@ -556,6 +556,23 @@ hipError_t launch_vrec(int32_t n, const SolverCopy &c, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// Entry p of the working copy's out-lists as one record: head, weight, edge
+// id (the position when the copy is the CSR itself), the head's out_wmin.
+__global__ void out_rec_kernel(int32_t m, const int32_t *out_dst, const int32_t *out_w,
+                               const int32_t *out_eid, const int32_t *out_wmin, int4 *rec) {
+  for (int32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+    const int32_t y = out_dst[p];
+    rec[p] = make_int4(y, out_w[p], out_eid ? out_eid[p] : p, out_wmin[y]);
+  }
+}
+
+hipError_t launch_out_rec(int32_t m, const SolverCopy &c, hipStream_t stream) {
+  if (m > 0)
+    hipLaunchKernelGGL(out_rec_kernel, dim3(grid_for(m)), dim3(256), 0, stream, m, c.out_dst,
+                       c.out_w, c.out_eid, c.out_wmin, (int4 *)c.out_rec);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------- reweighting
 __global__ void set_weights_kernel(const int32_t *w, const int32_t *in_eid, int32_t m,
                                    int32_t *out_w, int32_t *in_w, const int32_t *s_out_eid,

@@ -873,19 +873,18 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
           it[j] = window_item(S.epfx, qc);
           pos[j] = S.epos[it[j]] + (int32_t)(qc - (uint32_t)S.epfx[it[j]]);
         }
+        // one record per edge: head, weight, edge id (the caller's CSR
+        // position) and the head's out_wmin
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          // the edge id is the caller's CSR position (out_eid under a
-          // renumbering; without one the load reads out_dst again)
-          const GraphDev &G = graph_of<BATCH>(a, S.gi[it[j]]);
-          const int32_t *E = G.out_eid ? G.out_eid : G.out_dst;
-          y[j] = G.out_dst[pos[j]];
-          wt[j] = G.out_w[pos[j]];
-          eid[j] = E[pos[j]];
+          const int4 e = graph_of<BATCH>(a, S.gi[it[j]]).out_rec[pos[j]];
+          y[j] = e.x;
+          wt[j] = e.y;
+          eid[j] = e.z;
+          wm[j] = e.w;
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-          if (!graph_of<BATCH>(a, S.gi[it[j]]).out_eid) eid[j] = pos[j];
           cand[j] = V::add(S.dx[it[j]], wt[j]);
           gy[j] = S.sb[it[j]] + y[j];
         }
@@ -913,8 +912,8 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
         for (int j = 0; j < EPT; ++j)
           if (doa[j]) old[j] = atomicMin(&a.D64[gy[j]], key[j]);
         // Offers to minD and thr.  With the key read first, every candidate
-        // below the D it read is offered, with its head's out_wmin, while
-        // the atomics are in flight.  That covers every value D[y] takes in
+        // below the D it read is offered, with its head's out_wmin (from the
+        // edge record), while the atomics are in flight.  That covers every value D[y] takes in
         // the phase (the candidate that first brings D[y] to a value read a
         // larger D), and a candidate that lost a race to a smaller one is
         // at least y's final D, itself offered: both minima are exact.
@@ -926,9 +925,6 @@ __device__ void relax_phase(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl
 #pragma unroll
           for (int j = 0; j < EPT; ++j) off[j] = doa[j] && cand[j] < (int32_t)(old[j] >> 32);
         }
-#pragma unroll
-        for (int j = 0; j < EPT; ++j)
-          if (off[j]) wm[j] = graph_of<BATCH>(a, S.gi[it[j]]).out_wmin[y[j]];
         uint32_t nmask = 0;
 #pragma unroll
         for (int j = 0; j < EPT; ++j)

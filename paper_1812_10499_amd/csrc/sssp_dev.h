@@ -48,11 +48,14 @@ __device__ __forceinline__ int32_t kmax(int32_t a, int32_t b) { return a > b ? a
 // vrec: per solver vertex {out_off, out_degree, in_off, in_degree,
 // out_wmin, in_src and in_w of the lightest in-edge (0, 0 if none), 0}
 // (one 32-byte record).  in_sw: (in_src, in_w) of each in-list entry side
-// by side, one 8-byte read per in-edge where a scan needs both.
+// by side, one 8-byte read per in-edge where a scan needs both.  out_rec:
+// per out-list entry {out_dst, out_w, edge id (out_eid, else the
+// position), out_wmin of the head}, one 16-byte read per relaxed edge.
 struct GraphDev {
   const int32_t *out_off, *out_dst, *out_w, *out_eid;
   const int32_t *in_off, *in_src, *in_w;
   const int2 *in_sw;
+  const int4 *out_rec;
   const int32_t *out_wmin;
   const int4 *vrec;
   const int32_t *vid, *rank;

@@ -240,6 +240,7 @@ struct SolverCopy {
   int32_t *out_off, *out_dst, *out_w, *out_eid;
   int32_t *in_off, *in_src, *in_eid, *in_w;
   int32_t *in_sw;  // (in_src, in_w) pairs
+  int32_t *out_rec;  // (out_dst, out_w, edge id, out_wmin of the head) per out-list entry
   int32_t *out_wmin;
   int32_t *vrec;  // 8 ints per vertex
 };
@@ -267,6 +268,8 @@ hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t
                            const BuildTemps &t, hipStream_t stream);
 // the per-vertex records of the copy (after its offsets and out_wmin)
 hipError_t launch_vrec(int32_t n, const SolverCopy &c, hipStream_t stream);
+// c.out_rec from the working copy's out-lists and out_wmin (after launch_vrec's inputs are final)
+hipError_t launch_out_rec(int32_t m, const SolverCopy &c, hipStream_t stream);
 // new weights (validated by the caller) into the CSR/CSC, out_wmin and the
 // copy's out-lists; the copy's in-lists are rebuilt by launch_in_lists
 hipError_t launch_set_weights(int32_t n, int32_t m, bool f32, const int32_t *w,
