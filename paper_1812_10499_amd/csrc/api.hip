@@ -24,6 +24,7 @@ enum Slot {
   S_GTAB, S_ITAB,
   S_BK_KA, S_BK_KB, S_BK_VA, S_BK_VB, S_BK_HIST, S_BK_TAIL, S_BK_STATUS,
   S_BW_ACC, S_BW_LV, S_BW_LI, S_BW_LOFF, S_BW_CTL, S_BW_GOFF, S_BW_GINST, S_BW_EBASE,
+  S_BW_CS, S_BW_LACC,
   S_TRACE, S_FLAGS, S_PART, S_D64, S_FX, S_OX0, S_OX1, S_LV0, S_LV1, S_DR, S_INSTOF, S_IDEAD,
   NSLOTS
 };
@@ -1411,6 +1412,8 @@ sssp_status sssp_backward(const sssp_csr *graphs, int32_t num_graphs, const int3
   if ((s = ws_arr(ws, S_BW_LV, (size_t)total, &b.lv_v))) return s;
   if ((s = ws_arr(ws, S_BW_LI, (size_t)total, &b.lv_i))) return s;
   if ((s = ws_arr(ws, S_BW_LOFF, (size_t)total + 2, &b.lv_off))) return s;
+  if ((s = ws_arr(ws, S_BW_CS, (size_t)total, &b.lv_cs))) return s;
+  if ((s = ws_arr(ws, S_BW_LACC, (size_t)total, &b.lv_acc))) return s;
   if ((s = ws_arr(ws, S_BW_CTL, 8, &bctl))) return s;
   if ((s = ws_arr(ws, S_BW_GOFF, (size_t)num_graphs + 1, &goff))) return s;
   if ((s = ws_arr(ws, S_BW_GINST, (size_t)num_inst, &ginst))) return s;

@@ -174,7 +174,12 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
 // (blocks loop over the instances) and block barriers only: for deep trees
 // (grids, meshes), whose levels are many and small.  Instance i's level
 // list occupies lv_v[sbase_i, sbase_i + n_i) and the ends of its levels
-// lv_i[sbase_i + l] (a tree has at most n_i levels).
+// lv_i[sbase_i + l] (a tree has at most n_i levels).  The top-down pass
+// appends each entry's children together, in edge order, and entries'
+// children in list order, so the children of the entry at position p are
+// the list positions [lv_cs[p], lv_cs[p + 1]) (the list's end for the last
+// entry); the bottom-up pass sums them from lv_acc, the subtree sums by
+// list position, in that order (edge order, as the grid-wide pass does).
 __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
   __shared__ uint64_t scan[BBS / SSSP_WAVE + 1];
   __shared__ int32_t cnt;
@@ -184,7 +189,8 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
     const InstDev id = a.insts[ins];
     const GraphDev G = a.graphs[id.graph];  // by value: its fields stay in registers
     const int32_t sb = id.sbase;
-    int32_t *V = a.lv_v + sb, *LE = a.lv_i + sb;
+    int32_t *V = a.lv_v + sb, *LE = a.lv_i + sb, *CS = a.lv_cs + sb;
+    float *AL = a.lv_acc + sb;
     if (tid == 0) {
       V[0] = id.source;  // graph-local ids in this path
       cnt = 1;
@@ -227,6 +233,7 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
         }
         uint64_t tot;
         const uint64_t ex = block_excl_scan64<BBS>((uint64_t)nch, scan, &tot);
+        if (idx < e) CS[idx] = cnt + (int32_t)ex;  // (cnt is current: the scan's barriers)
         if (tot > 0) {
           uint32_t p = (uint32_t)cnt + (uint32_t)ex;
           if (idx < e && nch) {
@@ -253,29 +260,17 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
       __syncthreads();
     }
     lmax = L > lmax ? L : lmax;
-    // ---- bottom-up: deepest level first, children in edge-id order
+    // ---- bottom-up: deepest level first; an entry's children are the
+    // list range its top-down step recorded, summed in list (edge) order
+    const int nv = e;  // the tree's size: the list's end
     for (int lv = L - 1; lv >= 0; --lv) {
       const int ls = lv == 0 ? 0 : LE[lv - 1], le = LE[lv];
       for (int idx = ls + tid; idx < le; idx += BBS) {
         const int32_t y = V[idx];
+        const int32_t c0 = CS[idx], c1 = idx + 1 < nv ? CS[idx + 1] : nv;
         float acc = a.gcost[sb + y];
-        const int32_t k0 = G.u_out_off[y], k1 = G.u_out_off[y + 1];
-        // as above, four out-edges at a time; a head's subtree sum loads
-        // with its parent entry and counts only for a child (in edge order)
-        for (int32_t kb = k0; kb < k1; kb += 4) {
-          int32_t c[4], pr[4];
-          float av[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) c[q] = G.u_out_dst[kb + q < k1 ? kb + q : kb];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            pr[q] = a.pred[sb + c[q]];
-            av[q] = a.acc[sb + c[q]];
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (kb + q < k1 && c[q] != id.source && pr[q] == kb + q) acc = __fadd_rn(acc, av[q]);
-        }
+        for (int32_t p = c0; p < c1; ++p) acc = __fadd_rn(acc, AL[p]);
+        AL[idx] = acc;
         a.acc[sb + y] = acc;
       }
       __syncthreads();

@@ -137,9 +137,10 @@ __global__ __launch_bounds__(SBS) void small_rounds_kernel(RoundArgs a) {
         // the last window item with pfx <= e (an 8-ary search: four LDS steps)
         const int lo = search1024(s.pfx, (uint32_t)e);
         const int32_t pos = s.wbase[lo] + (e - s.pfx[lo]);
-        const int32_t y = G.out_dst[pos];
-        const int32_t w = G.out_w[pos];
-        const int32_t eid = G.out_eid ? G.out_eid[pos] : pos;
+        const int4 er = G.out_rec[pos];  // head, weight, edge id, the head's out_wmin
+        const int32_t y = er.x;
+        const int32_t w = er.y;
+        const int32_t eid = er.z;
         const int32_t dx = s.wdx[lo];
         const int32_t cand = V::add(dx, w);
         atomicMin(&s.D[y], make_key(cand, eid, cand == dx));

@@ -291,6 +291,10 @@ struct BackArgs {
   const float *gcost;
   float *acc;
   int32_t *lv_v, *lv_i;       // level lists (vertex state index, instance)
+  // one-workgroup path, per list position: where the entry's children start
+  // in the list, and the entry's subtree sum
+  int32_t *lv_cs;
+  float *lv_acc;
   int32_t *lv_off;            // level offsets, capacity total + 2
   int32_t *nlevels;           // device scalar: number of non-empty levels
   unsigned int *flags;        // grid barrier flags, kMaxBlocks * kFlagStride
