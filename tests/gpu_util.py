@@ -115,6 +115,17 @@ def check_solver_copy(G, n, src, dst, w):
             assert np.array_equal(vr[has, 5], nbr[order][first])
             assert np.array_equal(vr[has, 6], bits(np.ascontiguousarray(ow[order]))[first])
             assert not vr[~has, 5:7].any()
+            # the same in-lists as (tail, weight) pairs
+            assert np.array_equal(S["in_sw"][:, 0], nbr[order])
+            assert np.array_equal(S["in_sw"][:, 1], bits(np.ascontiguousarray(ow[order])))
+    # out-edge records of the working copy's out-lists (in input order the CSR
+    # itself): head solver id, weight, edge id, the head's out_wmin
+    oo = sides.get("out", eid)
+    rec = S["out_rec"]
+    assert np.array_equal(rec[:, 0], rank[head][oo])
+    assert np.array_equal(rec[:, 1], bits(np.ascontiguousarray(ow[oo])))
+    assert np.array_equal(rec[:, 2], oo)
+    assert np.array_equal(rec[:, 3], bits(np.ascontiguousarray(wmin[head[oo]])))
 
 
 def pool_map(fn, items):
