@@ -160,7 +160,9 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  *   {out_off, out_degree, in_off, in_degree, out_wmin, s_in_src and s_in_w
  *   of the first in-list entry (0, 0 with no in-edges), 0}, so that a round
  *   reads a vertex's offsets, out_wmin and lightest in-edge from one cache
- *   line.
+ *   line; and s_vin[4n], the record's in-side half {in_off, in_degree,
+ *   s_in_src and s_in_w of the first in-list entry} for passes that need
+ *   only that.
  * With SSSP_ORDER_INPUT, solver ids are vertex ids: vid, rank and
  * s_out_eid are NULL and s_out_off/dst/w/wmin alias the CSR arrays.
  * These arrays are library-internal; callers only keep them valid.
@@ -198,6 +200,7 @@ typedef struct {
   const int32_t *s_vrec;
   const int32_t *s_in_sw;
   const int32_t *s_out_rec;
+  const int32_t *s_vin;
 } sssp_csr;
 
 /*

@@ -50,7 +50,8 @@ class Csr(ctypes.Structure):
                 ("s_in_off", ctypes.c_void_p), ("s_in_src", ctypes.c_void_p),
                 ("s_in_eid", ctypes.c_void_p), ("s_in_w", ctypes.c_void_p),
                 ("s_out_wmin", ctypes.c_void_p), ("s_vrec", ctypes.c_void_p),
-                ("s_in_sw", ctypes.c_void_p), ("s_out_rec", ctypes.c_void_p)]
+                ("s_in_sw", ctypes.c_void_p), ("s_out_rec", ctypes.c_void_p),
+                ("s_vin", ctypes.c_void_p)]
 
 
 class Policy(ctypes.Structure):

@@ -194,7 +194,7 @@ bool csr_ok(const sssp_csr *g) {
         g->s_out_wmin && g->s_vrec &&
         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
                        g->s_out_dst && g->s_out_w && g->s_in_src && g->s_in_eid && g->s_in_w && g->s_in_sw &&
-                       g->s_out_rec))))
+                       g->s_out_rec && g->s_vin))))
     return false;
   if (g->order == SSSP_ORDER_INPUT) return true;
   return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && (g->m == 0 || g->s_out_eid);
@@ -266,6 +266,7 @@ GraphDev graph_dev(const sssp_csr *g) {
   d.in_w = (const int32_t *)g->s_in_w;
   d.in_sw = (const int2 *)g->s_in_sw;
   d.out_rec = (const int4 *)g->s_out_rec;
+  d.vin = (const int4 *)g->s_vin;
   d.out_wmin = (const int32_t *)g->s_out_wmin;
   d.vrec = (const int4 *)g->s_vrec;
   d.vid = g->vid;
@@ -288,7 +289,7 @@ GraphDev graph_dev(const sssp_csr *g) {
 // weight-ordered in-lists, then (degree order) the renumbered CSR.
 enum BufArr {
   B_OUT_OFF, B_OUT_DST, B_OUT_W, B_IN_OFF, B_IN_SRC, B_IN_EID, B_IN_W, B_OUT_WMIN,
-  B_S_IN_OFF, B_S_IN_SRC, B_S_IN_EID, B_S_IN_W, B_S_VREC, B_S_IN_SW, B_S_OUT_REC,
+  B_S_IN_OFF, B_S_IN_SRC, B_S_IN_EID, B_S_IN_W, B_S_VREC, B_S_IN_SW, B_S_OUT_REC, B_S_VIN,
   B_VID, B_RANK, B_S_OUT_OFF, B_S_OUT_DST, B_S_OUT_W, B_S_OUT_EID, B_S_OUT_WMIN, B_COUNT
 };
 
@@ -302,7 +303,7 @@ Layout build_layout(int32_t n, int32_t m, bool renumber) {
   size_t o = 0;
   const size_t N = (size_t)n, M = (size_t)m;
   const size_t count[B_COUNT] = {N + 1, M, M, N + 1, M, M, M, N, N + 1, M, M, M, 8 * N, 2 * M,
-                                 4 * M, N, N, N + 1, M, M, M, N};
+                                 4 * M, 4 * N, N, N, N + 1, M, M, M, N};
   const int narr = renumber ? B_COUNT : B_VID;
   for (int i = 0; i < B_COUNT; ++i) {
     L.off[i] = o;
@@ -327,6 +328,7 @@ SolverCopy solver_copy(const sssp_csr *g) {
   c.in_w = (int32_t *)g->s_in_w;
   c.in_sw = (int32_t *)g->s_in_sw;
   c.out_rec = (int32_t *)g->s_out_rec;
+  c.vin = (int32_t *)g->s_vin;
   c.out_wmin = (int32_t *)g->s_out_wmin;
   c.vrec = (int32_t *)g->s_vrec;
   return c;
@@ -652,6 +654,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   c.in_w = arr(B_S_IN_W);
   c.in_sw = arr(B_S_IN_SW);
   c.out_rec = arr(B_S_OUT_REC);
+  c.vin = arr(B_S_VIN);
   c.vrec = arr(B_S_VREC);
   if (m > 0) {
     HIPCHK(launch_degree(n, out_off, in_off, t, stream));
@@ -691,6 +694,7 @@ sssp_status sssp_build_csr(int32_t n, int32_t m, sssp_dtype dtype, sssp_order or
   out->s_in_w = c.in_w;
   out->s_in_sw = c.in_sw;
   out->s_out_rec = c.out_rec;
+  out->s_vin = c.vin;
   out->s_out_wmin = c.out_wmin;
   HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipEventRecord(ws.last, stream));

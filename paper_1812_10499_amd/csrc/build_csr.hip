@@ -542,17 +542,19 @@ hipError_t launch_in_lists(int32_t n, int32_t m, int32_t wkey_max, const int32_t
 // of one line of in_src and one of in_w per vertex.
 __global__ void vrec_kernel(int32_t n, const int32_t *out_off, const int32_t *in_off,
                             const int32_t *in_src, const int32_t *in_w,
-                            const int32_t *out_wmin, int4 *vrec) {
+                            const int32_t *out_wmin, int4 *vrec, int4 *vin) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const int32_t o = out_off[v], i = in_off[v], ideg = in_off[v + 1] - i;
+    const int32_t s0 = ideg ? in_src[i] : 0, w0 = ideg ? in_w[i] : 0;
     vrec[2 * v] = make_int4(o, out_off[v + 1] - o, i, ideg);
-    vrec[2 * v + 1] = make_int4(out_wmin[v], ideg ? in_src[i] : 0, ideg ? in_w[i] : 0, 0);
+    vrec[2 * v + 1] = make_int4(out_wmin[v], s0, w0, 0);
+    vin[v] = make_int4(i, ideg, s0, w0);
   }
 }
 
 hipError_t launch_vrec(int32_t n, const SolverCopy &c, hipStream_t stream) {
   hipLaunchKernelGGL(vrec_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, c.out_off,
-                     c.in_off, c.in_src, c.in_w, c.out_wmin, (int4 *)c.vrec);
+                     c.in_off, c.in_src, c.in_w, c.out_wmin, (int4 *)c.vrec, (int4 *)c.vin);
   return hipGetLastError();
 }
 

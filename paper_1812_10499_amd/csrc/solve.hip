@@ -1049,7 +1049,7 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
     int32_t y[LPT], ins[LPT], sb[LPT], gi[LPT], mdi[LPT], c[LPT];
     int32_t c0[LPT];
     unsigned long long dk[LPT];
-    int4 rec[LPT], rec2[LPT];
+    int4 rec[LPT];  // in_off, in_degree, lightest in-edge's tail and weight
     bool val[LPT], keep[LPT];
 #pragma unroll
     for (int k = 0; k < LPT; ++k) {
@@ -1081,30 +1081,26 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
         mdi[k] = ld_relaxed(&a.imin[s_now * I + ins[k]]);
       }
     }
-    // out_off, out_degree, in_off, in_degree; out_wmin, the lightest
-    // in-edge's tail and weight (the same line)
+    // the in-side half of the vertex record: in_off, in_degree, the
+    // lightest in-edge's tail and weight (16 bytes, not the 32 of vrec)
 #pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const GraphDev &G = graph_of<BATCH>(a, gi[k]);
-      rec[k] = G.vrec[2 * (y[k] - sb[k])];
-      rec2[k] = G.vrec[2 * (y[k] - sb[k]) + 1];
-    }
+    for (int k = 0; k < LPT; ++k) rec[k] = graph_of<BATCH>(a, gi[k]).vin[y[k] - sb[k]];
     // A batch also gathers the lightest in-edge's tail C here; a single
     // solve only where the tests below pass (measured faster there).  Round
     // 1 reads the initial C: 0 for every vertex but the source, and the
     // source is no tail of an undiscovered vertex, its out-edges having been
     // relaxed.
 #pragma unroll
-    for (int k = 0; k < LPT; ++k) c0[k] = (r == 1 || !BATCH) ? 0 : Cold[sb[k] + rec2[k].y];
+    for (int k = 0; k < LPT; ++k) c0[k] = (r == 1 || !BATCH) ? 0 : Cold[sb[k] + rec[k].z];
 #pragma unroll
     for (int k = 0; k < LPT; ++k)
-      asm volatile("" : "+v"(dk[k]), "+v"(c[k]), "+v"(c0[k]), "+v"(rec[k].z), "+v"(rec[k].w),
-                   "+v"(rec2[k].z));
+      asm volatile("" : "+v"(dk[k]), "+v"(c[k]), "+v"(c0[k]), "+v"(rec[k].x), "+v"(rec[k].y),
+                   "+v"(rec[k].w));
 #pragma unroll
     for (int k = 0; k < LPT; ++k) {
       const GraphDev &G = graph_of<BATCH>(a, gi[k]);
       if (!(val[k] && G.all && mdi[k] != V::INF && (int32_t)(dk[k] >> 32) == V::INF)) continue;
-      const int32_t b = rec[k].z, deg = rec[k].w;
+      const int32_t b = rec[k].x, deg = rec[k].y;
       const int32_t *Cg = Cold + sb[k];  // the instance's C, by graph-local id
       if constexpr (BATCH) {
         if (I > kLdsInst) atomicAdd(&a.iscanned[3 * ins[k]], (unsigned long long)deg);
@@ -1130,8 +1126,8 @@ __device__ void live_pass(const RoundArgs &a, SmemAll &sm, BatchLds<BATCH> &bl,
       const int32_t mk = mdi[k];
       if (deg > 0) {
         // the lightest in-edge alone first: its tail usually decides m
-        const int32_t w0 = rec2[k].z;
-        const int32_t cz = (BATCH || r == 1) ? c0[k] : Cg[rec2[k].y];
+        const int32_t w0 = rec[k].w;
+        const int32_t cz = (BATCH || r == 1) ? c0[k] : Cg[rec[k].z];
         if (cz != V::INF) m = V::add(kmax(cz, mk), w0);
         j = (V::add(mk, w0) >= m) ? deg : 1;
       }

@@ -56,6 +56,7 @@ struct GraphDev {
   const int32_t *in_off, *in_src, *in_w;
   const int2 *in_sw;
   const int4 *out_rec;
+  const int4 *vin;  // per vertex {in_off, in_degree, lightest in-edge's tail, its weight}
   const int32_t *out_wmin;
   const int4 *vrec;
   const int32_t *vid, *rank;

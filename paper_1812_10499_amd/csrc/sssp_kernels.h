@@ -243,6 +243,7 @@ struct SolverCopy {
   int32_t *out_rec;  // (out_dst, out_w, edge id, out_wmin of the head) per out-list entry
   int32_t *out_wmin;
   int32_t *vrec;  // 8 ints per vertex
+  int32_t *vin;   // 4 ints per vertex: vrec's in_off, in_degree, lightest tail and weight
 };
 size_t build_hist_entries(int32_t m);
 hipError_t launch_validate(int32_t n, int32_t m, bool f32, const int32_t *src,

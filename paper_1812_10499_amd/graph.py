@@ -194,14 +194,16 @@ class Graph:
     def solver_arrays(self) -> dict:
         """Views of the solver's working copy: the weight-ordered in-lists (also
         as (tail, weight-bits) pairs), the out-edge records (head, weight bits,
-        edge id, the head's out_wmin bits), the vertex records, and in degree
+        edge id, the head's out_wmin bits), the vertex records and their
+        in-side halves, and in degree
         order also vid, rank and the renumbered out-lists."""
         c, n, m, vt = self.csr, self.n, self.m, self.value_dtype
         out = dict(in_off=self._view(c.s_in_off, n + 1), in_src=self._view(c.s_in_src, m),
                    in_eid=self._view(c.s_in_eid, m), in_w=self._view(c.s_in_w, m, vt),
                    in_sw=self._view(c.s_in_sw, 2 * m).view(m, 2),
                    out_rec=self._view(c.s_out_rec, 4 * m).view(m, 4),
-                   vrec=self._view(c.s_vrec, 8 * n).view(n, 8))
+                   vrec=self._view(c.s_vrec, 8 * n).view(n, 8),
+                   vin=self._view(c.s_vin, 4 * n).view(n, 4))
         if self.csr.order == SSSP_ORDER_DEGREE:
             out.update(vid=self._view(c.vid, n), rank=self._view(c.rank, n),
                        out_off=self._view(c.s_out_off, n + 1),

@@ -99,6 +99,9 @@ def check_solver_copy(G, n, src, dst, w):
     assert np.array_equal(vr[:, 2], in_off_s[:-1]) and np.array_equal(vr[:, 3], np.diff(in_off_s))
     assert np.array_equal(vr[:, 4], bits(np.ascontiguousarray(wmin_s)))
     assert not vr[:, 7].any()
+    # the in-side half: in_off, in_degree, the lightest in-edge's tail and weight
+    vin = S["vin"]
+    assert np.array_equal(vin[:, 0:2], vr[:, 2:4]) and np.array_equal(vin[:, 2:4], vr[:, 5:7])
     for side, order in sides.items():
         key = rank[tail] if side == "out" else rank[head]
         nbr = rank[head] if side == "out" else rank[tail]

@@ -72,7 +72,7 @@ def _fake_csr(sp, n=10, m=20, dtype=0, w_max=5.0):
     c.n, c.m, c.dtype, c.w_max, c.order = n, m, dtype, w_max, sp.SSSP_ORDER_INPUT
     for f in ("out_off", "out_dst", "out_w", "in_off", "in_src", "in_eid", "in_w", "out_wmin",
               "s_out_off", "s_out_dst", "s_out_w", "s_in_off", "s_in_src", "s_in_eid", "s_in_w",
-              "s_out_wmin", "s_vrec", "s_in_sw", "s_out_rec"):
+              "s_out_wmin", "s_vrec", "s_in_sw", "s_out_rec", "s_vin"):
         setattr(c, f, 0x1000)  # never dereferenced: every call below fails its host checks
     return c
 
