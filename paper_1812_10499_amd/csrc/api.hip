@@ -191,10 +191,10 @@ bool csr_ok(const sssp_csr *g) {
         g->relax >= SSSP_RELAX_AUTO && g->relax <= SSSP_RELAX_CORRECTING && g->delta >= 0 &&
         g->delta <= (g->dtype == SSSP_F32 ? 0x7f800000 : 0x7fffffff) &&
         g->out_off && g->in_off && g->out_wmin && g->s_out_off && g->s_in_off &&
-        g->s_out_wmin && g->s_vrec &&
+        g->s_out_wmin && g->s_vrec && g->s_vin &&
         (g->m == 0 || (g->out_dst && g->out_w && g->in_src && g->in_eid && g->in_w &&
-                       g->s_out_dst && g->s_out_w && g->s_in_src && g->s_in_eid && g->s_in_w && g->s_in_sw &&
-                       g->s_out_rec && g->s_vin))))
+                       g->s_out_dst && g->s_out_w && g->s_in_src && g->s_in_eid && g->s_in_w &&
+                       g->s_in_sw && g->s_out_rec))))
     return false;
   if (g->order == SSSP_ORDER_INPUT) return true;
   return g->order == SSSP_ORDER_DEGREE && g->vid && g->rank && (g->m == 0 || g->s_out_eid);
