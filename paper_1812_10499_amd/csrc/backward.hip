@@ -180,9 +180,15 @@ __global__ __launch_bounds__(BBS) void bw_levels_kernel(BackArgs a) {
 // the list positions [lv_cs[p], lv_cs[p + 1]) (the list's end for the last
 // entry); the bottom-up pass sums them from lv_acc, the subtree sums by
 // list position, in that order (edge order, as the grid-wide pass does).
+// The top-down step also keeps the level it builds in LDS (the first
+// kLevelLds entries, double-buffered by level parity), so the next step reads
+// its entries there instead of from the global list it has just written.
+constexpr int kLevelLds = 4096;
+
 __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
   __shared__ uint64_t scan[BBS / SSSP_WAVE + 1];
   __shared__ int32_t cnt;
+  __shared__ int32_t lvl[2][kLevelLds];
   const int tid = threadIdx.x;
   int lmax = 0;
   for (int ins = blockIdx.x; ins < a.num_inst; ins += gridDim.x) {
@@ -193,12 +199,16 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
     float *AL = a.lv_acc + sb;
     if (tid == 0) {
       V[0] = id.source;  // graph-local ids in this path
+      lvl[0][0] = id.source;
       cnt = 1;
     }
     __syncthreads();
-    // ---- top-down: level L occupies [s, e) of V
+    // ---- top-down: level L occupies [s, e) of V, and its first kLevelLds
+    // entries lvl[L & 1]
     int s = 0, e = 1, L = 0;
     while (s < e) {
+      const int32_t *cur = lvl[L & 1];
+      int32_t *nxt = lvl[(L & 1) ^ 1];
       for (int b0 = s; b0 < e; b0 += BBS) {
         const int idx = b0 + tid;
         int32_t k0 = 0, k1 = 0;
@@ -207,7 +217,7 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
         uint32_t cm = 0;
         int32_t cc[4] = {0, 0, 0, 0};
         if (idx < e) {
-          const int32_t x = V[idx];
+          const int32_t x = idx - s < kLevelLds ? cur[idx - s] : V[idx];
           k0 = G.u_out_off[x];
           k1 = G.u_out_off[x + 1];
           // four out-edges at a time: their heads, then the heads' parent
@@ -237,14 +247,24 @@ __global__ __launch_bounds__(BBS) void bw_wg_kernel(BackArgs a) {
         if (tot > 0) {
           uint32_t p = (uint32_t)cnt + (uint32_t)ex;
           if (idx < e && nch) {
+            // the next level starts at e: entry p is its entry p - e
             if (k1 - k0 <= 4) {
 #pragma unroll
-              for (int q = 0; q < 4; ++q)
-                if ((cm >> q) & 1u) V[p++] = cc[q];
+              for (int q = 0; q < 4; ++q) {
+                if ((cm >> q) & 1u) {
+                  V[p] = cc[q];
+                  if (p - (uint32_t)e < (uint32_t)kLevelLds) nxt[p - e] = cc[q];
+                  ++p;
+                }
+              }
             } else {
               for (int32_t k = k0; k < k1; ++k) {
                 const int32_t c = G.u_out_dst[k];
-                if (c != id.source && a.pred[sb + c] == k) V[p++] = c;
+                if (c != id.source && a.pred[sb + c] == k) {
+                  V[p] = c;
+                  if (p - (uint32_t)e < (uint32_t)kLevelLds) nxt[p - e] = c;
+                  ++p;
+                }
               }
             }
           }
