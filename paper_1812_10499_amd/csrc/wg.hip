@@ -15,6 +15,9 @@ namespace sssp {
 constexpr int WBS = 1024;  // threads of the workgroup
 static_assert(WBS == 1024, "the relax window search covers 1024 items");
 constexpr int kWgItems = 2;  // open-list entries per thread and pass of the bound step
+// relax items kept in LDS (x, D to relax from, out-offset, out-degree); the
+// rest of a longer relax set lives in the global arrays
+constexpr int kRelLds = 2048;
 
 struct WgLds {
   int32_t pfx[WBS + 1];  // out-degree prefix of a window of relax items
@@ -24,6 +27,7 @@ struct WgLds {
   int32_t red[2 * (WBS / SSSP_WAVE)];
   int32_t nF, nF2, nO, nO2, target_hit;
   unsigned long long relaxed, scanned, visits, settled;
+  int4 rel[kRelLds];  // relax items [0, kRelLds): written by the fix step, read by the relax
 };
 
 // The open entries' payload by list parity, as two int4 arrays of
@@ -32,6 +36,21 @@ struct WgLds {
 // record holds 0).
 __device__ __forceinline__ int4 *wg_payload(const RoundArgs &a, int parity, int32_t sb) {
   return (int4 *)(parity ? a.open_x1[0] : a.open_x0[0]) + sb;
+}
+
+// Relax item q of the next round: in LDS when it fits, else in the global
+// arrays.
+__device__ __forceinline__ void push_rel(WgLds &s, int32_t *F, int32_t *FD, int32_t *FO,
+                                         int32_t *FG, int q, int32_t x, int32_t fd, int32_t fo,
+                                         int32_t fg) {
+  if (q < kRelLds) {
+    s.rel[q] = make_int4(x, fd, fo, fg);
+  } else {
+    F[q] = x;
+    FD[q] = fd;
+    FO[q] = fo;
+    FG[q] = fg;
+  }
 }
 
 template <class V, bool BATCH>
@@ -73,7 +92,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
     // and read by plain accesses of this workgroup only
     unsigned long long *D = a.D64 + sb;
     int32_t *C[2] = {a.C0 + sb, a.C1 + sb};
-    // relax items: vertex, D to relax from, out-offset, out-degree
+    // relax items beyond the first kRelLds (those stay in LDS): vertex, D
+    // to relax from, out-offset, out-degree
     int32_t *F = a.front_v + sb, *FD = a.front_x[FX_D] + sb;
     int32_t *FO = a.front_x[FX_OOFF] + sb, *FG = a.front_p + sb;
     // open entries by parity: the vertex, its payload (wg_payload) and the
@@ -88,10 +108,8 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
       C[0][y] = C[1][y] = is_s ? V::INF : 0;  // the source is fixed from the start
     }
     if (tid == 0) {
-      F[0] = src;
-      FD[0] = 0;
-      FO[0] = G.out_off[src];
-      FG[0] = G.out_off[src + 1] - FO[0];
+      const int32_t o0 = G.out_off[src];
+      s.rel[0] = make_int4(src, 0, o0, G.out_off[src + 1] - o0);
       s.nF = 1;
       s.nO = 0;
       s.target_hit = (tgt >= 0 && tgt == src) ? 1 : 0;
@@ -129,13 +147,16 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
         const int i = i0 + tid;
         int32_t deg = 0;
         if (i < nF) {
-          const int32_t x = F[i];
-          const int32_t fd = FD[i];
+          // (x, relax D, out-offset, out-degree), from LDS for the first
+          // kRelLds items
+          const int4 f = i < kRelLds ? s.rel[i] : make_int4(F[i], FD[i], 0, 0);
+          const int32_t x = f.x;
+          const int32_t fd = f.y;
           const int32_t dx = fd & 0x7fffffff;
           if (fd >= 0) Cnew[x] = V::INF;
           if (dx != V::INF) {
-            deg = FG[i];
-            s.wbase[tid] = FO[i];
+            deg = i < kRelLds ? f.w : FG[i];
+            s.wbase[tid] = i < kRelLds ? f.z : FO[i];
             s.wdx[tid] = dx;
           }
         }
@@ -294,10 +315,7 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             ++nfix;
             if (y[u] == tgt) s.target_hit = 1;
             const int q = atomicAdd(&s.nF2, 1);
-            F[q] = y[u];
-            FD[q] = relax_again ? dy[u] : V::INF;
-            FO[q] = ra[u].x;
-            FG[q] = ra[u].y;
+            push_rel(s, F, FD, FO, FG, q, y[u], relax_again ? dy[u] : V::INF, ra[u].x, ra[u].y);
           } else {
             Cnew[y[u]] = cn;
             // label-correcting: relaxed again from its lower D (while in the
@@ -313,10 +331,7 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             sth = kmin(sth, V::add(dy[u], rb[u].x));
             if (again) {
               const int p = atomicAdd(&s.nF2, 1);
-              F[p] = y[u];
-              FD[p] = dy[u] | kOpenRelax;
-              FO[p] = ra[u].x;
-              FG[p] = ra[u].y;
+              push_rel(s, F, FD, FO, FG, p, y[u], dy[u] | kOpenRelax, ra[u].x, ra[u].y);
             }
           }
         }
