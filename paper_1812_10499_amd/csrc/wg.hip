@@ -18,18 +18,6 @@ constexpr int kWgItems = 2;  // open-list entries per thread and pass of the bou
 // relax items kept in LDS (x, D to relax from, out-offset, out-degree); the
 // rest of a longer relax set lives in the global arrays
 constexpr int kRelLds = 2048;
-// open-list entries kept in LDS per list parity: the first pass slot of the
-// bound step (entries [0, WBS)) reads them there
-constexpr int kOpenLds = WBS;
-
-// The first kOpenLds entries of an open list: vertex, D it was last relaxed
-// with, and the payload (the vertex record's two halves, C in the last word).
-struct WgOpenLds {
-  int32_t y[kOpenLds];
-  int32_t dr[kOpenLds];
-  int4 p[kOpenLds];
-  int4 q[kOpenLds];
-};
 
 struct WgLds {
   int32_t pfx[WBS + 1];  // out-degree prefix of a window of relax items
@@ -40,7 +28,6 @@ struct WgLds {
   int32_t nF, nF2, nO, nO2, target_hit;
   unsigned long long relaxed, scanned, visits, settled;
   int4 rel[kRelLds];  // relax items [0, kRelLds): written by the fix step, read by the relax
-  WgOpenLds open[2];  // by list parity
 };
 
 // The open entries' payload by list parity, as two int4 arrays of
@@ -197,11 +184,7 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
           }
           // a first discovery joins the open list after the survivors, with
           // no payload: its bound step reads the vertex record
-          if (od == V::INF) {
-            const int q = atomicAdd(&s.nO, 1);
-            if (q < kOpenLds) s.open[o].y[q] = y;
-            else O[o][q] = y;
-          }
+          if (od == V::INF) O[o][atomicAdd(&s.nO, 1)] = y;
         }
         __syncthreads();
       }
@@ -256,17 +239,10 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             const int i = i0 + u * WBS + tid;
             const int ic = ok[u] ? i : 0;
             const int ip = i < nS ? i : 0;  // (first discoveries: one line for all)
-            if (i0 + u * WBS < kOpenLds) {  // (block-uniform: the first slot of the first pass)
-              y[u] = s.open[o].y[ic];
-              ra[u] = s.open[o].p[ip];
-              rb[u] = s.open[o].q[ip];
-              dr[u] = s.open[o].dr[ip];
-            } else {
-              y[u] = O[o][ic];
-              ra[u] = Pc[ip];
-              rb[u] = Qc[ip];
-              dr[u] = OR[o][ip];
-            }
+            y[u] = O[o][ic];
+            ra[u] = Pc[ip];
+            rb[u] = Qc[ip];
+            dr[u] = OR[o][ip];
           }
         }
         bool fdw = false;
@@ -346,19 +322,11 @@ __global__ __launch_bounds__(WBS) void wg_rounds_kernel(RoundArgs a) {
             // first bucket above minD)
             const bool again = lc && relax_again && dy[u] < V::add(md, G.delta);
             const int q = atomicAdd(&s.nO2, 1);
-            const int32_t drn = again ? dy[u] : dr[u];
+            O[o ^ 1][q] = y[u];
             rb[u].w = cn;
-            if (q < kOpenLds) {
-              s.open[o ^ 1].y[q] = y[u];
-              s.open[o ^ 1].p[q] = ra[u];
-              s.open[o ^ 1].q[q] = rb[u];
-              s.open[o ^ 1].dr[q] = drn;
-            } else {
-              O[o ^ 1][q] = y[u];
-              Pn[q] = ra[u];
-              Qn[q] = rb[u];
-              OR[o ^ 1][q] = drn;
-            }
+            Pn[q] = ra[u];
+            Qn[q] = rb[u];
+            OR[o ^ 1][q] = again ? dy[u] : dr[u];
             smd = kmin(smd, dy[u]);
             sth = kmin(sth, V::add(dy[u], rb[u].x));
             if (again) {
