@@ -126,6 +126,16 @@ def test_host_argument_errors(sp):
     bad = _fake_csr(sp)
     bad.s_in_w = None  # the in-list copy is required in every order
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
+    # so are the paired in-lists, the out-edge records and the in-records
+    for f in ("s_in_sw", "s_out_rec", "s_vin"):
+        bad = _fake_csr(sp)
+        setattr(bad, f, None)
+        assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S, f
+    # an edgeless graph needs no per-edge arrays, but still its in-records
+    bad = _fake_csr(sp, m=0)
+    bad.s_in_sw = bad.s_out_rec = None
+    bad.s_vin = None
+    assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
     bad = _fake_csr(sp)
     bad.scope = 3  # not an sssp_scope
     assert _status(lambda: sp.sssp_solve(bad, 0, 0x1000, None, None, None)) == S
