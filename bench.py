@@ -45,6 +45,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """A device-to-device copy of nbytes (torch's copy kernel), read plus
+    written bytes over its mean time in GB/s: the practical HBM rate the
+    roofline fraction is also quoted against.  Measured after the timed
+    region, on the current stream."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def measured_traffic(workload: str):
     """HBM bytes per round-kernel launch from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
@@ -505,6 +526,9 @@ def main():
     traffic = measured_traffic(args.workload) if g.n > 4096 else None
     log("step %.3f ms, round kernel %.3f ms (%d launches), %.2f GTEPS, %.1f GB/s algorithmic"
         % (ms_step, k_ms, launches, gteps, achieved))
+    copy_gbps = copy_bandwidth(torch) if g.n > 4096 else None
+    if copy_gbps:
+        log("device-to-device copy %.1f GB/s" % copy_gbps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -544,7 +568,9 @@ def main():
                      "kernel": G.kernel,
                      "kernel_ms": round(k_ms, 4), "algorithmic_bytes": alg_bytes,
                      "traffic_gbps": (round(traffic / (k_ms * 1e-3) / 1e9, 1)
-                                      if traffic is not None else None)},
+                                      if traffic is not None else None),
+                     "copy_gbps": round(copy_gbps, 1) if copy_gbps else None,
+                     "frac_of_copy": round(achieved / copy_gbps, 4) if copy_gbps else None},
         "cpu_baseline": cpu,
     }
     if G.kernel in ("small_rounds_kernel", "wg_rounds_kernel"):
