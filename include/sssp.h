@@ -150,19 +150,22 @@ typedef enum { SSSP_RELAX_AUTO = 0, SSSP_RELAX_SETTING = 1, SSSP_RELAX_CORRECTIN
  *   s_out_off[n+1], s_out_dst[m] (solver ids), s_out_w[m], s_out_eid[m]
  *       each out-list ascending by (head solver id, edge id)
  *   s_out_wmin[n]  out_wmin by solver id
- * and s_in_sw[2m]: s_in_src and s_in_w of each in-list entry side by side
- *   (entry j at 2j, 2j + 1), so that a scan reads an in-edge's tail and
- *   weight from one place.
- * and s_out_rec[4m]: per entry of the working copy's out-lists (s_out_*),
- *   {head solver id, weight, edge id, out_wmin of the head}, so that a
- *   relax reads an out-edge and its head's out_wmin from one place.
- * Always, too: s_vrec[8n], one 32-byte record per solver vertex,
- *   {out_off, out_degree, in_off, in_degree, out_wmin, s_in_src and s_in_w
- *   of the first in-list entry (0, 0 with no in-edges), 0}, so that a round
- *   reads a vertex's offsets, out_wmin and lightest in-edge from one cache
- *   line; and s_vin[4n], the record's in-side half {in_off, in_degree,
- *   s_in_src and s_in_w of the first in-list entry} for passes that need
- *   only that.
+ * Always, too:
+ *   s_in_sw[2m]: s_in_src and s_in_w of each in-list entry side by side
+ *     (entry j at 2j, 2j + 1), so that a scan reads an in-edge's tail and
+ *     weight from one place;
+ *   s_out_rec[4m]: per entry of the out-lists s_out_* (the CSR itself in
+ *     input order), {head solver id, weight, edge id, out_wmin of the
+ *     head}, so that a relax reads an out-edge and its head's out_wmin
+ *     from one place;
+ *   s_vrec[8n], one 32-byte record per solver vertex,
+ *     {out_off, out_degree, in_off, in_degree, out_wmin, s_in_src and s_in_w
+ *     of the first in-list entry (0, 0 with no in-edges), 0}, so that a
+ *     round reads a vertex's offsets, out_wmin and lightest in-edge from one
+ *     cache line;
+ *   s_vin[4n], the record's in-side half {in_off, in_degree, s_in_src and
+ *     s_in_w of the first in-list entry}, for passes that need only that.
+ * sssp_set_weights rebuilds every weight-dependent array among them.
  * With SSSP_ORDER_INPUT, solver ids are vertex ids: vid, rank and
  * s_out_eid are NULL and s_out_off/dst/w/wmin alias the CSR arrays.
  * These arrays are library-internal; callers only keep them valid.
